@@ -1,0 +1,215 @@
+/*
+ * wvl.h -- C ABI of the MI355X local-Hamiltonian library for linear-scaling
+ * Daubechies-wavelet DFT (Mohr et al., arXiv:1401.7441).
+ *
+ * The library applies the local Kohn-Sham Hamiltonian (kinetic energy plus a
+ * local potential) to many localized support functions, each stored
+ * compressed on its own localization region, and forms the sparse overlap
+ * and Hamiltonian matrices between support functions whose regions overlap.
+ *
+ * Problem statement followed by every call (paper sections):
+ *   Sec. II.B, Eq. (Phi): two-level basis on a uniform coarse grid of spacing
+ *     h with the origin in a corner; a coarse point carries one scaling
+ *     function, a fine point one scaling function plus seven wavelets of the
+ *     least-asymmetric Daubechies family of order 16.
+ *   Sec. III: a support function keeps only the coefficients within R_cut of
+ *     its centre (the projector L); Sec. III.B: H is applied as
+ *     L' H L |phi> with L' the region grown by `ext` grid points (8 in the
+ *     paper).
+ *   Sec. II.A: S_ab = <phi_a|phi_b>, H_ab = <phi_a|H|phi_b>.
+ *
+ * Memory: every pointer documented as "device" is a caller-owned device
+ * buffer (HIP global memory, e.g. a torch tensor's data_ptr()); the library
+ * never frees caller memory.  "host" pointers are read during the call only.
+ * Element type of coefficient, potential and box buffers: float for WVL_F32,
+ * double for WVL_F64.  Energies and matrix values are always double.
+ *
+ * Asynchrony: compute calls only enqueue work on the context's stream and
+ * return; results are ready after that stream is synchronized.  Exceptions:
+ * wvl_plan_create (waits for its host-to-device copies) and the pattern phase
+ * of wvl_sparse_overlap (returns nnz to the host, so it synchronizes).
+ *
+ * Errors: every call returns a wvl_status.  WVL_EINVAL means the arguments
+ * were rejected before anything was launched; wvl_last_error() names the
+ * offending support function or segment.  WVL_EDEVICE reports a HIP failure.
+ * No C++ exception crosses this interface.
+ *
+ * Threading: a context is bound to one HIP stream and must not be used from
+ * two threads at once.  Plans are immutable after creation and may be
+ * applied any number of times.
+ */
+#ifndef WVL_H
+#define WVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WVL_ABI_VERSION 1
+
+typedef enum {
+  WVL_OK = 0,
+  WVL_EINVAL = -1,       /* invalid argument, nothing launched             */
+  WVL_ENOMEM = -2,       /* device allocation by the library failed         */
+  WVL_EDEVICE = -3,      /* a HIP call or kernel launch failed              */
+  WVL_EUNSUPPORTED = -4  /* valid request this build does not support       */
+} wvl_status;
+
+typedef enum { WVL_F32 = 0, WVL_F64 = 1 } wvl_dtype;
+
+/* terms of wvl_apply_local_ham */
+enum { WVL_KIN = 1u, WVL_POT = 2u };
+
+/* Global grid (Sec. II.B).  n[0..2] coarse points along x, y, z; coarse point
+ * (i1, i2, i3) sits at h*(i1, i2, i3) bohr.  The potential lives on the fine
+ * grid of 2n+29 points per axis, spacing h/2; fine point p sits at
+ * (p - 14)*h/2, and is stored V[p3][p2][p1] with p1 fastest. */
+typedef struct {
+  double h;
+  int32_t n[3];
+} wvl_grid;
+
+/* One segment: the coarse points i1 = i1s..i1e (inclusive) at fixed (i2, i3),
+ * in global coarse indices.  `off` is the position of point i1s in the
+ * compressed component array the segment belongs to (scaling coefficients
+ * for coarse segments, each wavelet component for fine segments). */
+typedef struct {
+  int32_t i1s, i1e, i2, i3;
+  int64_t off;
+} wvl_seg;
+
+/* One localization region (Sec. III) and where its coefficients live.
+ *
+ * Input pattern: coarse segments seg[seg_c .. seg_c+nseg_c), fine segments
+ * seg[seg_f .. seg_f+nseg_f).  Output (L') pattern: oseg_c/noseg_c and
+ * oseg_f/noseg_f.  Segment lists are sorted by (i3, i2, i1s), disjoint, with
+ * `off` the running sum of lengths starting at 0; every fine segment lies
+ * inside a coarse segment of the same pattern.
+ *
+ * Input box: lo[a] .. lo[a]+dims[a]-1 per axis (inside the grid), holding the
+ * input pattern.  Output box: the input box grown by `ext` on every side
+ * (0 <= ext <= 16); the output pattern lies inside it and inside the grid.
+ *
+ * Compressed layout (SoA) of the input coefficients, starting at element
+ * coef_off of the batch buffer: [s: n_c][d1: n_f]...[d7: n_f], where n_c and
+ * n_f are the coarse and fine point counts of the input pattern; wavelet
+ * component l = a1 + 2 a2 + 4 a3 (a_d = 1: wavelet along axis d).  Output
+ * coefficients likewise at ocoef_off with on_c, on_f.
+ *
+ * center/radius/fine_radius describe the sphere the pattern was built from
+ * (informational; radius <= 0 for patterns not built from a sphere). */
+typedef struct {
+  double center[3];
+  double radius;
+  double fine_radius;
+  int32_t ext;
+  int32_t lo[3];
+  int32_t dims[3];
+  int32_t pad_;
+  int64_t seg_c, nseg_c, seg_f, nseg_f;
+  int64_t oseg_c, noseg_c, oseg_f, noseg_f;
+  int64_t coef_off, n_c, n_f;
+  int64_t ocoef_off, on_c, on_f;
+} wvl_locreg;
+
+typedef struct {
+  int64_t nsf;
+  int64_t in_coefs;     /* elements of the input coefficient buffer       */
+  int64_t out_coefs;    /* elements of the output coefficient buffer      */
+  int64_t in_box;       /* elements of the dense input boxes (uncompress) */
+  int64_t out_box;      /* elements of the dense output boxes (compress)  */
+  int64_t workspace_f32;/* workspace bytes for WVL_F32                     */
+  int64_t workspace_f64;/* workspace bytes for WVL_F64                     */
+  int64_t chunks;       /* support-function chunks one apply iterates     */
+} wvl_plan_info;
+
+typedef struct wvl_ctx wvl_ctx;
+typedef struct wvl_plan wvl_plan;
+
+/* Localization regions of spheres (Sec. III; host-only, no device use).
+ * Coarse set of function k: grid points with
+ *   (h*i1-X)^2 + (h*i2-Y)^2 + (h*i3-Z)^2 <= R*R
+ * evaluated in double precision in exactly that order without contraction;
+ * input box = its bounding box.  Fine set: the coarse points within
+ * fine_radii[k].  Output coarse set: points within R + ext*h that lie in the
+ * input box grown by ext and in the grid.  Output fine set: output coarse
+ * points belonging to the union of all functions' input fine sets.
+ * Coefficient offsets are laid out back to back in function order.
+ *   centers: host [nsf][3]; radii, fine_radii: host [nsf]
+ *   lr: host out [nsf]; segs: host out [*nsegs] or NULL
+ *   nsegs: in = capacity of segs, out = segments needed.  With segs NULL or
+ *   too small, fills lr's counts, sets *nsegs and returns WVL_OK only when
+ *   segs was NULL (WVL_EINVAL when a non-NULL segs is too small).
+ * Errors: WVL_EINVAL for h <= 0, an empty region, or radii < 0. */
+wvl_status wvl_build_locregs(const wvl_grid* grid, int32_t nsf, const double* centers,
+                             const double* radii, const double* fine_radii, int32_t ext,
+                             wvl_locreg* lr, wvl_seg* segs, int64_t* nsegs);
+
+/* Context bound to a grid and a HIP stream (hipStream_t; NULL = default). */
+wvl_status wvl_create(wvl_ctx** ctx, const wvl_grid* grid, void* hip_stream);
+void wvl_destroy(wvl_ctx* ctx);
+/* Message of the last failed call on ctx (ctx NULL: of the last failed
+ * context-free call on this thread).  Never NULL. */
+const char* wvl_last_error(const wvl_ctx* ctx);
+
+/* Validates and uploads a batch of localization regions (host arrays lr[nsf],
+ * segs[nsegs]).  max_workspace_bytes bounds the FP64 workspace (0: no bound);
+ * functions are then processed in chunks that fit.  *workspace_bytes
+ * receives the FP64 workspace size (wvl_plan_info gives both dtypes). */
+wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, const wvl_seg* segs,
+                           int64_t nsegs, size_t max_workspace_bytes, wvl_plan** plan,
+                           size_t* workspace_bytes);
+void wvl_plan_destroy(wvl_plan* plan);
+wvl_status wvl_plan_info_get(const wvl_plan* plan, wvl_plan_info* info);
+
+/* Uncompress (Sec. III, compressed storage): psi_c (device, input pattern
+ * layout) -> psi_box (device): function k's dense box
+ * [8][dims2][dims1][dims0] (component, z, y, x; x fastest) starting at the
+ * running sum of 8*prod(dims) of the functions before it; zero off-pattern. */
+wvl_status wvl_uncompress(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* psi_box);
+
+/* Compress onto the output (L') pattern: box (device, function k's dense
+ * output box [8][dims2+2e][dims1+2e][dims0+2e] at the running sum of their
+ * sizes) -> hpsi_c (device, output layout, overwritten). */
+wvl_status wvl_compress(wvl_plan* plan, wvl_dtype dt, const void* box, void* hpsi_c);
+
+/* Local Hamiltonian (Sec. III.B): hpsi = L' (T + V) L psi for every function.
+ *   terms: WVL_KIN and/or WVL_POT.
+ *   psi_c: device, input layout.  pot: device global fine-grid potential
+ *   (see wvl_grid), may be NULL without WVL_POT.  hpsi_c: device, output
+ *   layout, overwritten.  e_kin / e_pot: device double[nsf] or NULL:
+ *   <phi|T|phi> and the potential energy sum_r V f(r)^2 on the fine grid.
+ *   workspace: device, at least the plan's workspace size for dt.
+ * T is the exact Galerkin kinetic operator of the two-level basis; V is the
+ * magic-filter quadrature of the local potential on the fine grid. */
+wvl_status wvl_apply_local_ham(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                               const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                               void* workspace);
+
+/* Kinetic term only (Sec. III.B, the -1/2 nabla^2 part), ACCUMULATED into
+ * hpsi_c (device, output layout): hpsi += L' T L psi.  e_kin as above. */
+wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hpsi_c,
+                       double* e_kin, void* workspace);
+
+/* Sparse overlap (ket_is_output = 0: S_ab = <phi_a|phi_b>, ket in the input
+ * layout) or Hamiltonian (1: H_ab = <phi_a|H phi_b>, ket = the output of
+ * wvl_apply_local_ham in the output layout) matrix (Sec. II.A).
+ * Pattern: (a, b) is present when a's input coarse set shares a point with
+ * b's input (S) or output (H) coarse set.  CSR, rows ascending, columns
+ * ascending within a row.
+ * Two phases: with rowptr, col and val all NULL the pattern is computed on
+ * the device, cached in the plan, *nnz set (the call synchronizes the
+ * stream).  Otherwise rowptr (device int64[nsf+1]), col (device int32[nnz])
+ * and val (device double[nnz]) are filled, each optional; values are dot
+ * products accumulated in double in an order fixed per pair. */
+wvl_status wvl_sparse_overlap(wvl_plan* plan, const void* bra_c, int ket_is_output,
+                              const void* ket_c, wvl_dtype dt, int64_t* nnz, int64_t* rowptr,
+                              int32_t* col, double* val);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WVL_H */

@@ -1,0 +1,327 @@
+"""MI355X-native local-Hamiltonian path of linear-scaling Daubechies-wavelet
+DFT (Mohr et al., arXiv:1401.7441), Python binding.
+
+The compute lives in libwvl.so (HIP kernels for gfx950 behind the C ABI of
+include/wvl.h).  This module only marshals arguments: numpy arrays for the
+host-side descriptions (localization regions, segment lists), torch tensors
+for device buffers and streams.  Every operation runs in the library's
+kernels; there is no fallback, and importing the package fails if the
+library has not been built (``python -m paper_1401_7441_amd.build``).
+
+Names follow the C ABI: build_locregs, Context (wvl_create), Plan
+(wvl_plan_create), uncompress, compress, apply_local_ham, kinetic,
+sparse_overlap.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+# torch first: its HIP runtime must be the one libwvl.so binds to (the library
+# needs libamdhip64.so.7, which the already-loaded torch runtime satisfies);
+# torch's streams and device pointers are only meaningful to that runtime.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwvl.so")
+
+WVL_OK, WVL_EINVAL, WVL_ENOMEM, WVL_EDEVICE, WVL_EUNSUPPORTED = 0, -1, -2, -3, -4
+F32, F64 = 0, 1
+KIN, POT = 1, 2
+
+SEG_DTYPE = np.dtype([("i1s", "<i4"), ("i1e", "<i4"), ("i2", "<i4"), ("i3", "<i4"),
+                      ("off", "<i8")], align=True)
+LOCREG_DTYPE = np.dtype([
+    ("center", "<f8", (3,)), ("radius", "<f8"), ("fine_radius", "<f8"),
+    ("ext", "<i4"), ("lo", "<i4", (3,)), ("dims", "<i4", (3,)), ("pad_", "<i4"),
+    ("seg_c", "<i8"), ("nseg_c", "<i8"), ("seg_f", "<i8"), ("nseg_f", "<i8"),
+    ("oseg_c", "<i8"), ("noseg_c", "<i8"), ("oseg_f", "<i8"), ("noseg_f", "<i8"),
+    ("coef_off", "<i8"), ("n_c", "<i8"), ("n_f", "<i8"),
+    ("ocoef_off", "<i8"), ("on_c", "<i8"), ("on_f", "<i8")], align=True)
+
+EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
+            "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
+            "wvl_compress", "wvl_apply_local_ham", "wvl_kinetic", "wvl_sparse_overlap")
+
+
+class WvlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"wvl status {status}: {msg}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("n", ctypes.c_int32 * 3)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("nsf", "in_coefs", "out_coefs", "in_box", "out_box",
+                                               "workspace_f32", "workspace_f64", "chunks")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1401_7441_amd.build` (no fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    runtimes = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    runtimes.add(line.split()[-1])
+    except OSError:
+        pass
+    if len(runtimes) > 1:
+        raise ImportError(f"two HIP runtimes are loaded in this process ({sorted(runtimes)}); "
+                          "import torch before loading libwvl.so")
+    P, I32, I64, U32, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                           ctypes.c_double)
+    sig = {
+        "wvl_build_locregs": [ctypes.POINTER(_Grid), I32, P, P, P, I32, P, P,
+                              ctypes.POINTER(I64)],
+        "wvl_create": [ctypes.POINTER(P), ctypes.POINTER(_Grid), P],
+        "wvl_destroy": [P],
+        "wvl_last_error": [P],
+        "wvl_plan_create": [P, I32, P, P, I64, ctypes.c_size_t, ctypes.POINTER(P),
+                            ctypes.POINTER(ctypes.c_size_t)],
+        "wvl_plan_destroy": [P],
+        "wvl_plan_info_get": [P, ctypes.POINTER(_PlanInfo)],
+        "wvl_uncompress": [P, ctypes.c_int, P, P],
+        "wvl_compress": [P, ctypes.c_int, P, P],
+        "wvl_apply_local_ham": [P, ctypes.c_int, U32, P, P, P, P, P, P],
+        "wvl_kinetic": [P, ctypes.c_int, P, P, P, P],
+        "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.wvl_destroy.restype = None
+    lib.wvl_plan_destroy.restype = None
+    lib.wvl_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != WVL_OK:
+        msg = _lib.wvl_last_error(ctx)
+        raise WvlError(status, msg.decode() if msg else "")
+
+
+def _grid(h, n):
+    g = _Grid()
+    g.h = float(h)
+    for a in range(3):
+        g.n[a] = int(n[a])
+    return g
+
+
+def build_locregs(h, grid_n, centers, radii, fine_radii, ext):
+    """wvl_build_locregs: sphere localization regions -> (locregs, segs) as
+    numpy structured arrays (LOCREG_DTYPE, SEG_DTYPE)."""
+    c = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, dtype=np.float64)
+    f = np.ascontiguousarray(fine_radii, dtype=np.float64)
+    nsf = len(c)
+    g = _grid(h, grid_n)
+    lr = np.zeros(nsf, LOCREG_DTYPE)
+    n = ctypes.c_int64(0)
+    _check(_lib.wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
+                                  f.ctypes.data, int(ext), lr.ctypes.data, None, ctypes.byref(n)))
+    segs = np.zeros(n.value, SEG_DTYPE)
+    _check(_lib.wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
+                                  f.ctypes.data, int(ext), lr.ctypes.data, segs.ctypes.data,
+                                  ctypes.byref(n)))
+    return lr, segs
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(*tensors):
+    import torch
+    dts = {t.dtype for t in tensors if t is not None}
+    if len(dts) != 1:
+        raise WvlError(WVL_EINVAL, f"mixed or missing dtypes {dts}")
+    dt = dts.pop()
+    if dt == torch.float32:
+        return F32
+    if dt == torch.float64:
+        return F64
+    raise WvlError(WVL_EINVAL, f"unsupported dtype {dt}")
+
+
+def _need_cuda(*tensors):
+    for t in tensors:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise WvlError(WVL_EINVAL, "device buffers must be contiguous GPU tensors")
+
+
+class Context:
+    """wvl_create: a grid (spacing h, coarse points n) bound to a HIP stream
+    (a torch.cuda.Stream; None = torch's current stream)."""
+
+    def __init__(self, h, grid_n, stream=None):
+        import torch
+        self.h = float(h)
+        self.grid_n = tuple(int(v) for v in grid_n)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ptr = ctypes.c_void_p()
+        g = _grid(h, grid_n)
+        _check(_lib.wvl_create(ctypes.byref(self._ptr), ctypes.byref(g),
+                               ctypes.c_void_p(self.stream.cuda_stream)))
+
+    @property
+    def handle(self):
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            _lib.wvl_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """wvl_plan_create: validated, device-resident batch of localization
+    regions.  `max_workspace` bounds the FP64 workspace in bytes (0: none)."""
+
+    def __init__(self, ctx: Context, locregs, segs, max_workspace=0):
+        self.ctx = ctx
+        self.locregs = np.ascontiguousarray(locregs, dtype=LOCREG_DTYPE)
+        self.segs = np.ascontiguousarray(segs, dtype=SEG_DTYPE)
+        self._ptr = ctypes.c_void_p()
+        ws = ctypes.c_size_t(0)
+        _check(_lib.wvl_plan_create(ctx.handle, len(self.locregs), self.locregs.ctypes.data,
+                                    self.segs.ctypes.data, len(self.segs), int(max_workspace),
+                                    ctypes.byref(self._ptr), ctypes.byref(ws)), ctx.handle)
+        info = _PlanInfo()
+        _check(_lib.wvl_plan_info_get(self._ptr, ctypes.byref(info)), ctx.handle)
+        self.info = {k: int(getattr(info, k)) for k, _ in _PlanInfo._fields_}
+
+    @property
+    def nsf(self):
+        return self.info["nsf"]
+
+    def workspace_bytes(self, dtype_code):
+        return self.info["workspace_f64" if dtype_code == F64 else "workspace_f32"]
+
+    def new_workspace(self, dtype):
+        """A uint8 device tensor large enough for `dtype` (torch.float32/64)."""
+        import torch
+        code = F64 if dtype == torch.float64 else F32
+        return torch.empty(max(1, self.workspace_bytes(code)), dtype=torch.uint8, device="cuda")
+
+    def close(self):
+        if self._ptr:
+            _lib.wvl_plan_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_sizes(plan, psi_c, hpsi_c, e_kin, e_pot, workspace, dt):
+    if psi_c.numel() < plan.info["in_coefs"]:
+        raise WvlError(WVL_EINVAL, "input coefficient buffer smaller than the plan's layout")
+    if hpsi_c.numel() < plan.info["out_coefs"]:
+        raise WvlError(WVL_EINVAL, "output coefficient buffer smaller than the plan's layout")
+    for e in (e_kin, e_pot):
+        if e is not None and (e.dtype.itemsize != 8 or e.numel() < plan.nsf):
+            raise WvlError(WVL_EINVAL, "energy buffers must be float64 with nsf entries")
+    if workspace is not None and workspace.numel() * workspace.element_size() < \
+            plan.workspace_bytes(dt):
+        raise WvlError(WVL_EINVAL, "workspace smaller than the plan needs")
+
+
+def uncompress(plan: Plan, psi_c, psi_box):
+    _need_cuda(psi_c, psi_box)
+    dt = _dtype_code(psi_c, psi_box)
+    if psi_c.numel() < plan.info["in_coefs"] or psi_box.numel() < plan.info["in_box"]:
+        raise WvlError(WVL_EINVAL, "buffer smaller than the plan's layout")
+    _check(_lib.wvl_uncompress(plan._ptr, dt, _ptr(psi_c), _ptr(psi_box)), plan.ctx.handle)
+
+
+def compress(plan: Plan, box, hpsi_c):
+    _need_cuda(box, hpsi_c)
+    dt = _dtype_code(box, hpsi_c)
+    if box.numel() < plan.info["out_box"] or hpsi_c.numel() < plan.info["out_coefs"]:
+        raise WvlError(WVL_EINVAL, "buffer smaller than the plan's layout")
+    _check(_lib.wvl_compress(plan._ptr, dt, _ptr(box), _ptr(hpsi_c)), plan.ctx.handle)
+
+
+def apply_local_ham(plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None, workspace=None,
+                    terms=KIN | POT):
+    """wvl_apply_local_ham; e_kin / e_pot are float64 device tensors [nsf] or None."""
+    _need_cuda(psi_c, pot, hpsi_c, e_kin, e_pot, workspace)
+    dt = _dtype_code(psi_c, pot, hpsi_c)
+    _check_sizes(plan, psi_c, hpsi_c, e_kin, e_pot, workspace, dt)
+    if pot is not None:
+        n = plan.ctx.grid_n
+        need = (2 * n[0] + 29) * (2 * n[1] + 29) * (2 * n[2] + 29)
+        if pot.numel() != need:
+            raise WvlError(WVL_EINVAL, f"potential has {pot.numel()} points, the grid needs {need}")
+    if workspace is None:
+        workspace = plan.new_workspace(psi_c.dtype)
+    _check(_lib.wvl_apply_local_ham(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
+                                    _ptr(hpsi_c), _ptr(e_kin), _ptr(e_pot), _ptr(workspace)),
+           plan.ctx.handle)
+
+
+def kinetic(plan: Plan, psi_c, hpsi_c, e_kin=None, workspace=None):
+    """wvl_kinetic: hpsi_c += L' T L psi_c."""
+    _need_cuda(psi_c, hpsi_c, e_kin, workspace)
+    dt = _dtype_code(psi_c, hpsi_c)
+    _check_sizes(plan, psi_c, hpsi_c, e_kin, None, workspace, dt)
+    if workspace is None:
+        workspace = plan.new_workspace(psi_c.dtype)
+    _check(_lib.wvl_kinetic(plan._ptr, dt, _ptr(psi_c), _ptr(hpsi_c), _ptr(e_kin),
+                            _ptr(workspace)), plan.ctx.handle)
+
+
+def sparse_pattern_nnz(plan: Plan, ket_is_output: bool):
+    n = ctypes.c_int64(0)
+    _check(_lib.wvl_sparse_overlap(plan._ptr, None, int(bool(ket_is_output)), None, F64,
+                                   ctypes.byref(n), None, None, None), plan.ctx.handle)
+    return n.value
+
+
+def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None):
+    """wvl_sparse_overlap -> (rowptr int64[nsf+1], col int32[nnz], val float64[nnz]),
+    device tensors.  `out` may hold preallocated (rowptr, col, val)."""
+    import torch
+    _need_cuda(bra_c, ket_c)
+    dt = _dtype_code(bra_c, ket_c)
+    if bra_c.numel() < plan.info["in_coefs"] or ket_c.numel() < plan.info[
+            "out_coefs" if ket_is_output else "in_coefs"]:
+        raise WvlError(WVL_EINVAL, "coefficient buffer smaller than the plan's layout")
+    nnz = sparse_pattern_nnz(plan, ket_is_output)
+    if out is None:
+        rowptr = torch.empty(plan.nsf + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(nnz, 1), dtype=torch.float64, device="cuda")
+    else:
+        rowptr, col, val = out
+    n = ctypes.c_int64(0)
+    _check(_lib.wvl_sparse_overlap(plan._ptr, _ptr(bra_c), int(bool(ket_is_output)), _ptr(ket_c),
+                                   dt, ctypes.byref(n), _ptr(rowptr), _ptr(col), _ptr(val)),
+           plan.ctx.handle)
+    return rowptr, col[:nnz], val[:nnz]

@@ -1,0 +1,798 @@
+// Host side of the C ABI declared in include/wvl.h: argument validation,
+// localization-region construction, plans (device copies of the segment
+// lists, row tables, workspace layout in chunks) and launch sequencing.
+// Built with -ffp-contract=off so that the sphere membership test rounds
+// exactly as written.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wvl_internal.h"
+
+using namespace wvl;
+
+struct wvl_ctx {
+  wvl_grid grid;
+  hipStream_t stream;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+wvl_status fail(wvl_ctx* ctx, wvl_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx)
+    ctx->err = buf;
+  else
+    g_err = buf;
+  return st;
+}
+
+#define WVL_HIP(ctx, call)                                                               \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, WVL_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+#define WVL_LAUNCH(ctx, what, call)                                                      \
+  do {                                                                                   \
+    int e_ = (call);                                                                     \
+    if (e_ != 0)                                                                         \
+      return fail(ctx, WVL_EDEVICE, "launch of %s failed: %s", what,                     \
+                  hipGetErrorString((hipError_t)e_));                                    \
+  } while (0)
+
+inline int64_t align64(int64_t n) { return (n + 63) & ~int64_t(63); }
+inline int64_t align_bytes(int64_t n) { return (n + 255) & ~int64_t(255); }
+
+struct PatternCache {
+  bool ready = false;
+  int64_t nnz = 0;
+  int64_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  int32_t* d_row = nullptr;
+};
+
+}  // namespace
+
+struct wvl_plan {
+  wvl_ctx* ctx = nullptr;
+  int nsf = 0;
+  std::vector<SfDev> h_sf;
+  std::vector<SfWork> h_wk;
+  std::vector<ChunkDev> chunks;
+  std::vector<int64_t> chunk_elems;   // elements of the compute type per chunk
+  std::vector<int64_t> chunk_parts;   // doubles of partials per chunk
+  SfDev* d_sf = nullptr;
+  wvl_seg* d_seg = nullptr;
+  int32_t* d_rt = nullptr;
+  SfWork* d_wk = nullptr;
+  wvl_plan_info info{};
+  PatternCache pat[2];
+};
+
+namespace {
+
+// --------------------------------------------------------------------------
+// validation
+// --------------------------------------------------------------------------
+
+int64_t seg_len(const wvl_seg& s) { return (int64_t)s.i1e - s.i1s + 1; }
+
+// checks one segment list: sorted, disjoint, inside [blo, bhi] box and the
+// grid, offsets = running sums; returns total length or -1
+int64_t check_list(wvl_ctx* ctx, wvl_status* st, int k, const char* name, const wvl_seg* segs,
+                   int64_t nsegs, int64_t first, int64_t count, const int* blo, const int* bhi,
+                   const int32_t* gn) {
+  if (first < 0 || count < 0 || first > nsegs || count > nsegs - first) {
+    *st = fail(ctx, WVL_EINVAL, "function %d: %s segment range [%lld, +%lld) outside [0, %lld)", k,
+               name, (long long)first, (long long)count, (long long)nsegs);
+    return -1;
+  }
+  int64_t total = 0;
+  for (int64_t q = 0; q < count; ++q) {
+    const wvl_seg& s = segs[first + q];
+    if (s.i1s > s.i1e) {
+      *st = fail(ctx, WVL_EINVAL, "function %d: %s segment %lld has i1s > i1e", k, name,
+                 (long long)(first + q));
+      return -1;
+    }
+    if (s.i1s < blo[0] || s.i1e > bhi[0] || s.i2 < blo[1] || s.i2 > bhi[1] || s.i3 < blo[2] ||
+        s.i3 > bhi[2] || s.i1s < 0 || s.i1e >= gn[0] || s.i2 < 0 || s.i2 >= gn[1] || s.i3 < 0 ||
+        s.i3 >= gn[2]) {
+      *st = fail(ctx, WVL_EINVAL, "function %d: %s segment %lld lies outside its box or the grid",
+                 k, name, (long long)(first + q));
+      return -1;
+    }
+    if (q > 0) {
+      const wvl_seg& p = segs[first + q - 1];
+      const bool later_row = s.i3 > p.i3 || (s.i3 == p.i3 && s.i2 > p.i2);
+      const bool same_row_after = s.i3 == p.i3 && s.i2 == p.i2 && s.i1s > p.i1e;
+      if (!later_row && !same_row_after) {
+        *st = fail(ctx, WVL_EINVAL,
+                   "function %d: %s segment %lld not sorted by (i3, i2, i1) or overlaps the one "
+                   "before",
+                   k, name, (long long)(first + q));
+        return -1;
+      }
+    }
+    if (s.off != total) {
+      *st = fail(ctx, WVL_EINVAL,
+                 "function %d: %s segment %lld has off %lld, expected running sum %lld", k, name,
+                 (long long)(first + q), (long long)s.off, (long long)total);
+      return -1;
+    }
+    total += seg_len(s);
+  }
+  return total;
+}
+
+// every fine segment inside a coarse segment of the same row
+bool fine_in_coarse(const wvl_seg* segs, int64_t c0, int64_t nc, int64_t f0, int64_t nf,
+                    int64_t* bad) {
+  int64_t q = 0;
+  for (int64_t r = 0; r < nf; ++r) {
+    const wvl_seg& f = segs[f0 + r];
+    while (q < nc) {
+      const wvl_seg& c = segs[c0 + q];
+      if (c.i3 < f.i3 || (c.i3 == f.i3 && c.i2 < f.i2) ||
+          (c.i3 == f.i3 && c.i2 == f.i2 && c.i1e < f.i1s))
+        ++q;
+      else
+        break;
+    }
+    if (q >= nc) {
+      *bad = f0 + r;
+      return false;
+    }
+    const wvl_seg& c = segs[c0 + q];
+    if (!(c.i3 == f.i3 && c.i2 == f.i2 && c.i1s <= f.i1s && f.i1e <= c.i1e)) {
+      *bad = f0 + r;
+      return false;
+    }
+  }
+  return true;
+}
+
+void bbox(const wvl_seg* segs, int64_t first, int64_t count, int32_t* bb) {
+  bb[0] = bb[2] = bb[4] = 1 << 30;
+  bb[1] = bb[3] = bb[5] = -(1 << 30);
+  for (int64_t q = 0; q < count; ++q) {
+    const wvl_seg& s = segs[first + q];
+    bb[0] = std::min(bb[0], s.i1s);
+    bb[1] = std::max(bb[1], s.i1e);
+    bb[2] = std::min(bb[2], s.i2);
+    bb[3] = std::max(bb[3], s.i2);
+    bb[4] = std::min(bb[4], s.i3);
+    bb[5] = std::max(bb[5], s.i3);
+  }
+}
+
+// row table of one pattern: rt[r] .. rt[r+1] are the global segment indices
+// of box row r = (i3 - oz) * by + (i2 - oy)
+void row_table(const wvl_seg* segs, int64_t first, int64_t count, int ox, int oy, int oz, int by,
+               int bz, std::vector<int32_t>& rt) {
+  (void)ox;
+  const int64_t nrows = (int64_t)by * bz;
+  const size_t base = rt.size();
+  rt.resize(base + nrows + 1, 0);
+  std::vector<int32_t> cnt(nrows, 0);
+  for (int64_t q = 0; q < count; ++q) {
+    const wvl_seg& s = segs[first + q];
+    cnt[(int64_t)(s.i3 - oz) * by + (s.i2 - oy)]++;
+  }
+  int32_t run = (int32_t)first;
+  for (int64_t r = 0; r < nrows; ++r) {
+    rt[base + r] = run;
+    run += cnt[r];
+  }
+  rt[base + nrows] = run;
+}
+
+template <typename P>
+wvl_status upload(wvl_ctx* ctx, P** dst, const void* src, size_t bytes) {
+  *dst = nullptr;
+  if (bytes == 0) return WVL_OK;
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) {
+    *dst = nullptr;
+    return fail(ctx, WVL_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  WVL_HIP(ctx, hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  return WVL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// public entry points
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* wvl_last_error(const wvl_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+wvl_status wvl_build_locregs(const wvl_grid* grid, int32_t nsf, const double* centers,
+                             const double* radii, const double* fine_radii, int32_t ext,
+                             wvl_locreg* lr, wvl_seg* segs, int64_t* nsegs) {
+  if (!grid || !nsegs || nsf < 0 || (nsf > 0 && (!centers || !radii || !fine_radii || !lr)))
+    return fail(nullptr, WVL_EINVAL, "wvl_build_locregs: null argument or nsf < 0");
+  const double h = grid->h;
+  const int32_t* gn = grid->n;
+  if (!(h > 0) || gn[0] <= 0 || gn[1] <= 0 || gn[2] <= 0 || ext < 0 || ext > 16)
+    return fail(nullptr, WVL_EINVAL, "wvl_build_locregs: bad grid or ext");
+  struct Box {
+    int lo[3], hi[3];
+    std::vector<uint8_t> m, f;  // coarse / fine masks over the box [z][y][x]
+  };
+  std::vector<Box> boxes(nsf);
+  // union F of input fine sets, as a sorted list of global linear indices
+  std::vector<int64_t> Fpts;
+  auto inside = [&](const double* c, double r, int i1, int i2, int i3) {
+    const double dx = h * (double)i1 - c[0];
+    const double dy = h * (double)i2 - c[1];
+    const double dz = h * (double)i3 - c[2];
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    return d2 <= r * r;
+  };
+  for (int k = 0; k < nsf; ++k) {
+    const double* c = centers + 3 * k;
+    const double R = radii[k];
+    if (!(R >= 0) || !(fine_radii[k] >= 0))
+      return fail(nullptr, WVL_EINVAL, "function %d: negative radius", k);
+    int clo[3], chi[3];
+    for (int a = 0; a < 3; ++a) {
+      clo[a] = std::max(0, (int)std::floor((c[a] - R) / h) - 1);
+      chi[a] = std::min(gn[a] - 1, (int)std::ceil((c[a] + R) / h) + 1);
+    }
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (int i3 = clo[2]; i3 <= chi[2]; ++i3)
+      for (int i2 = clo[1]; i2 <= chi[1]; ++i2)
+        for (int i1 = clo[0]; i1 <= chi[0]; ++i1)
+          if (inside(c, R, i1, i2, i3)) {
+            lo[0] = std::min(lo[0], i1); hi[0] = std::max(hi[0], i1);
+            lo[1] = std::min(lo[1], i2); hi[1] = std::max(hi[1], i2);
+            lo[2] = std::min(lo[2], i3); hi[2] = std::max(hi[2], i3);
+          }
+    if (hi[0] < 0) return fail(nullptr, WVL_EINVAL, "function %d: empty localization region", k);
+    Box& b = boxes[k];
+    std::copy(lo, lo + 3, b.lo);
+    std::copy(hi, hi + 3, b.hi);
+    const int n0 = hi[0] - lo[0] + 1, n1 = hi[1] - lo[1] + 1, n2 = hi[2] - lo[2] + 1;
+    b.m.assign((size_t)n0 * n1 * n2, 0);
+    b.f.assign((size_t)n0 * n1 * n2, 0);
+    for (int i3 = lo[2]; i3 <= hi[2]; ++i3)
+      for (int i2 = lo[1]; i2 <= hi[1]; ++i2)
+        for (int i1 = lo[0]; i1 <= hi[0]; ++i1) {
+          const size_t p = ((size_t)(i3 - lo[2]) * n1 + (i2 - lo[1])) * n0 + (i1 - lo[0]);
+          if (inside(c, R, i1, i2, i3)) {
+            b.m[p] = 1;
+            if (inside(c, fine_radii[k], i1, i2, i3)) {
+              b.f[p] = 1;
+              Fpts.push_back(((int64_t)i3 * gn[1] + i2) * gn[0] + i1);
+            }
+          }
+        }
+  }
+  std::sort(Fpts.begin(), Fpts.end());
+  Fpts.erase(std::unique(Fpts.begin(), Fpts.end()), Fpts.end());
+  auto inF = [&](int i1, int i2, int i3) {
+    const int64_t key = ((int64_t)i3 * gn[1] + i2) * gn[0] + i1;
+    return std::binary_search(Fpts.begin(), Fpts.end(), key);
+  };
+  // emit segments
+  const int64_t cap = *nsegs;
+  int64_t nout = 0, coef = 0, ocoef = 0;
+  auto emit_rows = [&](const std::vector<uint8_t>& m, const int* olo, int n0, int n1, int n2,
+                       int64_t* total) {
+    int64_t first = nout, off = 0;
+    for (int z = 0; z < n2; ++z)
+      for (int y = 0; y < n1; ++y) {
+        int x = 0;
+        while (x < n0) {
+          if (m[((size_t)z * n1 + y) * n0 + x]) {
+            const int x0 = x;
+            while (x < n0 && m[((size_t)z * n1 + y) * n0 + x]) ++x;
+            if (segs && nout < cap) {
+              wvl_seg& s = segs[nout];
+              s.i1s = olo[0] + x0;
+              s.i1e = olo[0] + x - 1;
+              s.i2 = olo[1] + y;
+              s.i3 = olo[2] + z;
+              s.off = off;
+            }
+            ++nout;
+            off += x - x0;
+          } else {
+            ++x;
+          }
+        }
+      }
+    *total = off;
+    return first;
+  };
+  for (int k = 0; k < nsf; ++k) {
+    const Box& b = boxes[k];
+    const double* c = centers + 3 * k;
+    const int n0 = b.hi[0] - b.lo[0] + 1, n1 = b.hi[1] - b.lo[1] + 1, n2 = b.hi[2] - b.lo[2] + 1;
+    wvl_locreg& L = lr[k];
+    std::memset(&L, 0, sizeof L);
+    std::copy(c, c + 3, L.center);
+    L.radius = radii[k];
+    L.fine_radius = fine_radii[k];
+    L.ext = ext;
+    std::copy(b.lo, b.lo + 3, L.lo);
+    L.dims[0] = n0; L.dims[1] = n1; L.dims[2] = n2;
+    int64_t tot;
+    L.seg_c = emit_rows(b.m, b.lo, n0, n1, n2, &tot);
+    L.nseg_c = nout - L.seg_c;
+    L.n_c = tot;
+    L.seg_f = emit_rows(b.f, b.lo, n0, n1, n2, &tot);
+    L.nseg_f = nout - L.seg_f;
+    L.n_f = tot;
+    // output pattern over the grown box, clipped to the grid
+    int olo[3], ohi[3];
+    for (int a = 0; a < 3; ++a) {
+      olo[a] = std::max(0, b.lo[a] - ext);
+      ohi[a] = std::min(gn[a] - 1, b.hi[a] + ext);
+    }
+    const int m0 = ohi[0] - olo[0] + 1, m1 = ohi[1] - olo[1] + 1, m2 = ohi[2] - olo[2] + 1;
+    std::vector<uint8_t> om((size_t)m0 * m1 * m2, 0), of((size_t)m0 * m1 * m2, 0);
+    const double Rp = radii[k] + ext * h;
+    for (int i3 = olo[2]; i3 <= ohi[2]; ++i3)
+      for (int i2 = olo[1]; i2 <= ohi[1]; ++i2)
+        for (int i1 = olo[0]; i1 <= ohi[0]; ++i1)
+          if (inside(c, Rp, i1, i2, i3)) {
+            const size_t p = ((size_t)(i3 - olo[2]) * m1 + (i2 - olo[1])) * m0 + (i1 - olo[0]);
+            om[p] = 1;
+            if (inF(i1, i2, i3)) of[p] = 1;
+          }
+    L.oseg_c = emit_rows(om, olo, m0, m1, m2, &tot);
+    L.noseg_c = nout - L.oseg_c;
+    L.on_c = tot;
+    L.oseg_f = emit_rows(of, olo, m0, m1, m2, &tot);
+    L.noseg_f = nout - L.oseg_f;
+    L.on_f = tot;
+    L.coef_off = coef;
+    coef += L.n_c + 7 * L.n_f;
+    L.ocoef_off = ocoef;
+    ocoef += L.on_c + 7 * L.on_f;
+  }
+  *nsegs = nout;
+  if (segs && nout > cap)
+    return fail(nullptr, WVL_EINVAL, "wvl_build_locregs: segs holds %lld, %lld needed",
+                (long long)cap, (long long)nout);
+  return WVL_OK;
+}
+
+wvl_status wvl_create(wvl_ctx** ctx, const wvl_grid* grid, void* hip_stream) {
+  if (!ctx || !grid) return fail(nullptr, WVL_EINVAL, "wvl_create: null argument");
+  *ctx = nullptr;
+  if (!(grid->h > 0) || grid->n[0] <= 0 || grid->n[1] <= 0 || grid->n[2] <= 0)
+    return fail(nullptr, WVL_EINVAL, "wvl_create: grid needs h > 0 and n > 0");
+  wvl_ctx* c = new (std::nothrow) wvl_ctx;
+  if (!c) return fail(nullptr, WVL_ENOMEM, "wvl_create: out of host memory");
+  c->grid = *grid;
+  c->stream = (hipStream_t)hip_stream;
+  *ctx = c;
+  return WVL_OK;
+}
+
+void wvl_destroy(wvl_ctx* ctx) { delete ctx; }
+
+static void free_pattern(PatternCache& p) {
+  if (p.d_rowptr) (void)hipFree(p.d_rowptr);
+  if (p.d_col) (void)hipFree(p.d_col);
+  if (p.d_row) (void)hipFree(p.d_row);
+  p = PatternCache{};
+}
+
+void wvl_plan_destroy(wvl_plan* plan) {
+  if (!plan) return;
+  if (plan->d_sf) (void)hipFree(plan->d_sf);
+  if (plan->d_seg) (void)hipFree(plan->d_seg);
+  if (plan->d_rt) (void)hipFree(plan->d_rt);
+  if (plan->d_wk) (void)hipFree(plan->d_wk);
+  free_pattern(plan->pat[0]);
+  free_pattern(plan->pat[1]);
+  delete plan;
+}
+
+wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, const wvl_seg* segs,
+                           int64_t nsegs, size_t max_workspace_bytes, wvl_plan** plan_out,
+                           size_t* workspace_bytes) {
+  if (!ctx) return fail(nullptr, WVL_EINVAL, "wvl_plan_create: null context");
+  if (!plan_out) return fail(ctx, WVL_EINVAL, "wvl_plan_create: null plan pointer");
+  *plan_out = nullptr;
+  if (nsf < 0 || nsegs < 0 || (nsf > 0 && !lr) || (nsegs > 0 && !segs))
+    return fail(ctx, WVL_EINVAL, "wvl_plan_create: bad counts or null arrays");
+  if (nsegs >= (int64_t)1 << 31)
+    return fail(ctx, WVL_EUNSUPPORTED, "wvl_plan_create: more than 2^31 segments");
+  const int32_t* gn = ctx->grid.n;
+  wvl_status st = WVL_OK;
+  std::vector<std::pair<int64_t, int64_t>> outs;
+  for (int k = 0; k < nsf; ++k) {
+    const wvl_locreg& L = lr[k];
+    for (int a = 0; a < 3; ++a) {
+      if (L.dims[a] < 1 || L.lo[a] < 0 || (int64_t)L.lo[a] + L.dims[a] > gn[a])
+        return fail(ctx, WVL_EINVAL, "function %d: input box outside the grid (axis %d)", k, a);
+      if (L.dims[a] > 4096)
+        return fail(ctx, WVL_EUNSUPPORTED, "function %d: box wider than 4096 points", k);
+    }
+    if (L.ext < 0 || L.ext > 16) return fail(ctx, WVL_EINVAL, "function %d: ext outside [0, 16]", k);
+    int blo[3], bhi[3], olo[3], ohi[3];
+    for (int a = 0; a < 3; ++a) {
+      blo[a] = L.lo[a];
+      bhi[a] = L.lo[a] + L.dims[a] - 1;
+      olo[a] = L.lo[a] - L.ext;
+      ohi[a] = bhi[a] + L.ext;
+    }
+    const int64_t nc = check_list(ctx, &st, k, "input coarse", segs, nsegs, L.seg_c, L.nseg_c, blo,
+                                  bhi, gn);
+    if (nc < 0) return st;
+    const int64_t nf = check_list(ctx, &st, k, "input fine", segs, nsegs, L.seg_f, L.nseg_f, blo,
+                                  bhi, gn);
+    if (nf < 0) return st;
+    const int64_t onc = check_list(ctx, &st, k, "output coarse", segs, nsegs, L.oseg_c, L.noseg_c,
+                                   olo, ohi, gn);
+    if (onc < 0) return st;
+    const int64_t onf = check_list(ctx, &st, k, "output fine", segs, nsegs, L.oseg_f, L.noseg_f,
+                                   olo, ohi, gn);
+    if (onf < 0) return st;
+    if (nc != L.n_c || nf != L.n_f || onc != L.on_c || onf != L.on_f)
+      return fail(ctx, WVL_EINVAL,
+                  "function %d: point counts (n_c %lld, n_f %lld, on_c %lld, on_f %lld) differ "
+                  "from the segment lists (%lld, %lld, %lld, %lld)",
+                  k, (long long)L.n_c, (long long)L.n_f, (long long)L.on_c, (long long)L.on_f,
+                  (long long)nc, (long long)nf, (long long)onc, (long long)onf);
+    int64_t bad = -1;
+    if (!fine_in_coarse(segs, L.seg_c, L.nseg_c, L.seg_f, L.nseg_f, &bad))
+      return fail(ctx, WVL_EINVAL, "function %d: input fine segment %lld not inside a coarse one",
+                  k, (long long)bad);
+    if (!fine_in_coarse(segs, L.oseg_c, L.noseg_c, L.oseg_f, L.noseg_f, &bad))
+      return fail(ctx, WVL_EINVAL, "function %d: output fine segment %lld not inside a coarse one",
+                  k, (long long)bad);
+    if (L.coef_off < 0 || L.ocoef_off < 0)
+      return fail(ctx, WVL_EINVAL, "function %d: negative coefficient offset", k);
+    outs.emplace_back(L.ocoef_off, L.on_c + 7 * L.on_f);
+  }
+  std::sort(outs.begin(), outs.end());
+  for (size_t q = 1; q < outs.size(); ++q)
+    if (outs[q].second > 0 && outs[q - 1].first + outs[q - 1].second > outs[q].first)
+      return fail(ctx, WVL_EINVAL, "output coefficient ranges of two functions overlap");
+
+  wvl_plan* P = new (std::nothrow) wvl_plan;
+  if (!P) return fail(ctx, WVL_ENOMEM, "wvl_plan_create: out of host memory");
+  P->ctx = ctx;
+  P->nsf = nsf;
+  P->h_sf.resize(nsf);
+  P->h_wk.resize(nsf);
+  std::vector<int32_t> rt;
+  int64_t box_in = 0, box_out = 0, in_coefs = 0, out_coefs = 0;
+  for (int k = 0; k < nsf; ++k) {
+    const wvl_locreg& L = lr[k];
+    SfDev& S = P->h_sf[k];
+    std::memset(&S, 0, sizeof S);
+    for (int a = 0; a < 3; ++a) {
+      S.lo[a] = L.lo[a];
+      S.n[a] = L.dims[a];
+    }
+    S.ext = L.ext;
+    S.cin = L.coef_off;
+    S.cout = L.ocoef_off;
+    S.n_c = L.n_c;
+    S.n_f = L.n_f;
+    S.on_c = L.on_c;
+    S.on_f = L.on_f;
+    S.box_in = box_in;
+    S.box_out = box_out;
+    const int e = L.ext;
+    box_in += 8ll * L.dims[0] * L.dims[1] * L.dims[2];
+    box_out += 8ll * (L.dims[0] + 2 * e) * (L.dims[1] + 2 * e) * (L.dims[2] + 2 * e);
+    in_coefs = std::max<int64_t>(in_coefs, L.coef_off + L.n_c + 7 * L.n_f);
+    out_coefs = std::max<int64_t>(out_coefs, L.ocoef_off + L.on_c + 7 * L.on_f);
+    const int64_t firsts[4] = {L.seg_c, L.seg_f, L.oseg_c, L.oseg_f};
+    const int64_t counts[4] = {L.nseg_c, L.nseg_f, L.noseg_c, L.noseg_f};
+    for (int p = 0; p < 4; ++p) {
+      const int g = p < 2 ? 0 : e;
+      S.rt[p] = (int64_t)rt.size();
+      row_table(segs, firsts[p], counts[p], L.lo[0] - g, L.lo[1] - g, L.lo[2] - g,
+                L.dims[1] + 2 * g, L.dims[2] + 2 * g, rt);
+    }
+    bbox(segs, L.seg_c, L.nseg_c, S.bb_in);
+    bbox(segs, L.oseg_c, L.noseg_c, S.bb_out);
+  }
+  // chunks and workspace layout
+  int64_t best_f32 = 0, best_f64 = 0;
+  {
+    int k = 0;
+    while (k < nsf) {
+      ChunkDev ch{};
+      ch.sf0 = k;
+      int64_t elems = 0, maxg = 0, maxc8 = 0;
+      int j = k;
+      for (; j < nsf; ++j) {
+        const SfDev& S = P->h_sf[j];
+        const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
+        const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29, r2 = 2 * n2 + 29;
+        const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
+        const int64_t need = align64(8 * n0 * n1 * n2) + align64(4 * r0 * n1 * n2) +
+                             align64(2 * r0 * r1 * n2) + align64(r0 * r1 * r2) +
+                             align64(2 * r0 * r1 * o2) + align64(4 * r0 * o1 * o2) +
+                             align64(8 * o0 * o1 * o2);
+        const int64_t mg = std::max(maxg, r0 * r1 * r2), mc = std::max(maxc8, 8 * n0 * n1 * n2);
+        const int64_t parts = (int64_t)(j - k + 1) * ((mg + 255) / 256 + (mc + 255) / 256);
+        const int64_t bytes = align_bytes((elems + need) * 8) + parts * 8;
+        if (j > k && max_workspace_bytes > 0 && (size_t)bytes > max_workspace_bytes) break;
+        if (j - k >= 65535) break;
+        elems += need;
+        maxg = mg;
+        maxc8 = mc;
+      }
+      ch.nsf = j - k;
+      // per-function offsets
+      int64_t off = 0;
+      for (int q = k; q < j; ++q) {
+        const SfDev& S = P->h_sf[q];
+        const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
+        const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29, r2 = 2 * n2 + 29;
+        const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
+        SfWork& W = P->h_wk[q];
+        const int64_t vol[P_NPASS] = {8 * n0 * n1 * n2, 4 * r0 * n1 * n2, 2 * r0 * r1 * n2,
+                                      r0 * r1 * r2,     2 * r0 * r1 * o2, 4 * r0 * o1 * o2,
+                                      8 * o0 * o1 * o2, 8 * o0 * o1 * o2, 8 * o0 * o1 * o2};
+        for (int p = 0; p < P_NPASS; ++p) ch.maxvol[p] = std::max(ch.maxvol[p], vol[p]);
+        W.c8 = off; off += align64(vol[0]);
+        W.a1 = off; off += align64(vol[1]);
+        W.a2 = off; off += align64(vol[2]);
+        W.g = off;  off += align64(vol[3]);
+        W.b1 = off; off += align64(vol[4]);
+        W.b2 = off; off += align64(vol[5]);
+        W.o8 = off; off += align64(vol[6]);
+      }
+      ch.nblk_pot = (int32_t)((ch.maxvol[P_UPZ] + 255) / 256);
+      ch.nblk_kin = (int32_t)((ch.maxvol[P_GATHER] + 255) / 256);
+      int64_t poff = 0;
+      for (int q = k; q < j; ++q) {
+        P->h_wk[q].epart = poff;
+        poff += ch.nblk_pot;
+        P->h_wk[q].kpart = poff;
+        poff += ch.nblk_kin;
+      }
+      P->chunks.push_back(ch);
+      P->chunk_elems.push_back(off);
+      P->chunk_parts.push_back(poff);
+      best_f32 = std::max(best_f32, align_bytes(off * 4) + poff * 8);
+      best_f64 = std::max(best_f64, align_bytes(off * 8) + poff * 8);
+      k = j;
+    }
+  }
+  P->info.nsf = nsf;
+  P->info.in_coefs = in_coefs;
+  P->info.out_coefs = out_coefs;
+  P->info.in_box = box_in;
+  P->info.out_box = box_out;
+  P->info.workspace_f32 = best_f32;
+  P->info.workspace_f64 = best_f64;
+  P->info.chunks = (int64_t)P->chunks.size();
+  if ((st = upload(ctx, &P->d_sf, P->h_sf.data(), sizeof(SfDev) * nsf)) != WVL_OK ||
+      (st = upload(ctx, &P->d_seg, segs, sizeof(wvl_seg) * nsegs)) != WVL_OK ||
+      (st = upload(ctx, &P->d_rt, rt.data(), sizeof(int32_t) * rt.size())) != WVL_OK ||
+      (st = upload(ctx, &P->d_wk, P->h_wk.data(), sizeof(SfWork) * nsf)) != WVL_OK) {
+    wvl_plan_destroy(P);
+    return st;
+  }
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    wvl_plan_destroy(P);
+    return fail(ctx, WVL_EDEVICE, "plan upload failed: %s", hipGetErrorString(e));
+  }
+  if (workspace_bytes) *workspace_bytes = (size_t)best_f64;
+  *plan_out = P;
+  return WVL_OK;
+}
+
+wvl_status wvl_plan_info_get(const wvl_plan* plan, wvl_plan_info* info) {
+  if (!plan || !info) return fail(nullptr, WVL_EINVAL, "wvl_plan_info_get: null argument");
+  *info = plan->info;
+  return WVL_OK;
+}
+
+static wvl_status check_dt(wvl_ctx* ctx, wvl_dtype dt) {
+  if (dt != WVL_F32 && dt != WVL_F64) return fail(ctx, WVL_EINVAL, "unknown dtype %d", (int)dt);
+  return WVL_OK;
+}
+
+wvl_status wvl_uncompress(wvl_plan* P, wvl_dtype dt, const void* psi_c, void* psi_box) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_uncompress: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (P->nsf > 0 && (!psi_c || !psi_box)) return fail(ctx, WVL_EINVAL, "wvl_uncompress: null buffer");
+  for (const ChunkDev& ch : P->chunks)
+    WVL_LAUNCH(ctx, "uncompress",
+               launch_gather(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, psi_c, psi_box,
+                             P->d_wk + ch.sf0, ch.sf0, ch.nsf, ch.maxvol[P_GATHER], 0));
+  return WVL_OK;
+}
+
+wvl_status wvl_compress(wvl_plan* P, wvl_dtype dt, const void* box, void* hpsi_c) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_compress: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (P->nsf > 0 && (!box || !hpsi_c)) return fail(ctx, WVL_EINVAL, "wvl_compress: null buffer");
+  for (const ChunkDev& ch : P->chunks)
+    WVL_LAUNCH(ctx, "compress",
+               launch_scatter(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, box, hpsi_c,
+                              P->d_wk + ch.sf0, ch.sf0, ch.nsf, ch.maxvol[P_SCATTER], 0, 0));
+  return WVL_OK;
+}
+
+static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                             const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                             void* workspace, int accumulate, const char* who) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "%s: null plan", who);
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if ((terms & ~(WVL_KIN | WVL_POT)) || terms == 0)
+    return fail(ctx, WVL_EINVAL, "%s: terms must be a non-empty mix of WVL_KIN and WVL_POT", who);
+  if (P->nsf == 0) return WVL_OK;
+  if (!psi_c || !hpsi_c || !workspace)
+    return fail(ctx, WVL_EINVAL, "%s: null coefficient or workspace buffer", who);
+  if ((terms & WVL_POT) && !pot) return fail(ctx, WVL_EINVAL, "%s: WVL_POT needs a potential", who);
+  const int f64 = dt == WVL_F64;
+  const int sz = f64 ? 8 : 4;
+  const int nf1 = 2 * ctx->grid.n[0] + 29, nf2 = 2 * ctx->grid.n[1] + 29;
+  const double fac = -2.0 / (ctx->grid.h * ctx->grid.h);   // -1/2 (2/h)^2
+  hipStream_t st = ctx->stream;
+  for (size_t c = 0; c < P->chunks.size(); ++c) {
+    const ChunkDev& ch = P->chunks[c];
+    const SfWork* wk = P->d_wk + ch.sf0;
+    double* parts = (double*)((char*)workspace + align_bytes(P->chunk_elems[c] * sz));
+    WVL_LAUNCH(ctx, "gather", launch_gather(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, workspace,
+                                            wk, ch.sf0, ch.nsf, ch.maxvol[P_GATHER], 1));
+    if (terms & WVL_KIN) {
+      for (int ax = 0; ax < 3; ++ax)
+        WVL_LAUNCH(ctx, "kinetic", launch_kin(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf,
+                                              ch.maxvol[P_KIN], workspace, ax > 0, fac));
+      if (e_kin) {
+        WVL_LAUNCH(ctx, "e_kin", launch_ekin_partials(f64, st, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                      ch.maxvol[P_GATHER], workspace, parts,
+                                                      ch.nblk_kin));
+        WVL_LAUNCH(ctx, "e_kin sum",
+                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.nblk_kin, e_kin));
+      }
+    }
+    if (terms & WVL_POT) {
+      const int64_t upv[3] = {ch.maxvol[P_UPX], ch.maxvol[P_UPY], ch.maxvol[P_UPZ]};
+      for (int ax = 0; ax < 3; ++ax)
+        WVL_LAUNCH(ctx, "up", launch_up(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, upv[ax],
+                                        workspace, pot, nf1, nf2, parts, ch.nblk_pot));
+      if (e_pot)
+        WVL_LAUNCH(ctx, "e_pot sum",
+                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.nblk_pot, e_pot));
+      const int64_t dnv[3] = {ch.maxvol[P_DOWNX], ch.maxvol[P_DOWNY], ch.maxvol[P_DOWNZ]};
+      for (int ax = 2; ax >= 0; --ax)
+        WVL_LAUNCH(ctx, "down", launch_down(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, dnv[ax],
+                                            workspace, (terms & WVL_KIN) ? 1 : 0));
+    }
+    WVL_LAUNCH(ctx, "scatter", launch_scatter(f64, st, P->d_sf, P->d_seg, P->d_rt, workspace,
+                                              hpsi_c, wk, ch.sf0, ch.nsf, ch.maxvol[P_SCATTER], 1,
+                                              accumulate));
+  }
+  return WVL_OK;
+}
+
+wvl_status wvl_apply_local_ham(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                               const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                               void* workspace) {
+  return apply_impl(plan, dt, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0,
+                    "wvl_apply_local_ham");
+}
+
+wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hpsi_c,
+                       double* e_kin, void* workspace) {
+  return apply_impl(plan, dt, WVL_KIN, psi_c, nullptr, hpsi_c, e_kin, nullptr, workspace, 1,
+                    "wvl_kinetic");
+}
+
+static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
+  wvl_ctx* ctx = P->ctx;
+  PatternCache& pc = P->pat[ket_out];
+  if (pc.ready) return WVL_OK;
+  const int nsf = P->nsf;
+  int64_t* d_count = nullptr;
+  std::vector<int64_t> cnt(nsf), rowptr(nsf + 1, 0);
+  if (nsf > 0) {
+    WVL_HIP(ctx, hipMalloc((void**)&d_count, sizeof(int64_t) * nsf));
+    int e = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, d_count,
+                           nullptr, nullptr);
+    if (e == 0)
+      e = (int)hipMemcpyAsync(cnt.data(), d_count, sizeof(int64_t) * nsf, hipMemcpyDeviceToHost,
+                              ctx->stream);
+    if (e == 0) e = (int)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d_count);
+    if (e != 0)
+      return fail(ctx, WVL_EDEVICE, "sparsity pattern count failed: %s",
+                  hipGetErrorString((hipError_t)e));
+  }
+  for (int a = 0; a < nsf; ++a) rowptr[a + 1] = rowptr[a] + cnt[a];
+  const int64_t nnz = rowptr[nsf];
+  std::vector<int32_t> row(nnz);
+  for (int a = 0; a < nsf; ++a)
+    for (int64_t q = rowptr[a]; q < rowptr[a + 1]; ++q) row[q] = a;
+  wvl_status st;
+  if ((st = upload(ctx, &pc.d_rowptr, rowptr.data(), sizeof(int64_t) * (nsf + 1))) != WVL_OK)
+    return st;
+  if ((st = upload(ctx, &pc.d_row, row.data(), sizeof(int32_t) * nnz)) != WVL_OK) {
+    free_pattern(pc);
+    return st;
+  }
+  if (nnz > 0) {
+    hipError_t e = hipMalloc((void**)&pc.d_col, sizeof(int32_t) * nnz);
+    if (e != hipSuccess) {
+      free_pattern(pc);
+      return fail(ctx, WVL_ENOMEM, "pattern columns: %s", hipGetErrorString(e));
+    }
+    int le = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, nullptr,
+                            pc.d_rowptr, pc.d_col);
+    if (le == 0) le = (int)hipStreamSynchronize(ctx->stream);
+    if (le != 0) {
+      free_pattern(pc);
+      return fail(ctx, WVL_EDEVICE, "sparsity pattern fill failed: %s",
+                  hipGetErrorString((hipError_t)le));
+    }
+  } else {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      free_pattern(pc);
+      return fail(ctx, WVL_EDEVICE, "pattern upload failed: %s", hipGetErrorString(e));
+    }
+  }
+  pc.nnz = nnz;
+  pc.ready = true;
+  return WVL_OK;
+}
+
+wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output, const void* ket_c,
+                              wvl_dtype dt, int64_t* nnz, int64_t* rowptr, int32_t* col,
+                              double* val) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_sparse_overlap: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (ket_is_output != 0 && ket_is_output != 1)
+    return fail(ctx, WVL_EINVAL, "wvl_sparse_overlap: ket_is_output must be 0 or 1");
+  wvl_status st = ensure_pattern(P, ket_is_output);
+  if (st != WVL_OK) return st;
+  const PatternCache& pc = P->pat[ket_is_output];
+  if (nnz) *nnz = pc.nnz;
+  if (rowptr)
+    WVL_HIP(ctx, hipMemcpyAsync(rowptr, pc.d_rowptr, sizeof(int64_t) * (P->nsf + 1),
+                                hipMemcpyDeviceToDevice, ctx->stream));
+  if (col && pc.nnz)
+    WVL_HIP(ctx, hipMemcpyAsync(col, pc.d_col, sizeof(int32_t) * pc.nnz, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+  if (val && pc.nnz) {
+    if (!bra_c || !ket_c) return fail(ctx, WVL_EINVAL, "wvl_sparse_overlap: null bra or ket");
+    WVL_LAUNCH(ctx, "sparse values",
+               launch_sparse_values(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt,
+                                    ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.nnz, val));
+  }
+  return WVL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances (stated by the target and derived in the design notes):
+  FP64 path: per-function relative L2 error of H|phi> <= 1e-12; energies and
+             matrix elements relative 1e-12.
+  FP32 path: per-function relative L2 error <= 1e-5; energies within 1e-6 Ha
+             per normalized function; matrix elements |dS_ab| <= 1e-5
+             sqrt(S_aa S_bb), |dH_ab| <= 1e-5 |phi_a| |H phi_b|.
+  Index work (segments, patterns, uncompress/compress) is bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import hamiltonian as Hm
+from oracle import locreg as LR
+from oracle import sparse as SP
+from tests.abi_helpers import from_abi, rel_err, to_abi
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_1401_7441_amd as W
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+class Case:
+    """A batch of support functions: oracle locregs, coefficients, potential."""
+
+    def __init__(self, g, lrs, smooth=False, normalize=True):
+        self.g = g
+        self.lrs = lrs
+        self.rec, self.segs = to_abi(lrs)
+        self.coefs = []
+        for k, l in enumerate(lrs):
+            pc = LR.points_from_segments(l.cseg)
+            pf = LR.points_from_segments(l.fseg)
+            self.coefs.append(inputs.coefficients(g, k, pc, pf, smooth=smooth,
+                                                  normalize=normalize))
+        self.psi = np.concatenate(self.coefs) if self.coefs else np.zeros(0)
+        self.pot = inputs.potential(g).numpy()
+
+    def oracle(self, k, **kw):
+        key = (k, tuple(sorted(kw.items())))
+        if not hasattr(self, "_memo"):
+            self._memo = {}
+        if key not in self._memo:
+            self._memo[key] = Hm.apply_local_ham(self.lrs[k], self.coefs[k], self.pot, self.g.h,
+                                                 **kw)
+        return self._memo[key]
+
+    def run(self, dtype, terms=None, max_workspace=0, plan=None):
+        ctx = W.Context(self.g.h, self.g.grid_n)
+        plan = plan or W.Plan(ctx, self.rec, self.segs, max_workspace=max_workspace)
+        psi = torch.tensor(self.psi, dtype=dtype, device="cuda")
+        pot = torch.tensor(self.pot, dtype=dtype, device="cuda")
+        out = torch.zeros(plan.info["out_coefs"], dtype=dtype, device="cuda")
+        ek = torch.zeros(len(self.lrs), dtype=torch.float64, device="cuda")
+        ep = torch.zeros_like(ek)
+        W.apply_local_ham(plan, psi, pot, out, ek, ep, terms=terms or (W.KIN | W.POT))
+        torch.cuda.synchronize()
+        return plan, psi, out.cpu().numpy(), ek.cpu().numpy(), ep.cpu().numpy()
+
+    def out_slice(self, k):
+        r = self.rec[k]
+        n = int(r["on_c"]) + 7 * int(r["on_f"])
+        return slice(int(r["ocoef_off"]), int(r["ocoef_off"]) + n)
+
+
+def _single_case():
+    g = inputs.geometry("single")
+    lo, dims, flo, fhi = inputs.single_box()
+    return Case(g, [LR.box_locreg(lo, dims, flo, fhi)], normalize=True)
+
+
+def _sphere_case(nsf=6, rlo=2.4, rhi=3.4, ext=8, seed_shift=0, fine=1.6):
+    g = inputs.geometry("batch1k", nsf=nsf, seed_offset=seed_shift)
+    rng = np.random.default_rng(99 + seed_shift)
+    # pull the centres together so that the functions overlap
+    g.centers[:] = g.centers.mean(0) + rng.uniform(-4.0, 4.0, (nsf, 3))
+    g.radii[:] = rng.uniform(rlo, rhi, nsf)
+    g.fine_radii[:] = fine
+    g.envelope_sigma[:] = g.radii / 2
+    lrs = LR.sphere_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, ext)
+    return Case(g, lrs)
+
+
+@pytest.fixture(scope="module")
+def single():
+    return _single_case()
+
+
+@pytest.fixture(scope="module")
+def spheres():
+    return _sphere_case()
+
+
+def test_single_function_fp64(single):
+    _print("case: single function, FP64")
+    _, _, out, ek, ep = single.run(torch.float64)
+    ref, rk, rp = single.oracle(0)
+    assert rel_err(out, ref) < 1e-12
+    assert abs(ek[0] - rk) < 1e-12 * abs(rk)
+    assert abs(ep[0] - rp) < 1e-12 * abs(rk)
+    psi = single.coefs[0]
+    assert abs(psi @ out - (rk + rp)) < 1e-12 * abs(rk)
+
+
+def test_single_function_fp32(single):
+    _print("case: single function, FP32")
+    _, _, out, ek, ep = single.run(torch.float32)
+    ref, rk, rp = single.oracle(0)
+    assert rel_err(out, ref) < 1e-5
+    assert abs(ek[0] - rk) < 1e-6
+    assert abs(ep[0] - rp) < 1e-6
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_sphere_batch_every_function(spheres, dtype, tol):
+    _print(f"case: 6 overlapping spheres, ext 8, {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    _, _, out, ek, ep = spheres.run(dt)
+    for k in range(len(spheres.lrs)):
+        ref, rk, rp = spheres.oracle(k)
+        assert rel_err(out[spheres.out_slice(k)], ref) < tol, k
+        etol = 1e-12 * abs(rk) if dtype == "f64" else 1e-6
+        assert abs(ek[k] - rk) < etol and abs(ep[k] - rp) < etol, k
+
+
+def test_kinetic_and_potential_terms_separately(spheres):
+    _print("case: separate terms FP64")
+    _, _, outk, ek, _ = spheres.run(torch.float64, terms=W.KIN)
+    _, _, outp, _, ep = spheres.run(torch.float64, terms=W.POT)
+    for k in range(len(spheres.lrs)):
+        refk, rk, _ = spheres.oracle(k, potential=False)
+        refp, _, rp = spheres.oracle(k, kinetic=False)
+        assert rel_err(outk[spheres.out_slice(k)], refk) < 1e-12
+        assert rel_err(outp[spheres.out_slice(k)], refp) < 1e-12
+
+
+def test_wvl_kinetic_accumulates(spheres):
+    _print("case: wvl_kinetic accumulate")
+    ctx = W.Context(spheres.g.h, spheres.g.grid_n)
+    plan = W.Plan(ctx, spheres.rec, spheres.segs)
+    psi = torch.tensor(spheres.psi, dtype=torch.float64, device="cuda")
+    base = torch.arange(plan.info["out_coefs"], dtype=torch.float64, device="cuda") * 1e-3
+    out = base.clone()
+    W.kinetic(plan, psi, out)
+    torch.cuda.synchronize()
+    got = (out - base).cpu().numpy()
+    for k in range(len(spheres.lrs)):
+        refk, _, _ = spheres.oracle(k, potential=False)
+        assert rel_err(got[spheres.out_slice(k)], refk) < 1e-12
+
+
+def test_uncompress_compress_bit_exact(spheres):
+    _print("case: uncompress / compress")
+    ctx = W.Context(spheres.g.h, spheres.g.grid_n)
+    plan = W.Plan(ctx, spheres.rec, spheres.segs)
+    psi = torch.tensor(spheres.psi, dtype=torch.float64, device="cuda")
+    box = torch.full((plan.info["in_box"],), float("nan"), dtype=torch.float64, device="cuda")
+    W.uncompress(plan, psi, box)
+    torch.cuda.synchronize()
+    b = box.cpu().numpy()
+    off = 0
+    obox_parts = []
+    for k, l in enumerate(spheres.lrs):
+        ref = Hm.uncompress(l, spheres.coefs[k])
+        assert np.array_equal(b[off:off + ref.size], ref.ravel()), k
+        off += ref.size
+        e = l.ext
+        ob = np.random.default_rng(k).standard_normal(
+            (8, l.dims[2] + 2 * e, l.dims[1] + 2 * e, l.dims[0] + 2 * e))
+        obox_parts.append(ob)
+    obox = torch.tensor(np.concatenate([o.ravel() for o in obox_parts]), device="cuda")
+    out = torch.full((plan.info["out_coefs"],), float("nan"), dtype=torch.float64, device="cuda")
+    W.compress(plan, obox, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for k, l in enumerate(spheres.lrs):
+        assert np.array_equal(o[spheres.out_slice(k)], Hm.compress_out(l, obox_parts[k]))
+
+
+def test_edge_boxes_fp64():
+    """1x1x1 and anisotropic boxes, empty fine set, fine set = whole box,
+    ext 0 and ext 16, a box in the grid corner (output pattern clipped)."""
+    _print("case: edge boxes")
+    g = inputs.geometry("batch1k", nsf=1)
+    g.grid_n = (40, 36, 44)
+    masks = []
+    rng = np.random.default_rng(5)
+    lrs = []
+    specs = [((0, 0, 0), (1, 1, 1), "all", 3), ((3, 4, 5), (5, 2, 7), "none", 0),
+             ((10, 8, 6), (6, 5, 4), "random", 16), ((0, 20, 30), (9, 7, 8), "random", 8),
+             ((25, 25, 30), (14, 11, 13), "all", 2)]
+    for lo, dims, fine, ext in specs:
+        m = rng.random((dims[2], dims[1], dims[0])) < 0.8
+        m.flat[0] = True
+        fm = {"all": m, "none": np.zeros_like(m), "random": m & (rng.random(m.shape) < 0.5)}[fine]
+        olo = [max(0, lo[a] - ext) for a in range(3)]
+        ohi = [min(g.grid_n[a] - 1, lo[a] + dims[a] - 1 + ext) for a in range(3)]
+        om = rng.random((ohi[2] - olo[2] + 1, ohi[1] - olo[1] + 1, ohi[0] - olo[0] + 1)) < 0.9
+        ofm = om & (rng.random(om.shape) < 0.6)
+        lrs.append(LR.Locreg(lo=lo, dims=dims, ext=ext, cseg=LR.segments_from_mask(m, lo),
+                             fseg=LR.segments_from_mask(fm, lo),
+                             ocseg=LR.segments_from_mask(om, olo),
+                             ofseg=LR.segments_from_mask(ofm, olo)))
+    g.centers = np.zeros((len(lrs), 3))
+    g.envelope_sigma = np.full(len(lrs), 100.0)
+    g.domain_lo = np.zeros(3)
+    g.domain_hi = np.array(g.grid_n) * g.h
+    case = Case(g, lrs, normalize=False)
+    _, _, out, ek, ep = case.run(torch.float64)
+    for k in range(len(lrs)):
+        ref, rk, rp = case.oracle(k)
+        assert rel_err(out[case.out_slice(k)], ref) < 1e-12, k
+        assert abs(ek[k] - rk) <= 1e-12 * max(1.0, abs(rk)), k
+
+
+def test_chunked_plan_matches_single_chunk_bitwise(spheres):
+    _print("case: chunked workspace")
+    plan1, _, out1, ek1, ep1 = spheres.run(torch.float64)
+    plan2, _, out2, ek2, ep2 = spheres.run(torch.float64, max_workspace=1)
+    assert plan2.info["chunks"] == len(spheres.lrs)
+    assert np.array_equal(out1, out2) and np.array_equal(ek1, ek2) and np.array_equal(ep1, ep2)
+
+
+def test_function_alone_equals_function_in_batch(spheres):
+    """Batch composition changes no function's result (bitwise)."""
+    _print("case: alone vs batch")
+    _, _, out, ek, ep = spheres.run(torch.float32)
+    k = 3
+    alone = Case(spheres.g, [spheres.lrs[k]])
+    alone.coefs = [spheres.coefs[k]]
+    alone.psi = spheres.coefs[k]
+    _, _, out1, ek1, ep1 = alone.run(torch.float32)
+    assert np.array_equal(out1, out[spheres.out_slice(k)])
+    assert ek1[0] == ek[k] and ep1[0] == ep[k]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sparse_overlap_and_hamiltonian(spheres, dtype):
+    """Pattern bit-exact; values against the oracle's S and H (the oracle's H
+    uses the oracle's own H|phi>)."""
+    _print(f"case: sparse S/H {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    plan, psi, out, _, _ = spheres.run(dt)
+    hpsi = torch.tensor(out, dtype=dt, device="cuda")
+    n = len(spheres.lrs)
+    ohs = [spheres.oracle(k)[0] for k in range(n)]
+    for ket_out in (False, True):
+        rowptr, col, val = W.sparse_overlap(plan, psi, hpsi if ket_out else psi, ket_out)
+        torch.cuda.synchronize()
+        kets = ohs if ket_out else spheres.coefs
+        rp, cl, vv = SP.matrix(spheres.lrs, spheres.coefs, kets, ket_out)
+        assert np.array_equal(rowptr.cpu().numpy(), rp)
+        assert np.array_equal(col.cpu().numpy(), cl)
+        v = val.cpu().numpy()
+        rtol = 1e-12 if dtype == "f64" else 1e-5
+        for a in range(n):
+            for j in range(rp[a], rp[a + 1]):
+                b = cl[j]
+                scale = np.linalg.norm(spheres.coefs[a]) * np.linalg.norm(kets[b])
+                assert abs(v[j] - vv[j]) <= rtol * scale, (a, b, v[j], vv[j])
+        if not ket_out:
+            for a in range(n):
+                diag = v[rp[a] + list(cl[rp[a]:rp[a + 1]]).index(a)]
+                assert abs(diag - 1.0) < (1e-13 if dtype == "f64" else 1e-6)
+
+
+def test_repeat_runs_bitwise_deterministic(spheres):
+    _print("case: determinism")
+    _, _, o1, e1, p1 = spheres.run(torch.float32)
+    _, _, o2, e2, p2 = spheres.run(torch.float32)
+    assert np.array_equal(o1, o2) and np.array_equal(e1, e2) and np.array_equal(p1, p2)
+
+
+def test_library_segments_feed_identical_results():
+    """Segments built by the library (wvl_build_locregs) equal the oracle's."""
+    _print("case: library-built locregs")
+    g = inputs.geometry("batch1k", nsf=40)
+    lr, segs = W.build_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
+    rec, oseg = to_abi(LR.sphere_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext))
+    assert np.array_equal(segs, oseg)
+    assert np.array_equal(lr["coef_off"], rec["coef_off"])
