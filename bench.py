@@ -1,0 +1,366 @@
+#!/usr/bin/env python3
+"""Benchmark: batched local-Hamiltonian application + sparse S/H on one MI355X.
+
+A step is one pass of the whole hot path over every support function of the
+workload: uncompress -> potential term (synthesis + magic filter up passes,
+potential multiply, down passes) -> kinetic term -> compress, then the S and
+H matrix values on their (resident) sparsity patterns.  Inputs are resident
+in HBM before the timed region starts; patterns are built once at set-up and
+timed separately (the localization regions do not change between steps).
+
+    python bench.py [--steps K] [--warmup W] [--workload batch1k|gpu16k|single]
+                    [--dtype f32|f64] [--no-cpu-baseline]
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+WORKLOAD_TEXT = {
+    "batch1k": "1,000 support functions, centres uniform in a 30 bohr cube, R ~ U(5,7) bohr, "
+               "h = 0.45 bohr, fine radius 3.5 bohr, L' margin 8; one H apply + S + H per step",
+    "gpu16k": "16,000 support functions, centres uniform in a 110 bohr cube, R ~ U(5,7) bohr, "
+              "h = 0.45 bohr, fine radius 3.5 bohr, L' margin 8; one H apply + S + H per step",
+    "single": "one support function, 20^3 coarse box at h = 0.5 bohr, fine region the inner 10^3",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work per kernel kind (bytes moved at minimum, flops) per launch
+# ---------------------------------------------------------------------------
+
+def _count_up(N):
+    """sum over output points of the number of coarse inputs a stride-2 up
+    pass reads (per channel pair), for a line of N coarse points."""
+    import numpy as np
+    l = np.arange(2 * N + 29)
+    lo = np.maximum(0, (l - 29) >> 1)
+    hi = np.minimum(N - 1, l >> 1)
+    return int(np.sum(np.maximum(0, hi - lo + 1)))
+
+
+def _count_down(N, e):
+    import numpy as np
+    p = np.arange(N + 2 * e)
+    two_i = 2 * (p - e)
+    lo = np.maximum(0, two_i)
+    hi = np.minimum(2 * N + 28, two_i + 30)
+    return int(np.sum(np.maximum(0, hi - lo + 1)))
+
+
+def work_model(locregs, sz, terms_kin=True):
+    """{kernel kind: (bytes, flops)} summed over all functions, one launch each."""
+    import numpy as np
+    out = {}
+
+    def add(k, b, f):
+        ob, of = out.get(k, (0.0, 0.0))
+        out[k] = (ob + b, of + f)
+    for r in locregs:
+        n0, n1, n2 = (int(v) for v in r["dims"])
+        e = int(r["ext"])
+        r0, r1, r2 = 2 * n0 + 29, 2 * n1 + 29, 2 * n2 + 29
+        o0, o1, o2 = n0 + 2 * e, n1 + 2 * e, n2 + 2 * e
+        nin = int(r["n_c"]) + 7 * int(r["n_f"])
+        nout = int(r["on_c"]) + 7 * int(r["on_f"])
+        c8, o8 = 8 * n0 * n1 * n2, 8 * o0 * o1 * o2
+        add("gather", sz * (nin + c8), 0)
+        # kinetic: outputs whose other coordinates lie in the input box; 58 MAC each
+        kin_out = [8 * o0 * n1 * n2, 8 * n0 * o1 * n2, 8 * n0 * n1 * o2]
+        for ax, name in enumerate(("kin_x", "kin_y", "kin_z")):
+            rw = 1 if ax == 0 else 2
+            add(name, sz * (c8 + rw * o8), 2 * 58 * kin_out[ax])
+        add("ekin", sz * 2 * c8, 2 * c8)
+        a1, a2, g = 4 * r0 * n1 * n2, 2 * r0 * r1 * n2, r0 * r1 * r2
+        b1, b2 = 2 * r0 * r1 * o2, 4 * r0 * o1 * o2
+        add("up_x", sz * (c8 + a1), 2 * 2 * 4 * n1 * n2 * _count_up(n0))
+        add("up_y", sz * (a1 + a2), 2 * 2 * 2 * r0 * n2 * _count_up(n1))
+        add("up_z", sz * (a2 + 2 * g), 2 * 2 * r0 * r1 * _count_up(n2) + 3 * g)
+        add("down_z", sz * (g + b1), 2 * 2 * r0 * r1 * _count_down(n2, e))
+        add("down_y", sz * (b1 + b2), 2 * 2 * 2 * r0 * o2 * _count_down(n1, e))
+        add("down_x", sz * (b2 + (2 if terms_kin else 1) * o8),
+            2 * 2 * 4 * o1 * o2 * _count_down(n0, e))
+        add("scatter", sz * 2 * nout, 0)
+    return out
+
+
+def path_bytes(locregs, sz):
+    """Algorithmic bytes of one step: compressed phi in, compressed H phi out,
+    each function's potential block, and one read of phi (S) and phi + H phi (H)."""
+    tot = 0
+    for r in locregs:
+        n = [int(v) for v in r["dims"]]
+        nin = int(r["n_c"]) + 7 * int(r["n_f"])
+        nout = int(r["on_c"]) + 7 * int(r["on_f"])
+        g = (2 * n[0] + 29) * (2 * n[1] + 29) * (2 * n[2] + 29)
+        tot += sz * (nin + nout + g) + sz * (nin + nin + nout)
+    return tot
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("wvl_kernels.hip", "wvl_host.cpp", "wvl_internal.h", "wvl_filters.h"):
+        with open(os.path.join(ROOT, "paper_1401_7441_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, dtype):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, when
+    they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            tab = json.load(f)
+        ent = tab.get(f"{workload}/{dtype}/{kernel}")
+        if ent and ent.get("source_hash") == source_hash():
+            return float(ent["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
+# ---------------------------------------------------------------------------
+# workload set-up
+# ---------------------------------------------------------------------------
+
+def setup(workload, dtype_name):
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1401_7441_amd as W
+
+    t0 = time.perf_counter()
+    g = inputs.geometry(workload)
+    if workload == "single":
+        raise SystemExit("the single-function workload is a parity case; use batch1k or gpu16k")
+    lr, segs = W.build_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
+    t_lr = time.perf_counter() - t0
+    dt = torch.float32 if dtype_name == "f32" else torch.float64
+    coefs = []
+    for k in range(len(lr)):
+        r = lr[k]
+        sc = segs[int(r["seg_c"]):int(r["seg_c"]) + int(r["nseg_c"])]
+        sf = segs[int(r["seg_f"]):int(r["seg_f"]) + int(r["nseg_f"])]
+        coefs.append(inputs.coefficients(g, k, _points(sc), _points(sf)))
+    psi = torch.tensor(np.concatenate(coefs), dtype=dt, device="cuda")
+    pot = inputs.potential(g, device="cuda").to(dt).contiguous()
+    ctx = W.Context(g.h, g.grid_n)
+    plan = W.Plan(ctx, lr, segs)
+    hpsi = torch.zeros(plan.info["out_coefs"], dtype=dt, device="cuda")
+    ek = torch.zeros(len(lr), dtype=torch.float64, device="cuda")
+    ep = torch.zeros_like(ek)
+    ws = plan.new_workspace(dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nnz_s = W.sparse_pattern_nnz(plan, False)
+    nnz_h = W.sparse_pattern_nnz(plan, True)
+    t_pat = time.perf_counter() - t1
+    s_out = (torch.empty(len(lr) + 1, dtype=torch.int64, device="cuda"),
+             torch.empty(max(1, nnz_s), dtype=torch.int32, device="cuda"),
+             torch.empty(max(1, nnz_s), dtype=torch.float64, device="cuda"))
+    h_out = (torch.empty(len(lr) + 1, dtype=torch.int64, device="cuda"),
+             torch.empty(max(1, nnz_h), dtype=torch.int32, device="cuda"),
+             torch.empty(max(1, nnz_h), dtype=torch.float64, device="cuda"))
+    return dict(g=g, lr=lr, segs=segs, psi=psi, pot=pot, ctx=ctx, plan=plan, hpsi=hpsi, ek=ek,
+                ep=ep, ws=ws, s_out=s_out, h_out=h_out, nnz_s=nnz_s, nnz_h=nnz_h,
+                t_locreg=t_lr, t_pattern=t_pat, dtype=dt)
+
+
+def _points(seg):
+    import numpy as np
+    pts = [np.stack([np.arange(s["i1s"], s["i1e"] + 1),
+                     np.full(s["i1e"] - s["i1s"] + 1, s["i2"]),
+                     np.full(s["i1e"] - s["i1s"] + 1, s["i3"])], axis=1) for s in seg]
+    return np.concatenate(pts) if pts else np.zeros((0, 3), np.int64)
+
+
+def step(S):
+    import paper_1401_7441_amd as W
+    W.apply_local_ham(S["plan"], S["psi"], S["pot"], S["hpsi"], S["ek"], S["ep"], S["ws"])
+    W.sparse_overlap(S["plan"], S["psi"], S["psi"], False, out=S["s_out"])
+    W.sparse_overlap(S["plan"], S["psi"], S["hpsi"], True, out=S["h_out"])
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the same workload
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(workload, budget_s=20.0, max_sf=64):
+    import numpy as np
+
+    import inputs
+    from oracle import hamiltonian, locreg
+    g = inputs.geometry(workload)
+    t0 = time.perf_counter()
+    lrs = locreg.sphere_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
+    pot = inputs.potential(g).numpy()
+    log(f"cpu baseline: oracle set-up {time.perf_counter() - t0:.1f} s")
+    done = 0
+    elapsed = 0.0
+    pts = 0
+    while done < max_sf and (elapsed < budget_s or done < 2):
+        l = lrs[done]
+        c = inputs.coefficients(g, done, locreg.points_from_segments(l.cseg),
+                                locreg.points_from_segments(l.fseg))
+        t = time.perf_counter()
+        hamiltonian.apply_local_ham(l, c, pot, g.h)
+        elapsed += time.perf_counter() - t
+        pts += int(np.prod([2 * d + 29 for d in l.dims]))
+        done += 1
+    return {"value": done / elapsed, "unit": "SF H-applies/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {len(lrs)} support functions of {workload}, local H "
+                      f"apply only (no S/H), FP64 numpy oracle, {elapsed:.1f} s",
+            "fine_grid_pts_per_s": pts / elapsed}
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch1k", choices=["batch1k", "gpu16k"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-trace", action="store_true",
+                    help="do not bracket kernels with events during the timed steps")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design in the notes, not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    import paper_1401_7441_amd as W  # noqa: F401  (fails loudly without libwvl.so)
+
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    log(f"set-up: workload {args.workload}, {args.dtype}")
+    S = setup(args.workload, args.dtype)
+    nsf = len(S["lr"])
+    log(f"set-up done: {nsf} functions, locregs {S['t_locreg']:.2f} s, patterns "
+        f"{S['t_pattern'] * 1e3:.1f} ms (S nnz {S['nnz_s']}, H nnz {S['nnz_h']}), "
+        f"workspace {S['ws'].numel() / 2**30:.2f} GiB")
+    for _ in range(args.warmup):
+        step(S)
+    torch.cuda.synchronize()
+    ctx = S["ctx"]
+    if not args.no_trace:
+        ctx.profile(True)
+        ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(S)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    prof = {}
+    if not args.no_trace:
+        prof = ctx.profile_read()
+        ctx.profile(False)
+    ms_step = dt_s * 1e3 / args.steps
+    value = nsf * args.steps / dt_s
+    sz = 4 if args.dtype == "f32" else 8
+    fine_pts = sum(int((2 * r["dims"][0] + 29) * (2 * r["dims"][1] + 29) * (2 * r["dims"][2] + 29))
+                   for r in S["lr"])
+    model = work_model(S["lr"], sz)
+    # sparse values: one read of the coefficients each for S, phi + H phi for H
+    info = S["plan"].info
+    model["sparse_values"] = (sz * (2 * info["in_coefs"] + info["out_coefs"]),
+                              2.0 * (S["nnz_s"] + S["nnz_h"]))
+    kernels = {}
+    for k, (n, ms) in prof.items():
+        if n:
+            per_launch = ms / n
+            launches_per_step = n / args.steps
+            b, f = model.get(k, (0.0, 0.0))
+            b /= max(1.0, launches_per_step) if k == "sparse_values" else 1.0
+            kernels[k] = {"launches": n, "avg_ms": per_launch,
+                          "gbps": (b / (per_launch * 1e-3) / 1e9) if b else None,
+                          "tflops": (f / (per_launch * 1e-3) / 1e12) if f else None}
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        b, f = model.get(dom, (0.0, 0.0))
+        if dom == "sparse_values":
+            b /= 2.0
+        avg = kernels[dom]["avg_ms"] * 1e-3
+        peak_f = FP32_PEAK_TFLOPS if args.dtype == "f32" else FP64_PEAK_TFLOPS
+        ridge = peak_f * 1e12 / (HBM_PEAK_GBPS * 1e9)
+        if f and f / max(b, 1.0) > ridge:
+            ach = f / avg / 1e12
+            roofline = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": peak_f,
+                        "unit": "TFLOP/s", "frac": ach / peak_f}
+        else:
+            ach = b / avg / 1e9
+            roofline = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS,
+                        "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS}
+        roofline["algorithmic_bytes_per_launch"] = b
+        roofline["flops_per_launch"] = f
+        roofline["avg_launch_ms"] = kernels[dom]["avg_ms"]
+        roofline["traffic"] = load_traffic(dom, args.workload, args.dtype)
+    pb = path_bytes(S["lr"], sz)
+    res = {
+        "metric": "support-function H-applies/s (fine grid pts/s, % HBM peak); p50/p99 request "
+                  "latency",
+        "value": value,
+        "unit": "SF H-applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
+                   "nsf": nsf, "h_bohr": S["g"].h, "ext": int(S["g"].ext),
+                   "grid": list(S["g"].grid_n), "conv_dtype": args.dtype,
+                   "reduction_dtype": "f64", "s_nnz": S["nnz_s"], "h_nnz": S["nnz_h"]},
+        "fine_grid_pts_per_s": fine_pts * args.steps / dt_s,
+        "path_hbm": {"algorithmic_bytes_per_step": pb, "gbps": pb / (ms_step * 1e-3) / 1e9,
+                     "frac": pb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+        "roofline": roofline,
+        "kernels": kernels,
+        "setup": {"locregs_s": S["t_locreg"], "patterns_ms": S["t_pattern"] * 1e3},
+        "source_hash": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

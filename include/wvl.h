@@ -209,6 +209,19 @@ wvl_status wvl_sparse_overlap(wvl_plan* plan, const void* bra_c, int ket_is_outp
                               const void* ket_c, wvl_dtype dt, int64_t* nnz, int64_t* rowptr,
                               int32_t* col, double* val);
 
+/* Kernel tracing.  With profiling enabled, every kernel the context launches
+ * is bracketed by two HIP events recorded on the context's stream; times
+ * are aggregated per kernel kind.  wvl_profile_read synchronizes the stream,
+ * folds pending events into the totals and returns, for kernel kind `id`
+ * (0 <= id < wvl_profile_count()), its name, launch count and summed
+ * duration in milliseconds.  wvl_profile_reset clears the totals.
+ * Errors: WVL_EINVAL for a NULL context or an id out of range. */
+wvl_status wvl_profile_enable(wvl_ctx* ctx, int enable);
+wvl_status wvl_profile_reset(wvl_ctx* ctx);
+int32_t wvl_profile_count(void);
+wvl_status wvl_profile_read(wvl_ctx* ctx, int32_t id, const char** name, int64_t* launches,
+                            double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

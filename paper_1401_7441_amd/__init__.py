@@ -42,7 +42,8 @@ LOCREG_DTYPE = np.dtype([
 
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
-            "wvl_compress", "wvl_apply_local_ham", "wvl_kinetic", "wvl_sparse_overlap")
+            "wvl_compress", "wvl_apply_local_ham", "wvl_kinetic", "wvl_sparse_overlap",
+            "wvl_profile_enable", "wvl_profile_reset", "wvl_profile_count", "wvl_profile_read")
 
 
 class WvlError(RuntimeError):
@@ -93,6 +94,11 @@ def _load():
         "wvl_apply_local_ham": [P, ctypes.c_int, U32, P, P, P, P, P, P],
         "wvl_kinetic": [P, ctypes.c_int, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
+        "wvl_profile_enable": [P, ctypes.c_int],
+        "wvl_profile_reset": [P],
+        "wvl_profile_count": [],
+        "wvl_profile_read": [P, I32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(I64),
+                             ctypes.POINTER(D)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -104,16 +110,26 @@ def _load():
     return lib
 
 
-_lib = _load()
+_lib = None
+_load_error = None
+try:
+    _lib = _load()
+except (OSError, AttributeError, ImportError) as _e:   # missing or stale build
+    _load_error = _e
 
 
 def lib():
+    """The loaded libwvl.so.  Raises when it is missing or stale: there is no
+    fallback implementation."""
+    if _lib is None:
+        raise ImportError(f"libwvl.so is not usable ({_load_error}); build it with "
+                          "`python -m paper_1401_7441_amd.build`")
     return _lib
 
 
 def _check(status, ctx=None):
     if status != WVL_OK:
-        msg = _lib.wvl_last_error(ctx)
+        msg = lib().wvl_last_error(ctx)
         raise WvlError(status, msg.decode() if msg else "")
 
 
@@ -135,10 +151,10 @@ def build_locregs(h, grid_n, centers, radii, fine_radii, ext):
     g = _grid(h, grid_n)
     lr = np.zeros(nsf, LOCREG_DTYPE)
     n = ctypes.c_int64(0)
-    _check(_lib.wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
+    _check(lib().wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
                                   f.ctypes.data, int(ext), lr.ctypes.data, None, ctypes.byref(n)))
     segs = np.zeros(n.value, SEG_DTYPE)
-    _check(_lib.wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
+    _check(lib().wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
                                   f.ctypes.data, int(ext), lr.ctypes.data, segs.ctypes.data,
                                   ctypes.byref(n)))
     return lr, segs
@@ -178,16 +194,35 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._ptr = ctypes.c_void_p()
         g = _grid(h, grid_n)
-        _check(_lib.wvl_create(ctypes.byref(self._ptr), ctypes.byref(g),
+        _check(lib().wvl_create(ctypes.byref(self._ptr), ctypes.byref(g),
                                ctypes.c_void_p(self.stream.cuda_stream)))
 
     @property
     def handle(self):
         return self._ptr
 
+    def profile(self, enable=True):
+        """Bracket every kernel launch with HIP events on this context's stream."""
+        _check(lib().wvl_profile_enable(self._ptr, int(bool(enable))), self._ptr)
+
+    def profile_reset(self):
+        _check(lib().wvl_profile_reset(self._ptr), self._ptr)
+
+    def profile_read(self):
+        """{kernel kind: (launches, total_ms)} of the traced launches so far."""
+        out = {}
+        for k in range(lib().wvl_profile_count()):
+            name = ctypes.c_char_p()
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            _check(lib().wvl_profile_read(self._ptr, k, ctypes.byref(name), ctypes.byref(n),
+                                         ctypes.byref(ms)), self._ptr)
+            out[name.value.decode()] = (int(n.value), float(ms.value))
+        return out
+
     def close(self):
         if self._ptr:
-            _lib.wvl_destroy(self._ptr)
+            lib().wvl_destroy(self._ptr)
             self._ptr = ctypes.c_void_p()
 
     def __del__(self):
@@ -207,11 +242,11 @@ class Plan:
         self.segs = np.ascontiguousarray(segs, dtype=SEG_DTYPE)
         self._ptr = ctypes.c_void_p()
         ws = ctypes.c_size_t(0)
-        _check(_lib.wvl_plan_create(ctx.handle, len(self.locregs), self.locregs.ctypes.data,
+        _check(lib().wvl_plan_create(ctx.handle, len(self.locregs), self.locregs.ctypes.data,
                                     self.segs.ctypes.data, len(self.segs), int(max_workspace),
                                     ctypes.byref(self._ptr), ctypes.byref(ws)), ctx.handle)
         info = _PlanInfo()
-        _check(_lib.wvl_plan_info_get(self._ptr, ctypes.byref(info)), ctx.handle)
+        _check(lib().wvl_plan_info_get(self._ptr, ctypes.byref(info)), ctx.handle)
         self.info = {k: int(getattr(info, k)) for k, _ in _PlanInfo._fields_}
 
     @property
@@ -229,7 +264,7 @@ class Plan:
 
     def close(self):
         if self._ptr:
-            _lib.wvl_plan_destroy(self._ptr)
+            lib().wvl_plan_destroy(self._ptr)
             self._ptr = ctypes.c_void_p()
 
     def __del__(self):
@@ -257,7 +292,7 @@ def uncompress(plan: Plan, psi_c, psi_box):
     dt = _dtype_code(psi_c, psi_box)
     if psi_c.numel() < plan.info["in_coefs"] or psi_box.numel() < plan.info["in_box"]:
         raise WvlError(WVL_EINVAL, "buffer smaller than the plan's layout")
-    _check(_lib.wvl_uncompress(plan._ptr, dt, _ptr(psi_c), _ptr(psi_box)), plan.ctx.handle)
+    _check(lib().wvl_uncompress(plan._ptr, dt, _ptr(psi_c), _ptr(psi_box)), plan.ctx.handle)
 
 
 def compress(plan: Plan, box, hpsi_c):
@@ -265,7 +300,7 @@ def compress(plan: Plan, box, hpsi_c):
     dt = _dtype_code(box, hpsi_c)
     if box.numel() < plan.info["out_box"] or hpsi_c.numel() < plan.info["out_coefs"]:
         raise WvlError(WVL_EINVAL, "buffer smaller than the plan's layout")
-    _check(_lib.wvl_compress(plan._ptr, dt, _ptr(box), _ptr(hpsi_c)), plan.ctx.handle)
+    _check(lib().wvl_compress(plan._ptr, dt, _ptr(box), _ptr(hpsi_c)), plan.ctx.handle)
 
 
 def apply_local_ham(plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None, workspace=None,
@@ -281,7 +316,7 @@ def apply_local_ham(plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None, work
             raise WvlError(WVL_EINVAL, f"potential has {pot.numel()} points, the grid needs {need}")
     if workspace is None:
         workspace = plan.new_workspace(psi_c.dtype)
-    _check(_lib.wvl_apply_local_ham(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
+    _check(lib().wvl_apply_local_ham(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
                                     _ptr(hpsi_c), _ptr(e_kin), _ptr(e_pot), _ptr(workspace)),
            plan.ctx.handle)
 
@@ -293,13 +328,13 @@ def kinetic(plan: Plan, psi_c, hpsi_c, e_kin=None, workspace=None):
     _check_sizes(plan, psi_c, hpsi_c, e_kin, None, workspace, dt)
     if workspace is None:
         workspace = plan.new_workspace(psi_c.dtype)
-    _check(_lib.wvl_kinetic(plan._ptr, dt, _ptr(psi_c), _ptr(hpsi_c), _ptr(e_kin),
+    _check(lib().wvl_kinetic(plan._ptr, dt, _ptr(psi_c), _ptr(hpsi_c), _ptr(e_kin),
                             _ptr(workspace)), plan.ctx.handle)
 
 
 def sparse_pattern_nnz(plan: Plan, ket_is_output: bool):
     n = ctypes.c_int64(0)
-    _check(_lib.wvl_sparse_overlap(plan._ptr, None, int(bool(ket_is_output)), None, F64,
+    _check(lib().wvl_sparse_overlap(plan._ptr, None, int(bool(ket_is_output)), None, F64,
                                    ctypes.byref(n), None, None, None), plan.ctx.handle)
     return n.value
 
@@ -321,7 +356,7 @@ def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None):
     else:
         rowptr, col, val = out
     n = ctypes.c_int64(0)
-    _check(_lib.wvl_sparse_overlap(plan._ptr, _ptr(bra_c), int(bool(ket_is_output)), _ptr(ket_c),
+    _check(lib().wvl_sparse_overlap(plan._ptr, _ptr(bra_c), int(bool(ket_is_output)), _ptr(ket_c),
                                    dt, ctypes.byref(n), _ptr(rowptr), _ptr(col), _ptr(val)),
            plan.ctx.handle)
     return rowptr, col[:nnz], val[:nnz]

@@ -17,10 +17,25 @@
 
 using namespace wvl;
 
+// kernel kinds for tracing
+enum KernelKind {
+  KK_GATHER, KK_KIN_X, KK_KIN_Y, KK_KIN_Z, KK_EKIN, KK_FINALIZE, KK_UP_X, KK_UP_Y, KK_UP_Z,
+  KK_DOWN_Z, KK_DOWN_Y, KK_DOWN_X, KK_SCATTER, KK_PATTERN, KK_SPARSE, KK_COUNT
+};
+static const char* kKernelNames[KK_COUNT] = {
+    "gather", "kin_x", "kin_y", "kin_z", "ekin", "finalize", "up_x", "up_y", "up_z",
+    "down_z", "down_y", "down_x", "scatter", "pattern", "sparse_values"};
+
 struct wvl_ctx {
   wvl_grid grid;
   hipStream_t stream;
   std::string err;
+  bool prof = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[KK_COUNT] = {};
+  double ms[KK_COUNT] = {};
 };
 
 namespace {
@@ -47,11 +62,49 @@ wvl_status fail(wvl_ctx* ctx, wvl_status st, const char* fmt, ...) {
       return fail(ctx, WVL_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
   } while (0)
 
-#define WVL_LAUNCH(ctx, what, call)                                                      \
+hipEvent_t take_event(wvl_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// brackets one launch with events when tracing is on
+struct Trace {
+  wvl_ctx* ctx;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  Trace(wvl_ctx* c, int k) : ctx(c), kind(k) {
+    if (ctx->prof) {
+      a = take_event(ctx);
+      b = take_event(ctx);
+      if (a && b) (void)hipEventRecord(a, ctx->stream);
+    }
+  }
+  ~Trace() {
+    if (ctx->prof && a && b) {
+      (void)hipEventRecord(b, ctx->stream);
+      ctx->pending.push_back({kind, a, b});
+    } else {
+      if (a) ctx->pool.push_back(a);
+      if (b) ctx->pool.push_back(b);
+    }
+  }
+};
+
+#define WVL_LAUNCH(ctx, kind, call)                                                      \
   do {                                                                                   \
-    int e_ = (call);                                                                     \
+    int e_;                                                                              \
+    {                                                                                    \
+      Trace tr_(ctx, kind);                                                              \
+      e_ = (call);                                                                       \
+    }                                                                                    \
     if (e_ != 0)                                                                         \
-      return fail(ctx, WVL_EDEVICE, "launch of %s failed: %s", what,                     \
+      return fail(ctx, WVL_EDEVICE, "launch of %s failed: %s", kKernelNames[kind],       \
                   hipGetErrorString((hipError_t)e_));                                    \
   } while (0)
 
@@ -393,7 +446,61 @@ wvl_status wvl_create(wvl_ctx** ctx, const wvl_grid* grid, void* hip_stream) {
   return WVL_OK;
 }
 
-void wvl_destroy(wvl_ctx* ctx) { delete ctx; }
+void wvl_destroy(wvl_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& r : ctx->pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+wvl_status wvl_profile_enable(wvl_ctx* ctx, int enable) {
+  if (!ctx) return fail(nullptr, WVL_EINVAL, "wvl_profile_enable: null context");
+  ctx->prof = enable != 0;
+  return WVL_OK;
+}
+
+static wvl_status fold_events(wvl_ctx* ctx) {
+  if (ctx->pending.empty()) return WVL_OK;
+  WVL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& r : ctx->pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      ctx->launches[r.kind] += 1;
+      ctx->ms[r.kind] += t;
+    }
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  return WVL_OK;
+}
+
+wvl_status wvl_profile_reset(wvl_ctx* ctx) {
+  if (!ctx) return fail(nullptr, WVL_EINVAL, "wvl_profile_reset: null context");
+  wvl_status st = fold_events(ctx);
+  for (int k = 0; k < KK_COUNT; ++k) {
+    ctx->launches[k] = 0;
+    ctx->ms[k] = 0.0;
+  }
+  return st;
+}
+
+int32_t wvl_profile_count(void) { return KK_COUNT; }
+
+wvl_status wvl_profile_read(wvl_ctx* ctx, int32_t id, const char** name, int64_t* launches,
+                            double* total_ms) {
+  if (!ctx || id < 0 || id >= KK_COUNT)
+    return fail(ctx, WVL_EINVAL, "wvl_profile_read: null context or id out of range");
+  wvl_status st = fold_events(ctx);
+  if (st != WVL_OK) return st;
+  if (name) *name = kKernelNames[id];
+  if (launches) *launches = ctx->launches[id];
+  if (total_ms) *total_ms = ctx->ms[id];
+  return WVL_OK;
+}
 
 static void free_pattern(PatternCache& p) {
   if (p.d_rowptr) (void)hipFree(p.d_rowptr);
@@ -624,7 +731,7 @@ wvl_status wvl_uncompress(wvl_plan* P, wvl_dtype dt, const void* psi_c, void* ps
   if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
   if (P->nsf > 0 && (!psi_c || !psi_box)) return fail(ctx, WVL_EINVAL, "wvl_uncompress: null buffer");
   for (const ChunkDev& ch : P->chunks)
-    WVL_LAUNCH(ctx, "uncompress",
+    WVL_LAUNCH(ctx, KK_GATHER,
                launch_gather(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, psi_c, psi_box,
                              P->d_wk + ch.sf0, ch.sf0, ch.nsf, ch.maxvol[P_GATHER], 0));
   return WVL_OK;
@@ -636,7 +743,7 @@ wvl_status wvl_compress(wvl_plan* P, wvl_dtype dt, const void* box, void* hpsi_c
   if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
   if (P->nsf > 0 && (!box || !hpsi_c)) return fail(ctx, WVL_EINVAL, "wvl_compress: null buffer");
   for (const ChunkDev& ch : P->chunks)
-    WVL_LAUNCH(ctx, "compress",
+    WVL_LAUNCH(ctx, KK_SCATTER,
                launch_scatter(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, box, hpsi_c,
                               P->d_wk + ch.sf0, ch.sf0, ch.nsf, ch.maxvol[P_SCATTER], 0, 0));
   return WVL_OK;
@@ -663,34 +770,34 @@ static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
     const ChunkDev& ch = P->chunks[c];
     const SfWork* wk = P->d_wk + ch.sf0;
     double* parts = (double*)((char*)workspace + align_bytes(P->chunk_elems[c] * sz));
-    WVL_LAUNCH(ctx, "gather", launch_gather(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, workspace,
+    WVL_LAUNCH(ctx, KK_GATHER, launch_gather(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, workspace,
                                             wk, ch.sf0, ch.nsf, ch.maxvol[P_GATHER], 1));
     if (terms & WVL_KIN) {
       for (int ax = 0; ax < 3; ++ax)
-        WVL_LAUNCH(ctx, "kinetic", launch_kin(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf,
+        WVL_LAUNCH(ctx, KK_KIN_X + ax, launch_kin(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf,
                                               ch.maxvol[P_KIN], workspace, ax > 0, fac));
       if (e_kin) {
-        WVL_LAUNCH(ctx, "e_kin", launch_ekin_partials(f64, st, P->d_sf, wk, ch.sf0, ch.nsf,
+        WVL_LAUNCH(ctx, KK_EKIN, launch_ekin_partials(f64, st, P->d_sf, wk, ch.sf0, ch.nsf,
                                                       ch.maxvol[P_GATHER], workspace, parts,
                                                       ch.nblk_kin));
-        WVL_LAUNCH(ctx, "e_kin sum",
+        WVL_LAUNCH(ctx, KK_FINALIZE,
                    launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.nblk_kin, e_kin));
       }
     }
     if (terms & WVL_POT) {
       const int64_t upv[3] = {ch.maxvol[P_UPX], ch.maxvol[P_UPY], ch.maxvol[P_UPZ]};
       for (int ax = 0; ax < 3; ++ax)
-        WVL_LAUNCH(ctx, "up", launch_up(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, upv[ax],
+        WVL_LAUNCH(ctx, KK_UP_X + ax, launch_up(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, upv[ax],
                                         workspace, pot, nf1, nf2, parts, ch.nblk_pot));
       if (e_pot)
-        WVL_LAUNCH(ctx, "e_pot sum",
+        WVL_LAUNCH(ctx, KK_FINALIZE,
                    launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.nblk_pot, e_pot));
       const int64_t dnv[3] = {ch.maxvol[P_DOWNX], ch.maxvol[P_DOWNY], ch.maxvol[P_DOWNZ]};
       for (int ax = 2; ax >= 0; --ax)
-        WVL_LAUNCH(ctx, "down", launch_down(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, dnv[ax],
+        WVL_LAUNCH(ctx, KK_DOWN_X - ax, launch_down(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, dnv[ax],
                                             workspace, (terms & WVL_KIN) ? 1 : 0));
     }
-    WVL_LAUNCH(ctx, "scatter", launch_scatter(f64, st, P->d_sf, P->d_seg, P->d_rt, workspace,
+    WVL_LAUNCH(ctx, KK_SCATTER, launch_scatter(f64, st, P->d_sf, P->d_seg, P->d_rt, workspace,
                                               hpsi_c, wk, ch.sf0, ch.nsf, ch.maxvol[P_SCATTER], 1,
                                               accumulate));
   }
@@ -719,8 +826,12 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
   std::vector<int64_t> cnt(nsf), rowptr(nsf + 1, 0);
   if (nsf > 0) {
     WVL_HIP(ctx, hipMalloc((void**)&d_count, sizeof(int64_t) * nsf));
-    int e = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, d_count,
-                           nullptr, nullptr);
+    int e;
+    {
+      Trace tr(ctx, KK_PATTERN);
+      e = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, d_count, nullptr,
+                         nullptr);
+    }
     if (e == 0)
       e = (int)hipMemcpyAsync(cnt.data(), d_count, sizeof(int64_t) * nsf, hipMemcpyDeviceToHost,
                               ctx->stream);
@@ -748,8 +859,12 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
       free_pattern(pc);
       return fail(ctx, WVL_ENOMEM, "pattern columns: %s", hipGetErrorString(e));
     }
-    int le = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, nullptr,
-                            pc.d_rowptr, pc.d_col);
+    int le;
+    {
+      Trace tr(ctx, KK_PATTERN);
+      le = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, nullptr,
+                          pc.d_rowptr, pc.d_col);
+    }
     if (le == 0) le = (int)hipStreamSynchronize(ctx->stream);
     if (le != 0) {
       free_pattern(pc);
@@ -788,7 +903,7 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
                                 ctx->stream));
   if (val && pc.nnz) {
     if (!bra_c || !ket_c) return fail(ctx, WVL_EINVAL, "wvl_sparse_overlap: null bra or ket");
-    WVL_LAUNCH(ctx, "sparse values",
+    WVL_LAUNCH(ctx, KK_SPARSE,
                launch_sparse_values(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt,
                                     ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.nnz, val));
   }
