@@ -51,16 +51,19 @@ def build(regen_filters: bool = True) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
-    kobj = os.path.join(bdir, "wvl_kernels.o")
+    kobjs = []
+    for src in ("wvl_kernels.hip", "wvl_fused.hip"):
+        obj = os.path.join(bdir, src.replace(".hip", ".o"))
+        _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        kobjs.append(obj)
     hobj = os.path.join(bdir, "wvl_host.o")
-    _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "wvl_kernels.hip"), "-o", kobj])
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
           "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c",
           os.path.join(CSRC, "wvl_host.cpp"), "-o", hobj])
     tmp = LIB + ".tmp"
     tlib = _torch_lib_dir()
     # plain host link: the device code is already embedded in wvl_kernels.o
-    _run(["g++", "-shared", "-fPIC", "-o", tmp, kobj, hobj, f"-L{tlib}", "-l:libamdhip64.so",
+    _run(["g++", "-shared", "-fPIC", "-o", tmp, *kobjs, hobj, f"-L{tlib}", "-l:libamdhip64.so",
           f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined"])
     os.replace(tmp, LIB)
     return LIB

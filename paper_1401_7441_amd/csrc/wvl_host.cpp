@@ -19,12 +19,16 @@ using namespace wvl;
 
 // kernel kinds for tracing
 enum KernelKind {
-  KK_GATHER, KK_KIN_X, KK_KIN_Y, KK_KIN_Z, KK_EKIN, KK_FINALIZE, KK_UP_X, KK_UP_Y, KK_UP_Z,
-  KK_DOWN_Z, KK_DOWN_Y, KK_DOWN_X, KK_SCATTER, KK_PATTERN, KK_SPARSE, KK_COUNT
+  KK_GATHER, KK_SCATTER, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_ZCOL, KK_BACK_PLANE, KK_FINALIZE,
+  KK_PATTERN, KK_SPARSE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
-    "gather", "kin_x", "kin_y", "kin_z", "ekin", "finalize", "up_x", "up_y", "up_z",
-    "down_z", "down_y", "down_x", "scatter", "pattern", "sparse_values"};
+    "uncompress", "compress", "fwd_plane", "pot_column", "kin_zcol", "back_plane", "finalize",
+    "pattern", "sparse_values"};
+
+// LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
+// less what their fixed-order reductions declare statically
+static const int64_t kLdsBudget = 160 * 1024 - 1024;
 
 struct wvl_ctx {
   wvl_grid grid;
@@ -625,55 +629,103 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
     bbox(segs, L.oseg_c, L.noseg_c, S.bb_out);
   }
   // chunks and workspace layout
+  auto sf_elems = [&](const SfDev& S) {
+    const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
+    const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
+    const int64_t o2 = n2 + 2 * e;
+    return align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) + align64(2 * o2 * r0 * r1) +
+           align64(8 * o2 * n0 * n1);
+  };
   int64_t best_f32 = 0, best_f64 = 0;
   {
     int k = 0;
     while (k < nsf) {
       ChunkDev ch{};
       ch.sf0 = k;
-      int64_t elems = 0, maxg = 0, maxc8 = 0;
+      int64_t elems = 0;
       int j = k;
       for (; j < nsf; ++j) {
-        const SfDev& S = P->h_sf[j];
-        const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
-        const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29, r2 = 2 * n2 + 29;
-        const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
-        const int64_t need = align64(8 * n0 * n1 * n2) + align64(4 * r0 * n1 * n2) +
-                             align64(2 * r0 * r1 * n2) + align64(r0 * r1 * r2) +
-                             align64(2 * r0 * r1 * o2) + align64(4 * r0 * o1 * o2) +
-                             align64(8 * o0 * o1 * o2);
-        const int64_t mg = std::max(maxg, r0 * r1 * r2), mc = std::max(maxc8, 8 * n0 * n1 * n2);
-        const int64_t parts = (int64_t)(j - k + 1) * ((mg + 255) / 256 + (mc + 255) / 256);
-        const int64_t bytes = align_bytes((elems + need) * 8) + parts * 8;
+        const int64_t need = sf_elems(P->h_sf[j]);
+        // partial slots are at most a few per 256 output points
+        const int64_t bytes = align_bytes((elems + need) * 8) + (int64_t)(j - k + 1) * 4096 * 8;
         if (j > k && max_workspace_bytes > 0 && (size_t)bytes > max_workspace_bytes) break;
         if (j - k >= 65535) break;
         elems += need;
-        maxg = mg;
-        maxc8 = mc;
       }
       ch.nsf = j - k;
-      // per-function offsets
       int64_t off = 0;
       for (int q = k; q < j; ++q) {
         const SfDev& S = P->h_sf[q];
         const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
-        const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29, r2 = 2 * n2 + 29;
+        const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
         const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
         SfWork& W = P->h_wk[q];
-        const int64_t vol[P_NPASS] = {8 * n0 * n1 * n2, 4 * r0 * n1 * n2, 2 * r0 * r1 * n2,
-                                      r0 * r1 * r2,     2 * r0 * r1 * o2, 4 * r0 * o1 * o2,
-                                      8 * o0 * o1 * o2, 8 * o0 * o1 * o2, 8 * o0 * o1 * o2};
-        for (int p = 0; p < P_NPASS; ++p) ch.maxvol[p] = std::max(ch.maxvol[p], vol[p]);
-        W.c8 = off; off += align64(vol[0]);
-        W.a1 = off; off += align64(vol[1]);
-        W.a2 = off; off += align64(vol[2]);
-        W.g = off;  off += align64(vol[3]);
-        W.b1 = off; off += align64(vol[4]);
-        W.b2 = off; off += align64(vol[5]);
-        W.o8 = off; off += align64(vol[6]);
+        W.c8 = off; off += align64(8 * n0 * n1 * n2);
+        W.g1 = off; off += align64(2 * n2 * r0 * r1);
+        W.g2 = off; off += align64(2 * o2 * r0 * r1);
+        W.oz = off; off += align64(8 * o2 * n0 * n1);
+        ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
+        ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
+        ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
+        ch.grid_kz = (int32_t)std::max<int64_t>(ch.grid_kz, (4 * n0 * n1 + 255) / 256);
       }
-      ch.nblk_pot = (int32_t)((ch.maxvol[P_UPZ] + 255) / 256);
-      ch.nblk_kin = (int32_t)((ch.maxvol[P_GATHER] + 255) / 256);
+      for (int d = 0; d < 2; ++d) {
+        const int64_t sz = d ? 8 : 4;
+        // k_fwd_plane: the largest row tile (of fine output rows) that fits
+        int64_t r1max = 0;
+        for (int q = k; q < j; ++q) r1max = std::max<int64_t>(r1max, 2 * P->h_sf[q].n[1] + 29);
+        auto lds_f = [&](int64_t T) {
+          int64_t m = 0;
+          for (int q = k; q < j; ++q) {
+            const SfDev& S = P->h_sf[q];
+            const int64_t ny = std::min<int64_t>(S.n[1], T / 2 + 17);
+            m = std::max<int64_t>(m, (4 * ny * S.n[0] + 2 * ny * (2 * S.n[0] + 29)) * sz);
+          }
+          return m;
+        };
+        int64_t tf = r1max;
+        while (tf > 2 && lds_f(tf) > kLdsBudget) tf = (tf + 1) / 2;
+        ch.tile_f[d] = (int32_t)tf;
+        ch.lds_f[d] = lds_f(tf);
+        int64_t gf = 0;
+        for (int q = k; q < j; ++q) {
+          const SfDev& S = P->h_sf[q];
+          gf = std::max<int64_t>(gf, (int64_t)S.n[2] * 2 * ((2 * S.n[1] + 29 + tf - 1) / tf));
+        }
+        ch.grid_f[d] = (int32_t)gf;
+        // k_back_plane: the largest tile of output rows that fits
+        int64_t o1max = 0;
+        for (int q = k; q < j; ++q) o1max = std::max<int64_t>(o1max, P->h_sf[q].n[1] + 2 * P->h_sf[q].ext);
+        auto lds_c = [&](int64_t T) {
+          int64_t m = 0;
+          for (int q = k; q < j; ++q) {
+            const SfDev& S = P->h_sf[q];
+            const int64_t r0 = 2 * S.n[0] + 29, r1 = 2 * S.n[1] + 29;
+            const int64_t nq = std::min<int64_t>(r1, 2 * T + 29);
+            const int64_t nyi = std::min<int64_t>(S.n[1], T + 28);
+            m = std::max<int64_t>(m, (nq * r0 + 2 * T * r0 + 4 * nyi * S.n[0]) * sz);
+          }
+          return m;
+        };
+        int64_t tc = o1max;
+        while (tc > 1 && lds_c(tc) > kLdsBudget) tc = (tc + 1) / 2;
+        ch.tile_c[d] = (int32_t)tc;
+        ch.lds_c[d] = lds_c(tc);
+        int64_t gc = 0;
+        for (int q = k; q < j; ++q) {
+          const SfDev& S = P->h_sf[q];
+          const int64_t o1 = S.n[1] + 2 * S.ext, o2 = S.n[2] + 2 * S.ext;
+          gc = std::max<int64_t>(gc, o2 * 2 * ((o1 + tc - 1) / tc));
+        }
+        ch.grid_c[d] = (int32_t)gc;
+        if (ch.lds_f[d] > kLdsBudget || ch.lds_c[d] > kLdsBudget) {
+          wvl_plan_destroy(P);
+          return fail(ctx, WVL_EUNSUPPORTED, "functions %d..%d: boxes too large for the LDS tiles",
+                      k, j - 1);
+        }
+      }
+      ch.nblk_pot = ch.grid_b;
+      ch.nblk_kin = std::max(ch.grid_c[0], ch.grid_c[1]);
       int64_t poff = 0;
       for (int q = k; q < j; ++q) {
         P->h_wk[q].epart = poff;
@@ -733,7 +785,7 @@ wvl_status wvl_uncompress(wvl_plan* P, wvl_dtype dt, const void* psi_c, void* ps
   for (const ChunkDev& ch : P->chunks)
     WVL_LAUNCH(ctx, KK_GATHER,
                launch_gather(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, psi_c, psi_box,
-                             P->d_wk + ch.sf0, ch.sf0, ch.nsf, ch.maxvol[P_GATHER], 0));
+                             ch.sf0, ch.nsf, ch.maxbox_in));
   return WVL_OK;
 }
 
@@ -745,7 +797,7 @@ wvl_status wvl_compress(wvl_plan* P, wvl_dtype dt, const void* box, void* hpsi_c
   for (const ChunkDev& ch : P->chunks)
     WVL_LAUNCH(ctx, KK_SCATTER,
                launch_scatter(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, box, hpsi_c,
-                              P->d_wk + ch.sf0, ch.sf0, ch.nsf, ch.maxvol[P_SCATTER], 0, 0));
+                              ch.sf0, ch.nsf, ch.maxbox_out));
   return WVL_OK;
 }
 
@@ -766,40 +818,34 @@ static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
   const int nf1 = 2 * ctx->grid.n[0] + 29, nf2 = 2 * ctx->grid.n[1] + 29;
   const double fac = -2.0 / (ctx->grid.h * ctx->grid.h);   // -1/2 (2/h)^2
   hipStream_t st = ctx->stream;
+  const int d = f64 ? 1 : 0;
+  const int pot_on = (terms & WVL_POT) ? 1 : 0, kin_on = (terms & WVL_KIN) ? 1 : 0;
   for (size_t c = 0; c < P->chunks.size(); ++c) {
     const ChunkDev& ch = P->chunks[c];
     const SfWork* wk = P->d_wk + ch.sf0;
     double* parts = (double*)((char*)workspace + align_bytes(P->chunk_elems[c] * sz));
-    WVL_LAUNCH(ctx, KK_GATHER, launch_gather(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, workspace,
-                                            wk, ch.sf0, ch.nsf, ch.maxvol[P_GATHER], 1));
-    if (terms & WVL_KIN) {
-      for (int ax = 0; ax < 3; ++ax)
-        WVL_LAUNCH(ctx, KK_KIN_X + ax, launch_kin(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf,
-                                              ch.maxvol[P_KIN], workspace, ax > 0, fac));
-      if (e_kin) {
-        WVL_LAUNCH(ctx, KK_EKIN, launch_ekin_partials(f64, st, P->d_sf, wk, ch.sf0, ch.nsf,
-                                                      ch.maxvol[P_GATHER], workspace, parts,
-                                                      ch.nblk_kin));
-        WVL_LAUNCH(ctx, KK_FINALIZE,
-                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.nblk_kin, e_kin));
-      }
-    }
-    if (terms & WVL_POT) {
-      const int64_t upv[3] = {ch.maxvol[P_UPX], ch.maxvol[P_UPY], ch.maxvol[P_UPZ]};
-      for (int ax = 0; ax < 3; ++ax)
-        WVL_LAUNCH(ctx, KK_UP_X + ax, launch_up(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, upv[ax],
-                                        workspace, pot, nf1, nf2, parts, ch.nblk_pot));
+    WVL_LAUNCH(ctx, KK_FWD_PLANE,
+               launch_fwd_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, wk, ch.sf0, ch.nsf,
+                                ch.grid_f[d], ch.tile_f[d], (size_t)ch.lds_f[d], workspace,
+                                pot_on));
+    if (pot_on) {
+      WVL_LAUNCH(ctx, KK_POT_COLUMN,
+                 launch_pot_column(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_b, workspace, pot,
+                                   nf1, nf2, parts));
       if (e_pot)
         WVL_LAUNCH(ctx, KK_FINALIZE,
-                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.nblk_pot, e_pot));
-      const int64_t dnv[3] = {ch.maxvol[P_DOWNX], ch.maxvol[P_DOWNY], ch.maxvol[P_DOWNZ]};
-      for (int ax = 2; ax >= 0; --ax)
-        WVL_LAUNCH(ctx, KK_DOWN_X - ax, launch_down(f64, st, ax, P->d_sf, wk, ch.sf0, ch.nsf, dnv[ax],
-                                            workspace, (terms & WVL_KIN) ? 1 : 0));
+                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.grid_b, e_pot));
     }
-    WVL_LAUNCH(ctx, KK_SCATTER, launch_scatter(f64, st, P->d_sf, P->d_seg, P->d_rt, workspace,
-                                              hpsi_c, wk, ch.sf0, ch.nsf, ch.maxvol[P_SCATTER], 1,
-                                              accumulate));
+    if (kin_on)
+      WVL_LAUNCH(ctx, KK_KIN_ZCOL,
+                 launch_kin_zcol(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_kz, workspace, fac));
+    WVL_LAUNCH(ctx, KK_BACK_PLANE,
+               launch_back_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf,
+                                 ch.grid_c[d], ch.tile_c[d], (size_t)ch.lds_c[d], workspace, hpsi_c,
+                                 fac, pot_on, kin_on, accumulate, parts));
+    if (kin_on && e_kin)
+      WVL_LAUNCH(ctx, KK_FINALIZE,
+                 launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.grid_c[d], e_kin));
   }
   return WVL_OK;
 }

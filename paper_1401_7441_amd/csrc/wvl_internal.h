@@ -32,46 +32,47 @@ struct SfDev {
 };
 
 // Workspace offsets (elements of the compute type) of one support function
-// inside its chunk's workspace.
+// inside its chunk's workspace:
+//   c8  dense input box      [8][N2][N1][N0]
+//   g1  after the x, y up passes   [2][N2][R1][R0]      (R = 2N + 29)
+//   g2  after the z column pass    [2][O2][R1][R0]      (O = N + 2 ext)
+//   oz  z part of the kinetic term [8][O2][N1][N0]
 struct SfWork {
-  int64_t c8, a1, a2, g, b1, b2, o8;
+  int64_t c8, g1, g2, oz;
   int64_t epart;      // offset (in doubles) of its e_pot partials
   int64_t kpart;      // offset (in doubles) of its e_kin partials
 };
 
-enum Pass {
-  P_GATHER = 0,  // compressed -> C8
-  P_UPX, P_UPY, P_UPZ,
-  P_DOWNZ, P_DOWNY, P_DOWNX,
-  P_KIN,         // C8 -> O8 (any axis)
-  P_SCATTER,     // O8 -> compressed
-  P_NPASS
-};
-
-// one chunk of support functions processed together
+// per-chunk launch geometry of the fused kernels, for dtype d (0 f32, 1 f64)
 struct ChunkDev {
   int32_t sf0, nsf;
-  int64_t maxvol[P_NPASS];
-  int32_t nblk_pot, nblk_kin;
+  int64_t maxbox_in, maxbox_out;   // largest dense input / output box (elements)
+  int32_t grid_f[2], tile_f[2];    // k_fwd_plane
+  int64_t lds_f[2];
+  int32_t grid_b;                  // k_pot_column
+  int32_t grid_kz;                 // k_kin_zcol
+  int32_t grid_c[2], tile_c[2];    // k_back_plane
+  int64_t lds_c[2];
+  int32_t nblk_pot, nblk_kin;      // partial slots per function
 };
 
 // launchers implemented in wvl_kernels.hip; all return hipError_t as int
 int launch_gather(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                  const void* psi, void* box, const SfWork* wk, int sf0, int nsf, int64_t maxvol,
-                  int use_work);
+                  const void* psi, void* box, int sf0, int nsf, int64_t maxvol);
 int launch_scatter(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                   const void* box, void* out, const SfWork* wk, int sf0, int nsf, int64_t maxvol,
-                   int use_work, int accumulate);
-int launch_up(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-              int64_t maxvol, void* ws, const void* pot, int nf1, int nf2, double* epart,
-              int nblk);
-int launch_down(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
-                int nsf, int64_t maxvol, void* ws, int accumulate);
-int launch_kin(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
-               int nsf, int64_t maxvol, void* ws, int accumulate, double fac);
+                   const void* box, void* out, int sf0, int nsf, int64_t maxvol);
 int launch_fill(int f64, void* stream, void* ptr, int64_t n);
-int launch_ekin_partials(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0,
-                         int nsf, int64_t maxvol, void* ws, double* kpart, int nblk);
+int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
+                     const int32_t* rt, const void* psi, const SfWork* wk, int sf0, int nsf,
+                     int gridx, int tile_rows, size_t lds, void* ws, int up_on);
+int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                      int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart);
+int launch_kin_zcol(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                    int gridx, void* ws, double fac);
+int launch_back_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
+                      const int32_t* rt, const SfWork* wk, int sf0, int nsf, int gridx,
+                      int tile_rows, size_t lds, const void* ws, void* out, double fac, int pot_on,
+                      int kin_on, int accumulate, double* kpart);
 int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const double* parts,
                     int which, int nblk, double* out);
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,

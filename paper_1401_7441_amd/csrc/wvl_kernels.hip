@@ -1,60 +1,26 @@
-// HIP kernels for gfx950 (MI355X): local Hamiltonian on batched localization
-// regions, and sparse overlap / Hamiltonian matrix elements.
-//
-// Operator factorization used here (exactly equal, in exact arithmetic, to
-// L' (T + R^T W^T V W R) L of the paper's Sec. III.B):
-//   potential:  per axis, synthesis followed by the magic filter is one
-//               stride-2 upsampling filter C_b (b = scaling/wavelet channel,
-//               31 taps); the adjoint chain (transposed magic filter then
-//               analysis) is the matching stride-2 downsampling with C_b.
-//               Three up passes lead to the fine real-space grid, the
-//               potential multiplies there, three down passes come back.
-//   kinetic:    the second-derivative filter at h/2 seen from the coarse
-//               two-level basis, K_ab = R^T a R along each axis (29 taps,
-//               2x2 channels), applied directly on the coarse box.
-// Each pass is one launch over every support function of a chunk
-// (blockIdx.y = function); threads map to output points, x fastest, so
-// global loads and stores along x are coalesced for every axis.
+// HIP kernels for gfx950 (MI355X): the dense-box <-> compressed copies of the
+// standalone uncompress / compress entry points, fixed-order energy sums, and
+// the sparse overlap / Hamiltonian matrix elements.  The local Hamiltonian
+// itself runs in the fused kernels of wvl_fused.hip.
 #include <hip/hip_runtime.h>
 
-#include "wvl_filters.h"
 #include "wvl_internal.h"
 
 namespace wvl {
 
-__constant__ double cC64[2][31] = {WVL_C0_F64, WVL_C1_F64};
-__constant__ float cC32[2][31] = {WVL_C0_F32, WVL_C1_F32};
-__constant__ double cK64[2][2][29] = {{WVL_K00_F64, WVL_K01_F64}, {WVL_K10_F64, WVL_K11_F64}};
-__constant__ float cK32[2][2][29] = {{WVL_K00_F32, WVL_K01_F32}, {WVL_K10_F32, WVL_K11_F32}};
-__constant__ double cKD64[2] = WVL_KD_F64;
-
-template <typename T>
-__device__ __forceinline__ T ctab(int b, int n);
-template <>
-__device__ __forceinline__ double ctab<double>(int b, int n) { return cC64[b][n]; }
-template <>
-__device__ __forceinline__ float ctab<float>(int b, int n) { return cC32[b][n]; }
-template <typename T>
-__device__ __forceinline__ T ktab(int a, int b, int n);
-template <>
-__device__ __forceinline__ double ktab<double>(int a, int b, int n) { return cK64[a][b][n]; }
-template <>
-__device__ __forceinline__ float ktab<float>(int a, int b, int n) { return cK32[a][b][n]; }
-
 constexpr int TPB = 256;
 
-__device__ __forceinline__ int nr_of(int n) { return 2 * n + 29; }
-
-// deterministic block sum of one double per thread (blockDim.x == TPB)
+// deterministic block sum of one double per thread: a fixed shuffle tree in
+// each 64-lane wave, then the wave sums in order
 __device__ double block_sum(double v) {
-  __shared__ double red[TPB];
-  red[threadIdx.x] = v;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __shared__ double part[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) part[wv] = v;
   __syncthreads();
-  for (int s = TPB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = red[0];
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r += part[k];
   __syncthreads();
   return r;
 }
@@ -69,8 +35,7 @@ __global__ __launch_bounds__(TPB) void k_gather(const SfDev* __restrict__ sfs,
                                                 const wvl_seg* __restrict__ seg,
                                                 const int32_t* __restrict__ rt,
                                                 const T* __restrict__ psi, T* __restrict__ dst,
-                                                const SfWork* __restrict__ wk, int sf0,
-                                                int use_work) {
+                                                int sf0) {
   const int s = blockIdx.y;
   const SfDev& sf = sfs[sf0 + s];
   const int n0 = sf.n[0], n1 = sf.n[1], n2 = sf.n[2];
@@ -96,8 +61,7 @@ __global__ __launch_bounds__(TPB) void k_gather(const SfDev* __restrict__ sfs,
       break;
     }
   }
-  T* out = use_work ? dst + wk[s].c8 : dst + sf.box_in;
-  out[idx] = v;
+  dst[sf.box_in + idx] = v;
 }
 
 // Compress onto the output pattern: thread per dense point of the output box.
@@ -106,8 +70,7 @@ __global__ __launch_bounds__(TPB) void k_scatter(const SfDev* __restrict__ sfs,
                                                  const wvl_seg* __restrict__ seg,
                                                  const int32_t* __restrict__ rt,
                                                  const T* __restrict__ src, T* __restrict__ out,
-                                                 const SfWork* __restrict__ wk, int sf0,
-                                                 int use_work, int accumulate) {
+                                                 int sf0) {
   const int s = blockIdx.y;
   const SfDev& sf = sfs[sf0 + s];
   const int e = sf.ext;
@@ -130,238 +93,10 @@ __global__ __launch_bounds__(TPB) void k_scatter(const SfDev* __restrict__ sfs,
     if (gx >= g.i1s && gx <= g.i1e) {
       const int64_t k = g.off + (gx - g.i1s);
       const int64_t o = c == 0 ? sf.cout + k : sf.cout + sf.on_c + (int64_t)(c - 1) * sf.on_f + k;
-      const T* in = use_work ? src + wk[s].o8 : src + sf.box_out;
-      const T v = in[idx];
-      out[o] = accumulate ? out[o] + v : v;
+      out[o] = src[sf.box_out + idx];
       return;
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// potential part: up passes (coarse two-level -> fine real space)
-// ---------------------------------------------------------------------------
-
-// Pass along axis AX: out(l) = sum_i C_0[l-2i] in_{2c}(i) + C_1[l-2i] in_{2c+1}(i)
-// Input dims: axes < AX fine (2n+29), axes >= AX coarse (n).  With WITHV the
-// output is multiplied by the potential and the partial sums of V f^2 are
-// written per block.
-template <typename T, int AX, bool WITHV>
-__global__ __launch_bounds__(TPB) void k_up(const SfDev* __restrict__ sfs,
-                                            const SfWork* __restrict__ wk, int sf0,
-                                            T* __restrict__ ws, const T* __restrict__ pot, int nf1,
-                                            int nf2, double* __restrict__ epart) {
-  const int s = blockIdx.y;
-  const SfDev& sf = sfs[sf0 + s];
-  const SfWork& w = wk[s];
-  const int n[3] = {sf.n[0], sf.n[1], sf.n[2]};
-  int id[3], od[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    id[a] = a < AX ? nr_of(n[a]) : n[a];
-    od[a] = a <= AX ? nr_of(n[a]) : n[a];
-  }
-  const int och = 4 >> AX;
-  const int64_t vol = (int64_t)och * od[0] * od[1] * od[2];
-  const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  double eacc = 0.0;
-  if (idx < vol) {
-    const int x = (int)(idx % od[0]);
-    int64_t t = idx / od[0];
-    const int y = (int)(t % od[1]);
-    t /= od[1];
-    const int z = (int)(t % od[2]);
-    const int c = (int)(t / od[2]);
-    const T* in = ws + (AX == 0 ? w.c8 : AX == 1 ? w.a1 : w.a2);
-    T* out = ws + (AX == 0 ? w.a1 : AX == 1 ? w.a2 : w.g);
-    const int64_t chvol = (int64_t)id[0] * id[1] * id[2];
-    const int p = AX == 0 ? x : AX == 1 ? y : z;
-    const int64_t stride = AX == 0 ? 1 : AX == 1 ? id[0] : (int64_t)id[0] * id[1];
-    const int64_t base = (AX == 0 ? ((int64_t)z * id[1] + y) * id[0]
-                          : AX == 1 ? (int64_t)z * id[1] * id[0] + x
-                                    : (int64_t)y * id[0] + x);
-    const T* in0 = in + (int64_t)(2 * c) * chvol + base;
-    const T* in1 = in0 + chvol;
-    const int N = n[AX];
-    const int ilo = max(0, (p - 29) >> 1);
-    const int ihi = min(N - 1, p >> 1);
-    T acc = T(0);
-    for (int i = ilo; i <= ihi; ++i) {
-      const int ci = p - 2 * i;
-      acc += ctab<T>(0, ci) * in0[i * stride] + ctab<T>(1, ci) * in1[i * stride];
-    }
-    if (WITHV) {
-      const int64_t gi = ((int64_t)(2 * sf.lo[2] + z) * nf2 + (2 * sf.lo[1] + y)) * nf1 +
-                         (2 * sf.lo[0] + x);
-      const T v = pot[gi];
-      eacc = (double)v * (double)acc * (double)acc;
-      acc = v * acc;
-    }
-    out[idx] = acc;
-  }
-  if (WITHV) {
-    const double b = block_sum(eacc);
-    if (threadIdx.x == 0) epart[w.epart + blockIdx.x] = b;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// potential part: down passes (fine real space -> coarse two-level, L' box)
-// ---------------------------------------------------------------------------
-
-// Pass along axis AX: out_{2c+b}(i) = sum_l C_b[l-2i] in_c(l), i in [-e, n+e).
-// Input dims: axes <= AX fine, axes > AX output coarse (n+2e).
-template <typename T, int AX, bool ACC>
-__global__ __launch_bounds__(TPB) void k_down(const SfDev* __restrict__ sfs,
-                                              const SfWork* __restrict__ wk, int sf0,
-                                              T* __restrict__ ws) {
-  const int s = blockIdx.y;
-  const SfDev& sf = sfs[sf0 + s];
-  const SfWork& w = wk[s];
-  const int e = sf.ext;
-  int id[3], od[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int nr = nr_of(sf.n[a]), no = sf.n[a] + 2 * e;
-    id[a] = a > AX ? no : nr;
-    od[a] = a >= AX ? no : nr;
-  }
-  const int och = 2 << (2 - AX);
-  const int64_t vol = (int64_t)och * od[0] * od[1] * od[2];
-  const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (idx >= vol) return;
-  const int x = (int)(idx % od[0]);
-  int64_t t = idx / od[0];
-  const int y = (int)(t % od[1]);
-  t /= od[1];
-  const int z = (int)(t % od[2]);
-  const int co = (int)(t / od[2]);
-  const int c = co >> 1, b = co & 1;
-  const T* in = ws + (AX == 2 ? w.g : AX == 1 ? w.b1 : w.b2);
-  T* out = ws + (AX == 2 ? w.b1 : AX == 1 ? w.b2 : w.o8);
-  const int64_t chvol = (int64_t)id[0] * id[1] * id[2];
-  const int p = AX == 0 ? x : AX == 1 ? y : z;
-  const int64_t stride = AX == 0 ? 1 : AX == 1 ? id[0] : (int64_t)id[0] * id[1];
-  const int64_t base = (AX == 0 ? ((int64_t)z * id[1] + y) * id[0]
-                        : AX == 1 ? (int64_t)z * id[1] * id[0] + x
-                                  : (int64_t)y * id[0] + x);
-  const T* src = in + (int64_t)c * chvol + base;
-  const int nr = id[AX];
-  const int two_i = 2 * (p - e);  // 2 i, i = p - e
-  const int qlo = max(0, two_i), qhi = min(nr - 1, two_i + 30);
-  T acc = T(0);
-  for (int q = qlo; q <= qhi; ++q) acc += ctab<T>(b, q - two_i) * src[q * stride];
-  if (ACC) acc += out[idx];
-  out[idx] = acc;
-}
-
-// ---------------------------------------------------------------------------
-// kinetic part on the coarse box
-// ---------------------------------------------------------------------------
-
-// out_c(i) (+)= fac * sum_j sum_b K_{a b}[j] in_{c_b}(i + j) along AX, with a
-// the output channel's bit for AX and c_b the input channel with that bit b.
-// FP32: off-diagonal taps accumulate in FP32, the scaling channel in the
-// difference form sum_{j != 0} K_j (x_{i+j} - x_i) (its filter sums to zero
-// exactly, not after rounding); the diagonal terms and the factor
-// fac = -1/2 (2/h)^2 are applied in FP64 before the one final rounding, so
-// that no FP32 tap rounding biases <phi|T|phi>.
-template <typename T, int AX, bool ACC>
-__global__ __launch_bounds__(TPB) void k_kin(const SfDev* __restrict__ sfs,
-                                             const SfWork* __restrict__ wk, int sf0,
-                                             T* __restrict__ ws, double fac) {
-  const int s = blockIdx.y;
-  const SfDev& sf = sfs[sf0 + s];
-  const SfWork& w = wk[s];
-  const int e = sf.ext;
-  const int n[3] = {sf.n[0], sf.n[1], sf.n[2]};
-  const int od[3] = {n[0] + 2 * e, n[1] + 2 * e, n[2] + 2 * e};
-  const int64_t vol = 8ll * od[0] * od[1] * od[2];
-  const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (idx >= vol) return;
-  const int x = (int)(idx % od[0]);
-  int64_t t = idx / od[0];
-  const int y = (int)(t % od[1]);
-  t /= od[1];
-  const int z = (int)(t % od[2]);
-  const int c = (int)(t / od[2]);
-  const int ic[3] = {x - e, y - e, z - e};
-  T* out = ws + w.o8;
-  bool inside = true;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-    if (a != AX && (ic[a] < 0 || ic[a] >= n[a])) inside = false;
-  T res = T(0);
-  if (inside) {
-    const T* in = ws + w.c8;
-    const int64_t chvol = (int64_t)n[0] * n[1] * n[2];
-    const int a = (c >> AX) & 1;
-    const int c0 = c & ~(1 << AX), c1 = c | (1 << AX);
-    const int64_t stride = AX == 0 ? 1 : AX == 1 ? n[0] : (int64_t)n[0] * n[1];
-    const int64_t base = AX == 0 ? ((int64_t)ic[2] * n[1] + ic[1]) * n[0]
-                         : AX == 1 ? (int64_t)ic[2] * n[1] * n[0] + ic[0]
-                                   : (int64_t)ic[1] * n[0] + ic[0];
-    const T* in0 = in + (int64_t)c0 * chvol + base;
-    const T* in1 = in + (int64_t)c1 * chvol + base;
-    const int i = ic[AX], N = n[AX];
-    const int jlo = max(-14, -i), jhi = min(14, N - 1 - i);
-    if (sizeof(T) == 4) {
-      const bool in_box = i >= 0 && i < N;
-      const T self = in_box ? in0[i * stride] : T(0);
-      const T self1 = in_box ? in1[i * stride] : T(0);
-      T acc = T(0);
-      for (int j = jlo; j <= min(jhi, -1); ++j)
-        acc += ktab<T>(a, 0, j + 14) * (in0[(i + j) * stride] - self) +
-               ktab<T>(a, 1, j + 14) * in1[(i + j) * stride];
-      for (int j = max(jlo, 1); j <= jhi; ++j)
-        acc += ktab<T>(a, 0, j + 14) * (in0[(i + j) * stride] - self) +
-               ktab<T>(a, 1, j + 14) * in1[(i + j) * stride];
-      // taps whose input lies outside the box still carry the -self term
-      T outside = T(0);
-      for (int j = -14; j < jlo; ++j) outside += ktab<T>(a, 0, j + 14);
-      for (int j = jhi + 1; j <= 14; ++j) outside += ktab<T>(a, 0, j + 14);
-      acc -= outside * self;
-      const double r = (double)acc + cKD64[a] * (double)self + cK64[a][1][14] * (double)self1;
-      res = (T)(fac * r);
-    } else {
-      double acc = 0.0;
-      for (int j = jlo; j <= jhi; ++j)
-        acc += cK64[a][0][j + 14] * (double)in0[(i + j) * stride] +
-               cK64[a][1][j + 14] * (double)in1[(i + j) * stride];
-      res = (T)(fac * acc);
-    }
-  }
-  if (ACC) res += out[idx];
-  out[idx] = res;
-}
-
-// e_kin partials: sum over the input box of C8 * O8 (O8 holding T C8 only)
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_ekin(const SfDev* __restrict__ sfs,
-                                              const SfWork* __restrict__ wk, int sf0,
-                                              const T* __restrict__ ws,
-                                              double* __restrict__ kpart) {
-  const int s = blockIdx.y;
-  const SfDev& sf = sfs[sf0 + s];
-  const SfWork& w = wk[s];
-  const int e = sf.ext;
-  const int n0 = sf.n[0], n1 = sf.n[1], n2 = sf.n[2];
-  const int64_t vol = 8ll * n0 * n1 * n2;
-  const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  double v = 0.0;
-  if (idx < vol) {
-    const int x = (int)(idx % n0);
-    int64_t t = idx / n0;
-    const int y = (int)(t % n1);
-    t /= n1;
-    const int z = (int)(t % n2);
-    const int c = (int)(t / n2);
-    const int m0 = n0 + 2 * e, m1 = n1 + 2 * e, m2 = n2 + 2 * e;
-    const int64_t o = (((int64_t)c * m2 + z + e) * m1 + y + e) * m0 + x + e;
-    v = (double)ws[w.c8 + idx] * (double)ws[w.o8 + o];
-  }
-  const double b = block_sum(v);
-  if (threadIdx.x == 0) kpart[w.kpart + blockIdx.x] = b;
 }
 
 // one block per function: fixed-order sum of its partials
@@ -459,8 +194,11 @@ __global__ __launch_bounds__(64) void k_pattern(const SfDev* __restrict__ sfs,
   if (rowptr == nullptr && lane == 0) count[a] = n;
 }
 
-// one wavefront per nonzero; lanes take rows of the overlap box in a fixed
-// order, partial sums combine in a fixed shuffle tree
+// one wavefront per nonzero (a, b).  The wave splits into four 16-lane groups;
+// group g takes rows g, g+4, ... of the box where both patterns may meet, and
+// its lanes walk the overlapping runs of that row with contiguous loads.
+// Lane partial sums combine in a fixed shuffle tree, so every value has an
+// order fixed by the pair alone.
 template <typename T>
 __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ sfs,
                                                       const wvl_seg* __restrict__ seg,
@@ -472,6 +210,7 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
                                                       double* __restrict__ val) {
   const int64_t k = blockIdx.x;
   const int lane = threadIdx.x;
+  const int grp = lane >> 4, gl = lane & 15;
   const SfDev& A = sfs[rowi[k]];
   const SfDev& B = sfs[coli[k]];
   const int32_t* bb = ket_out ? B.bb_out : B.bb_in;
@@ -484,27 +223,31 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
   const int ny = y1 - y0 + 1;
   const int nrows = (y1 >= y0 && z1 >= z0) ? ny * (z1 - z0 + 1) : 0;
   double acc = 0.0;
-  for (int r = lane; r < nrows; r += 64) {
+  for (int r = grp; r < nrows; r += 4) {
     const int y = y0 + r % ny, z = z0 + r / ny;
     const int64_t ra = (int64_t)(z - A.lo[2]) * A.n[1] + (y - A.lo[1]);
     const int64_t rb = (int64_t)(z - pb.oz) * pb.by + (y - pb.oy);
     for (int fine = 0; fine < 2; ++fine) {
-      int qa = rt[A.rt[fine] + ra], qa1 = rt[A.rt[fine] + ra + 1];
+      int qa = rt[A.rt[fine] + ra];
+      const int qa1 = rt[A.rt[fine] + ra + 1];
       const int pB = fine ? pf : pc;
-      int qb = rt[B.rt[pB] + rb], qb1 = rt[B.rt[pB] + rb + 1];
+      int qb = rt[B.rt[pB] + rb];
+      const int qb1 = rt[B.rt[pB] + rb + 1];
       while (qa < qa1 && qb < qb1) {
         const wvl_seg sa = seg[qa], sb = seg[qb];
         const int x0 = max(sa.i1s, sb.i1s), x1 = min(sa.i1e, sb.i1e);
         if (x0 <= x1) {
+          const int len = x1 - x0 + 1;
           if (!fine) {
             const T* pa = bra + A.cin + sa.off + (x0 - sa.i1s);
             const T* pk = ket + bc + sb.off + (x0 - sb.i1s);
-            for (int x = 0; x <= x1 - x0; ++x) acc += (double)pa[x] * (double)pk[x];
+            for (int x = gl; x < len; x += 16) acc += (double)pa[x] * (double)pk[x];
           } else {
-            for (int comp = 0; comp < 7; ++comp) {
-              const T* pa = bra + A.cin + A.n_c + comp * A.n_f + sa.off + (x0 - sa.i1s);
-              const T* pk = ket + bc + bnc + comp * bnf + sb.off + (x0 - sb.i1s);
-              for (int x = 0; x <= x1 - x0; ++x) acc += (double)pa[x] * (double)pk[x];
+            const T* pa = bra + A.cin + A.n_c + sa.off + (x0 - sa.i1s);
+            const T* pk = ket + bc + bnc + sb.off + (x0 - sb.i1s);
+            for (int t = gl; t < 7 * len; t += 16) {
+              const int comp = t / len, x = t - comp * len;
+              acc += (double)pa[comp * A.n_f + x] * (double)pk[comp * bnf + x];
             }
           }
         }
@@ -525,112 +268,28 @@ static inline dim3 grid2(int64_t maxvol, int nsf) {
 }
 
 int launch_gather(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                  const void* psi, void* box, const SfWork* wk, int sf0, int nsf, int64_t maxvol,
-                  int use_work) {
+                  const void* psi, void* box, int sf0, int nsf, int64_t maxvol) {
   if (nsf == 0 || maxvol == 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   if (f64)
     hipLaunchKernelGGL(k_gather<double>, grid2(maxvol, nsf), dim3(TPB), 0, st, sf, seg, rt,
-                       (const double*)psi, (double*)box, wk, sf0, use_work);
+                       (const double*)psi, (double*)box, sf0);
   else
     hipLaunchKernelGGL(k_gather<float>, grid2(maxvol, nsf), dim3(TPB), 0, st, sf, seg, rt,
-                       (const float*)psi, (float*)box, wk, sf0, use_work);
+                       (const float*)psi, (float*)box, sf0);
   return (int)hipGetLastError();
 }
 
 int launch_scatter(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                   const void* box, void* out, const SfWork* wk, int sf0, int nsf, int64_t maxvol,
-                   int use_work, int accumulate) {
+                   const void* box, void* out, int sf0, int nsf, int64_t maxvol) {
   if (nsf == 0 || maxvol == 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   if (f64)
     hipLaunchKernelGGL(k_scatter<double>, grid2(maxvol, nsf), dim3(TPB), 0, st, sf, seg, rt,
-                       (const double*)box, (double*)out, wk, sf0, use_work, accumulate);
+                       (const double*)box, (double*)out, sf0);
   else
     hipLaunchKernelGGL(k_scatter<float>, grid2(maxvol, nsf), dim3(TPB), 0, st, sf, seg, rt,
-                       (const float*)box, (float*)out, wk, sf0, use_work, accumulate);
-  return (int)hipGetLastError();
-}
-
-template <typename T>
-static void up_t(hipStream_t st, int axis, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                 int64_t maxvol, T* ws, const T* pot, int nf1, int nf2, double* epart) {
-  const dim3 g = grid2(maxvol, nsf);
-  if (axis == 0)
-    hipLaunchKernelGGL((k_up<T, 0, false>), g, dim3(TPB), 0, st, sf, wk, sf0, ws, pot, nf1, nf2,
-                       epart);
-  else if (axis == 1)
-    hipLaunchKernelGGL((k_up<T, 1, false>), g, dim3(TPB), 0, st, sf, wk, sf0, ws, pot, nf1, nf2,
-                       epart);
-  else
-    hipLaunchKernelGGL((k_up<T, 2, true>), g, dim3(TPB), 0, st, sf, wk, sf0, ws, pot, nf1, nf2,
-                       epart);
-}
-
-int launch_up(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-              int64_t maxvol, void* ws, const void* pot, int nf1, int nf2, double* epart,
-              int nblk) {
-  (void)nblk;
-  if (nsf == 0 || maxvol == 0) return 0;
-  if (f64)
-    up_t<double>((hipStream_t)stream, axis, sf, wk, sf0, nsf, maxvol, (double*)ws,
-                 (const double*)pot, nf1, nf2, epart);
-  else
-    up_t<float>((hipStream_t)stream, axis, sf, wk, sf0, nsf, maxvol, (float*)ws,
-                (const float*)pot, nf1, nf2, epart);
-  return (int)hipGetLastError();
-}
-
-template <typename T>
-static void down_t(hipStream_t st, int axis, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                   int64_t maxvol, T* ws, int acc) {
-  const dim3 g = grid2(maxvol, nsf);
-  if (axis == 2)
-    hipLaunchKernelGGL((k_down<T, 2, false>), g, dim3(TPB), 0, st, sf, wk, sf0, ws);
-  else if (axis == 1)
-    hipLaunchKernelGGL((k_down<T, 1, false>), g, dim3(TPB), 0, st, sf, wk, sf0, ws);
-  else if (acc)
-    hipLaunchKernelGGL((k_down<T, 0, true>), g, dim3(TPB), 0, st, sf, wk, sf0, ws);
-  else
-    hipLaunchKernelGGL((k_down<T, 0, false>), g, dim3(TPB), 0, st, sf, wk, sf0, ws);
-}
-
-int launch_down(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
-                int nsf, int64_t maxvol, void* ws, int accumulate) {
-  if (nsf == 0 || maxvol == 0) return 0;
-  if (f64)
-    down_t<double>((hipStream_t)stream, axis, sf, wk, sf0, nsf, maxvol, (double*)ws, accumulate);
-  else
-    down_t<float>((hipStream_t)stream, axis, sf, wk, sf0, nsf, maxvol, (float*)ws, accumulate);
-  return (int)hipGetLastError();
-}
-
-template <typename T>
-static void kin_t(hipStream_t st, int axis, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                  int64_t maxvol, T* ws, int acc, double fac) {
-  const dim3 g = grid2(maxvol, nsf);
-#define WVL_KIN_CASE(AXV)                                                                   \
-  if (axis == AXV) {                                                                        \
-    if (acc)                                                                                \
-      hipLaunchKernelGGL((k_kin<T, AXV, true>), g, dim3(TPB), 0, st, sf, wk, sf0, ws, fac);  \
-    else                                                                                    \
-      hipLaunchKernelGGL((k_kin<T, AXV, false>), g, dim3(TPB), 0, st, sf, wk, sf0, ws, fac); \
-  }
-  WVL_KIN_CASE(0)
-  WVL_KIN_CASE(1)
-  WVL_KIN_CASE(2)
-#undef WVL_KIN_CASE
-}
-
-int launch_kin(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
-               int nsf, int64_t maxvol, void* ws, int accumulate, double fac) {
-  if (nsf == 0 || maxvol == 0) return 0;
-  if (f64)
-    kin_t<double>((hipStream_t)stream, axis, sf, wk, sf0, nsf, maxvol, (double*)ws, accumulate,
-                  fac);
-  else
-    kin_t<float>((hipStream_t)stream, axis, sf, wk, sf0, nsf, maxvol, (float*)ws, accumulate,
-                 fac);
+                       (const float*)box, (float*)out, sf0);
   return (int)hipGetLastError();
 }
 
@@ -641,19 +300,6 @@ int launch_fill(int f64, void* stream, void* ptr, int64_t n) {
     hipLaunchKernelGGL(k_fill<double>, g, dim3(TPB), 0, (hipStream_t)stream, (double*)ptr, n);
   else
     hipLaunchKernelGGL(k_fill<float>, g, dim3(TPB), 0, (hipStream_t)stream, (float*)ptr, n);
-  return (int)hipGetLastError();
-}
-
-int launch_ekin_partials(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0,
-                         int nsf, int64_t maxvol, void* ws, double* kpart, int nblk) {
-  (void)nblk;
-  if (nsf == 0 || maxvol == 0) return 0;
-  if (f64)
-    hipLaunchKernelGGL(k_ekin<double>, grid2(maxvol, nsf), dim3(TPB), 0, (hipStream_t)stream, sf,
-                       wk, sf0, (const double*)ws, kpart);
-  else
-    hipLaunchKernelGGL(k_ekin<float>, grid2(maxvol, nsf), dim3(TPB), 0, (hipStream_t)stream, sf,
-                       wk, sf0, (const float*)ws, kpart);
   return (int)hipGetLastError();
 }
 
