@@ -23,6 +23,7 @@ ARCH = "gfx950"
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-mllvm", "-pragma-unroll-threshold=1000000",
                "-Wall", "-Wno-unused-result"]
 
 

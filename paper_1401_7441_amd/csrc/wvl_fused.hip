@@ -11,11 +11,15 @@
 //   k_pot_column one fine (x, y) column per thread, streaming along z with
 //                register rings: up pass z, potential multiply (FP64 energy
 //                partials), down pass z -> G2.  Every input is read once.
-//   k_kin_zcol   one coarse (x, y, component pair) column per thread: the
-//                z-part of the kinetic term with a 32-slot register window.
-//   k_back_plane one output z-plane (row tile): down pass y and x from LDS,
-//                plus the x/y kinetic parts and the z part, e_kin partials,
-//                and the compress step straight into the output pattern.
+//   k_kin_col    one coarse column per thread (along x, y or z): that axis'
+//                part of the kinetic term with a 32-slot register window.
+//   k_back_y     one fine (channel, z', x) column per thread, streaming along y: the y
+//                down pass; an LDS stage transposes the result so that x is
+//                a slow axis of the x down pass' input.
+//   k_back_x     one output (z', y', channel) row per thread, streaming along
+//                x: the x down pass plus the three kinetic parts, e_kin
+//                partials, and the compress step walking the row's output
+//                segments in order.
 // Register ring slots are compile-time constants after unrolling by the ring
 // period, so the rings stay in VGPRs.
 #include <hip/hip_runtime.h>
@@ -120,13 +124,23 @@ __global__ __launch_bounds__(256) void k_fwd_plane(const SfDev* __restrict__ sfs
     A[idx] = coef_at<T>(sf, seg, rt, psi, c, (int64_t)z * N1 + iy0 + yy, sf.lo[0] + x);
   }
   if (tile == 0) {
+    // dense coarse plane in two layouts: x fastest (c8) and y fastest (c8x)
     T* c8 = ws + w.c8;
+    T* c8x = ws + w.c8x;
     for (int idx = tid; idx < 4 * N1 * N0; idx += nth) {
       const int x = idx % N0;
       const int t = idx / N0;
       const int y = t % N1, c4 = t / N1;
       const int c = c4 + 4 * a3;
       c8[((int64_t)c * N2 + z) * plane + (int64_t)y * N0 + x] =
+          coef_at<T>(sf, seg, rt, psi, c, (int64_t)z * N1 + y, sf.lo[0] + x);
+    }
+    for (int idx = tid; idx < 4 * N1 * N0; idx += nth) {
+      const int y = idx % N1;
+      const int t = idx / N1;
+      const int x = t % N0, c4 = t / N0;
+      const int c = c4 + 4 * a3;
+      c8x[(((int64_t)c * N2 + z) * N0 + x) * N1 + y] =
           coef_at<T>(sf, seg, rt, psi, c, (int64_t)z * N1 + y, sf.lo[0] + x);
     }
   }
@@ -264,32 +278,67 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
 }
 
 // ---------------------------------------------------------------------------
-// k_kin_zcol: thread = coarse column (x, y) of component pair p = a1 + 2 a2
+// k_kin_col: thread = coarse column of a component pair along axis AX of the
+// input box
 // ---------------------------------------------------------------------------
-// out_a(i') = fac sum_j sum_b K_ab[j] x_b(i'+j), x_b = component p + 4b; the
-// window holds x(i-28..i) when output i' = i - 14 is formed.
-template <typename T>
-__global__ __launch_bounds__(256) void k_kin_zcol(const SfDev* __restrict__ sfs,
-                                                  const SfWork* __restrict__ wk, int sf0,
-                                                  T* __restrict__ ws, double fac) {
+// out_a(i') = fac sum_j sum_b K_ab[j] x_b(i'+j) for i' = -e .. N+e-1, where
+// x_b is the component whose AX bit is b; the window holds x(i-28..i) when
+// output i' = i - 14 is formed.  Inputs and outputs (y fastest unless noted):
+//   AX = 0: c8x -> ox[8][N2][O0][N1]
+//   AX = 1: c8  -> oy[8][N2][O1][N0]   (x fastest)
+//   AX = 2: c8x -> oz[8][O2][N0][N1]
+template <typename T, int AX>
+__global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
+                                                 const SfWork* __restrict__ wk, int sf0,
+                                                 T* __restrict__ ws, double fac) {
   const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
-  const int O2 = N2 + 2 * e;
   const int64_t plane = (int64_t)N0 * N1;
+  const int NA = AX == 2 ? N2 : AX == 1 ? N1 : N0;
+  const int OA = NA + 2 * e;
+  const int64_t ncol = AX == 2 ? plane : AX == 1 ? (int64_t)N0 * N2 : (int64_t)N1 * N2;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 4 * plane) return;
-  const int pr = (int)(idx / plane);
-  const int64_t xy = idx % plane;
-  const T* in0 = ws + w.c8 + (int64_t)pr * N2 * plane + xy;
-  const T* in1 = ws + w.c8 + (int64_t)(pr + 4) * N2 * plane + xy;
-  T* out0 = ws + w.oz + (int64_t)pr * O2 * plane + xy;
-  T* out1 = ws + w.oz + (int64_t)(pr + 4) * O2 * plane + xy;
+  if (idx >= 4 * ncol) return;
+  const int pr = (int)(idx / ncol);
+  const int64_t col = idx % ncol;
+  // component with AX bit b: AX = 0 -> b + 2 pr (pr = a2 + 2 a3);
+  // AX = 1 -> a1 + 2b + 4 a3 (pr = a1 + 2 a3); AX = 2 -> pr + 4b (pr = a1 + 2 a2)
+  const int cb0 = AX == 2 ? pr : AX == 1 ? (pr & 1) + 4 * (pr >> 1) : 2 * pr;
+  const int cb1 = AX == 2 ? pr + 4 : AX == 1 ? cb0 + 2 : cb0 + 1;
+  int64_t ibase, obase, istride, ostride;
+  if (AX == 2) {          // column (x, y), y fastest
+    ibase = col;
+    istride = plane;
+    obase = col;
+    ostride = plane;
+  } else if (AX == 1) {   // column (x, z), x fastest
+    const int x = (int)(col % N0), z = (int)(col / N0);
+    ibase = (int64_t)z * plane + x;
+    istride = N0;
+    obase = (int64_t)z * OA * N0 + x;
+    ostride = N0;
+  } else {                // column (y, z), y fastest
+    const int y = (int)(col % N1), z = (int)(col / N1);
+    ibase = (int64_t)z * plane + y;
+    istride = N1;
+    obase = (int64_t)z * OA * N1 + y;
+    ostride = N1;
+  }
+  const int64_t icomp = (int64_t)N2 * plane;                          // component size
+  const int64_t ocomp = AX == 2 ? (int64_t)OA * plane : AX == 1 ? (int64_t)N2 * OA * N0
+                                                                : (int64_t)N2 * OA * N1;
+  const T* inb = ws + (AX == 1 ? w.c8 : w.c8x);
+  const T* in0 = inb + cb0 * icomp + ibase;
+  const T* in1 = inb + cb1 * icomp + ibase;
+  T* outb = ws + (AX == 2 ? w.oz : AX == 1 ? w.oy : w.ox);
+  T* out0 = outb + cb0 * ocomp + obase;
+  T* out1 = outb + cb1 * ocomp + obase;
   T x0[32], x1[32];
 #pragma unroll
   for (int k = 0; k < 32; ++k) x0[k] = x1[k] = T(0);
   const int istart = 14 - e;           // emits i' = -e first
-  const int iend = N2 - 1 + e + 14;    // emits i' = N2 - 1 + e last
+  const int iend = NA - 1 + e + 14;    // emits i' = NA - 1 + e last
   const int ilo = istart - 28;
   const int i0first = (ilo >= 0) ? (ilo & ~31) : -(((-ilo) + 31) & ~31);
   for (int i0 = i0first; i0 <= iend; i0 += 32) {
@@ -297,9 +346,9 @@ __global__ __launch_bounds__(256) void k_kin_zcol(const SfDev* __restrict__ sfs,
     for (int u = 0; u < 32; ++u) {
       const int i = i0 + u;
       if (i > iend) continue;
-      const bool ok = i >= 0 && i < N2;
-      x0[u] = ok ? in0[(int64_t)i * plane] : T(0);
-      x1[u] = ok ? in1[(int64_t)i * plane] : T(0);
+      const bool ok = i >= 0 && i < NA;
+      x0[u] = ok ? in0[(int64_t)i * istride] : T(0);
+      x1[u] = ok ? in1[(int64_t)i * istride] : T(0);
       if (i >= istart) {
         const int ip = i - 14;            // output coarse index i'
         const int sc = (u + 18) & 31;     // slot of x(i') = x(i - 14)
@@ -329,263 +378,245 @@ __global__ __launch_bounds__(256) void k_kin_zcol(const SfDev* __restrict__ sfs,
           r1 = (T)(fac * s1);
         }
         const int pp = ip + e;
-        out0[(int64_t)pp * plane] = r0;
-        out1[(int64_t)pp * plane] = r1;
+        out0[(int64_t)pp * ostride] = r0;
+        out1[(int64_t)pp * ostride] = r1;
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// k_back_plane: block = (function, output plane z', channel a3, row tile)
+// k_back_y: block = (function, 64 consecutive fine columns (a3, z', px))
 // ---------------------------------------------------------------------------
-// LDS: P[nq][R0] (G2 plane rows q0..q1), Q[2][T][R0] (after the y down pass,
-//      channel a2), Cin[4][nyi][N0] (input plane z = z' - e, rows yi0..yi1,
-//      components a1 + 2 a2 of channel a3).
-// threads per block of k_back_plane: FP64 keeps one wave per SIMD per block so
-// that its accumulators fit without spilling
+// Thread = fine column px of G2[a3][z'][.][px], streaming along y: fine pair
+// p = 2q, 2q+1 arrives and is scattered into the accumulators of coarse
+// i' = q-15..q (out_b(i') += C_b[p - 2i'] g_p, b = a2); i' = q-15 is then
+// complete.  Results are staged in LDS st[a2][y'][65] and written out as
+// Q[a2 + 2 a3][z'][px][y'] (y' fastest).
 template <typename T>
-constexpr int back_threads() { return sizeof(T) == 8 ? 256 : 512; }
-
-template <typename T>
-__global__ __launch_bounds__(back_threads<T>()) void k_back_plane(
-    const SfDev* __restrict__ sfs, const wvl_seg* __restrict__ seg,
-    const int32_t* __restrict__ rt, const SfWork* __restrict__ wk, int sf0,
-    const T* __restrict__ ws, T* __restrict__ out, int tile_rows, double fac, int pot_on,
-    int kin_on, int accumulate, double* __restrict__ kpart) {
+__global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
+                                               const SfWork* __restrict__ wk, int sf0,
+                                               T* __restrict__ ws) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
+  T* st = reinterpret_cast<T*>(smem_raw);
   const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int R0 = 2 * N0 + 29, R1 = 2 * N1 + 29;
-  const int O0 = N0 + 2 * e, O1 = N1 + 2 * e, O2 = N2 + 2 * e;
-  const int ntile = (O1 + tile_rows - 1) / tile_rows;
-  int bx = blockIdx.x;
-  const int tile = bx % ntile;
-  bx /= ntile;
-  const int a3 = bx & 1;
-  const int zp = bx >> 1;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  if (zp >= O2) {
-    if (tid == 0) kpart[w.kpart + blockIdx.x] = 0.0;
-    return;
+  const int O1 = N1 + 2 * e, O2 = N2 + 2 * e;
+  const int64_t ncols = 2ll * O2 * R0;           // columns (a3, z', px), px fastest
+  const int64_t col0 = (int64_t)blockIdx.x * 64;
+  if (col0 >= ncols) return;
+  const int lane = threadIdx.x;
+  const int64_t col = col0 + lane;
+  const bool active = col < ncols;
+  // G2[a3][z'][py][px]: column (a3, z', px) starts at (a3 O2 + z') R1 R0 + px
+  const int64_t slab = active ? col / R0 : 0;     // a3 * O2 + z'
+  const int px = active ? (int)(col % R0) : 0;
+  const T* in = ws + w.g2 + slab * R1 * R0 + px;
+  T a0[16], a1[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) a0[k] = a1[k] = T(0);
+  if (e == 16) {  // coarse i' = -16 lies beyond the filter reach
+    st[lane] = T(0);
+    st[O1 * 65 + lane] = T(0);
   }
-  const int y0 = tile * tile_rows, y1 = min(O1, y0 + tile_rows);
-  const int ty = y1 - y0;
-  const int z = zp - e;
-  const bool zin = kin_on && z >= 0 && z < N2;
-  // P rows: q in [2(y0-e), 2(y1-1-e)+30] within [0, R1)
-  const int q0 = max(0, 2 * (y0 - e)), q1 = min(R1 - 1, 2 * (y1 - 1 - e) + 30);
-  const int nq = max(0, q1 - q0 + 1);
-  const int yi0 = max(0, y0 - e - 14), yi1 = min(N1 - 1, y1 - 1 - e + 14);
-  const int nyi = zin ? max(0, yi1 - yi0 + 1) : 0;
-  T* P = sm;
-  T* Qb = P + (pot_on ? nq * R0 : 0);
-  T* Cin = Qb + (pot_on ? 2 * ty * R0 : 0);
-  const int64_t ncol = (int64_t)R0 * R1;
-  const int64_t plane = (int64_t)N0 * N1;
-  if (pot_on) {
-    const T* g2 = ws + w.g2 + ((int64_t)a3 * O2 + zp) * ncol;
-    for (int idx = tid; idx < nq * R0; idx += nth) P[idx] = g2[(int64_t)q0 * R0 + idx];
-  }
-  if (nyi > 0) {
-    for (int idx = tid; idx < 4 * nyi * N0; idx += nth) {
-      const int x = idx % N0;
-      const int t = idx / N0;
-      const int yy = t % nyi, c4 = t / nyi;
-      Cin[idx] = ws[w.c8 + ((int64_t)(c4 + 4 * a3) * N2 + z) * plane + (int64_t)(yi0 + yy) * N0 + x];
+  const int qend = N1 + e + 14;
+  for (int q0 = 0; q0 <= qend; q0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q0 + u;
+      if (q <= qend) {
+        const int p = 2 * q;
+        const T ge = (active && p < R1) ? in[(int64_t)p * R0] : T(0);
+        const T go = (active && p + 1 < R1) ? in[(int64_t)(p + 1) * R0] : T(0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int sl = (u - k) & 15;
+          a0[sl] += Ct<T>(0, 2 * k) * ge;
+          a1[sl] += Ct<T>(1, 2 * k) * ge;
+          if (k < 15) {
+            a0[sl] += Ct<T>(0, 2 * k + 1) * go;
+            a1[sl] += Ct<T>(1, 2 * k + 1) * go;
+          }
+        }
+        const int sl = (u + 1) & 15;
+        const int yp = q - 15 + e;
+        if (yp >= 0 && yp < O1) {
+          st[yp * 65 + lane] = a0[sl];
+          st[(O1 + yp) * 65 + lane] = a1[sl];
+        }
+        a0[sl] = T(0);
+        a1[sl] = T(0);
+      }
     }
   }
   __syncthreads();
-  if (pot_on) {
-    // down pass y: Qb[a2][yy][px] = sum_q C_a2[q - 2i'] P[q][px]; a thread makes
-    // rows yy, yy+1 of both channels a2 from the 33 inputs q = 2i'..2i'+32
-    const int npair = (ty + 1) >> 1;
-    for (int idx = tid; idx < npair * R0; idx += nth) {
-      const int px = idx % R0;
-      const int yy = 2 * (idx / R0);
-      const int two_i = 2 * (y0 + yy - e);
-      T r[2][2] = {{T(0), T(0)}, {T(0), T(0)}};   // [a2][row]
-#pragma unroll
-      for (int t = 0; t < 33; ++t) {
-        const int q = two_i + t;
-        const T v = (q >= q0 && q <= q1) ? P[(q - q0) * R0 + px] : T(0);
-#pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2) {
-          if (t <= 30) r[a2][0] += Ct<T>(a2, t) * v;
-          if (t >= 2) r[a2][1] += Ct<T>(a2, t - 2) * v;
-        }
-      }
-#pragma unroll
-      for (int a2 = 0; a2 < 2; ++a2) {
-        Qb[(a2 * ty + yy) * R0 + px] = r[a2][0];
-        if (yy + 1 < ty) Qb[(a2 * ty + yy + 1) * R0 + px] = r[a2][1];
-      }
-    }
-    __syncthreads();
+  // Q[a2 + 2 a3][z'][px][y'] = Q slab (a2 O2... ) : element offset of
+  // column (a3, z', px) for channel a2 is ((a2 + 2 a3) O2 + z') R0 O1 + px O1
+  const int ncl = (int)min<int64_t>(64, ncols - col0);
+  for (int t = lane; t < 2 * ncl * O1; t += 64) {
+    const int a2 = t / (ncl * O1);
+    const int rem = t - a2 * ncl * O1;
+    const int pl = rem / O1, yp = rem - pl * O1;
+    const int64_t c = col0 + pl;
+    const int64_t sl = c / R0;                     // a3 * O2 + z'
+    const int a3 = (int)(sl / O2), zp = (int)(sl % O2);
+    const int pxx = (int)(c % R0);
+    ws[w.q + (((int64_t)(a2 + 2 * a3) * O2 + zp) * R0 + pxx) * O1 + yp] =
+        st[(a2 * O1 + yp) * 65 + pl];
   }
-  // outputs: a thread makes columns xo, xo+1 of row yy for all four components
-  // c4 = a1 + 2 a2 of channel a3, so every filter index is a compile-time constant
-  const int npx = (O0 + 1) >> 1;
+}
+
+// ---------------------------------------------------------------------------
+// k_back_x: block = (function, output plane z', 64 (channel, y') rows)
+// ---------------------------------------------------------------------------
+// Thread = output row (y', z') of channel ch = a2 + 2 a3, components
+// c = a1 + 2 a2 + 4 a3 (a1 = 0, 1).  Streaming along x: fine pair p = 2q,
+// 2q+1 of Q[ch][z'][p][y'] is scattered into the potential accumulators of
+// coarse i' = q-15..q; i' = q-15 is then complete: potential part plus the
+// x, y and z kinetic parts (from k_kin_col), e_kin partial, and the compress
+// step into the output pattern.
+template <typename T>
+__device__ __forceinline__ void emit_out(const SfDev& sf, const wvl_seg* __restrict__ seg, int c,
+                                         int gx, int s1, int& cur, int& cs, int& ce,
+                                         int64_t& coff, T v, T* __restrict__ out,
+                                         int accumulate) {
+  while (cur < s1 && ce < gx) {
+    ++cur;
+    if (cur < s1) {
+      const wvl_seg g = seg[cur];
+      cs = g.i1s;
+      ce = g.i1e;
+      coff = g.off;
+    }
+  }
+  if (cur < s1 && cs <= gx) {
+    const int64_t k = coff + (gx - cs);
+    const int64_t o = c == 0 ? sf.cout + k : sf.cout + sf.on_c + (int64_t)(c - 1) * sf.on_f + k;
+    out[o] = accumulate ? out[o] + v : v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
+                                               const wvl_seg* __restrict__ seg,
+                                               const int32_t* __restrict__ rt,
+                                               const SfWork* __restrict__ wk, int sf0,
+                                               const T* __restrict__ ws, T* __restrict__ out,
+                                               double fac, int pot_on, int kin_on, int accumulate,
+                                               double* __restrict__ kpart) {
+  const SfDev& sf = sfs[sf0 + blockIdx.y];
+  const SfWork& w = wk[blockIdx.y];
+  const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
+  const int R0 = 2 * N0 + 29;
+  const int O0 = N0 + 2 * e, O1 = N1 + 2 * e, O2 = N2 + 2 * e;
+  const int nty = (4 * O1 + 63) >> 6;
+  const int bx = blockIdx.x;
+  const int tt = bx % nty, zp = bx / nty;
+  const int lane = threadIdx.x;
+  if (zp >= O2) {
+    if (lane == 0) kpart[w.kpart + blockIdx.x] = 0.0;
+    return;
+  }
+  const int id = tt * 64 + lane;
+  const bool active = id < 4 * O1;
+  const int ch = active ? id / O1 : 0, yp = active ? id % O1 : 0;
+  const int a2 = ch & 1, a3 = ch >> 1;
+  const int z = zp - e, y = yp - e;
+  const bool zin = kin_on && z >= 0 && z < N2;
+  const bool yin = y >= 0 && y < N1;
+  const int64_t plane = (int64_t)N0 * N1;
+  const T* qin = ws + w.q + ((int64_t)(ch * O2 + zp) * R0) * O1 + yp;
+  const int c0 = 0 + 2 * a2 + 4 * a3, c1 = c0 + 1;
+  // output row segments of both components
+  const int64_t r = (int64_t)zp * O1 + yp;
+  const int pat0 = c0 == 0 ? 2 : 3;
+  int cur0 = rt[sf.rt[pat0] + r], cur1 = rt[sf.rt[3] + r];
+  const int e0 = rt[sf.rt[pat0] + r + 1], e1 = rt[sf.rt[3] + r + 1];
+  int cs0 = 0, ce0 = -(1 << 30), cs1 = 0, ce1 = -(1 << 30);
+  int64_t co0 = 0, co1 = 0;
+  if (cur0 < e0) { const wvl_seg g = seg[cur0]; cs0 = g.i1s; ce0 = g.i1e; co0 = g.off; }
+  if (cur1 < e1) { const wvl_seg g = seg[cur1]; cs1 = g.i1s; ce1 = g.i1e; co1 = g.off; }
+  const int gx0 = sf.lo[0] - e;
+  if (active && e == 16) {  // coarse i' = -16 lies beyond every filter's reach
+    emit_out<T>(sf, seg, c0, gx0, e0, cur0, cs0, ce0, co0, T(0), out, accumulate);
+    emit_out<T>(sf, seg, c1, gx0, e1, cur1, cs1, ce1, co1, T(0), out, accumulate);
+  }
+  // kinetic parts (y fastest where the thread index runs over y')
+  const int64_t comp_x = (int64_t)N2 * O0 * N1, comp_y = (int64_t)N2 * O1 * N0;
+  const int64_t comp_z = (int64_t)O2 * plane, comp_c = (int64_t)N2 * plane;
+  const T* oxp = ws + w.ox + ((int64_t)(zin ? z : 0) * O0) * N1 + (yin ? y : 0);  // [c][z][x'][y]
+  const T* oyp = ws + w.oy + ((int64_t)(zin ? z : 0) * O1 + yp) * N0;             // [c][z][y'][x]
+  const T* ozp = ws + w.oz + (int64_t)zp * plane + (yin ? y : 0);                // [c][z'][x][y]
+  const T* cxp = ws + w.c8x + (int64_t)(zin ? z : 0) * plane + (yin ? y : 0);    // [c][z][x][y]
+  T p0[16], p1[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) p0[k] = p1[k] = T(0);
   double kacc = 0.0;
-  for (int idx = tid; idx < ty * npx; idx += nth) {
-    const int xp = idx % npx, yy = idx / npx;
-    const int yo = y0 + yy;           // output row within the grown box
-    const int iy = yo - e;            // input-box row
-    const int xo0 = 2 * xp;
-    const int ix0 = xo0 - e;
-    T val[4][2];
+  const int qend = N0 + e + 14;
+  for (int q0 = 0; q0 <= qend; q0 += 16) {
 #pragma unroll
-    for (int c4 = 0; c4 < 4; ++c4) val[c4][0] = val[c4][1] = T(0);
-    if (pot_on) {
-      const int two_i = 2 * ix0;
+    for (int u = 0; u < 16; ++u) {
+      const int q = q0 + u;
+      if (q > qend) continue;
+      if (pot_on) {
+        const int p = 2 * q;
+        const T ge = (active && p < R0) ? qin[(int64_t)p * O1] : T(0);
+        const T go = (active && p + 1 < R0) ? qin[(int64_t)(p + 1) * O1] : T(0);
 #pragma unroll
-      for (int a2 = 0; a2 < 2; ++a2) {
-        const T* qrow = Qb + (a2 * ty + yy) * R0;
-#pragma unroll
-        for (int t = 0; t < 33; ++t) {
-          const int q = two_i + t;
-          const T v = (q >= 0 && q < R0) ? qrow[q] : T(0);
-#pragma unroll
-          for (int a1 = 0; a1 < 2; ++a1) {
-            if (t <= 30) val[a1 + 2 * a2][0] += Ct<T>(a1, t) * v;
-            if (t >= 2) val[a1 + 2 * a2][1] += Ct<T>(a1, t - 2) * v;
+        for (int k = 0; k < 16; ++k) {
+          const int sl = (u - k) & 15;
+          p0[sl] += Ct<T>(0, 2 * k) * ge;
+          p1[sl] += Ct<T>(1, 2 * k) * ge;
+          if (k < 15) {
+            p0[sl] += Ct<T>(0, 2 * k + 1) * go;
+            p1[sl] += Ct<T>(1, 2 * k + 1) * go;
           }
         }
       }
-    }
-    T kin[4][2];
-#pragma unroll
-    for (int c4 = 0; c4 < 4; ++c4) kin[c4][0] = kin[c4][1] = T(0);
-    if (zin) {
-      // x part (rows inside the input box): inputs x = ix0 - 14 .. ix0 + 15 are
-      // streamed once and folded into both columns h and both channels a1
-      if (iy >= 0 && iy < N1) {
-#pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2) {
-          const T* r0p = Cin + ((0 + 2 * a2) * nyi + (iy - yi0)) * N0;
-          const T* r1p = Cin + ((1 + 2 * a2) * nyi + (iy - yi0)) * N0;
-          T s0[2], s1[2];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int x = ix0 + h;
-            const bool ok = x >= 0 && x < N0;
-            s0[h] = ok ? r0p[x] : T(0);
-            s1[h] = ok ? r1p[x] : T(0);
-          }
-          T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};   // [a1][h]
-#pragma unroll
-          for (int t = 0; t < 30; ++t) {
-            const int x = ix0 - 14 + t;
-            const bool ok = x >= 0 && x < N0;
-            const T v0 = ok ? r0p[x] : T(0);
-            const T v1 = ok ? r1p[x] : T(0);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int tt = t - h;
-              if (tt < 0 || tt > 28) continue;
-              if (sizeof(T) == 4) {
-                if (tt == 14) continue;
-                const T d0 = v0 - s0[h];
-#pragma unroll
-                for (int a1 = 0; a1 < 2; ++a1)
-                  acc[a1][h] += Kt<T>(a1, 0, tt) * d0 + Kt<T>(a1, 1, tt) * v1;
-              } else {
-#pragma unroll
-                for (int a1 = 0; a1 < 2; ++a1)
-                  acc[a1][h] += Kt<T>(a1, 0, tt) * v0 + Kt<T>(a1, 1, tt) * v1;
-              }
-            }
-          }
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int a1 = 0; a1 < 2; ++a1) {
-              if (sizeof(T) == 4)
-                kin[a1 + 2 * a2][h] += (T)(fac * ((double)acc[a1][h] + fKD64[a1] * (double)s0[h] +
-                                                  fK64[a1][1][14] * (double)s1[h]));
-              else
-                kin[a1 + 2 * a2][h] += (T)(fac * (double)acc[a1][h]);
-            }
+      // i' = q - 15 is complete
+      const int ip = q - 15;
+      const int xp = ip + e;
+      const int ps = (u + 1) & 15;
+      T v0 = p0[ps], v1 = p1[ps];
+      p0[ps] = T(0);
+      p1[ps] = T(0);
+      if (!active || xp < 0 || xp >= O0) continue;
+      const bool xin = ip >= 0 && ip < N0;
+      if (kin_on) {
+        if (zin && yin) {            // x part: ox[c][z][x'][y]
+          v0 += oxp[c0 * comp_x + (int64_t)xp * N1];
+          v1 += oxp[c1 * comp_x + (int64_t)xp * N1];
         }
-      }
-      // y part (columns inside the input box): inputs y = iy - 14 .. iy + 14
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int ix = ix0 + h;
-        if (ix < 0 || ix >= N0) continue;
-        const bool iny = iy >= 0 && iy < N1;
-#pragma unroll
-        for (int a1 = 0; a1 < 2; ++a1) {
-          const T* c0p = Cin + (a1 * nyi - yi0) * N0 + ix;         // a2 = 0 input
-          const T* c1p = Cin + ((a1 + 2) * nyi - yi0) * N0 + ix;   // a2 = 1 input
-          const T s0 = iny ? c0p[iy * N0] : T(0);
-          const T s1 = iny ? c1p[iy * N0] : T(0);
-          T acc[2] = {T(0), T(0)};   // [a2]
-#pragma unroll
-          for (int t = 0; t < 29; ++t) {
-            const int y = iy - 14 + t;
-            const bool ok = y >= 0 && y < N1;
-            const T v0 = ok ? c0p[y * N0] : T(0);
-            const T v1 = ok ? c1p[y * N0] : T(0);
-            if (sizeof(T) == 4) {
-              if (t == 14) continue;
-              const T d0 = v0 - s0;
-#pragma unroll
-              for (int a2 = 0; a2 < 2; ++a2) acc[a2] += Kt<T>(a2, 0, t) * d0 + Kt<T>(a2, 1, t) * v1;
-            } else {
-#pragma unroll
-              for (int a2 = 0; a2 < 2; ++a2) acc[a2] += Kt<T>(a2, 0, t) * v0 + Kt<T>(a2, 1, t) * v1;
-            }
+        if (xin) {
+          T k0 = T(0), k1 = T(0);
+          if (zin) {                 // y part: oy[c][z][y'][x]
+            k0 += oyp[c0 * comp_y + ip];
+            k1 += oyp[c1 * comp_y + ip];
           }
-#pragma unroll
-          for (int a2 = 0; a2 < 2; ++a2) {
-            if (sizeof(T) == 4)
-              kin[a1 + 2 * a2][h] += (T)(fac * ((double)acc[a2] + fKD64[a2] * (double)s0 +
-                                                fK64[a2][1][14] * (double)s1));
-            else
-              kin[a1 + 2 * a2][h] += (T)(fac * (double)acc[a2]);
+          if (yin) {                 // z part: oz[c][z'][x][y]
+            k0 += ozp[c0 * comp_z + (int64_t)ip * N1];
+            k1 += ozp[c1 * comp_z + (int64_t)ip * N1];
+          }
+          v0 += k0;
+          v1 += k1;
+          if (zin && yin) {          // e_kin on the input box: c (Ox + Oy + Oz)
+            const T x0v = cxp[c0 * comp_c + (int64_t)ip * N1];
+            const T x1v = cxp[c1 * comp_c + (int64_t)ip * N1];
+            const T kx0 = oxp[c0 * comp_x + (int64_t)xp * N1];
+            const T kx1 = oxp[c1 * comp_x + (int64_t)xp * N1];
+            kacc += (double)x0v * (double)(kx0 + k0) + (double)x1v * (double)(kx1 + k1);
           }
         }
       }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int xo = xo0 + h;
-      if (xo >= O0) continue;
-      const int ix = xo - e;
-      const bool inbox = kin_on && ix >= 0 && ix < N0 && iy >= 0 && iy < N1;
-      const int gx = sf.lo[0] - e + xo;
-#pragma unroll
-      for (int c4 = 0; c4 < 4; ++c4) {
-        const int c = c4 + 4 * a3;
-        T k = kin[c4][h];
-        if (inbox) {
-          // z part, computed by k_kin_zcol for every output plane
-          k += ws[w.oz + ((int64_t)c * O2 + zp) * plane + (int64_t)iy * N0 + ix];
-          if (zin) kacc += (double)Cin[(c4 * nyi + (iy - yi0)) * N0 + ix] * (double)k;
-        }
-        const T v = val[c4][h] + k;
-        // compress: the output pattern row (yo, zp) of component c
-        const int pat = c == 0 ? 2 : 3;
-        const int64_t r = (int64_t)zp * O1 + yo;
-        const int32_t s0 = rt[sf.rt[pat] + r], s1 = rt[sf.rt[pat] + r + 1];
-        for (int qq = s0; qq < s1; ++qq) {
-          const wvl_seg g = seg[qq];
-          if (gx >= g.i1s && gx <= g.i1e) {
-            const int64_t kk = g.off + (gx - g.i1s);
-            const int64_t o =
-                c == 0 ? sf.cout + kk : sf.cout + sf.on_c + (int64_t)(c - 1) * sf.on_f + kk;
-            out[o] = accumulate ? out[o] + v : v;
-            break;
-          }
-        }
-      }
+      const int gx = gx0 + xp;
+      emit_out<T>(sf, seg, c0, gx, e0, cur0, cs0, ce0, co0, v0, out, accumulate);
+      emit_out<T>(sf, seg, c1, gx, e1, cur1, cs1, ce1, co1, v1, out, accumulate);
     }
   }
   const double b = block_sum_any(kacc);
-  if (tid == 0) kpart[w.kpart + blockIdx.x] = b;
+  if (lane == 0) kpart[w.kpart + blockIdx.x] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -619,33 +650,53 @@ int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, 
   return (int)hipGetLastError();
 }
 
-int launch_kin_zcol(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                    int gridx, void* ws, double fac) {
+int launch_kin_col(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
+                   int nsf, int gridx, void* ws, double fac) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
-  if (f64)
-    hipLaunchKernelGGL(k_kin_zcol<double>, g, dim3(256), 0, (hipStream_t)stream, sf, wk, sf0,
-                       (double*)ws, fac);
-  else
-    hipLaunchKernelGGL(k_kin_zcol<float>, g, dim3(256), 0, (hipStream_t)stream, sf, wk, sf0,
-                       (float*)ws, fac);
+  hipStream_t st = (hipStream_t)stream;
+  if (f64) {
+    if (axis == 2)
+      hipLaunchKernelGGL((k_kin_col<double, 2>), g, dim3(256), 0, st, sf, wk, sf0, (double*)ws, fac);
+    else if (axis == 1)
+      hipLaunchKernelGGL((k_kin_col<double, 1>), g, dim3(256), 0, st, sf, wk, sf0, (double*)ws, fac);
+    else
+      hipLaunchKernelGGL((k_kin_col<double, 0>), g, dim3(256), 0, st, sf, wk, sf0, (double*)ws, fac);
+  } else {
+    if (axis == 2)
+      hipLaunchKernelGGL((k_kin_col<float, 2>), g, dim3(256), 0, st, sf, wk, sf0, (float*)ws, fac);
+    else if (axis == 1)
+      hipLaunchKernelGGL((k_kin_col<float, 1>), g, dim3(256), 0, st, sf, wk, sf0, (float*)ws, fac);
+    else
+      hipLaunchKernelGGL((k_kin_col<float, 0>), g, dim3(256), 0, st, sf, wk, sf0, (float*)ws, fac);
+  }
   return (int)hipGetLastError();
 }
 
-int launch_back_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
-                      const int32_t* rt, const SfWork* wk, int sf0, int nsf, int gridx,
-                      int tile_rows, size_t lds, const void* ws, void* out, double fac, int pot_on,
-                      int kin_on, int accumulate, double* kpart) {
+int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                  int gridx, size_t lds, void* ws) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
   if (f64)
-    hipLaunchKernelGGL(k_back_plane<double>, g, dim3(back_threads<double>()), lds, (hipStream_t)stream, sf, seg, rt,
-                       wk, sf0, (const double*)ws, (double*)out, tile_rows, fac, pot_on, kin_on,
-                       accumulate, kpart);
+    hipLaunchKernelGGL(k_back_y<double>, g, dim3(64), lds, (hipStream_t)stream, sf, wk, sf0,
+                       (double*)ws);
   else
-    hipLaunchKernelGGL(k_back_plane<float>, g, dim3(back_threads<float>()), lds, (hipStream_t)stream, sf, seg, rt,
-                       wk, sf0, (const float*)ws, (float*)out, tile_rows, fac, pot_on, kin_on,
-                       accumulate, kpart);
+    hipLaunchKernelGGL(k_back_y<float>, g, dim3(64), lds, (hipStream_t)stream, sf, wk, sf0,
+                       (float*)ws);
+  return (int)hipGetLastError();
+}
+
+int launch_back_x(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                  const SfWork* wk, int sf0, int nsf, int gridx, const void* ws, void* out,
+                  double fac, int pot_on, int kin_on, int accumulate, double* kpart) {
+  if (nsf == 0 || gridx == 0) return 0;
+  const dim3 g((unsigned)gridx, (unsigned)nsf);
+  if (f64)
+    hipLaunchKernelGGL(k_back_x<double>, g, dim3(64), 0, (hipStream_t)stream, sf, seg, rt, wk, sf0,
+                       (const double*)ws, (double*)out, fac, pot_on, kin_on, accumulate, kpart);
+  else
+    hipLaunchKernelGGL(k_back_x<float>, g, dim3(64), 0, (hipStream_t)stream, sf, seg, rt, wk, sf0,
+                       (const float*)ws, (float*)out, fac, pot_on, kin_on, accumulate, kpart);
   return (int)hipGetLastError();
 }
 

@@ -19,12 +19,12 @@ using namespace wvl;
 
 // kernel kinds for tracing
 enum KernelKind {
-  KK_GATHER, KK_SCATTER, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_ZCOL, KK_BACK_PLANE, KK_FINALIZE,
-  KK_PATTERN, KK_SPARSE, KK_COUNT
+  KK_GATHER, KK_SCATTER, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
+  KK_BACK_Y, KK_BACK_X, KK_FINALIZE, KK_PATTERN, KK_SPARSE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
-    "uncompress", "compress", "fwd_plane", "pot_column", "kin_zcol", "back_plane", "finalize",
-    "pattern", "sparse_values"};
+    "uncompress", "compress", "fwd_plane", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
+    "back_y", "back_x", "finalize", "pattern", "sparse_values"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -632,9 +632,11 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   auto sf_elems = [&](const SfDev& S) {
     const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
     const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
-    const int64_t o2 = n2 + 2 * e;
-    return align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) + align64(2 * o2 * r0 * r1) +
-           align64(8 * o2 * n0 * n1);
+    const int64_t o1 = n1 + 2 * e, o2 = n2 + 2 * e;
+    const int64_t o0 = n0 + 2 * e;
+    return 2 * align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) +
+           align64(2 * o2 * r0 * r1) + align64(4 * o2 * r0 * o1) + align64(8 * n2 * o0 * n1) +
+           align64(8 * n2 * o1 * n0) + align64(8 * o2 * n0 * n1);
   };
   int64_t best_f32 = 0, best_f64 = 0;
   {
@@ -660,14 +662,24 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
         const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
         const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
         SfWork& W = P->h_wk[q];
-        W.c8 = off; off += align64(8 * n0 * n1 * n2);
-        W.g1 = off; off += align64(2 * n2 * r0 * r1);
-        W.g2 = off; off += align64(2 * o2 * r0 * r1);
-        W.oz = off; off += align64(8 * o2 * n0 * n1);
+        W.c8 = off;  off += align64(8 * n0 * n1 * n2);
+        W.c8x = off; off += align64(8 * n0 * n1 * n2);
+        W.g1 = off;  off += align64(2 * n2 * r0 * r1);
+        W.g2 = off;  off += align64(2 * o2 * r0 * r1);
+        W.q = off;   off += align64(4 * o2 * r0 * o1);
+        W.ox = off;  off += align64(8 * n2 * o0 * n1);
+        W.oy = off;  off += align64(8 * n2 * o1 * n0);
+        W.oz = off;  off += align64(8 * o2 * n0 * n1);
         ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
         ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
         ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
         ch.grid_kz = (int32_t)std::max<int64_t>(ch.grid_kz, (4 * n0 * n1 + 255) / 256);
+        ch.grid_ky = (int32_t)std::max<int64_t>(ch.grid_ky, (4 * n0 * n2 + 255) / 256);
+        ch.grid_kx = (int32_t)std::max<int64_t>(ch.grid_kx, (4 * n1 * n2 + 255) / 256);
+        ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
+        ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, ((4 * o1 + 63) / 64) * o2);
+        for (int d = 0; d < 2; ++d)
+          ch.lds_by[d] = std::max<int64_t>(ch.lds_by[d], 2 * o1 * 65 * (d ? 8 : 4));
       }
       for (int d = 0; d < 2; ++d) {
         const int64_t sz = d ? 8 : 4;
@@ -693,39 +705,14 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
           gf = std::max<int64_t>(gf, (int64_t)S.n[2] * 2 * ((2 * S.n[1] + 29 + tf - 1) / tf));
         }
         ch.grid_f[d] = (int32_t)gf;
-        // k_back_plane: the largest tile of output rows that fits
-        int64_t o1max = 0;
-        for (int q = k; q < j; ++q) o1max = std::max<int64_t>(o1max, P->h_sf[q].n[1] + 2 * P->h_sf[q].ext);
-        auto lds_c = [&](int64_t T) {
-          int64_t m = 0;
-          for (int q = k; q < j; ++q) {
-            const SfDev& S = P->h_sf[q];
-            const int64_t r0 = 2 * S.n[0] + 29, r1 = 2 * S.n[1] + 29;
-            const int64_t nq = std::min<int64_t>(r1, 2 * T + 29);
-            const int64_t nyi = std::min<int64_t>(S.n[1], T + 28);
-            m = std::max<int64_t>(m, (nq * r0 + 2 * T * r0 + 4 * nyi * S.n[0]) * sz);
-          }
-          return m;
-        };
-        int64_t tc = o1max;
-        while (tc > 1 && lds_c(tc) > kLdsBudget) tc = (tc + 1) / 2;
-        ch.tile_c[d] = (int32_t)tc;
-        ch.lds_c[d] = lds_c(tc);
-        int64_t gc = 0;
-        for (int q = k; q < j; ++q) {
-          const SfDev& S = P->h_sf[q];
-          const int64_t o1 = S.n[1] + 2 * S.ext, o2 = S.n[2] + 2 * S.ext;
-          gc = std::max<int64_t>(gc, o2 * 2 * ((o1 + tc - 1) / tc));
-        }
-        ch.grid_c[d] = (int32_t)gc;
-        if (ch.lds_f[d] > kLdsBudget || ch.lds_c[d] > kLdsBudget) {
+        if (ch.lds_f[d] > kLdsBudget || ch.lds_by[d] > kLdsBudget) {
           wvl_plan_destroy(P);
           return fail(ctx, WVL_EUNSUPPORTED, "functions %d..%d: boxes too large for the LDS tiles",
                       k, j - 1);
         }
       }
       ch.nblk_pot = ch.grid_b;
-      ch.nblk_kin = std::max(ch.grid_c[0], ch.grid_c[1]);
+      ch.nblk_kin = ch.grid_bx;
       int64_t poff = 0;
       for (int q = k; q < j; ++q) {
         P->h_wk[q].epart = poff;
@@ -836,16 +823,23 @@ static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
         WVL_LAUNCH(ctx, KK_FINALIZE,
                    launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.grid_b, e_pot));
     }
-    if (kin_on)
-      WVL_LAUNCH(ctx, KK_KIN_ZCOL,
-                 launch_kin_zcol(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_kz, workspace, fac));
-    WVL_LAUNCH(ctx, KK_BACK_PLANE,
-               launch_back_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf,
-                                 ch.grid_c[d], ch.tile_c[d], (size_t)ch.lds_c[d], workspace, hpsi_c,
-                                 fac, pot_on, kin_on, accumulate, parts));
+    if (kin_on) {
+      WVL_LAUNCH(ctx, KK_KIN_XCOL, launch_kin_col(f64, st, 0, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                  ch.grid_kx, workspace, fac));
+      WVL_LAUNCH(ctx, KK_KIN_ZCOL, launch_kin_col(f64, st, 2, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                  ch.grid_kz, workspace, fac));
+      WVL_LAUNCH(ctx, KK_KIN_YCOL, launch_kin_col(f64, st, 1, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                  ch.grid_ky, workspace, fac));
+    }
+    if (pot_on)
+      WVL_LAUNCH(ctx, KK_BACK_Y, launch_back_y(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_by,
+                                               (size_t)ch.lds_by[d], workspace));
+    WVL_LAUNCH(ctx, KK_BACK_X,
+               launch_back_x(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf, ch.grid_bx,
+                             workspace, hpsi_c, fac, pot_on, kin_on, accumulate, parts));
     if (kin_on && e_kin)
       WVL_LAUNCH(ctx, KK_FINALIZE,
-                 launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.grid_c[d], e_kin));
+                 launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.grid_bx, e_kin));
   }
   return WVL_OK;
 }

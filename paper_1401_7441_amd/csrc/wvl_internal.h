@@ -32,13 +32,17 @@ struct SfDev {
 };
 
 // Workspace offsets (elements of the compute type) of one support function
-// inside its chunk's workspace:
-//   c8  dense input box      [8][N2][N1][N0]
-//   g1  after the x, y up passes   [2][N2][R1][R0]      (R = 2N + 29)
-//   g2  after the z column pass    [2][O2][R1][R0]      (O = N + 2 ext)
-//   oz  z part of the kinetic term [8][O2][N1][N0]
+// inside its chunk's workspace (R = 2N + 29, O = N + 2 ext):
+//   c8   dense input box, x fastest      [8][N2][N1][N0]
+//   c8x  dense input box, y fastest      [8][N2][N0][N1]
+//   g1   after the x, y up passes        [2][N2][R1][R0]
+//   g2   after the z column pass         [2][O2][R1][R0]
+//   q    after the y down pass           [4][O2][R0][O1]   (channel a2 + 2 a3)
+//   ox   x part of the kinetic term      [8][N2][O0][N1]
+//   oy   y part of the kinetic term      [8][N2][O1][N0]
+//   oz   z part of the kinetic term      [8][O2][N0][N1]
 struct SfWork {
-  int64_t c8, g1, g2, oz;
+  int64_t c8, c8x, g1, g2, q, ox, oy, oz;
   int64_t epart;      // offset (in doubles) of its e_pot partials
   int64_t kpart;      // offset (in doubles) of its e_kin partials
 };
@@ -50,9 +54,10 @@ struct ChunkDev {
   int32_t grid_f[2], tile_f[2];    // k_fwd_plane
   int64_t lds_f[2];
   int32_t grid_b;                  // k_pot_column
-  int32_t grid_kz;                 // k_kin_zcol
-  int32_t grid_c[2], tile_c[2];    // k_back_plane
-  int64_t lds_c[2];
+  int32_t grid_kx, grid_ky, grid_kz;   // k_kin_col (x, y, z)
+  int32_t grid_by;                 // k_back_y
+  int64_t lds_by[2];
+  int32_t grid_bx;                 // k_back_x
   int32_t nblk_pot, nblk_kin;      // partial slots per function
 };
 
@@ -67,12 +72,13 @@ int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                      int gridx, int tile_rows, size_t lds, void* ws, int up_on);
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                       int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart);
-int launch_kin_zcol(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                    int gridx, void* ws, double fac);
-int launch_back_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
-                      const int32_t* rt, const SfWork* wk, int sf0, int nsf, int gridx,
-                      int tile_rows, size_t lds, const void* ws, void* out, double fac, int pot_on,
-                      int kin_on, int accumulate, double* kpart);
+int launch_kin_col(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
+                   int nsf, int gridx, void* ws, double fac);
+int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                  int gridx, size_t lds, void* ws);
+int launch_back_x(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                  const SfWork* wk, int sf0, int nsf, int gridx, const void* ws, void* out,
+                  double fac, int pot_on, int kin_on, int accumulate, double* kpart);
 int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const double* parts,
                     int which, int nblk, double* out);
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,

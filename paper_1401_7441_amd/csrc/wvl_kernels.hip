@@ -194,11 +194,22 @@ __global__ __launch_bounds__(64) void k_pattern(const SfDev* __restrict__ sfs,
   if (rowptr == nullptr && lane == 0) count[a] = n;
 }
 
-// one wavefront per nonzero (a, b).  The wave splits into four 16-lane groups;
-// group g takes rows g, g+4, ... of the box where both patterns may meet, and
-// its lanes walk the overlapping runs of that row with contiguous loads.
-// Lane partial sums combine in a fixed shuffle tree, so every value has an
-// order fixed by the pair alone.
+// one wavefront per nonzero (a, b), in two phases per batch of 64 rows of the
+// box where both patterns may meet.  Phase 1: lane r resolves row r (row
+// tables, segment lists) to the first overlapping run of each kind (scaling /
+// wavelet) and keeps it in LDS; further runs of the same row, which sphere
+// patterns never produce, are summed by that lane directly.  Phase 2: four
+// 16-lane groups stream the kept runs with contiguous loads.  Every lane's
+// partial sum and the final shuffle tree have an order fixed by the pair.
+template <typename T>
+__device__ __forceinline__ double run_dot(const T* __restrict__ pa, const T* __restrict__ pk,
+                                          int len, int nfa, int64_t nfb, int ncomp) {
+  double acc = 0.0;
+  for (int comp = 0; comp < ncomp; ++comp)
+    for (int x = 0; x < len; ++x) acc += (double)pa[comp * (int64_t)nfa + x] * (double)pk[comp * nfb + x];
+  return acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ sfs,
                                                       const wvl_seg* __restrict__ seg,
@@ -208,6 +219,8 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
                                                       const int32_t* __restrict__ rowi,
                                                       const int32_t* __restrict__ coli,
                                                       double* __restrict__ val) {
+  __shared__ int64_t ea[2][64], eb[2][64];   // run start offsets (bra, ket) per kind
+  __shared__ int32_t el[2][64];              // run lengths (0: none)
   const int64_t k = blockIdx.x;
   const int lane = threadIdx.x;
   const int grp = lane >> 4, gl = lane & 15;
@@ -223,37 +236,62 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
   const int ny = y1 - y0 + 1;
   const int nrows = (y1 >= y0 && z1 >= z0) ? ny * (z1 - z0 + 1) : 0;
   double acc = 0.0;
-  for (int r = grp; r < nrows; r += 4) {
-    const int y = y0 + r % ny, z = z0 + r / ny;
-    const int64_t ra = (int64_t)(z - A.lo[2]) * A.n[1] + (y - A.lo[1]);
-    const int64_t rb = (int64_t)(z - pb.oz) * pb.by + (y - pb.oy);
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    // phase 1
+    const int r = r0 + lane;
+#pragma unroll
     for (int fine = 0; fine < 2; ++fine) {
-      int qa = rt[A.rt[fine] + ra];
-      const int qa1 = rt[A.rt[fine] + ra + 1];
-      const int pB = fine ? pf : pc;
-      int qb = rt[B.rt[pB] + rb];
-      const int qb1 = rt[B.rt[pB] + rb + 1];
-      while (qa < qa1 && qb < qb1) {
-        const wvl_seg sa = seg[qa], sb = seg[qb];
-        const int x0 = max(sa.i1s, sb.i1s), x1 = min(sa.i1e, sb.i1e);
-        if (x0 <= x1) {
-          const int len = x1 - x0 + 1;
-          if (!fine) {
-            const T* pa = bra + A.cin + sa.off + (x0 - sa.i1s);
-            const T* pk = ket + bc + sb.off + (x0 - sb.i1s);
-            for (int x = gl; x < len; x += 16) acc += (double)pa[x] * (double)pk[x];
-          } else {
-            const T* pa = bra + A.cin + A.n_c + sa.off + (x0 - sa.i1s);
-            const T* pk = ket + bc + bnc + sb.off + (x0 - sb.i1s);
-            for (int t = gl; t < 7 * len; t += 16) {
-              const int comp = t / len, x = t - comp * len;
-              acc += (double)pa[comp * A.n_f + x] * (double)pk[comp * bnf + x];
+      el[fine][lane] = 0;
+      if (r < nrows) {
+        const int y = y0 + r % ny, z = z0 + r / ny;
+        const int64_t ra = (int64_t)(z - A.lo[2]) * A.n[1] + (y - A.lo[1]);
+        const int64_t rb = (int64_t)(z - pb.oz) * pb.by + (y - pb.oy);
+        int qa = rt[A.rt[fine] + ra];
+        const int qa1 = rt[A.rt[fine] + ra + 1];
+        const int pB = fine ? pf : pc;
+        int qb = rt[B.rt[pB] + rb];
+        const int qb1 = rt[B.rt[pB] + rb + 1];
+        bool first = true;
+        while (qa < qa1 && qb < qb1) {
+          const wvl_seg sa = seg[qa], sb = seg[qb];
+          const int x0 = max(sa.i1s, sb.i1s), x1 = min(sa.i1e, sb.i1e);
+          if (x0 <= x1) {
+            const int64_t oa = A.cin + (fine ? A.n_c : 0) + sa.off + (x0 - sa.i1s);
+            const int64_t ob = bc + (fine ? bnc : 0) + sb.off + (x0 - sb.i1s);
+            if (first) {
+              ea[fine][lane] = oa;
+              eb[fine][lane] = ob;
+              el[fine][lane] = x1 - x0 + 1;
+              first = false;
+            } else {
+              acc += run_dot<T>(bra + oa, ket + ob, x1 - x0 + 1, (int)A.n_f, bnf, fine ? 7 : 1);
             }
           }
+          if (sa.i1e < sb.i1e) ++qa; else ++qb;
         }
-        if (sa.i1e < sb.i1e) ++qa; else ++qb;
       }
     }
+    __syncthreads();
+    // phase 2
+    const int nb = min(64, nrows - r0);
+    for (int q = grp; q < nb; q += 4) {
+      const int lc = el[0][q];
+      if (lc > 0) {
+        const T* pa = bra + ea[0][q];
+        const T* pk = ket + eb[0][q];
+        for (int x = gl; x < lc; x += 16) acc += (double)pa[x] * (double)pk[x];
+      }
+      const int lf = el[1][q];
+      if (lf > 0) {
+        const T* pa = bra + ea[1][q];
+        const T* pk = ket + eb[1][q];
+        for (int t = gl; t < 7 * lf; t += 16) {
+          const int comp = t / lf, x = t - comp * lf;
+          acc += (double)pa[comp * (int64_t)A.n_f + x] * (double)pk[comp * bnf + x];
+        }
+      }
+    }
+    __syncthreads();
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (lane == 0) val[k] = acc;

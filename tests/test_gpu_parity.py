@@ -288,3 +288,47 @@ def test_library_segments_feed_identical_results():
     rec, oseg = to_abi(LR.sphere_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext))
     assert np.array_equal(segs, oseg)
     assert np.array_equal(lr["coef_off"], rec["coef_off"])
+
+
+def test_sparse_on_rows_with_several_runs():
+    """Random-mask patterns: rows hold several runs, so both phases of the
+    sparse kernel (kept first run, lane-local further runs) are exercised."""
+    _print("case: sparse S/H, multi-run rows")
+    rng = np.random.default_rng(21)
+    g = inputs.geometry("batch1k", nsf=1)
+    g.grid_n = (30, 30, 30)
+    lrs = []
+    for k in range(5):
+        lo = tuple(int(v) for v in rng.integers(6, 12, 3))
+        dims = tuple(int(v) for v in rng.integers(5, 9, 3))
+        ext = 2
+        m = rng.random((dims[2], dims[1], dims[0])) < 0.55
+        m.flat[0] = True
+        fm = m & (rng.random(m.shape) < 0.5)
+        olo = [lo[a] - ext for a in range(3)]
+        om = rng.random((dims[2] + 2 * ext, dims[1] + 2 * ext, dims[0] + 2 * ext)) < 0.6
+        ofm = om & (rng.random(om.shape) < 0.5)
+        lrs.append(LR.Locreg(lo=lo, dims=dims, ext=ext, cseg=LR.segments_from_mask(m, lo),
+                             fseg=LR.segments_from_mask(fm, lo),
+                             ocseg=LR.segments_from_mask(om, olo),
+                             ofseg=LR.segments_from_mask(ofm, olo)))
+    g.centers = np.zeros((len(lrs), 3))
+    g.envelope_sigma = np.full(len(lrs), 100.0)
+    g.domain_lo = np.zeros(3)
+    g.domain_hi = np.array(g.grid_n) * g.h
+    case = Case(g, lrs, normalize=False)
+    plan, psi, out, _, _ = case.run(torch.float64)
+    hpsi = torch.tensor(out, dtype=torch.float64, device="cuda")
+    ohs = [case.oracle(k)[0] for k in range(len(lrs))]
+    for ket_out in (False, True):
+        rowptr, col, val = W.sparse_overlap(plan, psi, hpsi if ket_out else psi, ket_out)
+        torch.cuda.synchronize()
+        kets = ohs if ket_out else case.coefs
+        rp, cl, vv = SP.matrix(lrs, case.coefs, kets, ket_out)
+        assert np.array_equal(rowptr.cpu().numpy(), rp)
+        assert np.array_equal(col.cpu().numpy(), cl)
+        v = val.cpu().numpy()
+        for a in range(len(lrs)):
+            for j in range(rp[a], rp[a + 1]):
+                scale = np.linalg.norm(case.coefs[a]) * np.linalg.norm(kets[cl[j]])
+                assert abs(v[j] - vv[j]) <= 1e-12 * scale, (a, cl[j])
