@@ -66,9 +66,10 @@ def _count_down(N, e):
     return int(np.sum(np.maximum(0, hi - lo + 1)))
 
 
-def work_model(locregs, sz, terms_kin=True):
-    """{kernel kind: (bytes, flops)} summed over all functions, one launch each."""
-    import numpy as np
+def work_model(locregs, sz):
+    """{kernel kind: (bytes, flops)} of one launch over all functions (both
+    terms on).  Bytes count each kernel's inputs and outputs once; flops
+    count the multiply-adds of the filters as written (two per MAC)."""
     out = {}
 
     def add(k, b, f):
@@ -81,24 +82,23 @@ def work_model(locregs, sz, terms_kin=True):
         o0, o1, o2 = n0 + 2 * e, n1 + 2 * e, n2 + 2 * e
         nin = int(r["n_c"]) + 7 * int(r["n_f"])
         nout = int(r["on_c"]) + 7 * int(r["on_f"])
-        c8, o8 = 8 * n0 * n1 * n2, 8 * o0 * o1 * o2
-        add("gather", sz * (nin + c8), 0)
-        # kinetic: outputs whose other coordinates lie in the input box; 58 MAC each
-        kin_out = [8 * o0 * n1 * n2, 8 * n0 * o1 * n2, 8 * n0 * n1 * o2]
-        for ax, name in enumerate(("kin_x", "kin_y", "kin_z")):
-            rw = 1 if ax == 0 else 2
-            add(name, sz * (c8 + rw * o8), 2 * 58 * kin_out[ax])
-        add("ekin", sz * 2 * c8, 2 * c8)
-        a1, a2, g = 4 * r0 * n1 * n2, 2 * r0 * r1 * n2, r0 * r1 * r2
-        b1, b2 = 2 * r0 * r1 * o2, 4 * r0 * o1 * o2
-        add("up_x", sz * (c8 + a1), 2 * 2 * 4 * n1 * n2 * _count_up(n0))
-        add("up_y", sz * (a1 + a2), 2 * 2 * 2 * r0 * n2 * _count_up(n1))
-        add("up_z", sz * (a2 + 2 * g), 2 * 2 * r0 * r1 * _count_up(n2) + 3 * g)
-        add("down_z", sz * (g + b1), 2 * 2 * r0 * r1 * _count_down(n2, e))
-        add("down_y", sz * (b1 + b2), 2 * 2 * 2 * r0 * o2 * _count_down(n1, e))
-        add("down_x", sz * (b2 + (2 if terms_kin else 1) * o8),
-            2 * 2 * 4 * o1 * o2 * _count_down(n0, e))
-        add("scatter", sz * 2 * nout, 0)
+        c8 = 8 * n0 * n1 * n2
+        g = r0 * r1 * r2
+        g1, g2, q = 2 * n2 * r1 * r0, 2 * o2 * r1 * r0, 4 * o2 * r0 * o1
+        kx, ky, kz = 8 * o0 * n1 * n2, 8 * n0 * o1 * n2, 8 * n0 * n1 * o2
+        # compressed phi -> two dense copies of the coarse box + x, y up passes
+        add("fwd_plane", sz * (nin + 2 * c8 + g1),
+            2 * 2 * 4 * n1 * n2 * _count_up(n0) + 2 * 2 * 2 * r0 * n2 * _count_up(n1))
+        # z up pass, V multiply, e_pot partials, z down pass
+        add("pot_column", sz * (g1 + g + g2),
+            2 * 2 * r0 * r1 * _count_up(n2) + 3 * g + 2 * 2 * r0 * r1 * _count_down(n2, e))
+        # one axis of the kinetic term: 29 taps from each of two components
+        for name, kout in (("kin_xcol", kx), ("kin_ycol", ky), ("kin_zcol", kz)):
+            add(name, sz * (c8 + kout), 2 * 58 * kout)
+        add("back_y", sz * (g2 + q), 2 * 2 * 2 * r0 * o2 * _count_down(n1, e))
+        # x down pass + three kinetic parts + e_kin + compress
+        add("back_x", sz * (q + kx + ky + kz + c8 + nout),
+            2 * 2 * 4 * o1 * o2 * _count_down(n0, e) + 3 * 8 * o0 * o1 * o2 + 2 * c8)
     return out
 
 

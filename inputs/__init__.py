@@ -194,3 +194,18 @@ def single_box():
     """The single-function workload's box: lo (0,0,0), 20^3 coarse points,
     fine region the inner 10^3 (coarse indices 5..14)."""
     return (0, 0, 0), (20, 20, 20), (5, 5, 5), (14, 14, 14)
+
+
+def write_geometry(workload, path, nsf=None):
+    """Write a workload's geometry as a flat little-endian file for native
+    drivers: int32 nsf, int32 grid_n[3], int32 ext, int32 0, float64 h, then
+    float64 centers[nsf][3], radii[nsf], fine_radii[nsf]."""
+    g = geometry(workload, nsf=nsf)
+    m = len(g.radii)
+    with open(path, "wb") as f:
+        f.write(np.array([m, *g.grid_n, g.ext, 0], dtype="<i4").tobytes())
+        f.write(np.array([g.h], dtype="<f8").tobytes())
+        f.write(np.ascontiguousarray(g.centers, dtype="<f8").tobytes())
+        f.write(np.ascontiguousarray(g.radii, dtype="<f8").tobytes())
+        f.write(np.ascontiguousarray(g.fine_radii, dtype="<f8").tobytes())
+

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libwvl.so")
+BENCH_BIN = os.path.join(HERE, "wvl_bench")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
@@ -67,6 +68,12 @@ def build(regen_filters: bool = True) -> str:
     _run(["g++", "-shared", "-fPIC", "-o", tmp, *kobjs, hobj, f"-L{tlib}", "-l:libamdhip64.so",
           f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined"])
     os.replace(tmp, LIB)
+    # native driver (own HIP runtime from the ROCm install, no torch)
+    bobj = os.path.join(bdir, "wvl_bench_main.o")
+    _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "wvl_bench_main.hip"), "-o", bobj])
+    tmpb = BENCH_BIN + ".tmp"
+    _run([hipcc, "--offload-arch=gfx950", "-o", tmpb, bobj, *kobjs, hobj])
+    os.replace(tmpb, BENCH_BIN)
     return LIB
 
 

@@ -12,14 +12,16 @@
 //                register rings: up pass z, potential multiply (FP64 energy
 //                partials), down pass z -> G2.  Every input is read once.
 //   k_kin_col    one coarse column per thread (along x, y or z): that axis'
-//                part of the kinetic term with a 32-slot register window.
-//   k_back_y     one fine (channel, z', x) column per thread, streaming along y: the y
-//                down pass; an LDS stage transposes the result so that x is
-//                a slow axis of the x down pass' input.
+//                part of the kinetic term with a 32-slot register window,
+//                and that part's share of <phi|T|phi>.
+//   k_back_y     one fine (channel, z', x) column per thread, streaming along
+//                y: the y down pass; 16-wide LDS stages transpose the result
+//                so that y' is the fastest axis of the x down pass' input.
 //   k_back_x     one output (z', y', channel) row per thread, streaming along
-//                x: the x down pass plus the three kinetic parts, e_kin
-//                partials, and the compress step walking the row's output
-//                segments in order.
+//                x: the x down pass plus the three kinetic parts, written
+//                through 16-wide LDS stages to a dense x'-fastest box.
+//   k_pack_out   one dense output point per thread: compress onto the
+//                output pattern.
 // Register ring slots are compile-time constants after unrolling by the ring
 // period, so the rings stay in VGPRs.
 #include <hip/hip_runtime.h>
@@ -34,6 +36,11 @@ __constant__ float fC32[2][31] = {WVL_C0_F32, WVL_C1_F32};
 __constant__ double fK64[2][2][29] = {{WVL_K00_F64, WVL_K01_F64}, {WVL_K10_F64, WVL_K11_F64}};
 __constant__ float fK32[2][2][29] = {{WVL_K00_F32, WVL_K01_F32}, {WVL_K10_F32, WVL_K11_F32}};
 __constant__ double fKD64[2] = WVL_KD_F64;
+
+// LDS row stride of the 16-wide output stages: element (j, lane) at
+// j * kSP + lane; the flush reads (j = lane & 15, row = 4 it + lane >> 4),
+// whose banks 4 j + row are all distinct
+constexpr int kSP = 68;
 
 template <typename T>
 __device__ __forceinline__ T Ct(int b, int n);
@@ -283,14 +290,19 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
 // ---------------------------------------------------------------------------
 // out_a(i') = fac sum_j sum_b K_ab[j] x_b(i'+j) for i' = -e .. N+e-1, where
 // x_b is the component whose AX bit is b; the window holds x(i-28..i) when
-// output i' = i - 14 is formed.  Inputs and outputs (y fastest unless noted):
-//   AX = 0: c8x -> ox[8][N2][O0][N1]
-//   AX = 1: c8  -> oy[8][N2][O1][N0]   (x fastest)
-//   AX = 2: c8x -> oz[8][O2][N0][N1]
+// output i' = i - 14 is formed.  Each block also leaves the partial
+// sum_{i' in box} x_a(i') out_a(i') of <phi|T|phi> in its e_kin slot.
+// Inputs and outputs:
+//   AX = 0: c8x [c][z][x][y] -> ox[8][N2][O0][N1]   (256 threads, y fastest)
+//   AX = 1: c8  [c][z][y][x] -> oy[8][N2][N0][O1]   (64 threads, one column
+//           per lane along x; every 16 outputs are staged in LDS and written
+//           out 4 columns x 16 consecutive y' per store, y' fastest)
+//   AX = 2: c8x [c][z][x][y] -> oz[8][O2][N0][N1]   (256 threads, y fastest)
 template <typename T, int AX>
-__global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
-                                                 const SfWork* __restrict__ wk, int sf0,
-                                                 T* __restrict__ ws, double fac) {
+__global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
+    const SfDev* __restrict__ sfs, const SfWork* __restrict__ wk, int sf0, T* __restrict__ ws,
+    double fac, double* __restrict__ kpart) {
+  __shared__ T st[AX == 1 ? 2 * 16 * kSP : 1];   // AX = 1: [a][16 outputs][kSP]
   const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
@@ -298,10 +310,16 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
   const int NA = AX == 2 ? N2 : AX == 1 ? N1 : N0;
   const int OA = NA + 2 * e;
   const int64_t ncol = AX == 2 ? plane : AX == 1 ? (int64_t)N0 * N2 : (int64_t)N1 * N2;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 4 * ncol) return;
-  const int pr = (int)(idx / ncol);
-  const int64_t col = idx % ncol;
+  const int64_t idx0 = (int64_t)blockIdx.x * blockDim.x;
+  if (idx0 >= 4 * ncol) return;   // whole block beyond this function's columns
+  // this axis' first e_kin slot, counted on the function's own box
+  const int slot0 = AX == 0 ? 0
+                  : AX == 1 ? kin_blocks(0, N0, N1, N2)
+                            : kin_blocks(0, N0, N1, N2) + kin_blocks(1, N0, N1, N2);
+  const int64_t idx = idx0 + threadIdx.x;
+  const bool active = idx < 4 * ncol;
+  const int pr = active ? (int)(idx / ncol) : 0;
+  const int64_t col = active ? idx % ncol : 0;
   // component with AX bit b: AX = 0 -> b + 2 pr (pr = a2 + 2 a3);
   // AX = 1 -> a1 + 2b + 4 a3 (pr = a1 + 2 a3); AX = 2 -> pr + 4b (pr = a1 + 2 a2)
   const int cb0 = AX == 2 ? pr : AX == 1 ? (pr & 1) + 4 * (pr >> 1) : 2 * pr;
@@ -316,8 +334,8 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
     const int x = (int)(col % N0), z = (int)(col / N0);
     ibase = (int64_t)z * plane + x;
     istride = N0;
-    obase = (int64_t)z * OA * N0 + x;
-    ostride = N0;
+    obase = ((int64_t)z * N0 + x) * OA;
+    ostride = 1;
   } else {                // column (y, z), y fastest
     const int y = (int)(col % N1), z = (int)(col / N1);
     ibase = (int64_t)z * plane + y;
@@ -326,7 +344,7 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
     ostride = N1;
   }
   const int64_t icomp = (int64_t)N2 * plane;                          // component size
-  const int64_t ocomp = AX == 2 ? (int64_t)OA * plane : AX == 1 ? (int64_t)N2 * OA * N0
+  const int64_t ocomp = AX == 2 ? (int64_t)OA * plane : AX == 1 ? (int64_t)N2 * N0 * OA
                                                                 : (int64_t)N2 * OA * N1;
   const T* inb = ws + (AX == 1 ? w.c8 : w.c8x);
   const T* in0 = inb + cb0 * icomp + ibase;
@@ -334,9 +352,14 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
   T* outb = ws + (AX == 2 ? w.oz : AX == 1 ? w.oy : w.ox);
   T* out0 = outb + cb0 * ocomp + obase;
   T* out1 = outb + cb1 * ocomp + obase;
+  const int lane = threadIdx.x;
+  // AX = 1: where this lane's column starts in the output (-1: no column)
+  const int colbase0 = active ? (int)(out0 - outb) : -1;   // < 8 N2 N0 O1
+  const int colbase1 = active ? (int)(out1 - outb) : -1;
   T x0[32], x1[32];
 #pragma unroll
   for (int k = 0; k < 32; ++k) x0[k] = x1[k] = T(0);
+  double eacc = 0.0;
   const int istart = 14 - e;           // emits i' = -e first
   const int iend = NA - 1 + e + 14;    // emits i' = NA - 1 + e last
   const int ilo = istart - 28;
@@ -345,14 +368,13 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
       const int i = i0 + u;
-      if (i > iend) continue;
-      const bool ok = i >= 0 && i < NA;
+      const bool ok = active && i >= 0 && i < NA;
       x0[u] = ok ? in0[(int64_t)i * istride] : T(0);
       x1[u] = ok ? in1[(int64_t)i * istride] : T(0);
-      if (i >= istart) {
+      if (i >= istart && i <= iend) {
         const int ip = i - 14;            // output coarse index i'
         const int sc = (u + 18) & 31;     // slot of x(i') = x(i - 14)
-        T r0, r1;
+        double r0, r1;
         if (sizeof(T) == 4) {
           T s0 = T(0), s1 = T(0);
 #pragma unroll
@@ -364,8 +386,8 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
             s1 += Kt<T>(1, 0, t) * d0 + Kt<T>(1, 1, t) * x1[sl];
           }
           const double c0 = (double)x0[sc], c1 = (double)x1[sc];
-          r0 = (T)(fac * ((double)s0 + fKD64[0] * c0 + fK64[0][1][14] * c1));
-          r1 = (T)(fac * ((double)s1 + fKD64[1] * c0 + fK64[1][1][14] * c1));
+          r0 = fac * ((double)s0 + fKD64[0] * c0 + fK64[0][1][14] * c1);
+          r1 = fac * ((double)s1 + fKD64[1] * c0 + fK64[1][1][14] * c1);
         } else {
           double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -374,15 +396,42 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
             s0 += fK64[0][0][t] * (double)x0[sl] + fK64[0][1][t] * (double)x1[sl];
             s1 += fK64[1][0][t] * (double)x0[sl] + fK64[1][1][t] * (double)x1[sl];
           }
-          r0 = (T)(fac * s0);
-          r1 = (T)(fac * s1);
+          r0 = fac * s0;
+          r1 = fac * s1;
         }
+        if (ip >= 0 && ip < NA) eacc += (double)x0[sc] * r0 + (double)x1[sc] * r1;
         const int pp = ip + e;
-        out0[(int64_t)pp * ostride] = r0;
-        out1[(int64_t)pp * ostride] = r1;
+        if (AX == 1) {
+          st[(u & 15) * kSP + lane] = (T)r0;
+          st[(16 + (u & 15)) * kSP + lane] = (T)r1;
+        } else if (active) {
+          out0[(int64_t)pp * ostride] = (T)r0;
+          out1[(int64_t)pp * ostride] = (T)r1;
+        }
+      }
+      if (AX == 1 && (u & 15) == 15) {
+        // outputs pp = i0 + (u - 15) + j - 14 + e, j = 0..15, of the 64
+        // columns (those with 0 <= pp < OA were formed above): 4 columns x
+        // 16 consecutive y' per store
+        __syncthreads();
+        const int j = lane & 15;
+        const int pp = i0 + (u - 15) + j - 14 + e;
+        const bool okp = pp >= 0 && pp < OA;
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+          const int cl = it * 4 + (lane >> 4);
+          const int b0c = __shfl(colbase0, cl, 64), b1c = __shfl(colbase1, cl, 64);
+          if (okp && b0c >= 0) {
+            outb[b0c + pp] = st[j * kSP + cl];
+            outb[b1c + pp] = st[(16 + j) * kSP + cl];
+          }
+        }
+        __syncthreads();
       }
     }
   }
+  const double bs = block_sum_any(eacc);
+  if (threadIdx.x == 0) kpart[w.kpart + slot0 + blockIdx.x] = bs;
 }
 
 // ---------------------------------------------------------------------------
@@ -391,14 +440,13 @@ __global__ __launch_bounds__(256) void k_kin_col(const SfDev* __restrict__ sfs,
 // Thread = fine column px of G2[a3][z'][.][px], streaming along y: fine pair
 // p = 2q, 2q+1 arrives and is scattered into the accumulators of coarse
 // i' = q-15..q (out_b(i') += C_b[p - 2i'] g_p, b = a2); i' = q-15 is then
-// complete.  Results are staged in LDS st[a2][y'][65] and written out as
-// Q[a2 + 2 a3][z'][px][y'] (y' fastest).
+// complete.  Every 16 results are staged in LDS and written out as
+// Q[a2 + 2 a3][z'][px][y'] (y' fastest), 4 columns x 16 y' per store.
 template <typename T>
 __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
                                                const SfWork* __restrict__ wk, int sf0,
                                                T* __restrict__ ws) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* st = reinterpret_cast<T*>(smem_raw);
+  __shared__ T st[2 * 16 * kSP];
   const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
@@ -414,13 +462,18 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
   const int64_t slab = active ? col / R0 : 0;     // a3 * O2 + z'
   const int px = active ? (int)(col % R0) : 0;
   const T* in = ws + w.g2 + slab * R1 * R0 + px;
+  // Q[a2 + 2 a3][z'][px][y']: start of this column's y' run for a2 = 0
+  const int a3 = (int)(slab / O2), zp = (int)(slab - (int64_t)a3 * O2);
+  const int qcol = active ? ((2 * a3 * O2 + zp) * R0 + px) * O1 : -1;
+  const int qa = O2 * R0 * O1;                      // a2 stride (< 2^31 elements)
+  T* qo = ws + w.q;
+  if (e == 16 && active) {  // coarse i' = -16 lies beyond the filter reach
+    qo[qcol] = T(0);
+    qo[qa + qcol] = T(0);
+  }
   T a0[16], a1[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) a0[k] = a1[k] = T(0);
-  if (e == 16) {  // coarse i' = -16 lies beyond the filter reach
-    st[lane] = T(0);
-    st[O1 * 65 + lane] = T(0);
-  }
   const int qend = N1 + e + 14;
   for (int q0 = 0; q0 <= qend; q0 += 16) {
 #pragma unroll
@@ -441,30 +494,27 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
           }
         }
         const int sl = (u + 1) & 15;
-        const int yp = q - 15 + e;
-        if (yp >= 0 && yp < O1) {
-          st[yp * 65 + lane] = a0[sl];
-          st[(O1 + yp) * 65 + lane] = a1[sl];
-        }
+        st[u * kSP + lane] = a0[sl];          // y' = q - 15 + e
+        st[(16 + u) * kSP + lane] = a1[sl];
         a0[sl] = T(0);
         a1[sl] = T(0);
       }
     }
-  }
-  __syncthreads();
-  // Q[a2 + 2 a3][z'][px][y'] = Q slab (a2 O2... ) : element offset of
-  // column (a3, z', px) for channel a2 is ((a2 + 2 a3) O2 + z') R0 O1 + px O1
-  const int ncl = (int)min<int64_t>(64, ncols - col0);
-  for (int t = lane; t < 2 * ncl * O1; t += 64) {
-    const int a2 = t / (ncl * O1);
-    const int rem = t - a2 * ncl * O1;
-    const int pl = rem / O1, yp = rem - pl * O1;
-    const int64_t c = col0 + pl;
-    const int64_t sl = c / R0;                     // a3 * O2 + z'
-    const int a3 = (int)(sl / O2), zp = (int)(sl % O2);
-    const int pxx = (int)(c % R0);
-    ws[w.q + (((int64_t)(a2 + 2 * a3) * O2 + zp) * R0 + pxx) * O1 + yp] =
-        st[(a2 * O1 + yp) * 65 + pl];
+    // flush y' = q0 - 15 + e + j, j = 0..15
+    __syncthreads();
+    const int j = lane & 15;
+    const int yp = q0 - 15 + e + j;
+    const bool oky = yp >= 0 && yp < O1 && q0 + j <= qend;
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int cl = it * 4 + (lane >> 4);
+      const int qc = __shfl(qcol, cl, 64);
+      if (oky && qc >= 0) {
+        qo[qc + yp] = st[j * kSP + cl];
+        qo[qa + qc + yp] = st[(16 + j) * kSP + cl];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -474,38 +524,16 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
 // Thread = output row (y', z') of channel ch = a2 + 2 a3, components
 // c = a1 + 2 a2 + 4 a3 (a1 = 0, 1).  Streaming along x: fine pair p = 2q,
 // 2q+1 of Q[ch][z'][p][y'] is scattered into the potential accumulators of
-// coarse i' = q-15..q; i' = q-15 is then complete: potential part plus the
-// x, y and z kinetic parts (from k_kin_col), e_kin partial, and the compress
-// step into the output pattern.
-template <typename T>
-__device__ __forceinline__ void emit_out(const SfDev& sf, const wvl_seg* __restrict__ seg, int c,
-                                         int gx, int s1, int& cur, int& cs, int& ce,
-                                         int64_t& coff, T v, T* __restrict__ out,
-                                         int accumulate) {
-  while (cur < s1 && ce < gx) {
-    ++cur;
-    if (cur < s1) {
-      const wvl_seg g = seg[cur];
-      cs = g.i1s;
-      ce = g.i1e;
-      coff = g.off;
-    }
-  }
-  if (cur < s1 && cs <= gx) {
-    const int64_t k = coff + (gx - cs);
-    const int64_t o = c == 0 ? sf.cout + k : sf.cout + sf.on_c + (int64_t)(c - 1) * sf.on_f + k;
-    out[o] = accumulate ? out[o] + v : v;
-  }
-}
-
+// coarse i' = q-15..q; i' = q-15 is then complete and gets the x, y and z
+// kinetic parts (from k_kin_col, all read with y' across the lanes).  Every
+// 16 results are staged in LDS and written to the dense output box
+// OB[c][z'][y'][x'] (x' fastest), 4 rows x 16 x' per store; k_pack_out then
+// compresses OB onto the output pattern.
 template <typename T>
 __global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
-                                               const wvl_seg* __restrict__ seg,
-                                               const int32_t* __restrict__ rt,
                                                const SfWork* __restrict__ wk, int sf0,
-                                               const T* __restrict__ ws, T* __restrict__ out,
-                                               double fac, int pot_on, int kin_on, int accumulate,
-                                               double* __restrict__ kpart) {
+                                               T* __restrict__ ws, int pot_on, int kin_on) {
+  __shared__ T st[2 * 16 * kSP];
   const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
@@ -515,10 +543,7 @@ __global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
   const int bx = blockIdx.x;
   const int tt = bx % nty, zp = bx / nty;
   const int lane = threadIdx.x;
-  if (zp >= O2) {
-    if (lane == 0) kpart[w.kpart + blockIdx.x] = 0.0;
-    return;
-  }
+  if (zp >= O2) return;   // uniform over the block
   const int id = tt * 64 + lane;
   const bool active = id < 4 * O1;
   const int ch = active ? id / O1 : 0, yp = active ? id % O1 : 0;
@@ -528,32 +553,24 @@ __global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
   const bool yin = y >= 0 && y < N1;
   const int64_t plane = (int64_t)N0 * N1;
   const T* qin = ws + w.q + ((int64_t)(ch * O2 + zp) * R0) * O1 + yp;
-  const int c0 = 0 + 2 * a2 + 4 * a3, c1 = c0 + 1;
-  // output row segments of both components
-  const int64_t r = (int64_t)zp * O1 + yp;
-  const int pat0 = c0 == 0 ? 2 : 3;
-  int cur0 = rt[sf.rt[pat0] + r], cur1 = rt[sf.rt[3] + r];
-  const int e0 = rt[sf.rt[pat0] + r + 1], e1 = rt[sf.rt[3] + r + 1];
-  int cs0 = 0, ce0 = -(1 << 30), cs1 = 0, ce1 = -(1 << 30);
-  int64_t co0 = 0, co1 = 0;
-  if (cur0 < e0) { const wvl_seg g = seg[cur0]; cs0 = g.i1s; ce0 = g.i1e; co0 = g.off; }
-  if (cur1 < e1) { const wvl_seg g = seg[cur1]; cs1 = g.i1s; ce1 = g.i1e; co1 = g.off; }
-  const int gx0 = sf.lo[0] - e;
-  if (active && e == 16) {  // coarse i' = -16 lies beyond every filter's reach
-    emit_out<T>(sf, seg, c0, gx0, e0, cur0, cs0, ce0, co0, T(0), out, accumulate);
-    emit_out<T>(sf, seg, c1, gx0, e1, cur1, cs1, ce1, co1, T(0), out, accumulate);
+  const int c0 = 2 * a2 + 4 * a3, c1 = c0 + 1;
+  // OB row (c0, z', y') start; component c1 is one component further
+  const int orow = active ? ((c0 * O2 + zp) * O1 + yp) * O0 : -1;   // < 8 O2 O1 O0
+  const int oc = O2 * O1 * O0;
+  T* ob = ws + w.ob;
+  if (e == 16 && active) {  // coarse i' = -16 lies beyond every filter's reach
+    ob[orow] = T(0);
+    ob[oc + orow] = T(0);
   }
-  // kinetic parts (y fastest where the thread index runs over y')
-  const int64_t comp_x = (int64_t)N2 * O0 * N1, comp_y = (int64_t)N2 * O1 * N0;
-  const int64_t comp_z = (int64_t)O2 * plane, comp_c = (int64_t)N2 * plane;
+  // kinetic parts, each with y or y' across the lanes
+  const int64_t comp_x = (int64_t)N2 * O0 * N1, comp_y = (int64_t)N2 * N0 * O1;
+  const int64_t comp_z = (int64_t)O2 * plane;
   const T* oxp = ws + w.ox + ((int64_t)(zin ? z : 0) * O0) * N1 + (yin ? y : 0);  // [c][z][x'][y]
-  const T* oyp = ws + w.oy + ((int64_t)(zin ? z : 0) * O1 + yp) * N0;             // [c][z][y'][x]
+  const T* oyp = ws + w.oy + (int64_t)(zin ? z : 0) * N0 * O1 + yp;               // [c][z][x][y']
   const T* ozp = ws + w.oz + (int64_t)zp * plane + (yin ? y : 0);                // [c][z'][x][y]
-  const T* cxp = ws + w.c8x + (int64_t)(zin ? z : 0) * plane + (yin ? y : 0);    // [c][z][x][y]
   T p0[16], p1[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) p0[k] = p1[k] = T(0);
-  double kacc = 0.0;
   const int qend = N0 + e + 14;
   for (int q0 = 0; q0 <= qend; q0 += 16) {
 #pragma unroll
@@ -582,18 +599,17 @@ __global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
       T v0 = p0[ps], v1 = p1[ps];
       p0[ps] = T(0);
       p1[ps] = T(0);
-      if (!active || xp < 0 || xp >= O0) continue;
-      const bool xin = ip >= 0 && ip < N0;
-      if (kin_on) {
+      if (active && kin_on && xp >= 0 && xp < O0) {
+        const bool xin = ip >= 0 && ip < N0;
         if (zin && yin) {            // x part: ox[c][z][x'][y]
           v0 += oxp[c0 * comp_x + (int64_t)xp * N1];
           v1 += oxp[c1 * comp_x + (int64_t)xp * N1];
         }
         if (xin) {
           T k0 = T(0), k1 = T(0);
-          if (zin) {                 // y part: oy[c][z][y'][x]
-            k0 += oyp[c0 * comp_y + ip];
-            k1 += oyp[c1 * comp_y + ip];
+          if (zin) {                 // y part: oy[c][z][x][y']
+            k0 += oyp[c0 * comp_y + (int64_t)ip * O1];
+            k1 += oyp[c1 * comp_y + (int64_t)ip * O1];
           }
           if (yin) {                 // z part: oz[c][z'][x][y]
             k0 += ozp[c0 * comp_z + (int64_t)ip * N1];
@@ -601,22 +617,88 @@ __global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
           }
           v0 += k0;
           v1 += k1;
-          if (zin && yin) {          // e_kin on the input box: c (Ox + Oy + Oz)
-            const T x0v = cxp[c0 * comp_c + (int64_t)ip * N1];
-            const T x1v = cxp[c1 * comp_c + (int64_t)ip * N1];
-            const T kx0 = oxp[c0 * comp_x + (int64_t)xp * N1];
-            const T kx1 = oxp[c1 * comp_x + (int64_t)xp * N1];
-            kacc += (double)x0v * (double)(kx0 + k0) + (double)x1v * (double)(kx1 + k1);
-          }
         }
       }
-      const int gx = gx0 + xp;
-      emit_out<T>(sf, seg, c0, gx, e0, cur0, cs0, ce0, co0, v0, out, accumulate);
-      emit_out<T>(sf, seg, c1, gx, e1, cur1, cs1, ce1, co1, v1, out, accumulate);
+      st[u * kSP + lane] = v0;
+      st[(16 + u) * kSP + lane] = v1;
+    }
+    // flush x' = q0 - 15 + e + j, j = 0..15
+    __syncthreads();
+    const int j = lane & 15;
+    const int xp = q0 - 15 + e + j;
+    const bool okx = xp >= 0 && xp < O0 && q0 + j <= qend;
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int rl = it * 4 + (lane >> 4);
+      const int orl = __shfl(orow, rl, 64);
+      if (okx && orl >= 0) {
+        ob[orl + xp] = st[j * kSP + rl];
+        ob[oc + orl + xp] = st[(16 + j) * kSP + rl];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_pack_out: block = 64 consecutive segments of one output pattern of one
+// function (coarse pattern blocks first, then fine).  The segment
+// descriptors are staged in LDS once; the block then streams the covered
+// run of compressed coefficients (one contiguous range per component),
+// locating each coefficient's segment by a binary search in LDS and reading
+// its value from the dense box OB.
+// ---------------------------------------------------------------------------
+constexpr int kPackSegs = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
+                                                  const wvl_seg* __restrict__ seg,
+                                                  const int32_t* __restrict__ rt,
+                                                  const SfWork* __restrict__ wk, int sf0,
+                                                  const T* __restrict__ ws, T* __restrict__ out,
+                                                  int accumulate) {
+  __shared__ int s_off[kPackSegs + 1];   // coefficient offset relative to the first segment
+  __shared__ int s_ob[kPackSegs];        // OB index of the segment's first point (component 0)
+  const SfDev& sf = sfs[sf0 + blockIdx.y];
+  const SfWork& w = wk[blockIdx.y];
+  const int e = sf.ext;
+  const int O0 = sf.n[0] + 2 * e, O1 = sf.n[1] + 2 * e, O2 = sf.n[2] + 2 * e;
+  const int64_t nrows = (int64_t)O2 * O1;
+  const int cb0 = rt[sf.rt[2]], ce0 = rt[sf.rt[2] + nrows];   // coarse output segments
+  const int fb0 = rt[sf.rt[3]], fe0 = rt[sf.rt[3] + nrows];   // fine output segments
+  const int nbc = (ce0 - cb0 + kPackSegs - 1) / kPackSegs;
+  const int nbf = (fe0 - fb0 + kPackSegs - 1) / kPackSegs;
+  int bx = blockIdx.x;
+  const bool fine = bx >= nbc;
+  if (fine) bx -= nbc;
+  if (bx >= (fine ? nbf : nbc)) return;   // uniform over the block
+  const int sA = (fine ? fb0 : cb0) + bx * kPackSegs;
+  const int nseg = min(kPackSegs, (fine ? fe0 : ce0) - sA);
+  const int tid = threadIdx.x;
+  const int64_t off0 = seg[sA].off;
+  if (tid < nseg) {
+    const wvl_seg g = seg[sA + tid];
+    s_off[tid] = (int)(g.off - off0);
+    s_ob[tid] = ((g.i3 - (sf.lo[2] - e)) * O1 + (g.i2 - (sf.lo[1] - e))) * O0 +
+                (g.i1s - (sf.lo[0] - e));
+    if (tid == nseg - 1) s_off[nseg] = (int)(g.off - off0) + (g.i1e - g.i1s + 1);
+  }
+  __syncthreads();
+  const int total = s_off[nseg];
+  const int oc = O2 * O1 * O0;
+  const int cfirst = fine ? 1 : 0, clast = fine ? 7 : 0;
+  for (int k = tid; k < total; k += 256) {
+    int lo = 0, hi = nseg - 1;   // last segment with s_off <= k
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const int src = s_ob[lo] + (k - s_off[lo]);
+    for (int c = cfirst; c <= clast; ++c) {
+      const int64_t o = sf.cout + (c == 0 ? 0 : sf.on_c + (int64_t)(c - 1) * sf.on_f) + off0 + k;
+      const T v = ws[w.ob + (int64_t)c * oc + src];
+      out[o] = accumulate ? out[o] + v : v;
     }
   }
-  const double b = block_sum_any(kacc);
-  if (lane == 0) kpart[w.kpart + blockIdx.x] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -651,52 +733,69 @@ int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, 
 }
 
 int launch_kin_col(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
-                   int nsf, int gridx, void* ws, double fac) {
+                   int nsf, int gridx, void* ws, double fac, double* kpart) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
   hipStream_t st = (hipStream_t)stream;
   if (f64) {
+    double* w = (double*)ws;
     if (axis == 2)
-      hipLaunchKernelGGL((k_kin_col<double, 2>), g, dim3(256), 0, st, sf, wk, sf0, (double*)ws, fac);
+      hipLaunchKernelGGL((k_kin_col<double, 2>), g, dim3(256), 0, st, sf, wk, sf0, w, fac, kpart);
     else if (axis == 1)
-      hipLaunchKernelGGL((k_kin_col<double, 1>), g, dim3(256), 0, st, sf, wk, sf0, (double*)ws, fac);
+      hipLaunchKernelGGL((k_kin_col<double, 1>), g, dim3(64), 0, st, sf, wk, sf0, w, fac, kpart);
     else
-      hipLaunchKernelGGL((k_kin_col<double, 0>), g, dim3(256), 0, st, sf, wk, sf0, (double*)ws, fac);
+      hipLaunchKernelGGL((k_kin_col<double, 0>), g, dim3(256), 0, st, sf, wk, sf0, w, fac, kpart);
   } else {
+    float* w = (float*)ws;
     if (axis == 2)
-      hipLaunchKernelGGL((k_kin_col<float, 2>), g, dim3(256), 0, st, sf, wk, sf0, (float*)ws, fac);
+      hipLaunchKernelGGL((k_kin_col<float, 2>), g, dim3(256), 0, st, sf, wk, sf0, w, fac, kpart);
     else if (axis == 1)
-      hipLaunchKernelGGL((k_kin_col<float, 1>), g, dim3(256), 0, st, sf, wk, sf0, (float*)ws, fac);
+      hipLaunchKernelGGL((k_kin_col<float, 1>), g, dim3(64), 0, st, sf, wk, sf0, w, fac, kpart);
     else
-      hipLaunchKernelGGL((k_kin_col<float, 0>), g, dim3(256), 0, st, sf, wk, sf0, (float*)ws, fac);
+      hipLaunchKernelGGL((k_kin_col<float, 0>), g, dim3(256), 0, st, sf, wk, sf0, w, fac, kpart);
   }
   return (int)hipGetLastError();
 }
 
 int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                  int gridx, size_t lds, void* ws) {
+                  int gridx, void* ws) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
   if (f64)
-    hipLaunchKernelGGL(k_back_y<double>, g, dim3(64), lds, (hipStream_t)stream, sf, wk, sf0,
+    hipLaunchKernelGGL(k_back_y<double>, g, dim3(64), 0, (hipStream_t)stream, sf, wk, sf0,
                        (double*)ws);
   else
-    hipLaunchKernelGGL(k_back_y<float>, g, dim3(64), lds, (hipStream_t)stream, sf, wk, sf0,
+    hipLaunchKernelGGL(k_back_y<float>, g, dim3(64), 0, (hipStream_t)stream, sf, wk, sf0,
                        (float*)ws);
   return (int)hipGetLastError();
 }
 
-int launch_back_x(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                  const SfWork* wk, int sf0, int nsf, int gridx, const void* ws, void* out,
-                  double fac, int pot_on, int kin_on, int accumulate, double* kpart) {
+int launch_back_x(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                  int gridx, void* ws, int pot_on, int kin_on) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
   if (f64)
-    hipLaunchKernelGGL(k_back_x<double>, g, dim3(64), 0, (hipStream_t)stream, sf, seg, rt, wk, sf0,
-                       (const double*)ws, (double*)out, fac, pot_on, kin_on, accumulate, kpart);
+    hipLaunchKernelGGL(k_back_x<double>, g, dim3(64), 0, (hipStream_t)stream, sf, wk, sf0,
+                       (double*)ws, pot_on, kin_on);
   else
-    hipLaunchKernelGGL(k_back_x<float>, g, dim3(64), 0, (hipStream_t)stream, sf, seg, rt, wk, sf0,
-                       (const float*)ws, (float*)out, fac, pot_on, kin_on, accumulate, kpart);
+    hipLaunchKernelGGL(k_back_x<float>, g, dim3(64), 0, (hipStream_t)stream, sf, wk, sf0,
+                       (float*)ws, pot_on, kin_on);
+  return (int)hipGetLastError();
+}
+
+int launch_pack_out(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                    const SfWork* wk, int sf0, int nsf, int64_t maxsegs, const void* ws, void* out,
+                    int accumulate) {
+  // maxsegs: the chunk's largest (coarse + fine) output segment count, so
+  // that ceil(coarse / 64) + ceil(fine / 64) blocks fit in maxsegs / 64 + 2
+  if (nsf == 0) return 0;
+  const dim3 g((unsigned)(maxsegs / kPackSegs + 2), (unsigned)nsf);
+  if (f64)
+    hipLaunchKernelGGL(k_pack_out<double>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, wk,
+                       sf0, (const double*)ws, (double*)out, accumulate);
+  else
+    hipLaunchKernelGGL(k_pack_out<float>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, wk,
+                       sf0, (const float*)ws, (float*)out, accumulate);
   return (int)hipGetLastError();
 }
 

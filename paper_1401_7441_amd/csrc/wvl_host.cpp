@@ -20,11 +20,11 @@ using namespace wvl;
 // kernel kinds for tracing
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
-  KK_BACK_Y, KK_BACK_X, KK_FINALIZE, KK_PATTERN, KK_SPARSE, KK_COUNT
+  KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "fwd_plane", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
-    "back_y", "back_x", "finalize", "pattern", "sparse_values"};
+    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_values"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -636,7 +636,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
     const int64_t o0 = n0 + 2 * e;
     return 2 * align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) +
            align64(2 * o2 * r0 * r1) + align64(4 * o2 * r0 * o1) + align64(8 * n2 * o0 * n1) +
-           align64(8 * n2 * o1 * n0) + align64(8 * o2 * n0 * n1);
+           align64(8 * n2 * o1 * n0) + align64(8 * o2 * n0 * n1) + align64(8 * o0 * o1 * o2);
   };
   int64_t best_f32 = 0, best_f64 = 0;
   {
@@ -670,16 +670,16 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
         W.ox = off;  off += align64(8 * n2 * o0 * n1);
         W.oy = off;  off += align64(8 * n2 * o1 * n0);
         W.oz = off;  off += align64(8 * o2 * n0 * n1);
+        W.ob = off;  off += align64(8 * o0 * o1 * o2);
         ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
         ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
+        ch.maxsegs_out = std::max<int64_t>(ch.maxsegs_out, lr[q].noseg_c + lr[q].noseg_f);
         ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
-        ch.grid_kz = (int32_t)std::max<int64_t>(ch.grid_kz, (4 * n0 * n1 + 255) / 256);
-        ch.grid_ky = (int32_t)std::max<int64_t>(ch.grid_ky, (4 * n0 * n2 + 255) / 256);
-        ch.grid_kx = (int32_t)std::max<int64_t>(ch.grid_kx, (4 * n1 * n2 + 255) / 256);
+        ch.grid_kx = std::max(ch.grid_kx, kin_blocks(0, (int)n0, (int)n1, (int)n2));
+        ch.grid_ky = std::max(ch.grid_ky, kin_blocks(1, (int)n0, (int)n1, (int)n2));
+        ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2));
         ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
         ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, ((4 * o1 + 63) / 64) * o2);
-        for (int d = 0; d < 2; ++d)
-          ch.lds_by[d] = std::max<int64_t>(ch.lds_by[d], 2 * o1 * 65 * (d ? 8 : 4));
       }
       for (int d = 0; d < 2; ++d) {
         const int64_t sz = d ? 8 : 4;
@@ -705,19 +705,23 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
           gf = std::max<int64_t>(gf, (int64_t)S.n[2] * 2 * ((2 * S.n[1] + 29 + tf - 1) / tf));
         }
         ch.grid_f[d] = (int32_t)gf;
-        if (ch.lds_f[d] > kLdsBudget || ch.lds_by[d] > kLdsBudget) {
+        if (ch.lds_f[d] > kLdsBudget) {
           wvl_plan_destroy(P);
           return fail(ctx, WVL_EUNSUPPORTED, "functions %d..%d: boxes too large for the LDS tiles",
                       k, j - 1);
         }
       }
       ch.nblk_pot = ch.grid_b;
-      ch.nblk_kin = ch.grid_bx;
+      ch.nblk_kin = ch.grid_kx + ch.grid_ky + ch.grid_kz;
       int64_t poff = 0;
       for (int q = k; q < j; ++q) {
+        const SfDev& S = P->h_sf[q];
         P->h_wk[q].epart = poff;
         poff += ch.nblk_pot;
         P->h_wk[q].kpart = poff;
+        P->h_wk[q].nkpart = kin_blocks(0, S.n[0], S.n[1], S.n[2]) +
+                            kin_blocks(1, S.n[0], S.n[1], S.n[2]) +
+                            kin_blocks(2, S.n[0], S.n[1], S.n[2]);
         poff += ch.nblk_kin;
       }
       P->chunks.push_back(ch);
@@ -825,21 +829,25 @@ static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
     }
     if (kin_on) {
       WVL_LAUNCH(ctx, KK_KIN_XCOL, launch_kin_col(f64, st, 0, P->d_sf, wk, ch.sf0, ch.nsf,
-                                                  ch.grid_kx, workspace, fac));
-      WVL_LAUNCH(ctx, KK_KIN_ZCOL, launch_kin_col(f64, st, 2, P->d_sf, wk, ch.sf0, ch.nsf,
-                                                  ch.grid_kz, workspace, fac));
-      WVL_LAUNCH(ctx, KK_KIN_YCOL, launch_kin_col(f64, st, 1, P->d_sf, wk, ch.sf0, ch.nsf,
-                                                  ch.grid_ky, workspace, fac));
+                                                  ch.grid_kx, workspace, fac, parts));
+      WVL_LAUNCH(ctx, KK_KIN_YCOL,
+                 launch_kin_col(f64, st, 1, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_ky, workspace,
+                                fac, parts));
+      WVL_LAUNCH(ctx, KK_KIN_ZCOL,
+                 launch_kin_col(f64, st, 2, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_kz, workspace,
+                                fac, parts));
+      if (e_kin)
+        WVL_LAUNCH(ctx, KK_FINALIZE,
+                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.nblk_kin, e_kin));
     }
     if (pot_on)
       WVL_LAUNCH(ctx, KK_BACK_Y, launch_back_y(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_by,
-                                               (size_t)ch.lds_by[d], workspace));
-    WVL_LAUNCH(ctx, KK_BACK_X,
-               launch_back_x(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf, ch.grid_bx,
-                             workspace, hpsi_c, fac, pot_on, kin_on, accumulate, parts));
-    if (kin_on && e_kin)
-      WVL_LAUNCH(ctx, KK_FINALIZE,
-                 launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.grid_bx, e_kin));
+                                               workspace));
+    WVL_LAUNCH(ctx, KK_BACK_X, launch_back_x(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_bx,
+                                             workspace, pot_on, kin_on));
+    WVL_LAUNCH(ctx, KK_PACK_OUT,
+               launch_pack_out(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf,
+                               ch.maxsegs_out, workspace, hpsi_c, accumulate));
   }
   return WVL_OK;
 }

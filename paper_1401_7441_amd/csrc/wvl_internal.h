@@ -39,13 +39,23 @@ struct SfDev {
 //   g2   after the z column pass         [2][O2][R1][R0]
 //   q    after the y down pass           [4][O2][R0][O1]   (channel a2 + 2 a3)
 //   ox   x part of the kinetic term      [8][N2][O0][N1]
-//   oy   y part of the kinetic term      [8][N2][O1][N0]
+//   oy   y part of the kinetic term      [8][N2][N0][O1]
 //   oz   z part of the kinetic term      [8][O2][N0][N1]
+//   ob   dense output box                [8][O2][O1][O0]
 struct SfWork {
-  int64_t c8, c8x, g1, g2, q, ox, oy, oz;
+  int64_t c8, c8x, g1, g2, q, ox, oy, oz, ob;
   int64_t epart;      // offset (in doubles) of its e_pot partials
   int64_t kpart;      // offset (in doubles) of its e_kin partials
+  int64_t nkpart;     // number of e_kin partials: its own k_kin_col blocks
 };
+
+// e_kin partial slots of one function: the blocks of k_kin_col along x, then
+// y, then z, counted on the function's own box (so that the summation order
+// does not depend on the other functions of the chunk)
+__host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2) {
+  return axis == 0 ? (4 * n1 * n2 + 255) / 256
+                   : axis == 1 ? (4 * n0 * n2 + 63) / 64 : (4 * n0 * n1 + 255) / 256;
+}
 
 // per-chunk launch geometry of the fused kernels, for dtype d (0 f32, 1 f64)
 struct ChunkDev {
@@ -56,8 +66,8 @@ struct ChunkDev {
   int32_t grid_b;                  // k_pot_column
   int32_t grid_kx, grid_ky, grid_kz;   // k_kin_col (x, y, z)
   int32_t grid_by;                 // k_back_y
-  int64_t lds_by[2];
   int32_t grid_bx;                 // k_back_x
+  int64_t maxsegs_out;             // k_pack_out: largest output segment count
   int32_t nblk_pot, nblk_kin;      // partial slots per function
 };
 
@@ -73,12 +83,14 @@ int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                       int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart);
 int launch_kin_col(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
-                   int nsf, int gridx, void* ws, double fac);
+                   int nsf, int gridx, void* ws, double fac, double* kpart);
 int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                  int gridx, size_t lds, void* ws);
-int launch_back_x(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                  const SfWork* wk, int sf0, int nsf, int gridx, const void* ws, void* out,
-                  double fac, int pot_on, int kin_on, int accumulate, double* kpart);
+                  int gridx, void* ws);
+int launch_back_x(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                  int gridx, void* ws, int pot_on, int kin_on);
+int launch_pack_out(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                    const SfWork* wk, int sf0, int nsf, int64_t maxsegs, const void* ws, void* out,
+                    int accumulate);
 int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const double* parts,
                     int which, int nblk, double* out);
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,

@@ -105,6 +105,7 @@ __global__ __launch_bounds__(TPB) void k_finalize(const SfWork* __restrict__ wk,
                                                   int nblk, double* __restrict__ out) {
   const int s = blockIdx.x;
   const int64_t off = which == 0 ? wk[s].epart : wk[s].kpart;
+  if (which == 1) nblk = (int)wk[s].nkpart;   // only the function's own slots
   double v = 0.0;
   for (int i = threadIdx.x; i < nblk; i += TPB) v += parts[off + i];
   const double b = block_sum(v);
