@@ -96,9 +96,11 @@ def work_model(locregs, sz):
         for name, kout in (("kin_xcol", kx), ("kin_ycol", ky), ("kin_zcol", kz)):
             add(name, sz * (c8 + kout), 2 * 58 * kout)
         add("back_y", sz * (g2 + q), 2 * 2 * 2 * r0 * o2 * _count_down(n1, e))
-        # x down pass + three kinetic parts + e_kin + compress
-        add("back_x", sz * (q + kx + ky + kz + c8 + nout),
-            2 * 2 * 4 * o1 * o2 * _count_down(n0, e) + 3 * 8 * o0 * o1 * o2 + 2 * c8)
+        # x down pass + the three kinetic parts -> dense output box
+        add("back_x", sz * (q + kx + ky + kz + 8 * o0 * o1 * o2),
+            2 * 2 * 4 * o1 * o2 * _count_down(n0, e) + 3 * 8 * o0 * o1 * o2)
+        # dense output box -> compressed output pattern
+        add("pack_out", sz * 2 * nout, 0)
     return out
 
 
@@ -295,26 +297,24 @@ def main():
     fine_pts = sum(int((2 * r["dims"][0] + 29) * (2 * r["dims"][1] + 29) * (2 * r["dims"][2] + 29))
                    for r in S["lr"])
     model = work_model(S["lr"], sz)
-    # sparse values: one read of the coefficients each for S, phi + H phi for H
+    # S and H values: phi (and H phi) read once, CSR indices read, values written
     info = S["plan"].info
-    model["sparse_values"] = (sz * (2 * info["in_coefs"] + info["out_coefs"]),
-                              2.0 * (S["nnz_s"] + S["nnz_h"]))
+    model["sparse_s"] = (sz * info["in_coefs"] + 16.0 * S["nnz_s"], 0.0)
+    model["sparse_h"] = (sz * (info["in_coefs"] + info["out_coefs"]) + 16.0 * S["nnz_h"], 0.0)
     kernels = {}
     for k, (n, ms) in prof.items():
         if n:
             per_launch = ms / n
-            launches_per_step = n / args.steps
             b, f = model.get(k, (0.0, 0.0))
-            b /= max(1.0, launches_per_step) if k == "sparse_values" else 1.0
             kernels[k] = {"launches": n, "avg_ms": per_launch,
+                          "ms_per_step": ms / args.steps,
                           "gbps": (b / (per_launch * 1e-3) / 1e9) if b else None,
                           "tflops": (f / (per_launch * 1e-3) / 1e12) if f else None}
     roofline = None
     if kernels:
-        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        # dominant kernel: the largest share of a step
+        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         b, f = model.get(dom, (0.0, 0.0))
-        if dom == "sparse_values":
-            b /= 2.0
         avg = kernels[dom]["avg_ms"] * 1e-3
         peak_f = FP32_PEAK_TFLOPS if args.dtype == "f32" else FP64_PEAK_TFLOPS
         ridge = peak_f * 1e12 / (HBM_PEAK_GBPS * 1e9)

@@ -20,11 +20,12 @@ using namespace wvl;
 // kernel kinds for tracing
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
-  KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE, KK_COUNT
+  KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
+  KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "fwd_plane", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
-    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_values"};
+    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -951,7 +952,7 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
                                 ctx->stream));
   if (val && pc.nnz) {
     if (!bra_c || !ket_c) return fail(ctx, WVL_EINVAL, "wvl_sparse_overlap: null bra or ket");
-    WVL_LAUNCH(ctx, KK_SPARSE,
+    WVL_LAUNCH(ctx, ket_is_output ? KK_SPARSE_H : KK_SPARSE_S,
                launch_sparse_values(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt,
                                     ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.nnz, val));
   }
