@@ -122,7 +122,21 @@ struct PatternCache {
   int64_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;
   int32_t* d_row = nullptr;
+  int32_t* d_order = nullptr;   // processing order of the pairs (CSR positions)
 };
+
+// 3D Morton code of a non-negative grid point (10 bits per axis)
+inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint32_t v) {
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000ff;
+    v = (v | (v << 8)) & 0x0300f00f;
+    v = (v | (v << 4)) & 0x030c30c3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
 
 }  // namespace
 
@@ -511,6 +525,7 @@ static void free_pattern(PatternCache& p) {
   if (p.d_rowptr) (void)hipFree(p.d_rowptr);
   if (p.d_col) (void)hipFree(p.d_col);
   if (p.d_row) (void)hipFree(p.d_row);
+  if (p.d_order) (void)hipFree(p.d_order);
   p = PatternCache{};
 }
 
@@ -927,6 +942,36 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
       return fail(ctx, WVL_EDEVICE, "pattern upload failed: %s", hipGetErrorString(e));
     }
   }
+  // Value pairs are processed row by row in the Morton order of the rows'
+  // box centres, so that concurrently running pairs share bra and ket data
+  // in the caches (the values land at their CSR positions regardless).
+  if (nnz > 0) {
+    if (nnz > INT32_MAX) {
+      free_pattern(pc);
+      return fail(ctx, WVL_EUNSUPPORTED, "pattern with %lld pairs exceeds 2^31", (long long)nnz);
+    }
+    std::vector<std::pair<uint32_t, int>> key(nsf);
+    for (int a = 0; a < nsf; ++a) {
+      const SfDev& S = P->h_sf[a];
+      key[a] = {morton3((uint32_t)(S.lo[0] + S.n[0] / 2), (uint32_t)(S.lo[1] + S.n[1] / 2),
+                        (uint32_t)(S.lo[2] + S.n[2] / 2)), a};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> order;
+    order.reserve(nnz);
+    for (const auto& kv : key)
+      for (int64_t q = rowptr[kv.second]; q < rowptr[kv.second + 1]; ++q)
+        order.push_back((int32_t)q);
+    if ((st = upload(ctx, &pc.d_order, order.data(), sizeof(int32_t) * nnz)) != WVL_OK) {
+      free_pattern(pc);
+      return st;
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      free_pattern(pc);
+      return fail(ctx, WVL_EDEVICE, "pattern order upload failed: %s", hipGetErrorString(e));
+    }
+  }
   pc.nnz = nnz;
   pc.ready = true;
   return WVL_OK;
@@ -954,7 +999,8 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
     if (!bra_c || !ket_c) return fail(ctx, WVL_EINVAL, "wvl_sparse_overlap: null bra or ket");
     WVL_LAUNCH(ctx, ket_is_output ? KK_SPARSE_H : KK_SPARSE_S,
                launch_sparse_values(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt,
-                                    ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.nnz, val));
+                                    ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.d_order,
+                                    pc.nnz, val));
   }
   return WVL_OK;
 }

@@ -97,6 +97,7 @@ int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int3
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                          const int32_t* rt, int ket_out, const void* bra, const void* ket,
-                         const int32_t* row, const int32_t* col, int64_t nnz, double* val);
+                         const int32_t* row, const int32_t* col, const int32_t* order,
+                         int64_t nnz, double* val);
 
 }  // namespace wvl

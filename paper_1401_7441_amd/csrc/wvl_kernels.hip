@@ -219,10 +219,18 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
                                                       const T* __restrict__ ket,
                                                       const int32_t* __restrict__ rowi,
                                                       const int32_t* __restrict__ coli,
-                                                      double* __restrict__ val) {
+                                                      const int32_t* __restrict__ order,
+                                                      int64_t nnz, double* __restrict__ val) {
   __shared__ int64_t ea[2][64], eb[2][64];   // run start offsets (bra, ket) per kind
   __shared__ int32_t el[2][64];              // run lengths (0: none)
-  const int64_t k = blockIdx.x;
+  // Workgroups are dealt to the 8 XCDs in turn: block b runs on XCD b % 8.
+  // Each XCD walks its own contiguous eighth of the processing order, so the
+  // pairs resident on one XCD share rows (and, rows being in spatial order,
+  // most of their kets) in that XCD's L2.
+  const int64_t per = (nnz + 7) / 8;
+  const int64_t s = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (s >= nnz) return;
+  const int64_t k = order[s];
   const int lane = threadIdx.x;
   const int grp = lane >> 4, gl = lane & 15;
   const SfDev& A = sfs[rowi[k]];
@@ -360,16 +368,18 @@ int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int3
 
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                          const int32_t* rt, int ket_out, const void* bra, const void* ket,
-                         const int32_t* row, const int32_t* col, int64_t nnz, double* val) {
+                         const int32_t* row, const int32_t* col, const int32_t* order,
+                         int64_t nnz, double* val) {
   if (nnz == 0) return 0;
+  const unsigned nblk = (unsigned)(8 * ((nnz + 7) / 8));
   if (f64)
-    hipLaunchKernelGGL(k_sparse_values<double>, dim3((unsigned)nnz), dim3(64), 0,
-                       (hipStream_t)stream, sf, seg, rt, ket_out, (const double*)bra,
-                       (const double*)ket, row, col, val);
+    hipLaunchKernelGGL(k_sparse_values<double>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
+                       seg, rt, ket_out, (const double*)bra, (const double*)ket, row, col, order,
+                       nnz, val);
   else
-    hipLaunchKernelGGL(k_sparse_values<float>, dim3((unsigned)nnz), dim3(64), 0,
-                       (hipStream_t)stream, sf, seg, rt, ket_out, (const float*)bra,
-                       (const float*)ket, row, col, val);
+    hipLaunchKernelGGL(k_sparse_values<float>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
+                       seg, rt, ket_out, (const float*)bra, (const float*)ket, row, col, order,
+                       nnz, val);
   return (int)hipGetLastError();
 }
 
