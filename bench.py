@@ -35,6 +35,9 @@ WORKLOAD_TEXT = {
                "h = 0.45 bohr, fine radius 3.5 bohr, L' margin 8; one H apply + S + H per step",
     "gpu16k": "16,000 support functions, centres uniform in a 110 bohr cube, R ~ U(5,7) bohr, "
               "h = 0.45 bohr, fine radius 3.5 bohr, L' margin 8; one H apply + S + H per step",
+    "sweep2k": "2,000 support functions, cubic boxes of edge E ~ U{16..48} coarse points, "
+               "R = (E-1) h / 2, fine radius min(3.5, R) bohr, 0.012 centres per bohr^3, "
+               "h = 0.45 bohr, L' margin 8; one H apply + S + H per step",
     "single": "one support function, 20^3 coarse box at h = 0.5 bohr, fine region the inner 10^3",
 }
 
@@ -244,11 +247,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch1k", choices=["batch1k", "gpu16k"])
+    ap.add_argument("--workload", default="batch1k", choices=["batch1k", "gpu16k", "sweep2k"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true",
-                    help="do not bracket kernels with events during the timed steps")
+                    help="skip the traced eager pass (no per-kernel times, no roofline)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager library calls instead of replays of the captured step")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the plan's default schedule (one bin, largest row tiles)")
+    ap.add_argument("--autotune-reps", type=int, default=2)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -274,21 +282,39 @@ def main():
     log(f"set-up done: {nsf} functions, locregs {S['t_locreg']:.2f} s, patterns "
         f"{S['t_pattern'] * 1e3:.1f} ms (S nnz {S['nnz_s']}, H nnz {S['nnz_h']}), "
         f"workspace {S['ws'].numel() / 2**30:.2f} GiB")
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        best, tried = W.autotune(S["plan"], S["psi"], S["pot"], S["hpsi"], S["ws"],
+                                 reps=args.autotune_reps)
+        tune = {"best": best, "tried": tried, "seconds": time.perf_counter() - t0}
+        log(f"autotune: {best} ({len(tried)} layouts, {tune['seconds']:.1f} s)")
+    graph = None
+    if not args.eager:
+        graph = W.Graph(S["plan"], S["psi"], S["pot"], S["hpsi"], S["ek"], S["ep"],
+                        workspace=S["ws"], s_val=S["s_out"][2], h_val=S["h_out"][2])
+    run = graph.launch if graph is not None else (lambda: step(S))
     for _ in range(args.warmup):
-        step(S)
-    torch.cuda.synchronize()
-    ctx = S["ctx"]
-    if not args.no_trace:
-        ctx.profile(True)
-        ctx.profile_reset()
+        run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(S)
+        run()
     torch.cuda.synchronize()
     dt_s = time.perf_counter() - t0
+    # per-kernel times: library events around every launch of K eager steps
+    ctx = S["ctx"]
     prof = {}
+    eager_ms = None
     if not args.no_trace:
+        ctx.profile(True)
+        ctx.profile_reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step(S)
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - t1) * 1e3 / args.steps
         prof = ctx.profile_read()
         ctx.profile(False)
     ms_step = dt_s * 1e3 / args.steps
@@ -304,17 +330,21 @@ def main():
     kernels = {}
     for k, (n, ms) in prof.items():
         if n:
-            per_launch = ms / n
             b, f = model.get(k, (0.0, 0.0))
-            kernels[k] = {"launches": n, "avg_ms": per_launch,
+            step_s = ms * 1e-3 / args.steps          # this kind's time per step
+            kernels[k] = {"launches": n, "avg_ms": ms / n,
                           "ms_per_step": ms / args.steps,
-                          "gbps": (b / (per_launch * 1e-3) / 1e9) if b else None,
-                          "tflops": (f / (per_launch * 1e-3) / 1e12) if f else None}
+                          "gbps": (b / step_s / 1e9) if b else None,
+                          "tflops": (f / step_s / 1e12) if f else None}
     roofline = None
     if kernels:
-        # dominant kernel: the largest share of a step
+        # dominant kernel: the largest share of a step.  A kind launches once
+        # per chunk; the model's bytes and flops are per step, so per launch
+        # they are divided by the launches per step.
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
         b, f = model.get(dom, (0.0, 0.0))
+        per_step = kernels[dom]["launches"] / args.steps
+        b, f = b / per_step, f / per_step
         avg = kernels[dom]["avg_ms"] * 1e-3
         peak_f = FP32_PEAK_TFLOPS if args.dtype == "f32" else FP64_PEAK_TFLOPS
         ridge = peak_f * 1e12 / (HBM_PEAK_GBPS * 1e9)
@@ -329,7 +359,8 @@ def main():
         roofline["algorithmic_bytes_per_launch"] = b
         roofline["flops_per_launch"] = f
         roofline["avg_launch_ms"] = kernels[dom]["avg_ms"]
-        roofline["traffic"] = load_traffic(dom, args.workload, args.dtype)
+        tr = load_traffic(dom, args.workload, args.dtype)   # measured on a one-chunk layout
+        roofline["traffic"] = tr / per_step if tr is not None else None
     pb = path_bytes(S["lr"], sz)
     res = {
         "metric": "support-function H-applies/s (fine grid pts/s, % HBM peak); p50/p99 request "
@@ -354,6 +385,14 @@ def main():
                      "frac": pb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS},
         "roofline": roofline,
         "kernels": kernels,
+        "kernel_timing": "HIP events the library records around each launch on its stream, "
+                         "over a separate pass of the same number of eager steps",
+        "schedule": {"timed": "graph replay" if graph is not None else "eager calls",
+                     "eager_ms_per_step": eager_ms,
+                     "nbins": tune["best"]["nbins"] if tune else 1,
+                     "tile_div": tune["best"]["tile_div"] if tune else 1,
+                     "chunks": S["plan"].info["chunks"],
+                     "autotune": tune},
         "setup": {"locregs_s": S["t_locreg"], "patterns_ms": S["t_pattern"] * 1e3},
         "source_hash": source_hash(),
     }

@@ -209,6 +209,48 @@ wvl_status wvl_sparse_overlap(wvl_plan* plan, const void* bra_c, int ket_is_outp
                               const void* ket_c, wvl_dtype dt, int64_t* nnz, int64_t* rowptr,
                               int32_t* col, double* val);
 
+/* Batching of uneven boxes (Sec. III.B: each function is worked on inside
+ * its own localization region only).  A plan sorts the functions by box
+ * volume and cuts them into bins; every bin runs each stage as one launch
+ * over all its functions.  Without a workspace bound the bins use disjoint
+ * workspace regions and are independent.
+ *
+ * wvl_graph_create captures one step into a HIP graph: the local-H apply of
+ * every function (independent bins as parallel branches, on streams the plan
+ * owns), then, when s_val / h_val are non-NULL, the overlap values (bra =
+ * ket = psi_c) and the Hamiltonian values (bra psi_c, ket hpsi_c) on the
+ * plan's patterns, in the CSR order wvl_sparse_overlap reports.  Arguments
+ * are those of wvl_apply_local_ham; every buffer must stay valid while the
+ * graph lives.  Patterns are built before the capture (this synchronizes).
+ * wvl_graph_launch enqueues the graph on the context's stream; results are
+ * bitwise identical to the eager calls.  A graph taken before
+ * wvl_plan_autotune changed the plan's layout is rejected (WVL_EINVAL).
+ * Errors: WVL_EINVAL for bad arguments, WVL_EDEVICE for HIP failures. */
+typedef struct wvl_graph wvl_graph;
+wvl_status wvl_graph_create(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                            const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                            void* workspace, double* s_val, double* h_val, wvl_graph** graph);
+wvl_status wvl_graph_launch(wvl_graph* graph);
+void wvl_graph_destroy(wvl_graph* graph);
+
+/* Autotuner over the plan's schedule: for every bin count in {1, 2, 4, 8}
+ * and k_fwd_plane row-tile divisor in {1, 2, 4}, runs the apply `reps` times
+ * (after one warm-up) and keeps the fastest layout.  Buffers as for wvl_apply_local_ham (hpsi_c is overwritten; the
+ * workspace is the size wvl_plan_create reported, which covers every
+ * candidate).  tried (host, may be NULL) receives up to max_tried points,
+ * *ntried the number timed, *best the chosen one.  Synchronous; the plan
+ * must not be in use on another stream meanwhile.  Results of later calls
+ * do not depend on the layout chosen (bitwise). */
+typedef struct {
+  int32_t nbins;      /* bins of the size-sorted functions */
+  int32_t tile_div;   /* k_fwd_plane row tile = largest that fits / tile_div */
+  double ms;          /* mean duration of one apply */
+} wvl_tune_point;
+wvl_status wvl_plan_autotune(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                             const void* pot, void* hpsi_c, void* workspace, int32_t reps,
+                             wvl_tune_point* tried, int32_t max_tried, int32_t* ntried,
+                             wvl_tune_point* best);
+
 /* Kernel tracing.  With profiling enabled, every kernel the context launches
  * is bracketed by two HIP events recorded on the context's stream; times
  * are aggregated per kernel kind.  wvl_profile_read synchronizes the stream,

@@ -43,6 +43,7 @@ LOCREG_DTYPE = np.dtype([
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
             "wvl_compress", "wvl_apply_local_ham", "wvl_kinetic", "wvl_sparse_overlap",
+            "wvl_graph_create", "wvl_graph_launch", "wvl_graph_destroy", "wvl_plan_autotune",
             "wvl_profile_enable", "wvl_profile_reset", "wvl_profile_count", "wvl_profile_read")
 
 
@@ -54,6 +55,10 @@ class WvlError(RuntimeError):
 
 class _Grid(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("n", ctypes.c_int32 * 3)]
+
+
+class _TunePoint(ctypes.Structure):
+    _fields_ = [("nbins", ctypes.c_int32), ("tile_div", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -94,6 +99,11 @@ def _load():
         "wvl_apply_local_ham": [P, ctypes.c_int, U32, P, P, P, P, P, P],
         "wvl_kinetic": [P, ctypes.c_int, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
+        "wvl_graph_create": [P, ctypes.c_int, U32, P, P, P, P, P, P, P, P, ctypes.POINTER(P)],
+        "wvl_graph_launch": [P],
+        "wvl_graph_destroy": [P],
+        "wvl_plan_autotune": [P, ctypes.c_int, U32, P, P, P, P, I32, ctypes.POINTER(_TunePoint),
+                              I32, ctypes.POINTER(I32), ctypes.POINTER(_TunePoint)],
         "wvl_profile_enable": [P, ctypes.c_int],
         "wvl_profile_reset": [P],
         "wvl_profile_count": [],
@@ -106,6 +116,7 @@ def _load():
         fn.restype = ctypes.c_int
     lib.wvl_destroy.restype = None
     lib.wvl_plan_destroy.restype = None
+    lib.wvl_graph_destroy.restype = None
     lib.wvl_last_error.restype = ctypes.c_char_p
     return lib
 
@@ -245,9 +256,12 @@ class Plan:
         _check(lib().wvl_plan_create(ctx.handle, len(self.locregs), self.locregs.ctypes.data,
                                     self.segs.ctypes.data, len(self.segs), int(max_workspace),
                                     ctypes.byref(self._ptr), ctypes.byref(ws)), ctx.handle)
+        self.info = self._read_info()
+
+    def _read_info(self):
         info = _PlanInfo()
-        _check(lib().wvl_plan_info_get(self._ptr, ctypes.byref(info)), ctx.handle)
-        self.info = {k: int(getattr(info, k)) for k, _ in _PlanInfo._fields_}
+        _check(lib().wvl_plan_info_get(self._ptr, ctypes.byref(info)), self.ctx.handle)
+        return {k: int(getattr(info, k)) for k, _ in _PlanInfo._fields_}
 
     @property
     def nsf(self):
@@ -360,3 +374,61 @@ def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None):
                                    dt, ctypes.byref(n), _ptr(rowptr), _ptr(col), _ptr(val)),
            plan.ctx.handle)
     return rowptr, col[:nnz], val[:nnz]
+
+
+class Graph:
+    """One captured step (wvl_graph_create): the local-H apply of every
+    function, then optionally the S values (into s_val) and the H values
+    (into h_val) on the plan's patterns.  The tensors passed here must stay
+    alive while the graph does; launch() replays the step on the context's
+    stream."""
+
+    def __init__(self, plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None, workspace=None,
+                 s_val=None, h_val=None, terms=KIN | POT):
+        _need_cuda(psi_c, pot, hpsi_c, e_kin, e_pot, workspace, s_val, h_val)
+        dt = _dtype_code(psi_c, pot, hpsi_c)
+        _check_sizes(plan, psi_c, hpsi_c, e_kin, e_pot, workspace, dt)
+        for v, ket_out in ((s_val, False), (h_val, True)):
+            if v is not None and (v.dtype.itemsize != 8 or
+                                  v.numel() < sparse_pattern_nnz(plan, ket_out)):
+                raise WvlError(WVL_EINVAL, "S/H value buffers must be float64 with nnz entries")
+        if workspace is None:
+            raise WvlError(WVL_EINVAL, "a graph needs an explicit workspace tensor")
+        self.plan = plan
+        self._keep = (psi_c, pot, hpsi_c, e_kin, e_pot, workspace, s_val, h_val)
+        h = ctypes.c_void_p()
+        _check(lib().wvl_graph_create(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
+                                      _ptr(hpsi_c), _ptr(e_kin), _ptr(e_pot), _ptr(workspace),
+                                      _ptr(s_val), _ptr(h_val), ctypes.byref(h)),
+               plan.ctx.handle)
+        self._ptr = h
+
+    def launch(self):
+        _check(lib().wvl_graph_launch(self._ptr), self.plan.ctx.handle)
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            lib().wvl_graph_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(plan: Plan, psi_c, pot, hpsi_c, workspace, reps=3, terms=KIN | POT):
+    """wvl_plan_autotune -> (best, tried): dicts {nbins, tile_div, ms}."""
+    _need_cuda(psi_c, pot, hpsi_c, workspace)
+    dt = _dtype_code(psi_c, pot, hpsi_c)
+    _check_sizes(plan, psi_c, hpsi_c, None, None, workspace, dt)
+    tried = (_TunePoint * 32)()
+    n = ctypes.c_int32(0)
+    best = _TunePoint()
+    _check(lib().wvl_plan_autotune(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
+                                   _ptr(hpsi_c), _ptr(workspace), int(reps), tried, 32,
+                                   ctypes.byref(n), ctypes.byref(best)), plan.ctx.handle)
+    as_dict = lambda t: {"nbins": t.nbins, "tile_div": t.tile_div, "ms": t.ms}
+    plan.info = plan._read_info()
+    return as_dict(best), [as_dict(tried[i]) for i in range(n.value)]

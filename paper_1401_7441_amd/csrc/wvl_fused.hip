@@ -103,8 +103,8 @@ __global__ __launch_bounds__(256) void k_fwd_plane(const SfDev* __restrict__ sfs
                                                    T* __restrict__ ws, int tile_rows, int up_on) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
-  const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2];
   const int R0 = 2 * N0 + 29, R1 = 2 * N1 + 29;
   const int ntile = (R1 + tile_rows - 1) / tile_rows;
@@ -213,8 +213,8 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
                                                     T* __restrict__ ws, const T* __restrict__ pot,
                                                     int nf1, int nf2,
                                                     double* __restrict__ epart) {
-  const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int R0 = 2 * N0 + 29, R1 = 2 * N1 + 29, R2 = 2 * N2 + 29;
   const int O2 = N2 + 2 * e;
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
     const SfDev* __restrict__ sfs, const SfWork* __restrict__ wk, int sf0, T* __restrict__ ws,
     double fac, double* __restrict__ kpart) {
   __shared__ T st[AX == 1 ? 2 * 16 * kSP : 1];   // AX = 1: [a][16 outputs][kSP]
-  const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int64_t plane = (int64_t)N0 * N1;
   const int NA = AX == 2 ? N2 : AX == 1 ? N1 : N0;
@@ -447,8 +447,8 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
                                                const SfWork* __restrict__ wk, int sf0,
                                                T* __restrict__ ws) {
   __shared__ T st[2 * 16 * kSP];
-  const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int R0 = 2 * N0 + 29, R1 = 2 * N1 + 29;
   const int O1 = N1 + 2 * e, O2 = N2 + 2 * e;
@@ -534,8 +534,8 @@ __global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
                                                const SfWork* __restrict__ wk, int sf0,
                                                T* __restrict__ ws, int pot_on, int kin_on) {
   __shared__ T st[2 * 16 * kSP];
-  const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int R0 = 2 * N0 + 29;
   const int O0 = N0 + 2 * e, O1 = N1 + 2 * e, O2 = N2 + 2 * e;
@@ -658,8 +658,8 @@ __global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
                                                   int accumulate) {
   __shared__ int s_off[kPackSegs + 1];   // coefficient offset relative to the first segment
   __shared__ int s_ob[kPackSegs];        // OB index of the segment's first point (component 0)
-  const SfDev& sf = sfs[sf0 + blockIdx.y];
   const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
   const int e = sf.ext;
   const int O0 = sf.n[0] + 2 * e, O1 = sf.n[1] + 2 * e, O2 = sf.n[2] + 2 * e;
   const int64_t nrows = (int64_t)O2 * O1;
@@ -704,6 +704,27 @@ __global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+// Loads the code objects of every kernel an apply may launch (and with them
+// the filter tables in constant memory), so that no lazy load happens while
+// a stream is being captured.
+int preload_fused_kernels() {
+  const void* fns[] = {
+      (const void*)k_fwd_plane<float>,      (const void*)k_fwd_plane<double>,
+      (const void*)k_pot_column<float>,     (const void*)k_pot_column<double>,
+      (const void*)k_kin_col<float, 0>,     (const void*)k_kin_col<float, 1>,
+      (const void*)k_kin_col<float, 2>,     (const void*)k_kin_col<double, 0>,
+      (const void*)k_kin_col<double, 1>,    (const void*)k_kin_col<double, 2>,
+      (const void*)k_back_y<float>,         (const void*)k_back_y<double>,
+      (const void*)k_back_x<float>,         (const void*)k_back_x<double>,
+      (const void*)k_pack_out<float>,       (const void*)k_pack_out<double>};
+  for (const void* f : fns) {
+    hipFuncAttributes a;
+    const hipError_t e = hipFuncGetAttributes(&a, f);
+    if (e != hipSuccess) return (int)e;
+  }
+  return 0;
+}
 
 int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                      const int32_t* rt, const void* psi, const SfWork* wk, int sf0, int nsf,

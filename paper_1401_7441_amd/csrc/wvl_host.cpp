@@ -6,6 +6,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <new>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -140,14 +141,41 @@ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 
 }  // namespace
 
+// Workspace layout of a plan: the functions in processing order (sorted by
+// box volume, largest first), cut into `nbins` bins of equal count; a bin is
+// split further into chunks when a workspace bound is given.  Without a
+// bound every chunk has its own workspace region (chunks are independent and
+// may run concurrently); with one, chunks reuse the region one after the
+// other.
+struct Layout {
+  std::vector<ChunkDev> chunks;
+  std::vector<SfWork> wk;        // per position of the processing order
+  bool disjoint = true;
+  int nbins = 1, tile_div = 1;
+  int64_t elems_span = 0;        // elements of the compute type before the partials
+  int64_t parts_span = 0;        // doubles of energy partials
+  int64_t bytes(int sz) const { return align_bytes(elems_span * sz) + parts_span * 8; }
+};
+
+struct wvl_graph {
+  wvl_plan* plan = nullptr;
+  int64_t layout_version = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipEvent_t> events;   // fork/join events of the capture, kept with the graph
+};
+
 struct wvl_plan {
   wvl_ctx* ctx = nullptr;
   int nsf = 0;
   std::vector<SfDev> h_sf;
-  std::vector<SfWork> h_wk;
-  std::vector<ChunkDev> chunks;
-  std::vector<int64_t> chunk_elems;   // elements of the compute type per chunk
-  std::vector<int64_t> chunk_parts;   // doubles of partials per chunk
+  std::vector<int32_t> order;         // processing position -> function index
+  std::vector<int64_t> nsegs_out;     // output segments (coarse + fine) per function
+  size_t max_ws = 0;                  // the caller's workspace bound (0: none)
+  Layout lay;
+  int64_t ws_cap[2] = {0, 0};         // workspace bytes reported (F32, F64)
+  std::vector<hipStream_t> streams;   // branch streams of captured graphs
+  int64_t layout_version = 0;         // bumped when the autotuner changes the layout
   SfDev* d_sf = nullptr;
   wvl_seg* d_seg = nullptr;
   int32_t* d_rt = nullptr;
@@ -537,7 +565,142 @@ void wvl_plan_destroy(wvl_plan* plan) {
   if (plan->d_wk) (void)hipFree(plan->d_wk);
   free_pattern(plan->pat[0]);
   free_pattern(plan->pat[1]);
+  for (hipStream_t st : plan->streams) (void)hipStreamDestroy(st);
   delete plan;
+}
+
+// bin counts the autotuner tries (the plan's workspace covers all of them)
+static const int kTuneBins[] = {1, 2, 4, 8};
+
+static int64_t sf_elems(const SfDev& S) {
+  const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
+  const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
+  const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
+  return 2 * align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) + align64(2 * o2 * r0 * r1) +
+         align64(4 * o2 * r0 * o1) + align64(8 * n2 * o0 * n1) + align64(8 * n2 * o1 * n0) +
+         align64(8 * o2 * n0 * n1) + align64(8 * o0 * o1 * o2);
+}
+
+// Builds the layout for `nbins` bins and fwd_plane row tiles divided by
+// `tile_div`; false (with a message) when some box does not fit the LDS tiles.
+static bool make_layout(const wvl_plan* P, int nbins, int tile_div, Layout* L, std::string* err) {
+  const int nsf = P->nsf;
+  L->chunks.clear();
+  L->wk.assign(nsf, SfWork{});
+  L->nbins = nbins;
+  L->tile_div = tile_div;
+  L->disjoint = P->max_ws == 0;
+  L->elems_span = 0;
+  L->parts_span = 0;
+  nbins = std::max(1, std::min(nbins, nsf));
+  int64_t ebase = 0, pbase = 0;   // running offsets (disjoint layouts)
+  for (int bin = 0; bin < nbins; ++bin) {
+    const int b0 = (int)((int64_t)nsf * bin / nbins), b1 = (int)((int64_t)nsf * (bin + 1) / nbins);
+    int k = b0;
+    while (k < b1) {
+      ChunkDev ch{};
+      ch.sf0 = k;
+      int64_t elems = 0;
+      int j = k;
+      for (; j < b1; ++j) {
+        const int64_t need = sf_elems(P->h_sf[P->order[j]]);
+        // partial slots are at most a few per 256 output points
+        const int64_t bytes = align_bytes((elems + need) * 8) + (int64_t)(j - k + 1) * 4096 * 8;
+        if (j > k && P->max_ws > 0 && (size_t)bytes > P->max_ws) break;
+        if (j - k >= 65535) break;
+        elems += need;
+      }
+      ch.nsf = j - k;
+      int64_t off = L->disjoint ? ebase : 0;
+      const int64_t off0 = off;
+      for (int q = k; q < j; ++q) {
+        const int id = P->order[q];
+        const SfDev& S = P->h_sf[id];
+        const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
+        const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
+        const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
+        SfWork& W = L->wk[q];
+        W.id = id;
+        W.c8 = off;  off += align64(8 * n0 * n1 * n2);
+        W.c8x = off; off += align64(8 * n0 * n1 * n2);
+        W.g1 = off;  off += align64(2 * n2 * r0 * r1);
+        W.g2 = off;  off += align64(2 * o2 * r0 * r1);
+        W.q = off;   off += align64(4 * o2 * r0 * o1);
+        W.ox = off;  off += align64(8 * n2 * o0 * n1);
+        W.oy = off;  off += align64(8 * n2 * o1 * n0);
+        W.oz = off;  off += align64(8 * o2 * n0 * n1);
+        W.ob = off;  off += align64(8 * o0 * o1 * o2);
+        ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
+        ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
+        ch.maxsegs_out = std::max<int64_t>(ch.maxsegs_out, P->nsegs_out[id]);
+        ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
+        ch.grid_kx = std::max(ch.grid_kx, kin_blocks(0, (int)n0, (int)n1, (int)n2));
+        ch.grid_ky = std::max(ch.grid_ky, kin_blocks(1, (int)n0, (int)n1, (int)n2));
+        ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2));
+        ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
+        ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, ((4 * o1 + 63) / 64) * o2);
+      }
+      for (int d = 0; d < 2; ++d) {
+        const int64_t sz = d ? 8 : 4;
+        // k_fwd_plane: the largest row tile (of fine output rows) that fits,
+        // divided by tile_div
+        int64_t r1max = 0;
+        for (int q = k; q < j; ++q) r1max = std::max<int64_t>(r1max, 2 * P->h_sf[P->order[q]].n[1] + 29);
+        auto lds_f = [&](int64_t T) {
+          int64_t m = 0;
+          for (int q = k; q < j; ++q) {
+            const SfDev& S = P->h_sf[P->order[q]];
+            const int64_t ny = std::min<int64_t>(S.n[1], T / 2 + 17);
+            m = std::max<int64_t>(m, (4 * ny * S.n[0] + 2 * ny * (2 * S.n[0] + 29)) * sz);
+          }
+          return m;
+        };
+        int64_t tf = r1max;
+        while (tf > 2 && lds_f(tf) > kLdsBudget) tf = (tf + 1) / 2;
+        tf = std::max<int64_t>(2, tf / std::max(1, tile_div));
+        ch.tile_f[d] = (int32_t)tf;
+        ch.lds_f[d] = lds_f(tf);
+        int64_t gf = 0;
+        for (int q = k; q < j; ++q) {
+          const SfDev& S = P->h_sf[P->order[q]];
+          gf = std::max<int64_t>(gf, (int64_t)S.n[2] * 2 * ((2 * S.n[1] + 29 + tf - 1) / tf));
+        }
+        ch.grid_f[d] = (int32_t)gf;
+        if (ch.lds_f[d] > kLdsBudget) {
+          char buf[160];
+          snprintf(buf, sizeof buf, "functions %d..%d (processing order): boxes too large for "
+                   "the LDS tiles", k, j - 1);
+          *err = buf;
+          return false;
+        }
+      }
+      ch.nblk_pot = ch.grid_b;
+      ch.nblk_kin = ch.grid_kx + ch.grid_ky + ch.grid_kz;
+      int64_t poff = L->disjoint ? pbase : 0;
+      for (int q = k; q < j; ++q) {
+        const SfDev& S = P->h_sf[P->order[q]];
+        SfWork& W = L->wk[q];
+        W.epart = poff;
+        poff += ch.nblk_pot;
+        W.kpart = poff;
+        W.nkpart = kin_blocks(0, S.n[0], S.n[1], S.n[2]) + kin_blocks(1, S.n[0], S.n[1], S.n[2]) +
+                   kin_blocks(2, S.n[0], S.n[1], S.n[2]);
+        poff += ch.nblk_kin;
+      }
+      L->chunks.push_back(ch);
+      if (L->disjoint) {
+        ebase = off;
+        pbase = poff;
+        L->elems_span = ebase;
+        L->parts_span = pbase;
+      } else {
+        L->elems_span = std::max(L->elems_span, off - off0);
+        L->parts_span = std::max(L->parts_span, poff);
+      }
+      k = j;
+    }
+  }
+  return true;
 }
 
 wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, const wvl_seg* segs,
@@ -608,7 +771,6 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   P->ctx = ctx;
   P->nsf = nsf;
   P->h_sf.resize(nsf);
-  P->h_wk.resize(nsf);
   std::vector<int32_t> rt;
   int64_t box_in = 0, box_out = 0, in_coefs = 0, out_coefs = 0;
   for (int k = 0; k < nsf; ++k) {
@@ -644,110 +806,31 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
     bbox(segs, L.seg_c, L.nseg_c, S.bb_in);
     bbox(segs, L.oseg_c, L.noseg_c, S.bb_out);
   }
-  // chunks and workspace layout
-  auto sf_elems = [&](const SfDev& S) {
-    const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
-    const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
-    const int64_t o1 = n1 + 2 * e, o2 = n2 + 2 * e;
-    const int64_t o0 = n0 + 2 * e;
-    return 2 * align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) +
-           align64(2 * o2 * r0 * r1) + align64(4 * o2 * r0 * o1) + align64(8 * n2 * o0 * n1) +
-           align64(8 * n2 * o1 * n0) + align64(8 * o2 * n0 * n1) + align64(8 * o0 * o1 * o2);
-  };
-  int64_t best_f32 = 0, best_f64 = 0;
-  {
-    int k = 0;
-    while (k < nsf) {
-      ChunkDev ch{};
-      ch.sf0 = k;
-      int64_t elems = 0;
-      int j = k;
-      for (; j < nsf; ++j) {
-        const int64_t need = sf_elems(P->h_sf[j]);
-        // partial slots are at most a few per 256 output points
-        const int64_t bytes = align_bytes((elems + need) * 8) + (int64_t)(j - k + 1) * 4096 * 8;
-        if (j > k && max_workspace_bytes > 0 && (size_t)bytes > max_workspace_bytes) break;
-        if (j - k >= 65535) break;
-        elems += need;
-      }
-      ch.nsf = j - k;
-      int64_t off = 0;
-      for (int q = k; q < j; ++q) {
-        const SfDev& S = P->h_sf[q];
-        const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
-        const int64_t r0 = 2 * n0 + 29, r1 = 2 * n1 + 29;
-        const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
-        SfWork& W = P->h_wk[q];
-        W.c8 = off;  off += align64(8 * n0 * n1 * n2);
-        W.c8x = off; off += align64(8 * n0 * n1 * n2);
-        W.g1 = off;  off += align64(2 * n2 * r0 * r1);
-        W.g2 = off;  off += align64(2 * o2 * r0 * r1);
-        W.q = off;   off += align64(4 * o2 * r0 * o1);
-        W.ox = off;  off += align64(8 * n2 * o0 * n1);
-        W.oy = off;  off += align64(8 * n2 * o1 * n0);
-        W.oz = off;  off += align64(8 * o2 * n0 * n1);
-        W.ob = off;  off += align64(8 * o0 * o1 * o2);
-        ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
-        ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
-        ch.maxsegs_out = std::max<int64_t>(ch.maxsegs_out, lr[q].noseg_c + lr[q].noseg_f);
-        ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
-        ch.grid_kx = std::max(ch.grid_kx, kin_blocks(0, (int)n0, (int)n1, (int)n2));
-        ch.grid_ky = std::max(ch.grid_ky, kin_blocks(1, (int)n0, (int)n1, (int)n2));
-        ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2));
-        ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
-        ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, ((4 * o1 + 63) / 64) * o2);
-      }
-      for (int d = 0; d < 2; ++d) {
-        const int64_t sz = d ? 8 : 4;
-        // k_fwd_plane: the largest row tile (of fine output rows) that fits
-        int64_t r1max = 0;
-        for (int q = k; q < j; ++q) r1max = std::max<int64_t>(r1max, 2 * P->h_sf[q].n[1] + 29);
-        auto lds_f = [&](int64_t T) {
-          int64_t m = 0;
-          for (int q = k; q < j; ++q) {
-            const SfDev& S = P->h_sf[q];
-            const int64_t ny = std::min<int64_t>(S.n[1], T / 2 + 17);
-            m = std::max<int64_t>(m, (4 * ny * S.n[0] + 2 * ny * (2 * S.n[0] + 29)) * sz);
-          }
-          return m;
-        };
-        int64_t tf = r1max;
-        while (tf > 2 && lds_f(tf) > kLdsBudget) tf = (tf + 1) / 2;
-        ch.tile_f[d] = (int32_t)tf;
-        ch.lds_f[d] = lds_f(tf);
-        int64_t gf = 0;
-        for (int q = k; q < j; ++q) {
-          const SfDev& S = P->h_sf[q];
-          gf = std::max<int64_t>(gf, (int64_t)S.n[2] * 2 * ((2 * S.n[1] + 29 + tf - 1) / tf));
-        }
-        ch.grid_f[d] = (int32_t)gf;
-        if (ch.lds_f[d] > kLdsBudget) {
-          wvl_plan_destroy(P);
-          return fail(ctx, WVL_EUNSUPPORTED, "functions %d..%d: boxes too large for the LDS tiles",
-                      k, j - 1);
-        }
-      }
-      ch.nblk_pot = ch.grid_b;
-      ch.nblk_kin = ch.grid_kx + ch.grid_ky + ch.grid_kz;
-      int64_t poff = 0;
-      for (int q = k; q < j; ++q) {
-        const SfDev& S = P->h_sf[q];
-        P->h_wk[q].epart = poff;
-        poff += ch.nblk_pot;
-        P->h_wk[q].kpart = poff;
-        P->h_wk[q].nkpart = kin_blocks(0, S.n[0], S.n[1], S.n[2]) +
-                            kin_blocks(1, S.n[0], S.n[1], S.n[2]) +
-                            kin_blocks(2, S.n[0], S.n[1], S.n[2]);
-        poff += ch.nblk_kin;
-      }
-      P->chunks.push_back(ch);
-      P->chunk_elems.push_back(off);
-      P->chunk_parts.push_back(poff);
-      best_f32 = std::max(best_f32, align_bytes(off * 4) + poff * 8);
-      best_f64 = std::max(best_f64, align_bytes(off * 8) + poff * 8);
-      k = j;
-    }
+  // processing order: largest boxes first, ties by index
+  P->order.resize(nsf);
+  P->nsegs_out.resize(nsf);
+  for (int k = 0; k < nsf; ++k) {
+    P->order[k] = k;
+    P->nsegs_out[k] = lr[k].noseg_c + lr[k].noseg_f;
   }
+  std::stable_sort(P->order.begin(), P->order.end(), [&](int a, int b) {
+    const SfDev &A = P->h_sf[a], &B = P->h_sf[b];
+    return (int64_t)A.n[0] * A.n[1] * A.n[2] > (int64_t)B.n[0] * B.n[1] * B.n[2];
+  });
+  P->max_ws = max_workspace_bytes;
+  // the workspace reported covers every layout the autotuner may pick
+  for (int nb : kTuneBins) {
+    Layout L;
+    std::string err;
+    if (!make_layout(P, nb, 1, &L, &err)) {
+      wvl_plan_destroy(P);
+      return fail(ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
+    }
+    P->ws_cap[0] = std::max(P->ws_cap[0], L.bytes(4));
+    P->ws_cap[1] = std::max(P->ws_cap[1], L.bytes(8));
+    if (nb == 1) P->lay = std::move(L);
+  }
+  const int64_t best_f32 = P->ws_cap[0], best_f64 = P->ws_cap[1];
   P->info.nsf = nsf;
   P->info.in_coefs = in_coefs;
   P->info.out_coefs = out_coefs;
@@ -755,11 +838,11 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   P->info.out_box = box_out;
   P->info.workspace_f32 = best_f32;
   P->info.workspace_f64 = best_f64;
-  P->info.chunks = (int64_t)P->chunks.size();
+  P->info.chunks = (int64_t)P->lay.chunks.size();
   if ((st = upload(ctx, &P->d_sf, P->h_sf.data(), sizeof(SfDev) * nsf)) != WVL_OK ||
       (st = upload(ctx, &P->d_seg, segs, sizeof(wvl_seg) * nsegs)) != WVL_OK ||
       (st = upload(ctx, &P->d_rt, rt.data(), sizeof(int32_t) * rt.size())) != WVL_OK ||
-      (st = upload(ctx, &P->d_wk, P->h_wk.data(), sizeof(SfWork) * nsf)) != WVL_OK) {
+      (st = upload(ctx, &P->d_wk, P->lay.wk.data(), sizeof(SfWork) * nsf)) != WVL_OK) {
     wvl_plan_destroy(P);
     return st;
   }
@@ -789,10 +872,15 @@ wvl_status wvl_uncompress(wvl_plan* P, wvl_dtype dt, const void* psi_c, void* ps
   wvl_ctx* ctx = P->ctx;
   if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
   if (P->nsf > 0 && (!psi_c || !psi_box)) return fail(ctx, WVL_EINVAL, "wvl_uncompress: null buffer");
-  for (const ChunkDev& ch : P->chunks)
+  for (int s0 = 0; s0 < P->nsf; s0 += 65535) {
+    const int n = std::min(65535, P->nsf - s0);
+    int64_t mv = 0;
+    for (int k = s0; k < s0 + n; ++k)
+      mv = std::max<int64_t>(mv, 8ll * P->h_sf[k].n[0] * P->h_sf[k].n[1] * P->h_sf[k].n[2]);
     WVL_LAUNCH(ctx, KK_GATHER,
                launch_gather(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, psi_c, psi_box,
-                             ch.sf0, ch.nsf, ch.maxbox_in));
+                             s0, n, mv));
+  }
   return WVL_OK;
 }
 
@@ -801,16 +889,25 @@ wvl_status wvl_compress(wvl_plan* P, wvl_dtype dt, const void* box, void* hpsi_c
   wvl_ctx* ctx = P->ctx;
   if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
   if (P->nsf > 0 && (!box || !hpsi_c)) return fail(ctx, WVL_EINVAL, "wvl_compress: null buffer");
-  for (const ChunkDev& ch : P->chunks)
+  for (int s0 = 0; s0 < P->nsf; s0 += 65535) {
+    const int n = std::min(65535, P->nsf - s0);
+    int64_t mv = 0;
+    for (int k = s0; k < s0 + n; ++k) {
+      const SfDev& S = P->h_sf[k];
+      mv = std::max<int64_t>(mv, 8ll * (S.n[0] + 2 * S.ext) * (S.n[1] + 2 * S.ext) *
+                                     (S.n[2] + 2 * S.ext));
+    }
     WVL_LAUNCH(ctx, KK_SCATTER,
                launch_scatter(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, box, hpsi_c,
-                              ch.sf0, ch.nsf, ch.maxbox_out));
+                              s0, n, mv));
+  }
   return WVL_OK;
 }
 
-static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
-                             const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
-                             void* workspace, int accumulate, const char* who) {
+// checks shared by the eager and the captured apply
+static wvl_status apply_args(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                             const void* pot, const void* hpsi_c, const void* workspace,
+                             const char* who) {
   if (!P) return fail(nullptr, WVL_EINVAL, "%s: null plan", who);
   wvl_ctx* ctx = P->ctx;
   if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
@@ -820,51 +917,64 @@ static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
   if (!psi_c || !hpsi_c || !workspace)
     return fail(ctx, WVL_EINVAL, "%s: null coefficient or workspace buffer", who);
   if ((terms & WVL_POT) && !pot) return fail(ctx, WVL_EINVAL, "%s: WVL_POT needs a potential", who);
-  const int f64 = dt == WVL_F64;
+  return WVL_OK;
+}
+
+// Enqueues the stages of chunk c on stream st.
+static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, const void* psi_c,
+                              const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                              void* workspace, int accumulate, hipStream_t st) {
+  wvl_ctx* ctx = P->ctx;
   const int sz = f64 ? 8 : 4;
+  const int d = f64 ? 1 : 0;
   const int nf1 = 2 * ctx->grid.n[0] + 29, nf2 = 2 * ctx->grid.n[1] + 29;
   const double fac = -2.0 / (ctx->grid.h * ctx->grid.h);   // -1/2 (2/h)^2
-  hipStream_t st = ctx->stream;
-  const int d = f64 ? 1 : 0;
   const int pot_on = (terms & WVL_POT) ? 1 : 0, kin_on = (terms & WVL_KIN) ? 1 : 0;
-  for (size_t c = 0; c < P->chunks.size(); ++c) {
-    const ChunkDev& ch = P->chunks[c];
-    const SfWork* wk = P->d_wk + ch.sf0;
-    double* parts = (double*)((char*)workspace + align_bytes(P->chunk_elems[c] * sz));
-    WVL_LAUNCH(ctx, KK_FWD_PLANE,
-               launch_fwd_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, wk, ch.sf0, ch.nsf,
-                                ch.grid_f[d], ch.tile_f[d], (size_t)ch.lds_f[d], workspace,
-                                pot_on));
-    if (pot_on) {
-      WVL_LAUNCH(ctx, KK_POT_COLUMN,
-                 launch_pot_column(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_b, workspace, pot,
-                                   nf1, nf2, parts));
-      if (e_pot)
-        WVL_LAUNCH(ctx, KK_FINALIZE,
-                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.grid_b, e_pot));
-    }
-    if (kin_on) {
-      WVL_LAUNCH(ctx, KK_KIN_XCOL, launch_kin_col(f64, st, 0, P->d_sf, wk, ch.sf0, ch.nsf,
-                                                  ch.grid_kx, workspace, fac, parts));
-      WVL_LAUNCH(ctx, KK_KIN_YCOL,
-                 launch_kin_col(f64, st, 1, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_ky, workspace,
-                                fac, parts));
-      WVL_LAUNCH(ctx, KK_KIN_ZCOL,
-                 launch_kin_col(f64, st, 2, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_kz, workspace,
-                                fac, parts));
-      if (e_kin)
-        WVL_LAUNCH(ctx, KK_FINALIZE,
-                   launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.nblk_kin, e_kin));
-    }
-    if (pot_on)
-      WVL_LAUNCH(ctx, KK_BACK_Y, launch_back_y(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_by,
-                                               workspace));
-    WVL_LAUNCH(ctx, KK_BACK_X, launch_back_x(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_bx,
-                                             workspace, pot_on, kin_on));
-    WVL_LAUNCH(ctx, KK_PACK_OUT,
-               launch_pack_out(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf,
-                               ch.maxsegs_out, workspace, hpsi_c, accumulate));
+  const ChunkDev& ch = P->lay.chunks[c];
+  const SfWork* wk = P->d_wk + ch.sf0;
+  double* parts = (double*)((char*)workspace + align_bytes(P->lay.elems_span * sz));
+  WVL_LAUNCH(ctx, KK_FWD_PLANE,
+             launch_fwd_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, wk, ch.sf0, ch.nsf,
+                              ch.grid_f[d], ch.tile_f[d], (size_t)ch.lds_f[d], workspace, pot_on));
+  if (pot_on) {
+    WVL_LAUNCH(ctx, KK_POT_COLUMN,
+               launch_pot_column(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_b, workspace, pot,
+                                 nf1, nf2, parts));
+    if (e_pot)
+      WVL_LAUNCH(ctx, KK_FINALIZE,
+                 launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.grid_b, e_pot));
   }
+  if (kin_on) {
+    WVL_LAUNCH(ctx, KK_KIN_XCOL, launch_kin_col(f64, st, 0, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                ch.grid_kx, workspace, fac, parts));
+    WVL_LAUNCH(ctx, KK_KIN_YCOL, launch_kin_col(f64, st, 1, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                ch.grid_ky, workspace, fac, parts));
+    WVL_LAUNCH(ctx, KK_KIN_ZCOL, launch_kin_col(f64, st, 2, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                ch.grid_kz, workspace, fac, parts));
+    if (e_kin)
+      WVL_LAUNCH(ctx, KK_FINALIZE,
+                 launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.nblk_kin, e_kin));
+  }
+  if (pot_on)
+    WVL_LAUNCH(ctx, KK_BACK_Y,
+               launch_back_y(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_by, workspace));
+  WVL_LAUNCH(ctx, KK_BACK_X, launch_back_x(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_bx,
+                                           workspace, pot_on, kin_on));
+  WVL_LAUNCH(ctx, KK_PACK_OUT,
+             launch_pack_out(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf,
+                             ch.maxsegs_out, workspace, hpsi_c, accumulate));
+  return WVL_OK;
+}
+
+static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                             const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                             void* workspace, int accumulate, const char* who) {
+  wvl_status st = apply_args(P, dt, terms, psi_c, pot, hpsi_c, workspace, who);
+  if (st != WVL_OK || P->nsf == 0) return st;
+  for (size_t c = 0; c < P->lay.chunks.size(); ++c)
+    if ((st = apply_chunk(P, c, dt == WVL_F64, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace,
+                          accumulate, P->ctx->stream)) != WVL_OK)
+      return st;
   return WVL_OK;
 }
 
@@ -1002,6 +1112,216 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
                                     ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.d_order,
                                     pc.nnz, val));
   }
+  return WVL_OK;
+}
+
+// Captures the apply (and optional S/H values) into G.  Chunks with
+// disjoint workspace go to parallel branches.
+static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                               const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                               void* workspace, double* s_val, double* h_val, wvl_graph* G) {
+  wvl_ctx* ctx = P->ctx;
+  const int f64 = dt == WVL_F64;
+  const size_t nch = P->lay.chunks.size();
+  // kernels are loaded lazily on first use; a load (which also uploads the
+  // constant filter tables) must not happen inside the capture
+  int pe = preload_kernels();
+  if (pe == 0) pe = preload_fused_kernels();
+  if (pe != 0)
+    return fail(ctx, WVL_EDEVICE, "kernel preload failed: %s", hipGetErrorString((hipError_t)pe));
+  const size_t nbr = P->lay.disjoint ? std::min<size_t>(nch, 4) : 0;
+  // streams[0] is the capture origin (the context's stream may be the
+  // legacy default stream, which cannot be captured); 1.. are branches
+  while (P->streams.size() < nbr + 1) {
+    hipStream_t st = nullptr;
+    WVL_HIP(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    P->streams.push_back(st);
+  }
+  std::vector<hipEvent_t>& ev = G->events;
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  };
+  for (size_t k = 0; k < nbr + 1; ++k) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return fail(ctx, WVL_EDEVICE, "graph events could not be created");
+    }
+    ev.push_back(e);
+  }
+  const bool prof = ctx->prof;
+  ctx->prof = false;   // no tracing events inside a graph
+  hipStream_t cs = P->streams[0];
+  hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  wvl_status st = he == hipSuccess ? WVL_OK
+                                   : fail(ctx, WVL_EDEVICE, "capture: %s", hipGetErrorString(he));
+  if (st == WVL_OK && P->nsf > 0) {
+    if (nbr > 0) {
+      // fork: every branch waits for the capture origin
+      if (hipEventRecord(ev[0], cs) != hipSuccess) st = WVL_EDEVICE;
+      for (size_t b = 0; st == WVL_OK && b < nbr; ++b)
+        if (hipStreamWaitEvent(P->streams[b + 1], ev[0], 0) != hipSuccess) st = WVL_EDEVICE;
+      for (size_t c = 0; st == WVL_OK && c < nch; ++c)
+        st = apply_chunk(P, c, f64, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0,
+                         P->streams[1 + c % nbr]);
+      // join
+      for (size_t b = 0; st == WVL_OK && b < nbr; ++b) {
+        if (hipEventRecord(ev[b + 1], P->streams[b + 1]) != hipSuccess ||
+            hipStreamWaitEvent(cs, ev[b + 1], 0) != hipSuccess)
+          st = WVL_EDEVICE;
+      }
+      if (st == WVL_EDEVICE) st = fail(ctx, WVL_EDEVICE, "graph fork/join failed");
+    } else {
+      for (size_t c = 0; st == WVL_OK && c < nch; ++c)
+        st = apply_chunk(P, c, f64, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0, cs);
+    }
+    for (int ket_out = 0; st == WVL_OK && ket_out < 2; ++ket_out) {
+      double* val = ket_out ? h_val : s_val;
+      const PatternCache& pc = P->pat[ket_out];
+      if (!val || pc.nnz == 0) continue;
+      const int e = launch_sparse_values(f64, cs, P->d_sf, P->d_seg, P->d_rt, ket_out,
+                                         psi_c, ket_out ? hpsi_c : psi_c, pc.d_row, pc.d_col,
+                                         pc.d_order, pc.nnz, val);
+      if (e != 0) st = fail(ctx, WVL_EDEVICE, "capture of sparse values failed");
+    }
+  }
+  hipGraph_t g = nullptr;
+  if (he == hipSuccess) {
+    const hipError_t ee = hipStreamEndCapture(cs, &g);
+    if (st == WVL_OK && ee != hipSuccess)
+      st = fail(ctx, WVL_EDEVICE, "end of capture: %s", hipGetErrorString(ee));
+  }
+  ctx->prof = prof;
+  if (st != WVL_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    cleanup();
+    return st;
+  }
+  hipGraphExec_t x = nullptr;
+  he = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (he != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    cleanup();
+    return fail(ctx, WVL_EDEVICE, "graph instantiation: %s", hipGetErrorString(he));
+  }
+  G->plan = P;
+  G->graph = g;
+  G->exec = x;
+  G->layout_version = P->layout_version;
+  return WVL_OK;
+}
+
+wvl_status wvl_graph_create(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                            const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                            void* workspace, double* s_val, double* h_val, wvl_graph** graph) {
+  if (!graph) return fail(P ? P->ctx : nullptr, WVL_EINVAL, "wvl_graph_create: null graph pointer");
+  *graph = nullptr;
+  wvl_status st = apply_args(P, dt, terms, psi_c, pot, hpsi_c, workspace, "wvl_graph_create");
+  if (st != WVL_OK) return st;
+  if ((s_val || h_val) && P->nsf > 0 && !psi_c)
+    return fail(P->ctx, WVL_EINVAL, "wvl_graph_create: S/H values need psi_c");
+  if (s_val && (st = ensure_pattern(P, 0)) != WVL_OK) return st;
+  if (h_val && (st = ensure_pattern(P, 1)) != WVL_OK) return st;
+  wvl_graph* G = new (std::nothrow) wvl_graph;
+  if (!G) return fail(P->ctx, WVL_ENOMEM, "wvl_graph_create: out of host memory");
+  st = capture_step(P, dt, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, s_val, h_val, G);
+  if (st != WVL_OK) {
+    delete G;
+    return st;
+  }
+  *graph = G;
+  return WVL_OK;
+}
+
+wvl_status wvl_graph_launch(wvl_graph* G) {
+  if (!G || !G->plan) return fail(nullptr, WVL_EINVAL, "wvl_graph_launch: null graph");
+  wvl_ctx* ctx = G->plan->ctx;
+  if (G->layout_version != G->plan->layout_version)
+    return fail(ctx, WVL_EINVAL, "wvl_graph_launch: the plan's layout changed since the capture");
+  WVL_HIP(ctx, hipGraphLaunch(G->exec, ctx->stream));
+  return WVL_OK;
+}
+
+void wvl_graph_destroy(wvl_graph* G) {
+  if (!G) return;
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  for (hipEvent_t e : G->events) (void)hipEventDestroy(e);
+  delete G;
+}
+
+static wvl_status set_layout(wvl_plan* P, Layout&& L) {
+  wvl_ctx* ctx = P->ctx;
+  P->lay = std::move(L);
+  P->info.chunks = (int64_t)P->lay.chunks.size();
+  ++P->layout_version;
+  WVL_HIP(ctx, hipMemcpyAsync(P->d_wk, P->lay.wk.data(), sizeof(SfWork) * P->nsf,
+                              hipMemcpyHostToDevice, ctx->stream));
+  WVL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return WVL_OK;
+}
+
+wvl_status wvl_plan_autotune(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                             const void* pot, void* hpsi_c, void* workspace, int32_t reps,
+                             wvl_tune_point* tried, int32_t max_tried, int32_t* ntried,
+                             wvl_tune_point* best) {
+  wvl_status st = apply_args(P, dt, terms, psi_c, pot, hpsi_c, workspace, "wvl_plan_autotune");
+  if (st != WVL_OK) return st;
+  wvl_ctx* ctx = P->ctx;
+  if (reps < 1) return fail(ctx, WVL_EINVAL, "wvl_plan_autotune: reps must be >= 1");
+  if (ntried) *ntried = 0;
+  if (P->nsf == 0) return WVL_OK;
+  const int sz = dt == WVL_F64 ? 8 : 4;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  WVL_HIP(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ctx, WVL_EDEVICE, "wvl_plan_autotune: event creation failed");
+  }
+  wvl_tune_point top{0, 0, 1e300};
+  int n = 0;
+  for (int nb : kTuneBins) {
+    for (int td : {1, 2, 4}) {
+      Layout L;
+      std::string err;
+      if (!make_layout(P, nb, td, &L, &err) || L.bytes(sz) > P->ws_cap[sz == 8]) continue;
+      if ((st = set_layout(P, std::move(L))) != WVL_OK) break;
+      // warm-up, then `reps` timed eager applies of this layout
+      if ((st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
+                           "wvl_plan_autotune")) != WVL_OK)
+        break;
+      hipError_t he = hipEventRecord(e0, ctx->stream);
+      for (int r = 0; he == hipSuccess && st == WVL_OK && r < reps; ++r)
+        st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
+                        "wvl_plan_autotune");
+      if (st != WVL_OK) break;
+      if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        st = fail(ctx, WVL_EDEVICE, "wvl_plan_autotune: %s", hipGetErrorString(he));
+        break;
+      }
+      const wvl_tune_point pt{nb, td, (double)ms / reps};
+      if (tried && n < max_tried) tried[n] = pt;
+      ++n;
+      if (pt.ms < top.ms) top = pt;
+    }
+    if (st != WVL_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != WVL_OK) return st;
+  if (ntried) *ntried = n;
+  if (n == 0) return fail(ctx, WVL_EUNSUPPORTED, "wvl_plan_autotune: no candidate fits");
+  Layout L;
+  std::string err;
+  if (!make_layout(P, top.nbins, top.tile_div, &L, &err))
+    return fail(ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
+  if ((st = set_layout(P, std::move(L))) != WVL_OK) return st;
+  if (best) *best = top;
   return WVL_OK;
 }
 

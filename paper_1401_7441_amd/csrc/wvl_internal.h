@@ -32,7 +32,9 @@ struct SfDev {
 };
 
 // Workspace offsets (elements of the compute type) of one support function
-// inside its chunk's workspace (R = 2N + 29, O = N + 2 ext):
+// in the workspace (R = 2N + 29, O = N + 2 ext).  The plan keeps these
+// records in its processing order (functions sorted by box size, cut into
+// chunks); kernels find the function's SfDev through `id`.
 //   c8   dense input box, x fastest      [8][N2][N1][N0]
 //   c8x  dense input box, y fastest      [8][N2][N0][N1]
 //   g1   after the x, y up passes        [2][N2][R1][R0]
@@ -43,6 +45,7 @@ struct SfDev {
 //   oz   z part of the kinetic term      [8][O2][N0][N1]
 //   ob   dense output box                [8][O2][O1][O0]
 struct SfWork {
+  int64_t id;         // the function's index in the plan (SfDev array, outputs)
   int64_t c8, c8x, g1, g2, q, ox, oy, oz, ob;
   int64_t epart;      // offset (in doubles) of its e_pot partials
   int64_t kpart;      // offset (in doubles) of its e_kin partials
@@ -59,7 +62,7 @@ __host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2) {
 
 // per-chunk launch geometry of the fused kernels, for dtype d (0 f32, 1 f64)
 struct ChunkDev {
-  int32_t sf0, nsf;
+  int32_t sf0, nsf;                // positions [sf0, sf0 + nsf) of the processing order
   int64_t maxbox_in, maxbox_out;   // largest dense input / output box (elements)
   int32_t grid_f[2], tile_f[2];    // k_fwd_plane
   int64_t lds_f[2];
@@ -70,6 +73,10 @@ struct ChunkDev {
   int64_t maxsegs_out;             // k_pack_out: largest output segment count
   int32_t nblk_pot, nblk_kin;      // partial slots per function
 };
+
+// load every kernel's code object before a stream capture (hipError_t as int)
+int preload_kernels();         // wvl_kernels.hip
+int preload_fused_kernels();   // wvl_fused.hip
 
 // launchers implemented in wvl_kernels.hip; all return hipError_t as int
 int launch_gather(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,

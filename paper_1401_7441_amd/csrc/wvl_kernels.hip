@@ -109,7 +109,7 @@ __global__ __launch_bounds__(TPB) void k_finalize(const SfWork* __restrict__ wk,
   double v = 0.0;
   for (int i = threadIdx.x; i < nblk; i += TPB) v += parts[off + i];
   const double b = block_sum(v);
-  if (threadIdx.x == 0) out[sf0 + s] = b;
+  if (threadIdx.x == 0) out[wk[s].id] = b;
 }
 
 template <typename T>
@@ -312,6 +312,18 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
 
 static inline dim3 grid2(int64_t maxvol, int nsf) {
   return dim3((unsigned)((maxvol + TPB - 1) / TPB), (unsigned)nsf);
+}
+
+// Loads the code objects of the kernels a captured step may launch.
+int preload_kernels() {
+  const void* fns[] = {(const void*)k_finalize, (const void*)k_sparse_values<float>,
+                       (const void*)k_sparse_values<double>};
+  for (const void* f : fns) {
+    hipFuncAttributes a;
+    const hipError_t e = hipFuncGetAttributes(&a, f);
+    if (e != hipSuccess) return (int)e;
+  }
+  return 0;
 }
 
 int launch_gather(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
