@@ -209,6 +209,21 @@ wvl_status wvl_sparse_overlap(wvl_plan* plan, const void* bra_c, int ket_is_outp
                               const void* ket_c, wvl_dtype dt, int64_t* nnz, int64_t* rowptr,
                               int32_t* col, double* val);
 
+/* Support-function update step (the localized gradient step of Sec. III.A
+ * and IV.A, reduced to a fixed step length):
+ *   psi_a <- psi_a - eta (P_La (H psi)_a - H_aa psi_a)
+ * for every function a, where P_La keeps the coefficients of H psi on a's
+ * input pattern and H_aa is the diagonal entry of row a of the Hamiltonian
+ * matrix.  hpsi_c: device, output layout (the result of
+ * wvl_apply_local_ham); h_val: device double[nnz], the H values in the CSR
+ * order wvl_sparse_overlap(ket_is_output = 1) reports; psi_c: device, input
+ * layout, updated in place (arithmetic in double, one rounding per value).
+ * Builds the H pattern if needed (synchronizes once).  Errors: WVL_EINVAL for
+ * null buffers, a non-finite eta, or a plan whose input pattern is not inside
+ * its output pattern. */
+wvl_status wvl_update(wvl_plan* plan, wvl_dtype dt, double eta, const void* hpsi_c,
+                      const double* h_val, void* psi_c);
+
 /* Batching of uneven boxes (Sec. III.B: each function is worked on inside
  * its own localization region only).  A plan sorts the functions by box
  * volume and cuts them into bins; every bin runs each stage as one launch

@@ -22,6 +22,8 @@ hamiltonian  Localized application of the local Hamiltonian to one support
 sparse       Sparsity pattern and values of the overlap and Hamiltonian
              matrices S_ab = <phi_a|phi_b>, H_ab = <phi_a|H|phi_b>
              (paper Sec. II.A, below Eq. (band_structure_energy)).
+update       The support-function update step with the localized gradient
+             (paper Sec. III.A and IV.A), fixed step length.
 
 Parity status: every function here is pinned by a check that does not reuse
 its own formula (closed forms, invariants, brute force); see the tests marked

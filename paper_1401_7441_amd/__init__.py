@@ -43,7 +43,8 @@ LOCREG_DTYPE = np.dtype([
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
             "wvl_compress", "wvl_apply_local_ham", "wvl_kinetic", "wvl_sparse_overlap",
-            "wvl_graph_create", "wvl_graph_launch", "wvl_graph_destroy", "wvl_plan_autotune",
+            "wvl_update", "wvl_graph_create", "wvl_graph_launch", "wvl_graph_destroy",
+            "wvl_plan_autotune",
             "wvl_profile_enable", "wvl_profile_reset", "wvl_profile_count", "wvl_profile_read")
 
 
@@ -99,6 +100,7 @@ def _load():
         "wvl_apply_local_ham": [P, ctypes.c_int, U32, P, P, P, P, P, P],
         "wvl_kinetic": [P, ctypes.c_int, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
+        "wvl_update": [P, ctypes.c_int, D, P, P, P],
         "wvl_graph_create": [P, ctypes.c_int, U32, P, P, P, P, P, P, P, P, ctypes.POINTER(P)],
         "wvl_graph_launch": [P],
         "wvl_graph_destroy": [P],
@@ -374,6 +376,19 @@ def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None):
                                    dt, ctypes.byref(n), _ptr(rowptr), _ptr(col), _ptr(val)),
            plan.ctx.handle)
     return rowptr, col[:nnz], val[:nnz]
+
+
+def update(plan: Plan, psi_c, hpsi_c, h_val, eta):
+    """wvl_update: psi_c <- psi_c - eta (P_L hpsi_c - H_aa psi_c), in place;
+    h_val are the H values (float64, the plan's CSR order)."""
+    _need_cuda(psi_c, hpsi_c, h_val)
+    dt = _dtype_code(psi_c, hpsi_c)
+    if psi_c.numel() < plan.info["in_coefs"] or hpsi_c.numel() < plan.info["out_coefs"]:
+        raise WvlError(WVL_EINVAL, "coefficient buffer smaller than the plan's layout")
+    if h_val.dtype.itemsize != 8 or h_val.numel() < sparse_pattern_nnz(plan, True):
+        raise WvlError(WVL_EINVAL, "h_val must be float64 with the H pattern's nnz entries")
+    _check(lib().wvl_update(plan._ptr, dt, float(eta), _ptr(hpsi_c), _ptr(h_val), _ptr(psi_c)),
+           plan.ctx.handle)
 
 
 class Graph:

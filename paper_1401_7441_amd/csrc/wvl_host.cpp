@@ -22,11 +22,11 @@ using namespace wvl;
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
   KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
-  KK_COUNT
+  KK_UPDATE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "fwd_plane", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
-    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h"};
+    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -176,6 +176,8 @@ struct wvl_plan {
   int64_t ws_cap[2] = {0, 0};         // workspace bytes reported (F32, F64)
   std::vector<hipStream_t> streams;   // branch streams of captured graphs
   int64_t layout_version = 0;         // bumped when the autotuner changes the layout
+  bool in_sub_out = false;            // input patterns inside output patterns (wvl_update)
+  int64_t max_in_segs = 0;            // largest input segment count of a function
   SfDev* d_sf = nullptr;
   wvl_seg* d_seg = nullptr;
   int32_t* d_rt = nullptr;
@@ -715,6 +717,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
     return fail(ctx, WVL_EUNSUPPORTED, "wvl_plan_create: more than 2^31 segments");
   const int32_t* gn = ctx->grid.n;
   wvl_status st = WVL_OK;
+  bool in_sub_out = true;   // every input pattern inside its output pattern
   std::vector<std::pair<int64_t, int64_t>> outs;
   for (int k = 0; k < nsf; ++k) {
     const wvl_locreg& L = lr[k];
@@ -759,6 +762,11 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
                   k, (long long)bad);
     if (L.coef_off < 0 || L.ocoef_off < 0)
       return fail(ctx, WVL_EINVAL, "function %d: negative coefficient offset", k);
+    // wvl_update projects H psi (output pattern) onto the input pattern
+    int64_t bad2 = -1;
+    if (!fine_in_coarse(segs, L.oseg_c, L.noseg_c, L.seg_c, L.nseg_c, &bad2) ||
+        !fine_in_coarse(segs, L.oseg_f, L.noseg_f, L.seg_f, L.nseg_f, &bad2))
+      in_sub_out = false;
     outs.emplace_back(L.ocoef_off, L.on_c + 7 * L.on_f);
   }
   std::sort(outs.begin(), outs.end());
@@ -818,6 +826,9 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
     return (int64_t)A.n[0] * A.n[1] * A.n[2] > (int64_t)B.n[0] * B.n[1] * B.n[2];
   });
   P->max_ws = max_workspace_bytes;
+  P->in_sub_out = in_sub_out;
+  for (int k = 0; k < nsf; ++k)
+    P->max_in_segs = std::max<int64_t>(P->max_in_segs, lr[k].nseg_c + lr[k].nseg_f);
   // the workspace reported covers every layout the autotuner may pick
   for (int nb : kTuneBins) {
     Layout L;
@@ -1111,6 +1122,28 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
                launch_sparse_values(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt,
                                     ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.d_order,
                                     pc.nnz, val));
+  }
+  return WVL_OK;
+}
+
+wvl_status wvl_update(wvl_plan* P, wvl_dtype dt, double eta, const void* hpsi_c,
+                      const double* h_val, void* psi_c) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_update: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (P->nsf == 0) return WVL_OK;
+  if (!hpsi_c || !h_val || !psi_c) return fail(ctx, WVL_EINVAL, "wvl_update: null buffer");
+  if (!P->in_sub_out)
+    return fail(ctx, WVL_EINVAL, "wvl_update: an input pattern is not inside its output pattern");
+  if (!std::isfinite(eta)) return fail(ctx, WVL_EINVAL, "wvl_update: eta is not finite");
+  wvl_status st = ensure_pattern(P, 1);
+  if (st != WVL_OK) return st;
+  const PatternCache& pc = P->pat[1];
+  for (int s0 = 0; s0 < P->nsf; s0 += 65535) {
+    const int n = std::min(65535, P->nsf - s0);
+    WVL_LAUNCH(ctx, KK_UPDATE,
+               launch_update(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, eta, hpsi_c,
+                             pc.d_rowptr, pc.d_col, h_val, psi_c, s0, n, P->max_in_segs));
   }
   return WVL_OK;
 }

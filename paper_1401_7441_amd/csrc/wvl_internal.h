@@ -102,6 +102,9 @@ int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const doub
                     int which, int nblk, double* out);
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
+int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                  double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
+                  const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs);
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                          const int32_t* rt, int ket_out, const void* bra, const void* ket,
                          const int32_t* row, const int32_t* col, const int32_t* order,

@@ -307,6 +307,87 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// support-function update: psi <- psi - eta (P_L hpsi - H_aa psi)
+// ---------------------------------------------------------------------------
+// Block = 64 consecutive input segments of one function (coarse blocks, then
+// fine).  Every input segment lies inside one maximal output segment (the
+// input pattern is contained in the output pattern), so each segment maps
+// affinely into H psi; the map is found once per segment and staged in LDS.
+constexpr int kUpdSegs = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(const SfDev* __restrict__ sfs,
+                                                const wvl_seg* __restrict__ seg,
+                                                const int32_t* __restrict__ rt, double eta,
+                                                const T* __restrict__ hpsi,
+                                                const int64_t* __restrict__ hrow,
+                                                const int32_t* __restrict__ hcol,
+                                                const double* __restrict__ hval,
+                                                T* __restrict__ psi, int sf0) {
+  __shared__ int s_in[kUpdSegs + 1];     // coefficient offset relative to the first segment
+  __shared__ int64_t s_out[kUpdSegs];    // H psi index of the segment's first point
+  __shared__ double s_diag;
+  const int a = sf0 + blockIdx.y;
+  const SfDev& sf = sfs[a];
+  const int64_t nrows = (int64_t)sf.n[1] * sf.n[2];
+  const int cb0 = rt[sf.rt[0]], ce0 = rt[sf.rt[0] + nrows];
+  const int fb0 = rt[sf.rt[1]], fe0 = rt[sf.rt[1] + nrows];
+  const int nbc = (ce0 - cb0 + kUpdSegs - 1) / kUpdSegs;
+  const int nbf = (fe0 - fb0 + kUpdSegs - 1) / kUpdSegs;
+  int bx = blockIdx.x;
+  const bool fine = bx >= nbc;
+  if (fine) bx -= nbc;
+  if (bx >= (fine ? nbf : nbc)) return;   // uniform over the block
+  const int sA = (fine ? fb0 : cb0) + bx * kUpdSegs;
+  const int nseg = min(kUpdSegs, (fine ? fe0 : ce0) - sA);
+  const int tid = threadIdx.x;
+  const int64_t off0 = seg[sA].off;
+  const PatBox ob = pat_box(sf, 1);
+  if (tid < nseg) {
+    const wvl_seg g = seg[sA + tid];
+    s_in[tid] = (int)(g.off - off0);
+    if (tid == nseg - 1) s_in[nseg] = (int)(g.off - off0) + (g.i1e - g.i1s + 1);
+    const int64_t r = (int64_t)(g.i3 - ob.oz) * ob.by + (g.i2 - ob.oy);
+    const int pat = fine ? 3 : 2;
+    int64_t o = -1;
+    for (int q = rt[sf.rt[pat] + r]; q < rt[sf.rt[pat] + r + 1]; ++q) {
+      const wvl_seg h = seg[q];
+      if (g.i1s >= h.i1s && g.i1s <= h.i1e) {
+        o = h.off + (g.i1s - h.i1s);
+        break;
+      }
+    }
+    s_out[tid] = o;   // always found: the plan checks input inside output
+  }
+  if (tid == 0) {     // H_aa: the diagonal entry of row a
+    int64_t lo = hrow[a], hi = hrow[a + 1] - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (hcol[mid] < a) lo = mid + 1; else hi = mid;
+    }
+    s_diag = hval[lo];
+  }
+  __syncthreads();
+  const int total = s_in[nseg];
+  const double d = s_diag;
+  const int cfirst = fine ? 1 : 0, clast = fine ? 7 : 0;
+  for (int k = tid; k < total; k += 256) {
+    int lo = 0, hi = nseg - 1;   // last segment with s_in <= k
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_in[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    if (s_out[lo] < 0) continue;   // not reached: the host checks input inside output
+    const int64_t oi = s_out[lo] + (k - s_in[lo]);
+    for (int c = cfirst; c <= clast; ++c) {
+      const int64_t i = sf.cin + (c == 0 ? 0 : sf.n_c + (int64_t)(c - 1) * sf.n_f) + off0 + k;
+      const int64_t o = sf.cout + (c == 0 ? 0 : sf.on_c + (int64_t)(c - 1) * sf.on_f) + oi;
+      const double x = (double)psi[i];
+      psi[i] = (T)(x - eta * ((double)hpsi[o] - d * x));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -317,7 +398,8 @@ static inline dim3 grid2(int64_t maxvol, int nsf) {
 // Loads the code objects of the kernels a captured step may launch.
 int preload_kernels() {
   const void* fns[] = {(const void*)k_finalize, (const void*)k_sparse_values<float>,
-                       (const void*)k_sparse_values<double>};
+                       (const void*)k_sparse_values<double>, (const void*)k_update<float>,
+                       (const void*)k_update<double>};
   for (const void* f : fns) {
     hipFuncAttributes a;
     const hipError_t e = hipFuncGetAttributes(&a, f);
@@ -392,6 +474,20 @@ int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* 
     hipLaunchKernelGGL(k_sparse_values<float>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
                        seg, rt, ket_out, (const float*)bra, (const float*)ket, row, col, order,
                        nnz, val);
+  return (int)hipGetLastError();
+}
+
+int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                  double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
+                  const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs) {
+  if (nsf == 0) return 0;
+  const dim3 g((unsigned)(maxsegs / kUpdSegs + 2), (unsigned)nsf);
+  if (f64)
+    hipLaunchKernelGGL(k_update<double>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, eta,
+                       (const double*)hpsi, hrow, hcol, hval, (double*)psi, sf0);
+  else
+    hipLaunchKernelGGL(k_update<float>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, eta,
+                       (const float*)hpsi, hrow, hcol, hval, (float*)psi, sf0);
   return (int)hipGetLastError();
 }
 

@@ -1,0 +1,358 @@
+"""Request loop: continuous batching of independent systems on one GPU.
+
+Each request is one system of support functions (its own grid, potential,
+localization regions and coefficients) that needs `steps` update steps:
+local-H apply, overlap and Hamiltonian values on the resident patterns, then
+the update psi <- psi - eta (P_L H psi - H_aa psi) (wvl_update).  The compressed
+coefficients, H psi, the potential, the plan (keys and patterns) and the
+step graph stay on the device across the steps.  This reuse of resident
+support functions is what the method relies on between geometry steps and
+between neutral and charged runs (paper Sec. VIII).
+
+Scheduling:
+  * admission by HBM footprint: a waiting request is admitted at a tick
+    boundary, in arrival order, when its footprint (coefficients, H psi,
+    potential, workspace, patterns) fits in the budget left by the active
+    requests;
+  * continuous batching: every tick enqueues the next step of every active
+    request, each on its own HIP stream, so their kernels overlap on the
+    device; a tick ends when all of them are done; requests that finished
+    their last step leave and free their memory, new ones join;
+  * latency = arrival -> completion of the last step (host clock).
+
+The per-function baseline (`run_per_function`) is the plain path: FP64, one
+support function per apply (a one-function plan each), no graphs, one
+request at a time.
+
+Every step of the path runs in the library's kernels; this module only
+schedules them and moves data.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+from . import (Context, Graph, Plan, apply_local_ham, build_locregs, sparse_overlap,
+               sparse_pattern_nnz, update)
+
+
+@dataclasses.dataclass
+class Request:
+    """One system.  Host inputs are prepared before submission; `pot` is
+    the global fine-grid potential (numpy, z, y, x)."""
+    rid: int
+    h: float
+    grid_n: tuple
+    locregs: np.ndarray
+    segs: np.ndarray
+    psi: np.ndarray
+    pot: np.ndarray
+    arrival: float = 0.0
+    # filled by the engine
+    admitted: float = math.nan
+    done: float = math.nan
+    steps_done: int = 0
+    footprint: int = 0
+    result: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def nsf(self):
+        return len(self.locregs)
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+def footprint_bytes(locregs, grid_n, sz, workspace_bytes, nnz_bound=None):
+    """Device bytes a request holds while active (before its plan exists the
+    workspace size comes from the plan; patterns are bounded by 600 pairs per
+    function, each pair 12 bytes of CSR plus 8 of values, for S and H)."""
+    n_in = int(np.sum(locregs["n_c"] + 7 * locregs["n_f"]))
+    n_out = int(np.sum(locregs["on_c"] + 7 * locregs["on_f"]))
+    nf = (2 * grid_n[0] + 29) * (2 * grid_n[1] + 29) * (2 * grid_n[2] + 29)
+    nnz = nnz_bound if nnz_bound is not None else 600 * len(locregs)
+    return int(sz * (n_in + n_out + nf) + workspace_bytes + 2 * 20 * nnz + 64 * len(locregs))
+
+
+class _Active:
+    """Device state of an admitted request."""
+
+    def __init__(self, req: Request, dtype, eta, use_graph, max_workspace, stream):
+        import torch
+        self.req = req
+        self.stream = stream
+        with torch.cuda.stream(self.stream):
+            self.ctx = Context(req.h, req.grid_n, stream=self.stream)
+            self.plan = Plan(self.ctx, req.locregs, req.segs, max_workspace=max_workspace)
+            self.psi = torch.from_numpy(req.psi).to(dtype).to("cuda", non_blocking=True)
+            self.pot = torch.from_numpy(req.pot).to(dtype).to("cuda", non_blocking=True)
+            self.hpsi = torch.zeros(self.plan.info["out_coefs"], dtype=dtype, device="cuda")
+            self.ek = torch.zeros(req.nsf, dtype=torch.float64, device="cuda")
+            self.ep = torch.zeros_like(self.ek)
+            self.ws = self.plan.new_workspace(dtype)
+            self.nnz_s = sparse_pattern_nnz(self.plan, False)
+            self.nnz_h = sparse_pattern_nnz(self.plan, True)
+            self.s_out = (torch.zeros(req.nsf + 1, dtype=torch.int64, device="cuda"),
+                          torch.zeros(max(1, self.nnz_s), dtype=torch.int32, device="cuda"),
+                          torch.zeros(max(1, self.nnz_s), dtype=torch.float64, device="cuda"))
+            self.h_out = (torch.zeros(req.nsf + 1, dtype=torch.int64, device="cuda"),
+                          torch.zeros(max(1, self.nnz_h), dtype=torch.int32, device="cuda"),
+                          torch.zeros(max(1, self.nnz_h), dtype=torch.float64, device="cuda"))
+            self.s_val, self.h_val = self.s_out[2], self.h_out[2]
+        self.eta = eta
+        self.graph = None
+        if use_graph:
+            self.graph = Graph(self.plan, self.psi, self.pot, self.hpsi, self.ek, self.ep,
+                               workspace=self.ws, s_val=self.s_val, h_val=self.h_val)
+        self.done_event = None
+
+    def enqueue_step(self):
+        import torch
+        with torch.cuda.stream(self.stream):
+            if self.graph is not None:
+                self.graph.launch()
+            else:
+                apply_local_ham(self.plan, self.psi, self.pot, self.hpsi, self.ek, self.ep,
+                                workspace=self.ws)
+                sparse_overlap(self.plan, self.psi, self.psi, False, out=self.s_out)
+                sparse_overlap(self.plan, self.psi, self.hpsi, True, out=self.h_out)
+            update(self.plan, self.psi, self.hpsi, self.h_val, self.eta)
+            self.done_event = torch.cuda.Event()
+            self.done_event.record(self.stream)
+
+    def snapshot(self):
+        """Final state to host: psi, energies, S and H values."""
+        self.stream.synchronize()
+        return {"psi": self.psi.cpu().numpy(), "e_kin": self.ek.cpu().numpy(),
+                "e_pot": self.ep.cpu().numpy(),
+                "s_val": self.s_val[:self.nnz_s].cpu().numpy(),
+                "h_val": self.h_val[:self.nnz_h].cpu().numpy()}
+
+    def close(self):
+        self.stream.synchronize()
+        if self.graph is not None:
+            self.graph.close()
+        self.plan.close()
+        self.ctx.close()
+
+
+class Engine:
+    """Continuous-batching engine (see the module docstring)."""
+
+    def __init__(self, dtype="f32", hbm_budget=None, eta=0.01, steps=5, use_graph=True,
+                 max_workspace=8 << 30, keep_results=False, n_streams=8):
+        import torch
+        # a fixed pool of streams (default priority): requests take the one
+        # with the fewest active requests; buffers are allocated on it, so
+        # freed memory returns to a stream that stays in use
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.stream_load = [0] * n_streams
+        self.dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.sz = 4 if dtype == "f32" else 8
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(0.85 * free)
+        self.budget = int(hbm_budget)
+        self.eta = eta
+        self.steps = steps
+        self.use_graph = use_graph
+        self.max_workspace = int(max_workspace)
+        self.keep_results = keep_results
+        self.waiting = []
+        self.active = []
+        self.finished = []
+        self.rejected = []
+        self.used = 0
+        self.ticks = 0
+        self.sf_steps = 0
+
+    def _footprint(self, req):
+        # the workspace of a plan bounded by max_workspace is at most that bound
+        # plus one function's share; estimate it without creating the plan
+        ws = min(self.max_workspace + (64 << 20), 16 * (1 << 20) * req.nsf * self.sz // 4)
+        return footprint_bytes(req.locregs, req.grid_n, self.sz, ws)
+
+    def submit(self, req: Request):
+        req.footprint = self._footprint(req)
+        if req.footprint > self.budget:
+            self.rejected.append(req)
+        else:
+            self.waiting.append(req)
+
+    def _admit(self, now):
+        admitted = []
+        for r in admissible(self.waiting, now, self.budget - self.used):
+            self.waiting.remove(r)
+            r.admitted = time.perf_counter() - self.t0
+            self.used += r.footprint
+            si = min(range(len(self.streams)), key=lambda i: self.stream_load[i])
+            self.stream_load[si] += 1
+            act = _Active(r, self.dtype, self.eta, self.use_graph, self.max_workspace,
+                          self.streams[si])
+            act.stream_index = si
+            self.active.append(act)
+            admitted.append(r)
+        return admitted
+
+    def tick(self):
+        """One engine tick: admit, enqueue one step of every active request,
+        wait for them, retire the finished ones.  Returns False when idle
+        (nothing active and nothing admissible yet)."""
+        now = time.perf_counter() - self.t0
+        self._admit(now)
+        if not self.active:
+            return False
+        for a in self.active:
+            a.enqueue_step()
+        for a in self.active:
+            a.done_event.synchronize()
+        t = time.perf_counter() - self.t0
+        self.ticks += 1
+        still = []
+        for a in self.active:
+            a.req.steps_done += 1
+            self.sf_steps += a.req.nsf
+            if a.req.steps_done >= self.steps:
+                a.req.done = t
+                if self.keep_results:
+                    a.req.result = a.snapshot()
+                a.close()
+                self.stream_load[a.stream_index] -= 1
+                self.used -= a.req.footprint
+                self.finished.append(a.req)
+            else:
+                still.append(a)
+        self.active = still
+        return True
+
+    def run(self, requests, t0=None):
+        """Serve `requests` (their `arrival` times in seconds from now) until
+        all are finished.  Returns the finished requests."""
+        self.t0 = time.perf_counter() if t0 is None else t0
+        for r in requests:
+            self.submit(r)
+        while self.waiting or self.active:
+            if not self.tick():
+                # idle until the next arrival
+                nxt = min(r.arrival for r in self.waiting)
+                delay = nxt - (time.perf_counter() - self.t0)
+                if delay > 0:
+                    time.sleep(min(delay, 0.05))
+        return self.finished
+
+
+def admissible(waiting, now, free):
+    """Requests to admit now: those that have arrived, in arrival order, as
+    long as their footprints fit in `free` bytes; the first one that does
+    not fit stops the scan (no overtaking, so a large request is never
+    starved by smaller ones behind it)."""
+    out = []
+    for r in sorted(waiting, key=lambda r: (r.arrival, r.rid)):
+        if r.arrival > now or r.footprint > free:
+            break
+        out.append(r)
+        free -= r.footprint
+    return out
+
+
+def run_per_function(requests, eta=0.01, steps=5, keep_results=False):
+    """The plain baseline: FP64, each support function applied alone (a
+    one-function plan per function), no graphs, requests served one at a
+    time in arrival order.  Returns the requests with done / latency set."""
+    import torch
+    t0 = time.perf_counter()
+    out = []
+    for req in sorted(requests, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if now < req.arrival:
+            time.sleep(req.arrival - now)
+        ctx = Context(req.h, req.grid_n)
+        full = Plan(ctx, req.locregs, req.segs)
+        psi = torch.from_numpy(req.psi).to(torch.float64).cuda()
+        pot = torch.from_numpy(req.pot).to(torch.float64).cuda()
+        hpsi = torch.zeros(full.info["out_coefs"], dtype=torch.float64, device="cuda")
+        singles = []
+        for k in range(req.nsf):
+            one = req.locregs[k:k + 1].copy()
+            sg = req.segs
+            # a one-function plan over the same segment array and offsets
+            singles.append(_single_plan(ctx, one, sg))
+        for _ in range(steps):
+            for k, (plan1, in_off, out_off) in enumerate(singles):
+                n_in, n_out = plan1.info["in_coefs"], plan1.info["out_coefs"]
+                o = torch.zeros(n_out, dtype=torch.float64, device="cuda")
+                apply_local_ham(plan1, psi[in_off:in_off + n_in].contiguous(), pot, o)
+                hpsi[out_off:out_off + n_out] = o
+            sparse_overlap(full, psi, psi, False)
+            _, _, hv = sparse_overlap(full, psi, hpsi, True)
+            update(full, psi, hpsi, hv, eta)
+        torch.cuda.synchronize()
+        req.done = time.perf_counter() - t0
+        req.steps_done = steps
+        if keep_results:
+            req.result = {"psi": psi.cpu().numpy()}
+        for p, _, _ in singles:
+            p.close()
+        full.close()
+        ctx.close()
+        out.append(req)
+    return out
+
+
+def _single_plan(ctx, one, segs):
+    """A plan for one function whose coefficients start at offset 0 (the
+    function's own slices of the request's buffers)."""
+    in_off, out_off = int(one["coef_off"][0]), int(one["ocoef_off"][0])
+    one["coef_off"] = 0
+    one["ocoef_off"] = 0
+    return Plan(ctx, one, segs), in_off, out_off
+
+
+def make_requests(n, dtype_sz=4, rate=None, seed=0, max_nsf=None, ngauss=32):
+    """`n` serving requests drawn as the serving workload (systems of 50-4000
+    support functions, log-uniform) with Poisson arrivals at `rate` per
+    second (all at t = 0 when rate is None).  Host inputs only."""
+    import inputs
+    rng = np.random.default_rng(7000 + seed)
+    t = 0.0
+    reqs = []
+    for i in range(n):
+        g = inputs.geometry("serve", seed_offset=seed * 100000 + i)
+        if max_nsf is not None and len(g.radii) > max_nsf:
+            g = inputs.geometry("serve", nsf=max_nsf, seed_offset=seed * 100000 + i)
+        lr, segs = build_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
+        psi = np.concatenate([
+            inputs.coefficients(g, k, _pts(segs, lr[k], "c"), _pts(segs, lr[k], "f"))
+            for k in range(len(lr))])
+        params = inputs.potential_params(g, ngauss=min(ngauss, len(lr)))
+        pot = inputs.potential(g, device="cpu", params=params).numpy()
+        if rate is not None:
+            t += rng.exponential(1.0 / rate)
+        reqs.append(Request(rid=i, h=g.h, grid_n=tuple(g.grid_n), locregs=lr, segs=segs,
+                            psi=psi, pot=pot, arrival=t if rate is not None else 0.0))
+    return reqs
+
+
+def _pts(segs, r, kind):
+    a = int(r["seg_c" if kind == "c" else "seg_f"])
+    n = int(r["nseg_c" if kind == "c" else "nseg_f"])
+    rows = segs[a:a + n]
+    if n == 0:
+        return np.zeros((0, 3), np.int64)
+    return np.concatenate([np.stack([np.arange(s["i1s"], s["i1e"] + 1),
+                                     np.full(s["i1e"] - s["i1s"] + 1, s["i2"]),
+                                     np.full(s["i1e"] - s["i1s"] + 1, s["i3"])], axis=1)
+                           for s in rows])
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return math.nan
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)

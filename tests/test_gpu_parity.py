@@ -332,3 +332,30 @@ def test_sparse_on_rows_with_several_runs():
             for j in range(rp[a], rp[a + 1]):
                 scale = np.linalg.norm(case.coefs[a]) * np.linalg.norm(kets[cl[j]])
                 assert abs(v[j] - vv[j]) <= 1e-12 * scale, (a, cl[j])
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_update_step(spheres, dtype, tol):
+    """wvl_update against the oracle's step, with the oracle's own H phi and
+    H_aa: per-function relative L2 error of the updated coefficients."""
+    from oracle import update as U
+    _print(f"case: update step {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    plan, psi, out, _, _ = spheres.run(dt)
+    hpsi = torch.tensor(out, dtype=dt, device="cuda")
+    _, _, hv = W.sparse_overlap(plan, psi, hpsi, True)
+    n = len(spheres.lrs)
+    ohs = [spheres.oracle(k)[0] for k in range(n)]
+    rp, cl, ov = SP.matrix(spheres.lrs, spheres.coefs, ohs, True)
+    eta = 0.01
+    new = psi.clone()
+    W.update(plan, new, hpsi, hv, eta)
+    torch.cuda.synchronize()
+    got = new.cpu().numpy()
+    for k in range(n):
+        row = list(cl[rp[k]:rp[k + 1]])
+        h_aa = ov[rp[k] + row.index(k)]
+        want = U.update(spheres.lrs[k], spheres.coefs[k], ohs[k], h_aa, eta)
+        r = spheres.rec[k]
+        sl = slice(int(r["coef_off"]), int(r["coef_off"]) + int(r["n_c"]) + 7 * int(r["n_f"]))
+        assert rel_err(got[sl], want) < tol, k

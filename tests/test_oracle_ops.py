@@ -420,3 +420,42 @@ def test_sparse_matrices_against_dictionary_products():
     np.testing.assert_allclose(S, S.T, atol=1e-13)
     for a in range(6):
         assert abs(S[a, a] - bra[a] @ bra[a]) < 1e-12
+
+
+# P12: the update step's projection P_L is a pointwise restriction
+def test_update_restriction_matches_pointwise_dictionary():
+    from oracle import update as U
+    rng = np.random.default_rng(17)
+    g = inputs.geometry("batch1k", nsf=3)
+    lrs = LR.sphere_locregs(g.h, g.grid_n, g.centers, g.radii * 0.5, g.fine_radii * 0.5, 3)
+    for lr in lrs:
+        out = rng.standard_normal(lr.on_c + 7 * lr.on_f)
+        # dictionary: (component, point) -> value of the output-layout vector
+        d = {}
+        k = 0
+        for comp, segs in [(0, lr.ocseg)] + [(c, lr.ofseg) for c in range(1, 8)]:
+            for p in LR.points_from_segments(segs):
+                d[(comp, tuple(int(v) for v in p))] = out[k]
+                k += 1
+        want = []
+        for comp, segs in [(0, lr.cseg)] + [(c, lr.fseg) for c in range(1, 8)]:
+            for p in LR.points_from_segments(segs):
+                want.append(d[(comp, tuple(int(v) for v in p))])
+        got = U.restrict_to_input(lr, out)
+        assert np.array_equal(got, np.array(want))
+        psi = rng.standard_normal(lr.n_c + 7 * lr.n_f)
+        assert np.array_equal(U.update(lr, psi, out, 0.7, 0.0), psi)
+        # with H phi = c phi on the pattern the step leaves phi unchanged
+        emb = np.zeros_like(out)
+        k = 0
+        inv = {}
+        for comp, segs in [(0, lr.cseg)] + [(c, lr.fseg) for c in range(1, 8)]:
+            for p in LR.points_from_segments(segs):
+                inv[(comp, tuple(int(v) for v in p))] = psi[k]
+                k += 1
+        k = 0
+        for comp, segs in [(0, lr.ocseg)] + [(c, lr.ofseg) for c in range(1, 8)]:
+            for p in LR.points_from_segments(segs):
+                emb[k] = 2.5 * inv.get((comp, tuple(int(v) for v in p)), 0.0)
+                k += 1
+        assert np.allclose(U.update(lr, psi, emb, 2.5, 0.01), psi, rtol=0, atol=1e-15)

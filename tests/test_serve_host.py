@@ -1,0 +1,36 @@
+"""Host logic of the request loop (no GPU): admission order and footprints."""
+import numpy as np
+
+from paper_1401_7441_amd import serve as S
+
+
+class _R:
+    def __init__(self, rid, arrival, footprint):
+        self.rid, self.arrival, self.footprint = rid, arrival, footprint
+
+
+def test_admission_is_in_arrival_order_and_never_overtakes():
+    w = [_R(0, 0.0, 50), _R(1, 0.1, 80), _R(2, 0.2, 10), _R(3, 5.0, 1)]
+    # the second request does not fit: the third waits behind it
+    assert [r.rid for r in S.admissible(w, now=1.0, free=100)] == [0]
+    assert [r.rid for r in S.admissible(w, now=1.0, free=130)] == [0, 1]
+    assert [r.rid for r in S.admissible(w, now=1.0, free=1000)] == [0, 1, 2]
+    # not yet arrived
+    assert [r.rid for r in S.admissible(w, now=-1.0, free=1000)] == []
+    assert [r.rid for r in S.admissible(w, now=9.0, free=1000)] == [0, 1, 2, 3]
+
+
+def test_footprint_counts_every_resident_buffer():
+    lr = np.zeros(3, dtype=[("n_c", "<i8"), ("n_f", "<i8"), ("on_c", "<i8"), ("on_f", "<i8")])
+    lr["n_c"], lr["n_f"], lr["on_c"], lr["on_f"] = 100, 10, 300, 40
+    grid = (10, 10, 10)
+    nf = 49 ** 3
+    want = 4 * (3 * 170 + 3 * 580 + nf) + 1000 + 2 * 20 * 600 * 3 + 64 * 3
+    assert S.footprint_bytes(lr, grid, 4, 1000) == want
+
+
+def test_percentile_interpolates():
+    xs = [1.0, 2.0, 3.0, 4.0, 5.0]
+    assert S.percentile(xs, 50) == 3.0
+    assert S.percentile(xs, 100) == 5.0
+    assert abs(S.percentile(xs, 99) - 4.96) < 1e-12
