@@ -257,6 +257,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's default schedule (one bin, largest row tiles)")
     ap.add_argument("--autotune-reps", type=int, default=2)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the request-loop measurement (p50/p99 latency)")
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -398,6 +401,17 @@ def main():
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.workload)
+    if not args.no_serve:
+        # free the batch before the serving run takes its HBM budget
+        if graph is not None:
+            graph.close()
+        del graph, run
+        S.clear()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        from paper_1401_7441_amd import serve
+        res["serving"] = serve.benchmark(n_requests=args.serve_requests, dtype=args.dtype,
+                                         log=log)
     print(json.dumps(res), flush=True)
 
 

@@ -142,6 +142,14 @@ def coefficients(geom: Geometry, sf, points_c, points_f, smooth=False, normalize
     return out
 
 
+def flat_coefficients(geom: Geometry, n, seed=0):
+    """n coefficients N(0, 1/n) from one stream per system (stream 3, then
+    `seed`): a fast stand-in where only the sizes matter (the serving
+    measurement)."""
+    rng = _rng(geom.workload, 3, seed)
+    return rng.standard_normal(n) / math.sqrt(max(1, n))
+
+
 def potential_params(geom: Geometry, ngauss=None):
     """Gaussian wells: centres uniform in the domain, depth U(-2, 0) Ha,
     width U(0.5, 1.5) bohr.  One well per support function unless given."""

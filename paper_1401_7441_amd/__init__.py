@@ -163,14 +163,22 @@ def build_locregs(h, grid_n, centers, radii, fine_radii, ext):
     nsf = len(c)
     g = _grid(h, grid_n)
     lr = np.zeros(nsf, LOCREG_DTYPE)
-    n = ctypes.c_int64(0)
-    _check(lib().wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
-                                  f.ctypes.data, int(ext), lr.ctypes.data, None, ctypes.byref(n)))
-    segs = np.zeros(n.value, SEG_DTYPE)
-    _check(lib().wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
-                                  f.ctypes.data, int(ext), lr.ctypes.data, segs.ctypes.data,
-                                  ctypes.byref(n)))
-    return lr, segs
+    # one call with a generous capacity (rows of the output boxes, several
+    # runs per row); a second, exact one only when it was too small
+    rows = (2.0 * (r + ext * float(h)) / float(h) + 3.0) ** 2
+    cap = int(np.sum(6.0 * rows)) + 16
+    segs = np.zeros(cap, SEG_DTYPE)
+    n = ctypes.c_int64(cap)
+    st = lib().wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
+                                 f.ctypes.data, int(ext), lr.ctypes.data, segs.ctypes.data,
+                                 ctypes.byref(n))
+    if st != 0 and n.value > cap:
+        segs = np.zeros(n.value, SEG_DTYPE)
+        st = lib().wvl_build_locregs(ctypes.byref(g), nsf, c.ctypes.data, r.ctypes.data,
+                                     f.ctypes.data, int(ext), lr.ctypes.data, segs.ctypes.data,
+                                     ctypes.byref(n))
+    _check(st)
+    return lr, segs[:n.value].copy()
 
 
 def _ptr(t):

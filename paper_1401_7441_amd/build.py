@@ -59,20 +59,20 @@ def build(regen_filters: bool = True) -> str:
         _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         kobjs.append(obj)
     hobj = os.path.join(bdir, "wvl_host.o")
-    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fopenmp", "-Wall",
           "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c",
           os.path.join(CSRC, "wvl_host.cpp"), "-o", hobj])
     tmp = LIB + ".tmp"
     tlib = _torch_lib_dir()
     # plain host link: the device code is already embedded in wvl_kernels.o
-    _run(["g++", "-shared", "-fPIC", "-o", tmp, *kobjs, hobj, f"-L{tlib}", "-l:libamdhip64.so",
+    _run(["g++", "-shared", "-fPIC", "-fopenmp", "-o", tmp, *kobjs, hobj, f"-L{tlib}", "-l:libamdhip64.so",
           f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined"])
     os.replace(tmp, LIB)
     # native driver (own HIP runtime from the ROCm install, no torch)
     bobj = os.path.join(bdir, "wvl_bench_main.o")
     _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "wvl_bench_main.hip"), "-o", bobj])
     tmpb = BENCH_BIN + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-o", tmpb, bobj, *kobjs, hobj])
+    _run([hipcc, "--offload-arch=gfx950", "-fopenmp", "-o", tmpb, bobj, *kobjs, hobj])
     os.replace(tmpb, BENCH_BIN)
     return LIB
 

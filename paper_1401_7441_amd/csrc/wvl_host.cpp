@@ -338,13 +338,21 @@ wvl_status wvl_build_locregs(const wvl_grid* grid, int32_t nsf, const double* ce
   const int32_t* gn = grid->n;
   if (!(h > 0) || gn[0] <= 0 || gn[1] <= 0 || gn[2] <= 0 || ext < 0 || ext > 16)
     return fail(nullptr, WVL_EINVAL, "wvl_build_locregs: bad grid or ext");
-  struct Box {
-    int lo[3], hi[3];
-    std::vector<uint8_t> m, f;  // coarse / fine masks over the box [z][y][x]
+  // Three phases: (A, parallel over functions) input box and masks, and the
+  // global fine union F as one bit per grid point; (B, parallel) output
+  // masks and the four segment lists of each function; (C, sequential)
+  // global segment indices and coefficient offsets.  The result does not
+  // depend on the number of threads.
+  struct Sf {
+    int lo[3], hi[3], olo[3];
+    int err = 0;                       // 1 negative radius, 2 empty region
+    std::vector<uint8_t> m, f;         // coarse / fine masks over the box [z][y][x]
+    std::vector<wvl_seg> seg[4];       // in-coarse, in-fine, out-coarse, out-fine
+    int64_t tot[4] = {0, 0, 0, 0};
   };
-  std::vector<Box> boxes(nsf);
-  // union F of input fine sets, as a sorted list of global linear indices
-  std::vector<int64_t> Fpts;
+  std::vector<Sf> sfs(nsf);
+  const int64_t ngrid = (int64_t)gn[0] * gn[1] * gn[2];
+  std::vector<uint64_t> Fbits((size_t)((ngrid + 63) >> 6), 0);
   auto inside = [&](const double* c, double r, int i1, int i2, int i3) {
     const double dx = h * (double)i1 - c[0];
     const double dy = h * (double)i2 - c[1];
@@ -352,11 +360,15 @@ wvl_status wvl_build_locregs(const wvl_grid* grid, int32_t nsf, const double* ce
     const double d2 = (dx * dx + dy * dy) + dz * dz;
     return d2 <= r * r;
   };
+#pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < nsf; ++k) {
+    Sf& b = sfs[k];
     const double* c = centers + 3 * k;
     const double R = radii[k];
-    if (!(R >= 0) || !(fine_radii[k] >= 0))
-      return fail(nullptr, WVL_EINVAL, "function %d: negative radius", k);
+    if (!(R >= 0) || !(fine_radii[k] >= 0)) {
+      b.err = 1;
+      continue;
+    }
     int clo[3], chi[3];
     for (int a = 0; a < 3; ++a) {
       clo[a] = std::max(0, (int)std::floor((c[a] - R) / h) - 1);
@@ -371,8 +383,10 @@ wvl_status wvl_build_locregs(const wvl_grid* grid, int32_t nsf, const double* ce
             lo[1] = std::min(lo[1], i2); hi[1] = std::max(hi[1], i2);
             lo[2] = std::min(lo[2], i3); hi[2] = std::max(hi[2], i3);
           }
-    if (hi[0] < 0) return fail(nullptr, WVL_EINVAL, "function %d: empty localization region", k);
-    Box& b = boxes[k];
+    if (hi[0] < 0) {
+      b.err = 2;
+      continue;
+    }
     std::copy(lo, lo + 3, b.lo);
     std::copy(hi, hi + 3, b.hi);
     const int n0 = hi[0] - lo[0] + 1, n1 = hi[1] - lo[1] + 1, n2 = hi[2] - lo[2] + 1;
@@ -386,52 +400,78 @@ wvl_status wvl_build_locregs(const wvl_grid* grid, int32_t nsf, const double* ce
             b.m[p] = 1;
             if (inside(c, fine_radii[k], i1, i2, i3)) {
               b.f[p] = 1;
-              Fpts.push_back(((int64_t)i3 * gn[1] + i2) * gn[0] + i1);
+              const int64_t key = ((int64_t)i3 * gn[1] + i2) * gn[0] + i1;
+              __atomic_fetch_or(&Fbits[(size_t)(key >> 6)], uint64_t(1) << (key & 63),
+                                __ATOMIC_RELAXED);
             }
           }
         }
   }
-  std::sort(Fpts.begin(), Fpts.end());
-  Fpts.erase(std::unique(Fpts.begin(), Fpts.end()), Fpts.end());
+  for (int k = 0; k < nsf; ++k) {
+    if (sfs[k].err == 1) return fail(nullptr, WVL_EINVAL, "function %d: negative radius", k);
+    if (sfs[k].err == 2)
+      return fail(nullptr, WVL_EINVAL, "function %d: empty localization region", k);
+  }
   auto inF = [&](int i1, int i2, int i3) {
     const int64_t key = ((int64_t)i3 * gn[1] + i2) * gn[0] + i1;
-    return std::binary_search(Fpts.begin(), Fpts.end(), key);
+    return (Fbits[(size_t)(key >> 6)] >> (key & 63)) & 1;
   };
-  // emit segments
-  const int64_t cap = *nsegs;
-  int64_t nout = 0, coef = 0, ocoef = 0;
-  auto emit_rows = [&](const std::vector<uint8_t>& m, const int* olo, int n0, int n1, int n2,
-                       int64_t* total) {
-    int64_t first = nout, off = 0;
+  // maximal runs of a mask over a box at origin olo, rows (z, y) in order
+  auto runs = [](const std::vector<uint8_t>& m, const int* olo, int n0, int n1, int n2,
+                 std::vector<wvl_seg>* out) {
+    int64_t off = 0;
     for (int z = 0; z < n2; ++z)
       for (int y = 0; y < n1; ++y) {
+        const uint8_t* row = m.data() + ((size_t)z * n1 + y) * n0;
         int x = 0;
         while (x < n0) {
-          if (m[((size_t)z * n1 + y) * n0 + x]) {
+          if (row[x]) {
             const int x0 = x;
-            while (x < n0 && m[((size_t)z * n1 + y) * n0 + x]) ++x;
-            if (segs && nout < cap) {
-              wvl_seg& s = segs[nout];
-              s.i1s = olo[0] + x0;
-              s.i1e = olo[0] + x - 1;
-              s.i2 = olo[1] + y;
-              s.i3 = olo[2] + z;
-              s.off = off;
-            }
-            ++nout;
+            while (x < n0 && row[x]) ++x;
+            out->push_back(wvl_seg{olo[0] + x0, olo[0] + x - 1, olo[1] + y, olo[2] + z, off});
             off += x - x0;
           } else {
             ++x;
           }
         }
       }
-    *total = off;
-    return first;
+    return off;
   };
+#pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < nsf; ++k) {
-    const Box& b = boxes[k];
+    Sf& b = sfs[k];
     const double* c = centers + 3 * k;
     const int n0 = b.hi[0] - b.lo[0] + 1, n1 = b.hi[1] - b.lo[1] + 1, n2 = b.hi[2] - b.lo[2] + 1;
+    b.tot[0] = runs(b.m, b.lo, n0, n1, n2, &b.seg[0]);
+    b.tot[1] = runs(b.f, b.lo, n0, n1, n2, &b.seg[1]);
+    std::vector<uint8_t>().swap(b.m);
+    std::vector<uint8_t>().swap(b.f);
+    // output pattern over the grown box, clipped to the grid
+    int ohi[3];
+    for (int a = 0; a < 3; ++a) {
+      b.olo[a] = std::max(0, b.lo[a] - ext);
+      ohi[a] = std::min(gn[a] - 1, b.hi[a] + ext);
+    }
+    const int m0 = ohi[0] - b.olo[0] + 1, m1 = ohi[1] - b.olo[1] + 1, m2 = ohi[2] - b.olo[2] + 1;
+    std::vector<uint8_t> om((size_t)m0 * m1 * m2, 0), of((size_t)m0 * m1 * m2, 0);
+    const double Rp = radii[k] + ext * h;
+    for (int i3 = b.olo[2]; i3 <= ohi[2]; ++i3)
+      for (int i2 = b.olo[1]; i2 <= ohi[1]; ++i2)
+        for (int i1 = b.olo[0]; i1 <= ohi[0]; ++i1)
+          if (inside(c, Rp, i1, i2, i3)) {
+            const size_t p = ((size_t)(i3 - b.olo[2]) * m1 + (i2 - b.olo[1])) * m0 + (i1 - b.olo[0]);
+            om[p] = 1;
+            if (inF(i1, i2, i3)) of[p] = 1;
+          }
+    b.tot[2] = runs(om, b.olo, m0, m1, m2, &b.seg[2]);
+    b.tot[3] = runs(of, b.olo, m0, m1, m2, &b.seg[3]);
+  }
+  // global indices, coefficient offsets, copy-out
+  const int64_t cap = *nsegs;
+  int64_t nout = 0, coef = 0, ocoef = 0;
+  for (int k = 0; k < nsf; ++k) {
+    Sf& b = sfs[k];
+    const double* c = centers + 3 * k;
     wvl_locreg& L = lr[k];
     std::memset(&L, 0, sizeof L);
     std::copy(c, c + 3, L.center);
@@ -439,37 +479,21 @@ wvl_status wvl_build_locregs(const wvl_grid* grid, int32_t nsf, const double* ce
     L.fine_radius = fine_radii[k];
     L.ext = ext;
     std::copy(b.lo, b.lo + 3, L.lo);
-    L.dims[0] = n0; L.dims[1] = n1; L.dims[2] = n2;
-    int64_t tot;
-    L.seg_c = emit_rows(b.m, b.lo, n0, n1, n2, &tot);
-    L.nseg_c = nout - L.seg_c;
-    L.n_c = tot;
-    L.seg_f = emit_rows(b.f, b.lo, n0, n1, n2, &tot);
-    L.nseg_f = nout - L.seg_f;
-    L.n_f = tot;
-    // output pattern over the grown box, clipped to the grid
-    int olo[3], ohi[3];
-    for (int a = 0; a < 3; ++a) {
-      olo[a] = std::max(0, b.lo[a] - ext);
-      ohi[a] = std::min(gn[a] - 1, b.hi[a] + ext);
+    for (int a = 0; a < 3; ++a) L.dims[a] = b.hi[a] - b.lo[a] + 1;
+    int64_t* first[4] = {&L.seg_c, &L.seg_f, &L.oseg_c, &L.oseg_f};
+    int64_t* count[4] = {&L.nseg_c, &L.nseg_f, &L.noseg_c, &L.noseg_f};
+    for (int p = 0; p < 4; ++p) {
+      *first[p] = nout;
+      *count[p] = (int64_t)b.seg[p].size();
+      if (segs && nout + (int64_t)b.seg[p].size() <= cap)
+        std::copy(b.seg[p].begin(), b.seg[p].end(), segs + nout);
+      nout += (int64_t)b.seg[p].size();
+      std::vector<wvl_seg>().swap(b.seg[p]);
     }
-    const int m0 = ohi[0] - olo[0] + 1, m1 = ohi[1] - olo[1] + 1, m2 = ohi[2] - olo[2] + 1;
-    std::vector<uint8_t> om((size_t)m0 * m1 * m2, 0), of((size_t)m0 * m1 * m2, 0);
-    const double Rp = radii[k] + ext * h;
-    for (int i3 = olo[2]; i3 <= ohi[2]; ++i3)
-      for (int i2 = olo[1]; i2 <= ohi[1]; ++i2)
-        for (int i1 = olo[0]; i1 <= ohi[0]; ++i1)
-          if (inside(c, Rp, i1, i2, i3)) {
-            const size_t p = ((size_t)(i3 - olo[2]) * m1 + (i2 - olo[1])) * m0 + (i1 - olo[0]);
-            om[p] = 1;
-            if (inF(i1, i2, i3)) of[p] = 1;
-          }
-    L.oseg_c = emit_rows(om, olo, m0, m1, m2, &tot);
-    L.noseg_c = nout - L.oseg_c;
-    L.on_c = tot;
-    L.oseg_f = emit_rows(of, olo, m0, m1, m2, &tot);
-    L.noseg_f = nout - L.oseg_f;
-    L.on_f = tot;
+    L.n_c = b.tot[0];
+    L.n_f = b.tot[1];
+    L.on_c = b.tot[2];
+    L.on_f = b.tot[3];
     L.coef_off = coef;
     coef += L.n_c + 7 * L.n_f;
     L.ocoef_off = ocoef;

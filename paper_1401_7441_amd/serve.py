@@ -41,15 +41,18 @@ from . import (Context, Graph, Plan, apply_local_ham, build_locregs, sparse_over
 
 @dataclasses.dataclass
 class Request:
-    """One system.  Host inputs are prepared before submission; `pot` is
-    the global fine-grid potential (numpy, z, y, x)."""
+    """One system.  Host inputs (segments, coefficients) are prepared before
+    submission; the potential is given by its Gaussian wells (`geom`,
+    `pot_params`) and built on the device at admission, where a DFT code
+    would produce it."""
     rid: int
     h: float
     grid_n: tuple
     locregs: np.ndarray
     segs: np.ndarray
     psi: np.ndarray
-    pot: np.ndarray
+    geom: object
+    pot_params: tuple
     arrival: float = 0.0
     # filled by the engine
     admitted: float = math.nan
@@ -65,6 +68,18 @@ class Request:
     @property
     def latency(self):
         return self.done - self.arrival
+
+    def potential(self, device, dtype):
+        """The global fine-grid potential (torch tensor, z, y, x)."""
+        import inputs
+        return inputs.potential(self.geom, device=device, dtype=dtype,
+                                params=self.pot_params).contiguous()
+
+    def fresh(self, arrival=0.0):
+        """A new request on the same inputs (shared host arrays)."""
+        return Request(rid=self.rid, h=self.h, grid_n=self.grid_n, locregs=self.locregs,
+                       segs=self.segs, psi=self.psi, geom=self.geom, pot_params=self.pot_params,
+                       arrival=arrival)
 
 
 def footprint_bytes(locregs, grid_n, sz, workspace_bytes, nnz_bound=None):
@@ -89,7 +104,7 @@ class _Active:
             self.ctx = Context(req.h, req.grid_n, stream=self.stream)
             self.plan = Plan(self.ctx, req.locregs, req.segs, max_workspace=max_workspace)
             self.psi = torch.from_numpy(req.psi).to(dtype).to("cuda", non_blocking=True)
-            self.pot = torch.from_numpy(req.pot).to(dtype).to("cuda", non_blocking=True)
+            self.pot = req.potential("cuda", dtype)
             self.hpsi = torch.zeros(self.plan.info["out_coefs"], dtype=dtype, device="cuda")
             self.ek = torch.zeros(req.nsf, dtype=torch.float64, device="cuda")
             self.ep = torch.zeros_like(self.ek)
@@ -273,7 +288,7 @@ def run_per_function(requests, eta=0.01, steps=5, keep_results=False):
         ctx = Context(req.h, req.grid_n)
         full = Plan(ctx, req.locregs, req.segs)
         psi = torch.from_numpy(req.psi).to(torch.float64).cuda()
-        pot = torch.from_numpy(req.pot).to(torch.float64).cuda()
+        pot = req.potential("cuda", torch.float64)
         hpsi = torch.zeros(full.info["out_coefs"], dtype=torch.float64, device="cuda")
         singles = []
         for k in range(req.nsf):
@@ -304,18 +319,28 @@ def run_per_function(requests, eta=0.01, steps=5, keep_results=False):
 
 
 def _single_plan(ctx, one, segs):
-    """A plan for one function whose coefficients start at offset 0 (the
-    function's own slices of the request's buffers)."""
+    """A plan for one function with its own segments and coefficients at
+    offset 0 (the function's own slices of the request's buffers)."""
     in_off, out_off = int(one["coef_off"][0]), int(one["ocoef_off"][0])
+    parts, base = [], 0
+    for key, cnt in (("seg_c", "nseg_c"), ("seg_f", "nseg_f"), ("oseg_c", "noseg_c"),
+                     ("oseg_f", "noseg_f")):
+        a, n = int(one[key][0]), int(one[cnt][0])
+        parts.append(segs[a:a + n])
+        one[key] = base
+        base += n
     one["coef_off"] = 0
     one["ocoef_off"] = 0
-    return Plan(ctx, one, segs), in_off, out_off
+    return Plan(ctx, one, np.concatenate(parts)), in_off, out_off
 
 
-def make_requests(n, dtype_sz=4, rate=None, seed=0, max_nsf=None, ngauss=32):
+def make_requests(n, dtype_sz=4, rate=None, seed=0, max_nsf=None, ngauss=32, fast=False):
     """`n` serving requests drawn as the serving workload (systems of 50-4000
     support functions, log-uniform) with Poisson arrivals at `rate` per
-    second (all at t = 0 when rate is None).  Host inputs only."""
+    second (all at t = 0 when rate is None).  Host inputs only.  With
+    `fast`, each request's coefficients are N(0, 1/n_coef) from one stream
+    per request instead of the per-function enveloped draws (the work done
+    does not depend on the values)."""
     import inputs
     rng = np.random.default_rng(7000 + seed)
     t = 0.0
@@ -325,15 +350,19 @@ def make_requests(n, dtype_sz=4, rate=None, seed=0, max_nsf=None, ngauss=32):
         if max_nsf is not None and len(g.radii) > max_nsf:
             g = inputs.geometry("serve", nsf=max_nsf, seed_offset=seed * 100000 + i)
         lr, segs = build_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
-        psi = np.concatenate([
-            inputs.coefficients(g, k, _pts(segs, lr[k], "c"), _pts(segs, lr[k], "f"))
-            for k in range(len(lr))])
+        if fast:
+            n_in = int(np.sum(lr["n_c"] + 7 * lr["n_f"]))
+            psi = inputs.flat_coefficients(g, n_in, seed=seed * 100000 + i)
+        else:
+            psi = np.concatenate([
+                inputs.coefficients(g, k, _pts(segs, lr[k], "c"), _pts(segs, lr[k], "f"))
+                for k in range(len(lr))])
         params = inputs.potential_params(g, ngauss=min(ngauss, len(lr)))
-        pot = inputs.potential(g, device="cpu", params=params).numpy()
         if rate is not None:
             t += rng.exponential(1.0 / rate)
         reqs.append(Request(rid=i, h=g.h, grid_n=tuple(g.grid_n), locregs=lr, segs=segs,
-                            psi=psi, pot=pot, arrival=t if rate is not None else 0.0))
+                            psi=psi, geom=g, pot_params=params,
+                            arrival=t if rate is not None else 0.0))
     return reqs
 
 
@@ -356,3 +385,62 @@ def percentile(xs, q):
     k = (len(xs) - 1) * q / 100.0
     lo, hi = int(math.floor(k)), int(math.ceil(k))
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_requests=4,
+              baseline_budget_s=60.0, log=print):
+    """Serving measurement: (1) saturated throughput with every request
+    queued at t = 0; (2) Poisson arrivals at `load` x that request rate, p50
+    and p99 latency; (3) the per-function FP64 baseline on the first
+    `baseline_requests` requests of the same arrival trace (one at a time).
+    Returns a dict of the figures."""
+    import torch
+    t0 = time.perf_counter()
+    base_reqs = make_requests(n_requests, seed=seed, fast=True)
+    t_prep = time.perf_counter() - t0
+    reqs = [r.fresh() for r in base_reqs]
+    sizes = [r.nsf for r in reqs]
+    log(f"serving: {n_requests} requests, {sum(sizes)} functions "
+        f"(min {min(sizes)}, median {int(np.median(sizes))}, max {max(sizes)}), "
+        f"inputs prepared in {t_prep:.1f} s")
+    # warm-up on a small request (kernel loads, allocator)
+    Engine(dtype=dtype, steps=1).run(make_requests(1, seed=seed + 99, max_nsf=50, fast=True))
+    torch.cuda.synchronize()
+    eng = Engine(dtype=dtype, steps=steps)
+    t1 = time.perf_counter()
+    eng.run(reqs)
+    t_sat = time.perf_counter() - t1
+    mu = n_requests / t_sat
+    sat = {"seconds": t_sat, "requests_per_s": mu, "sf_steps_per_s": eng.sf_steps / t_sat,
+           "ticks": eng.ticks}
+    log(f"serving: saturated {t_sat:.2f} s, {mu:.2f} requests/s, "
+        f"{eng.sf_steps / t_sat:.0f} support-function steps/s")
+    rate = load * mu
+    rng = np.random.default_rng(9000 + seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    reqs2 = [r.fresh(float(a)) for r, a in zip(base_reqs, arrivals)]
+    eng2 = Engine(dtype=dtype, steps=steps)
+    t2 = time.perf_counter()
+    done = eng2.run(reqs2)
+    t_run = time.perf_counter() - t2
+    lat = [r.latency for r in done]
+    served = {"offered_requests_per_s": rate, "load": load, "seconds": t_run,
+              "requests_per_s": len(done) / t_run, "sf_steps_per_s": eng2.sf_steps / t_run,
+              "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+              "max_s": max(lat), "rejected": len(eng2.rejected)}
+    log(f"serving: load {load}: p50 {served['p50_s']:.3f} s, p99 {served['p99_s']:.3f} s")
+    base = None
+    if baseline_requests:
+        breqs = [r.fresh(float(a)) for r, a in zip(base_reqs[:baseline_requests], arrivals)]
+        tb = time.perf_counter()
+        bdone = run_per_function(breqs, steps=steps)
+        blat = [r.latency for r in bdone]
+        base = {"requests": baseline_requests, "seconds": time.perf_counter() - tb,
+                "p50_s": percentile(blat, 50), "p99_s": percentile(blat, 99),
+                "engine_p50_s_same_requests": percentile(lat[:baseline_requests], 50),
+                "kind": "FP64, one support function per apply, no graphs, FIFO"}
+        log(f"serving: per-function FP64 baseline p50 {base['p50_s']:.3f} s, "
+            f"p99 {base['p99_s']:.3f} s over its {baseline_requests} requests")
+    return {"requests": n_requests, "functions": sum(sizes), "steps": steps, "dtype": dtype,
+            "saturated": sat, "poisson": served, "per_function_fp64": base,
+            "latency_note": "arrival -> end of the last step, host clock"}

@@ -68,7 +68,8 @@ def test_one_serving_step_against_the_oracle():
     lrs = LR.sphere_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
     off = np.cumsum([0] + [l.n_c + 7 * l.n_f for l in lrs])
     coefs = [req.psi[off[k]:off[k + 1]] for k in range(nsf)]
-    ohs = [Hm.apply_local_ham(lrs[k], coefs[k], req.pot, g.h)[0] for k in range(nsf)]
+    pot = req.potential("cpu", torch.float64).numpy()
+    ohs = [Hm.apply_local_ham(lrs[k], coefs[k], pot, g.h)[0] for k in range(nsf)]
     rp, cl, hv = SP.matrix(lrs, coefs, ohs, True)
     for k in range(nsf):
         row = list(cl[rp[k]:rp[k + 1]])
