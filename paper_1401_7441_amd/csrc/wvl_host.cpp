@@ -181,6 +181,7 @@ struct wvl_plan {
   SfDev* d_sf = nullptr;
   wvl_seg* d_seg = nullptr;
   int32_t* d_rt = nullptr;
+  RowRun* d_rr = nullptr;
   SfWork* d_wk = nullptr;
   wvl_plan_info info{};
   PatternCache pat[2];
@@ -285,6 +286,24 @@ void bbox(const wvl_seg* segs, int64_t first, int64_t count, int32_t* bb) {
 
 // row table of one pattern: rt[r] .. rt[r+1] are the global segment indices
 // of box row r = (i3 - oz) * by + (i2 - oy)
+// compact per-row runs of one pattern over its box rows (see RowRun)
+void row_runs(const wvl_seg* segs, int64_t first, int64_t count, int oy, int oz, int by, int bz,
+              std::vector<RowRun>& rr) {
+  const size_t base = rr.size();
+  rr.resize(base + (size_t)by * bz, RowRun{0, 0, 0});
+  for (int64_t q = 0; q < count; ++q) {
+    const wvl_seg& s = segs[first + q];
+    RowRun& r = rr[base + (size_t)(s.i3 - oz) * by + (s.i2 - oy)];
+    if (r.len == 0) {
+      r.x0 = (uint16_t)s.i1s;
+      r.len = (uint16_t)(s.i1e - s.i1s + 1);
+      r.off = (int32_t)s.off;
+    } else {
+      r.len = kMultiRun;
+    }
+  }
+}
+
 void row_table(const wvl_seg* segs, int64_t first, int64_t count, int ox, int oy, int oz, int by,
                int bz, std::vector<int32_t>& rt) {
   (void)ox;
@@ -588,6 +607,7 @@ void wvl_plan_destroy(wvl_plan* plan) {
   if (plan->d_sf) (void)hipFree(plan->d_sf);
   if (plan->d_seg) (void)hipFree(plan->d_seg);
   if (plan->d_rt) (void)hipFree(plan->d_rt);
+  if (plan->d_rr) (void)hipFree(plan->d_rr);
   if (plan->d_wk) (void)hipFree(plan->d_wk);
   free_pattern(plan->pat[0]);
   free_pattern(plan->pat[1]);
@@ -740,6 +760,8 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   if (nsegs >= (int64_t)1 << 31)
     return fail(ctx, WVL_EUNSUPPORTED, "wvl_plan_create: more than 2^31 segments");
   const int32_t* gn = ctx->grid.n;
+  if (gn[0] > 65535)
+    return fail(ctx, WVL_EUNSUPPORTED, "wvl_plan_create: grid wider than 65535 points along x");
   wvl_status st = WVL_OK;
   bool in_sub_out = true;   // every input pattern inside its output pattern
   std::vector<std::pair<int64_t, int64_t>> outs;
@@ -804,6 +826,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   P->nsf = nsf;
   P->h_sf.resize(nsf);
   std::vector<int32_t> rt;
+  std::vector<RowRun> rr;
   int64_t box_in = 0, box_out = 0, in_coefs = 0, out_coefs = 0;
   for (int k = 0; k < nsf; ++k) {
     const wvl_locreg& L = lr[k];
@@ -834,6 +857,9 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
       S.rt[p] = (int64_t)rt.size();
       row_table(segs, firsts[p], counts[p], L.lo[0] - g, L.lo[1] - g, L.lo[2] - g,
                 L.dims[1] + 2 * g, L.dims[2] + 2 * g, rt);
+      S.rr[p] = (int64_t)rr.size();
+      row_runs(segs, firsts[p], counts[p], L.lo[1] - g, L.lo[2] - g, L.dims[1] + 2 * g,
+               L.dims[2] + 2 * g, rr);
     }
     bbox(segs, L.seg_c, L.nseg_c, S.bb_in);
     bbox(segs, L.oseg_c, L.noseg_c, S.bb_out);
@@ -877,6 +903,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   if ((st = upload(ctx, &P->d_sf, P->h_sf.data(), sizeof(SfDev) * nsf)) != WVL_OK ||
       (st = upload(ctx, &P->d_seg, segs, sizeof(wvl_seg) * nsegs)) != WVL_OK ||
       (st = upload(ctx, &P->d_rt, rt.data(), sizeof(int32_t) * rt.size())) != WVL_OK ||
+      (st = upload(ctx, &P->d_rr, rr.data(), sizeof(RowRun) * rr.size())) != WVL_OK ||
       (st = upload(ctx, &P->d_wk, P->lay.wk.data(), sizeof(SfWork) * nsf)) != WVL_OK) {
     wvl_plan_destroy(P);
     return st;
@@ -1144,8 +1171,8 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
     if (!bra_c || !ket_c) return fail(ctx, WVL_EINVAL, "wvl_sparse_overlap: null bra or ket");
     WVL_LAUNCH(ctx, ket_is_output ? KK_SPARSE_H : KK_SPARSE_S,
                launch_sparse_values(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt,
-                                    ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col, pc.d_order,
-                                    pc.nnz, val));
+                                    P->d_rr, ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col,
+                                    pc.d_order, pc.nnz, val));
   }
   return WVL_OK;
 }
@@ -1237,7 +1264,7 @@ static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const 
       double* val = ket_out ? h_val : s_val;
       const PatternCache& pc = P->pat[ket_out];
       if (!val || pc.nnz == 0) continue;
-      const int e = launch_sparse_values(f64, cs, P->d_sf, P->d_seg, P->d_rt, ket_out,
+      const int e = launch_sparse_values(f64, cs, P->d_sf, P->d_seg, P->d_rt, P->d_rr, ket_out,
                                          psi_c, ket_out ? hpsi_c : psi_c, pc.d_row, pc.d_col,
                                          pc.d_order, pc.nnz, val);
       if (e != 0) st = fail(ctx, WVL_EDEVICE, "capture of sparse values failed");

@@ -29,7 +29,19 @@ struct SfDev {
   // coarse patterns, global indices (empty pattern: x0 > x1).
   int32_t bb_in[6];
   int32_t bb_out[6];
+  // compact row runs: for pattern p, RowRun entry rr[p] + r describes box
+  // row r (same row numbering as rt)
+  int64_t rr[4];
 };
+
+// One box row of a pattern: its single run [x0, x0 + len) starting at
+// coefficient `off` of the pattern; len 0 = empty row, kMultiRun = several
+// runs (walk the segments through the row table instead).
+struct RowRun {
+  uint16_t x0, len;
+  int32_t off;
+};
+constexpr uint16_t kMultiRun = 0xFFFF;
 
 // Workspace offsets (elements of the compute type) of one support function
 // in the workspace (R = 2N + 29, O = N + 2 ext).  The plan keeps these
@@ -106,8 +118,8 @@ int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, co
                   double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
                   const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs);
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
-                         const int32_t* rt, int ket_out, const void* bra, const void* ket,
-                         const int32_t* row, const int32_t* col, const int32_t* order,
-                         int64_t nnz, double* val);
+                         const int32_t* rt, const RowRun* rr, int ket_out, const void* bra,
+                         const void* ket, const int32_t* row, const int32_t* col,
+                         const int32_t* order, int64_t nnz, double* val);
 
 }  // namespace wvl

@@ -214,7 +214,8 @@ __device__ __forceinline__ double run_dot(const T* __restrict__ pa, const T* __r
 template <typename T>
 __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ sfs,
                                                       const wvl_seg* __restrict__ seg,
-                                                      const int32_t* __restrict__ rt, int ket_out,
+                                                      const int32_t* __restrict__ rt,
+                                                      const RowRun* __restrict__ rr, int ket_out,
                                                       const T* __restrict__ bra,
                                                       const T* __restrict__ ket,
                                                       const int32_t* __restrict__ rowi,
@@ -255,9 +256,23 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
         const int y = y0 + r % ny, z = z0 + r / ny;
         const int64_t ra = (int64_t)(z - A.lo[2]) * A.n[1] + (y - A.lo[1]);
         const int64_t rb = (int64_t)(z - pb.oz) * pb.by + (y - pb.oy);
+        const int pB = fine ? pf : pc;
+        // compact row runs: one 8-byte record per row and side
+        const RowRun wa = rr[A.rr[fine] + ra], wb = rr[B.rr[pB] + rb];
+        if (wa.len == 0 || wb.len == 0) continue;
+        if (wa.len != kMultiRun && wb.len != kMultiRun) {
+          const int x0 = max((int)wa.x0, (int)wb.x0);
+          const int x1 = min((int)wa.x0 + wa.len, (int)wb.x0 + wb.len) - 1;
+          if (x0 <= x1) {
+            ea[fine][lane] = A.cin + (fine ? A.n_c : 0) + wa.off + (x0 - wa.x0);
+            eb[fine][lane] = bc + (fine ? bnc : 0) + wb.off + (x0 - wb.x0);
+            el[fine][lane] = x1 - x0 + 1;
+          }
+          continue;
+        }
+        // a row with several runs on either side: merge the segment lists
         int qa = rt[A.rt[fine] + ra];
         const int qa1 = rt[A.rt[fine] + ra + 1];
-        const int pB = fine ? pf : pc;
         int qb = rt[B.rt[pB] + rb];
         const int qb1 = rt[B.rt[pB] + rb + 1];
         bool first = true;
@@ -461,19 +476,19 @@ int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int3
 }
 
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
-                         const int32_t* rt, int ket_out, const void* bra, const void* ket,
-                         const int32_t* row, const int32_t* col, const int32_t* order,
-                         int64_t nnz, double* val) {
+                         const int32_t* rt, const RowRun* rr, int ket_out, const void* bra,
+                         const void* ket, const int32_t* row, const int32_t* col,
+                         const int32_t* order, int64_t nnz, double* val) {
   if (nnz == 0) return 0;
   const unsigned nblk = (unsigned)(8 * ((nnz + 7) / 8));
   if (f64)
     hipLaunchKernelGGL(k_sparse_values<double>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
-                       seg, rt, ket_out, (const double*)bra, (const double*)ket, row, col, order,
-                       nnz, val);
+                       seg, rt, rr, ket_out, (const double*)bra, (const double*)ket, row, col,
+                       order, nnz, val);
   else
     hipLaunchKernelGGL(k_sparse_values<float>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
-                       seg, rt, ket_out, (const float*)bra, (const float*)ket, row, col, order,
-                       nnz, val);
+                       seg, rt, rr, ket_out, (const float*)bra, (const float*)ket, row, col,
+                       order, nnz, val);
   return (int)hipGetLastError();
 }
 
