@@ -309,6 +309,7 @@ def main():
     ctx = S["ctx"]
     prof = {}
     eager_ms = None
+    conf_ms, cprof = None, {}
     if not args.no_trace:
         ctx.profile(True)
         ctx.profile_reset()
@@ -319,6 +320,17 @@ def main():
         torch.cuda.synchronize()
         eager_ms = (time.perf_counter() - t1) * 1e3 / args.steps
         prof = ctx.profile_read()
+        # the same applies with a confining potential a |r - R|^4 on every function
+        conf = torch.full((nsf,), 0.01, dtype=torch.float64, device="cuda")
+        ctx.profile_reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            W.apply_local_ham(S["plan"], S["psi"], S["pot"], S["hpsi"], S["ek"], S["ep"],
+                              S["ws"], conf=conf)
+        torch.cuda.synchronize()
+        conf_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        cprof = ctx.profile_read()
         ctx.profile(False)
     ms_step = dt_s * 1e3 / args.steps
     value = nsf * args.steps / dt_s
@@ -390,6 +402,11 @@ def main():
         "kernels": kernels,
         "kernel_timing": "HIP events the library records around each launch on its stream, "
                          "over a separate pass of the same number of eager steps",
+        "confinement": None if conf_ms is None else {
+            "apply_ms": conf_ms,
+            "pot_column_ms": cprof["pot_column"][1] / max(1, args.steps),
+            "pot_column_ms_without": prof["pot_column"][1] / max(1, args.steps),
+            "prefactor": 0.01},
         "schedule": {"timed": "graph replay" if graph is not None else "eager calls",
                      "eager_ms_per_step": eager_ms,
                      "nbins": tune["best"]["nbins"] if tune else 1,

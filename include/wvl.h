@@ -189,6 +189,17 @@ wvl_status wvl_apply_local_ham(wvl_plan* plan, wvl_dtype dt, uint32_t terms, con
                                const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
                                void* workspace);
 
+/* wvl_apply_local_ham with a confining potential per function (Sec. IV.A:
+ * the quartic confinement a_a |r - R_a|^4 of the trace and hybrid modes):
+ * on the fine grid the potential of function a becomes V(r) + conf[a]
+ * |r - center_a|^4, with center_a = wvl_locreg.center and the fine point l
+ * of an axis at (2 lo + l) h/2.  conf: device double[nsf] (0 = none for
+ * that function).  terms must contain WVL_POT; e_pot then includes the
+ * confinement energy.  Other arguments and errors as wvl_apply_local_ham. */
+wvl_status wvl_apply_local_ham_conf(wvl_plan* plan, wvl_dtype dt, uint32_t terms,
+                                    const void* psi_c, const void* pot, const double* conf,
+                                    void* hpsi_c, double* e_kin, double* e_pot, void* workspace);
+
 /* Kinetic term only (Sec. III.B, the -1/2 nabla^2 part), ACCUMULATED into
  * hpsi_c (device, output layout): hpsi += L' T L psi.  e_kin as above. */
 wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hpsi_c,

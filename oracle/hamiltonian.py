@@ -63,12 +63,28 @@ def potential_block(lr: Locreg, pot):
                2 * lo[0]:2 * lo[0] + 2 * n[0] + 29]
 
 
-def apply_local_ham(lr: Locreg, coef, pot, h, kinetic=True, potential=True):
+def confinement_block(lr: Locreg, h, a, center):
+    """a |r - center|^4 on the function's fine points (paper Sec. IV.A: the
+    confining potential of the trace and hybrid modes).  Local fine point l
+    sits at (2 lo + l) h/2, l = -14..2N+14."""
+    ax = []
+    for d in range(3):
+        l = np.arange(2 * lr.dims[d] + 29) - 14
+        ax.append((2 * lr.lo[d] + l) * (h / 2.0) - center[d])
+    r2 = ax[2][:, None, None] ** 2 + ax[1][None, :, None] ** 2 + ax[0][None, None, :] ** 2
+    return a * r2 * r2
+
+
+def apply_local_ham(lr: Locreg, coef, pot, h, kinetic=True, potential=True, conf=0.0,
+                    center=None):
     """Returns (hpsi_c, e_kin, e_pot) for one support function.
 
-    coef : compressed input coefficients on the input pattern (FP64)
-    pot  : global fine-grid potential, shape (2n3+29, 2n2+29, 2n1+29)
-    h    : coarse grid spacing (bohr)
+    coef   : compressed input coefficients on the input pattern (FP64)
+    pot    : global fine-grid potential, shape (2n3+29, 2n2+29, 2n1+29)
+    h      : coarse grid spacing (bohr)
+    conf   : prefactor a of the confining potential a |r - R|^4 added to the
+             potential (0: none); R = `center`, else the region's centre.
+             e_pot then includes the confinement energy.
     """
     n = lr.dims                      # (N1, N2, N3)
     nz = (n[2], n[1], n[0])          # z, y, x order for array axes
@@ -87,6 +103,8 @@ def apply_local_ham(lr: Locreg, coef, pot, h, kinetic=True, potential=True):
         f = W.magic_3d(sp, sp_lo, f_lo, f_n)
         v = potential_block(lr, pot)
         assert v.shape == f.shape, (v.shape, f.shape)
+        if conf:
+            v = v + confinement_block(lr, h, conf, lr.center if center is None else center)
         e_pot = float(np.sum(v * f * f))
         y += W.magic_t_3d(v * f, f_lo, b_lo, b_n)
     if kinetic:

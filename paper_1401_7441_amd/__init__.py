@@ -42,7 +42,8 @@ LOCREG_DTYPE = np.dtype([
 
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
-            "wvl_compress", "wvl_apply_local_ham", "wvl_kinetic", "wvl_sparse_overlap",
+            "wvl_compress", "wvl_apply_local_ham", "wvl_apply_local_ham_conf", "wvl_kinetic",
+            "wvl_sparse_overlap",
             "wvl_update", "wvl_graph_create", "wvl_graph_launch", "wvl_graph_destroy",
             "wvl_plan_autotune",
             "wvl_profile_enable", "wvl_profile_reset", "wvl_profile_count", "wvl_profile_read")
@@ -99,6 +100,7 @@ def _load():
         "wvl_compress": [P, ctypes.c_int, P, P],
         "wvl_apply_local_ham": [P, ctypes.c_int, U32, P, P, P, P, P, P],
         "wvl_kinetic": [P, ctypes.c_int, P, P, P, P],
+        "wvl_apply_local_ham_conf": [P, ctypes.c_int, U32, P, P, P, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
         "wvl_update": [P, ctypes.c_int, D, P, P, P],
         "wvl_graph_create": [P, ctypes.c_int, U32, P, P, P, P, P, P, P, P, ctypes.POINTER(P)],
@@ -328,9 +330,13 @@ def compress(plan: Plan, box, hpsi_c):
 
 
 def apply_local_ham(plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None, workspace=None,
-                    terms=KIN | POT):
-    """wvl_apply_local_ham; e_kin / e_pot are float64 device tensors [nsf] or None."""
-    _need_cuda(psi_c, pot, hpsi_c, e_kin, e_pot, workspace)
+                    terms=KIN | POT, conf=None):
+    """wvl_apply_local_ham (wvl_apply_local_ham_conf when `conf`, a float64
+    device tensor [nsf] of confinement prefactors, is given); e_kin / e_pot
+    are float64 device tensors [nsf] or None."""
+    _need_cuda(psi_c, pot, hpsi_c, e_kin, e_pot, workspace, conf)
+    if conf is not None and (conf.dtype.itemsize != 8 or conf.numel() < plan.nsf):
+        raise WvlError(WVL_EINVAL, "conf must be float64 with nsf entries")
     dt = _dtype_code(psi_c, pot, hpsi_c)
     _check_sizes(plan, psi_c, hpsi_c, e_kin, e_pot, workspace, dt)
     if pot is not None:
@@ -340,6 +346,11 @@ def apply_local_ham(plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None, work
             raise WvlError(WVL_EINVAL, f"potential has {pot.numel()} points, the grid needs {need}")
     if workspace is None:
         workspace = plan.new_workspace(psi_c.dtype)
+    if conf is not None:
+        _check(lib().wvl_apply_local_ham_conf(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
+                                              _ptr(conf), _ptr(hpsi_c), _ptr(e_kin), _ptr(e_pot),
+                                              _ptr(workspace)), plan.ctx.handle)
+        return
     _check(lib().wvl_apply_local_ham(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
                                     _ptr(hpsi_c), _ptr(e_kin), _ptr(e_pot), _ptr(workspace)),
            plan.ctx.handle)

@@ -212,9 +212,13 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
                                                     const SfWork* __restrict__ wk, int sf0,
                                                     T* __restrict__ ws, const T* __restrict__ pot,
                                                     int nf1, int nf2,
-                                                    double* __restrict__ epart) {
+                                                    double* __restrict__ epart,
+                                                    const double* __restrict__ conf, double hh) {
   const SfWork& w = wk[blockIdx.y];
   const SfDev& sf = sfs[w.id];
+  // confining potential a |r - R|^4 (a = 0: none); fine point p of an axis
+  // sits at (2 lo + p - 14) h/2
+  const double ca = conf ? conf[w.id] : 0.0;
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int R0 = 2 * N0 + 29, R1 = 2 * N1 + 29, R2 = 2 * N2 + 29;
   const int O2 = N2 + 2 * e;
@@ -230,6 +234,10 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
     const int64_t vstride = (int64_t)nf1 * nf2;
     const T* vp = pot + ((int64_t)(2 * sf.lo[2]) * nf2 + (2 * sf.lo[1] + py)) * nf1 +
                   (2 * sf.lo[0] + px);
+    const double cdx = (double)(2 * sf.lo[0] + px - 14) * hh - sf.c[0];
+    const double cdy = (double)(2 * sf.lo[1] + py - 14) * hh - sf.c[1];
+    const double cxy = cdx * cdx + cdy * cdy;
+    const double cz0 = (double)(2 * sf.lo[2] - 14) * hh - sf.c[2];
     T xs[16], xd[16], a0[16], a1[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) xs[k] = xd[k] = a0[k] = a1[k] = T(0);
@@ -253,8 +261,14 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
           if (k < 15) fo += Ct<T>(0, 2 * k + 1) * xs[sl] + Ct<T>(1, 2 * k + 1) * xd[sl];
         }
         const int p = 2 * q;
-        const T ve = p < R2 ? vp[(int64_t)p * vstride] : T(0);
-        const T vo = p + 1 < R2 ? vp[(int64_t)(p + 1) * vstride] : T(0);
+        T ve = p < R2 ? vp[(int64_t)p * vstride] : T(0);
+        T vo = p + 1 < R2 ? vp[(int64_t)(p + 1) * vstride] : T(0);
+        if (ca != 0.0) {
+          const double dze = cz0 + (double)p * hh, dzo = dze + hh;
+          const double re = cxy + dze * dze, ro = cxy + dzo * dzo;
+          ve = (T)((double)ve + ca * re * re);
+          vo = (T)((double)vo + ca * ro * ro);
+        }
         eacc += (double)ve * (double)fe * (double)fe + (double)vo * (double)fo * (double)fo;
         const T ge = ve * fe, go = vo * fo;
 #pragma unroll
@@ -741,15 +755,16 @@ int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
 }
 
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                      int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart) {
+                      int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart,
+                      const double* conf, double hh) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
   if (f64)
     hipLaunchKernelGGL(k_pot_column<double>, g, dim3(256), 0, (hipStream_t)stream, sf, wk, sf0,
-                       (double*)ws, (const double*)pot, nf1, nf2, epart);
+                       (double*)ws, (const double*)pot, nf1, nf2, epart, conf, hh);
   else
     hipLaunchKernelGGL(k_pot_column<float>, g, dim3(256), 0, (hipStream_t)stream, sf, wk, sf0,
-                       (float*)ws, (const float*)pot, nf1, nf2, epart);
+                       (float*)ws, (const float*)pot, nf1, nf2, epart, conf, hh);
   return (int)hipGetLastError();
 }
 

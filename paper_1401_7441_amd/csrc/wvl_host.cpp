@@ -842,6 +842,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
     S.n_c = L.n_c;
     S.n_f = L.n_f;
     S.on_c = L.on_c;
+    std::copy(L.center, L.center + 3, S.c);
     S.on_f = L.on_f;
     S.box_in = box_in;
     S.box_out = box_out;
@@ -985,7 +986,8 @@ static wvl_status apply_args(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
 // Enqueues the stages of chunk c on stream st.
 static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, const void* psi_c,
                               const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
-                              void* workspace, int accumulate, hipStream_t st) {
+                              void* workspace, int accumulate, hipStream_t st,
+                              const double* conf = nullptr) {
   wvl_ctx* ctx = P->ctx;
   const int sz = f64 ? 8 : 4;
   const int d = f64 ? 1 : 0;
@@ -1001,7 +1003,7 @@ static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, co
   if (pot_on) {
     WVL_LAUNCH(ctx, KK_POT_COLUMN,
                launch_pot_column(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_b, workspace, pot,
-                                 nf1, nf2, parts));
+                                 nf1, nf2, parts, conf, 0.5 * ctx->grid.h));
     if (e_pot)
       WVL_LAUNCH(ctx, KK_FINALIZE,
                  launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 0, ch.grid_b, e_pot));
@@ -1030,12 +1032,13 @@ static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, co
 
 static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
                              const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
-                             void* workspace, int accumulate, const char* who) {
+                             void* workspace, int accumulate, const char* who,
+                             const double* conf = nullptr) {
   wvl_status st = apply_args(P, dt, terms, psi_c, pot, hpsi_c, workspace, who);
   if (st != WVL_OK || P->nsf == 0) return st;
   for (size_t c = 0; c < P->lay.chunks.size(); ++c)
     if ((st = apply_chunk(P, c, dt == WVL_F64, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace,
-                          accumulate, P->ctx->stream)) != WVL_OK)
+                          accumulate, P->ctx->stream, conf)) != WVL_OK)
       return st;
   return WVL_OK;
 }
@@ -1045,6 +1048,17 @@ wvl_status wvl_apply_local_ham(wvl_plan* plan, wvl_dtype dt, uint32_t terms, con
                                void* workspace) {
   return apply_impl(plan, dt, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0,
                     "wvl_apply_local_ham");
+}
+
+wvl_status wvl_apply_local_ham_conf(wvl_plan* plan, wvl_dtype dt, uint32_t terms,
+                                    const void* psi_c, const void* pot, const double* conf,
+                                    void* hpsi_c, double* e_kin, double* e_pot, void* workspace) {
+  if (plan && !(terms & WVL_POT))
+    return fail(plan->ctx, WVL_EINVAL, "wvl_apply_local_ham_conf: the confinement needs WVL_POT");
+  if (plan && plan->nsf > 0 && !conf)
+    return fail(plan->ctx, WVL_EINVAL, "wvl_apply_local_ham_conf: null prefactors");
+  return apply_impl(plan, dt, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0,
+                    "wvl_apply_local_ham_conf", conf);
 }
 
 wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hpsi_c,

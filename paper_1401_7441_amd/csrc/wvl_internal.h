@@ -12,6 +12,7 @@ namespace wvl {
 // input coarse i in [0, n), fine real-space l in [-14, 2n+14] stored at
 // l + 14, output coarse i in [-ext, n+ext) stored at i + ext.
 struct SfDev {
+  double c[3];        // localization centre (bohr), for the confining potential
   int32_t lo[3];
   int32_t n[3];
   int32_t ext;
@@ -100,7 +101,8 @@ int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                      const int32_t* rt, const void* psi, const SfWork* wk, int sf0, int nsf,
                      int gridx, int tile_rows, size_t lds, void* ws, int up_on);
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                      int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart);
+                      int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart,
+                      const double* conf, double hh);
 int launch_kin_col(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
                    int nsf, int gridx, void* ws, double fac, double* kpart);
 int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,

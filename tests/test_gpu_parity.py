@@ -359,3 +359,32 @@ def test_update_step(spheres, dtype, tol):
         r = spheres.rec[k]
         sl = slice(int(r["coef_off"]), int(r["coef_off"]) + int(r["n_c"]) + 7 * int(r["n_f"]))
         assert rel_err(got[sl], want) < tol, k
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_confining_potential(spheres, dtype, tol):
+    """wvl_apply_local_ham_conf against the oracle with a |r - R|^4 added to
+    the potential of each function (own prefactor, own centre)."""
+    _print(f"case: confinement {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    n = len(spheres.lrs)
+    a = np.linspace(0.004, 0.05, n)
+    a[1] = 0.0                                  # one function without confinement
+    ctx = W.Context(spheres.g.h, spheres.g.grid_n)
+    plan = W.Plan(ctx, spheres.rec, spheres.segs)
+    psi = torch.tensor(spheres.psi, dtype=dt, device="cuda")
+    pot = torch.tensor(spheres.pot, dtype=dt, device="cuda")
+    out = torch.zeros(plan.info["out_coefs"], dtype=dt, device="cuda")
+    ek = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ep = torch.zeros_like(ek)
+    conf = torch.tensor(a, dtype=torch.float64, device="cuda")
+    W.apply_local_ham(plan, psi, pot, out, ek, ep, conf=conf)
+    torch.cuda.synchronize()
+    got, gek, gep = out.cpu().numpy(), ek.cpu().numpy(), ep.cpu().numpy()
+    for k in range(n):
+        oh, oek, oep = Hm.apply_local_ham(spheres.lrs[k], spheres.coefs[k], spheres.pot,
+                                          spheres.g.h, conf=float(a[k]))
+        assert rel_err(got[spheres.out_slice(k)], oh) < tol, k
+        etol = 1e-12 * max(1.0, abs(oep)) if dtype == "f64" else 1e-6
+        assert abs(gep[k] - oep) <= etol, (k, gep[k], oep)
+        assert abs(gek[k] - oek) <= (1e-12 * max(1.0, abs(oek)) if dtype == "f64" else 1e-6)

@@ -459,3 +459,28 @@ def test_update_restriction_matches_pointwise_dictionary():
                 emb[k] = 2.5 * inv.get((comp, tuple(int(v) for v in p)), 0.0)
                 k += 1
         assert np.allclose(U.update(lr, psi, emb, 2.5, 0.01), psi, rtol=0, atol=1e-15)
+
+
+# P13: the confining potential a |r - R|^4 on a Gaussian: <r^4> = 15 s^4 / 4
+def test_confinement_energy_of_a_gaussian():
+    h, sigma, n = 0.4, 1.2, 30
+    x0 = h * (n - 1) / 2
+    c8 = _gauss_box(h, sigma, x0, n)
+    lr = _full_box_locreg(n)
+    coef = _compress_full(lr, c8)
+    norm2 = (sigma * math.sqrt(math.pi)) ** 3
+    a = 0.037
+    zero = np.zeros((2 * n + 29,) * 3)
+    _, _, ep = Hm.apply_local_ham(lr, coef, zero, h, kinetic=False, conf=a,
+                                  center=(x0, x0, x0))
+    exact = a * 15.0 * sigma ** 4 / 4.0 * norm2
+    assert abs(ep / exact - 1) < 1e-8, ep / exact - 1
+    # an off-centre confinement adds the shift terms of (r - d)^4 averaged
+    d = np.array([0.3, -0.2, 0.1])
+    _, _, ep2 = Hm.apply_local_ham(lr, coef, zero, h, kinetic=False, conf=a,
+                                   center=tuple(x0 + d))
+    v = sigma ** 2 / 2                      # per-axis variance of |g|^2
+    dd = float(d @ d)
+    # E|x - d|^4 for an isotropic normal: 15 v^2 + 10 v |d|^2 + |d|^4
+    exact2 = a * (15 * v * v + 10 * v * dd + dd * dd) * norm2
+    assert abs(ep2 / exact2 - 1) < 1e-8, ep2 / exact2 - 1
