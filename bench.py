@@ -309,7 +309,7 @@ def main():
     ctx = S["ctx"]
     prof = {}
     eager_ms = None
-    conf_ms, cprof = None, {}
+    conf_ms, cprof, precond_ms = None, {}, None
     if not args.no_trace:
         ctx.profile(True)
         ctx.profile_reset()
@@ -332,6 +332,17 @@ def main():
         conf_ms = (time.perf_counter() - t1) * 1e3 / args.steps
         cprof = ctx.profile_read()
         ctx.profile(False)
+        # gradient preconditioning: 5 conjugate-gradient steps of
+        # (T + C - eps) x = -g for every function
+        eps = torch.full((nsf,), -0.5, dtype=torch.float64, device="cuda")
+        gx = torch.empty_like(S["psi"])
+        W.precondition(S["plan"], S["psi"], eps, 5, gx, conf=conf, workspace=S["ws"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        W.precondition(S["plan"], S["psi"], eps, 5, gx, conf=conf, workspace=S["ws"])
+        torch.cuda.synchronize()
+        precond_ms = (time.perf_counter() - t1) * 1e3
+        del gx
     ms_step = dt_s * 1e3 / args.steps
     value = nsf * args.steps / dt_s
     sz = 4 if args.dtype == "f32" else 8
@@ -407,6 +418,9 @@ def main():
             "pot_column_ms": cprof["pot_column"][1] / max(1, args.steps),
             "pot_column_ms_without": prof["pot_column"][1] / max(1, args.steps),
             "prefactor": 0.01},
+        "preconditioner": None if precond_ms is None else {
+            "ms": precond_ms, "cg_steps": 5, "confinement": 0.01, "eps": -0.5,
+            "note": "all functions, one apply (kinetic + confinement) per step"},
         "schedule": {"timed": "graph replay" if graph is not None else "eager calls",
                      "eager_ms_per_step": eager_ms,
                      "nbins": tune["best"]["nbins"] if tune else 1,

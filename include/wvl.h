@@ -235,6 +235,28 @@ wvl_status wvl_sparse_overlap(wvl_plan* plan, const void* bra_c, int ket_is_outp
 wvl_status wvl_update(wvl_plan* plan, wvl_dtype dt, double eta, const void* hpsi_c,
                       const double* h_val, void* psi_c);
 
+/* Preconditioning of support-function gradients (Sec. IV.A, Eq.
+ * (precond)): for every function a, approximately solve
+ *   (-1/2 nabla^2 + conf[a] |r - R_a|^4 - eps[a]) x_a = -g_a
+ * on its localization region (operator restricted to the input pattern on
+ * both sides: P_L (T + C) P_L - eps), by `niter` conjugate-gradient steps
+ * from x = 0.  eps values above 0 are taken as 0, so that the operator stays
+ * positive definite; a function whose residual vanishes stops moving.
+ *   g_c:   device, input layout (the localized gradient)
+ *   conf:  device double[nsf] confinement prefactors, or NULL (kinetic only)
+ *   eps:   device double[nsf] (the approximate Lagrange multipliers)
+ *   x_c:   device, input layout, overwritten with the preconditioned gradient
+ *   workspace: as for wvl_apply_local_ham
+ *   scratch:   device, at least 3 align(in_coefs sz) + align(out_coefs sz)
+ *              + 3 align(8 nsf) bytes, align(n) = n rounded up to 256 and
+ *              sz the size of the compute type
+ * Per-function scalars and dot products are in double, in a fixed order.
+ * Errors as wvl_apply_local_ham; WVL_EINVAL for niter < 0 or a plan whose
+ * input pattern is not inside its output pattern. */
+wvl_status wvl_precondition(wvl_plan* plan, wvl_dtype dt, const void* g_c, const double* conf,
+                            const double* eps, int32_t niter, void* x_c, void* workspace,
+                            void* scratch);
+
 /* Batching of uneven boxes (Sec. III.B: each function is worked on inside
  * its own localization region only).  A plan sorts the functions by box
  * volume and cuts them into bins; every bin runs each stage as one launch

@@ -24,6 +24,8 @@ sparse       Sparsity pattern and values of the overlap and Hamiltonian
              (paper Sec. II.A, below Eq. (band_structure_energy)).
 update       The support-function update step with the localized gradient
              (paper Sec. III.A and IV.A), fixed step length.
+precond      Kinetic + confinement preconditioning of the gradient (paper
+             Sec. IV.A, Eq. (precond)), conjugate-gradient steps.
 
 Parity status: every function here is pinned by a check that does not reuse
 its own formula (closed forms, invariants, brute force); see the tests marked

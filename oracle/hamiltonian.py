@@ -58,6 +58,8 @@ def potential_block(lr: Locreg, pot):
     pot[z, y, x]: local fine point l sits at global index 2*lo + l + 14,
     l = -14..2N+14."""
     lo, n = lr.lo, lr.dims
+    if pot is None:                      # no external potential
+        return np.zeros((2 * n[2] + 29, 2 * n[1] + 29, 2 * n[0] + 29))
     return pot[2 * lo[2]:2 * lo[2] + 2 * n[2] + 29,
                2 * lo[1]:2 * lo[1] + 2 * n[1] + 29,
                2 * lo[0]:2 * lo[0] + 2 * n[0] + 29]
@@ -80,7 +82,8 @@ def apply_local_ham(lr: Locreg, coef, pot, h, kinetic=True, potential=True, conf
     """Returns (hpsi_c, e_kin, e_pot) for one support function.
 
     coef   : compressed input coefficients on the input pattern (FP64)
-    pot    : global fine-grid potential, shape (2n3+29, 2n2+29, 2n1+29)
+    pot    : global fine-grid potential, shape (2n3+29, 2n2+29, 2n1+29), or
+             None for no external potential
     h      : coarse grid spacing (bohr)
     conf   : prefactor a of the confining potential a |r - R|^4 added to the
              potential (0: none); R = `center`, else the region's centre.

@@ -44,7 +44,8 @@ EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
             "wvl_compress", "wvl_apply_local_ham", "wvl_apply_local_ham_conf", "wvl_kinetic",
             "wvl_sparse_overlap",
-            "wvl_update", "wvl_graph_create", "wvl_graph_launch", "wvl_graph_destroy",
+            "wvl_update", "wvl_precondition", "wvl_graph_create", "wvl_graph_launch",
+            "wvl_graph_destroy",
             "wvl_plan_autotune",
             "wvl_profile_enable", "wvl_profile_reset", "wvl_profile_count", "wvl_profile_read")
 
@@ -103,6 +104,7 @@ def _load():
         "wvl_apply_local_ham_conf": [P, ctypes.c_int, U32, P, P, P, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
         "wvl_update": [P, ctypes.c_int, D, P, P, P],
+        "wvl_precondition": [P, ctypes.c_int, P, P, P, I32, P, P, P],
         "wvl_graph_create": [P, ctypes.c_int, U32, P, P, P, P, P, P, P, P, ctypes.POINTER(P)],
         "wvl_graph_launch": [P],
         "wvl_graph_destroy": [P],
@@ -408,6 +410,36 @@ def update(plan: Plan, psi_c, hpsi_c, h_val, eta):
         raise WvlError(WVL_EINVAL, "h_val must be float64 with the H pattern's nnz entries")
     _check(lib().wvl_update(plan._ptr, dt, float(eta), _ptr(hpsi_c), _ptr(h_val), _ptr(psi_c)),
            plan.ctx.handle)
+
+
+def precondition_scratch_bytes(plan: Plan, dtype_code):
+    """Scratch bytes wvl_precondition needs (see include/wvl.h)."""
+    sz = 8 if dtype_code == F64 else 4
+    al = lambda n: (n + 255) // 256 * 256
+    return 3 * al(plan.info["in_coefs"] * sz) + al(plan.info["out_coefs"] * sz) + \
+        3 * al(8 * plan.nsf)
+
+
+def precondition(plan: Plan, g_c, eps, niter, x_c, conf=None, workspace=None, scratch=None):
+    """wvl_precondition: x_c <- approx. solution of (T + conf |r-R|^4 - eps) x = -g_c
+    per function, `niter` conjugate-gradient steps; eps, conf float64 [nsf]."""
+    import torch
+    _need_cuda(g_c, x_c, eps, conf, workspace, scratch)
+    dt = _dtype_code(g_c, x_c)
+    if g_c.numel() < plan.info["in_coefs"] or x_c.numel() < plan.info["in_coefs"]:
+        raise WvlError(WVL_EINVAL, "coefficient buffer smaller than the plan's layout")
+    for v in (eps, conf):
+        if v is not None and (v.dtype.itemsize != 8 or v.numel() < plan.nsf):
+            raise WvlError(WVL_EINVAL, "eps / conf must be float64 with nsf entries")
+    if workspace is None:
+        workspace = plan.new_workspace(g_c.dtype)
+    need = precondition_scratch_bytes(plan, dt)
+    if scratch is None:
+        scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+    elif scratch.numel() * scratch.element_size() < need:
+        raise WvlError(WVL_EINVAL, "scratch smaller than wvl_precondition needs")
+    _check(lib().wvl_precondition(plan._ptr, dt, _ptr(g_c), _ptr(conf), _ptr(eps), int(niter),
+                                  _ptr(x_c), _ptr(workspace), _ptr(scratch)), plan.ctx.handle)
 
 
 class Graph:

@@ -232,8 +232,10 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
     T* out0 = ws + w.g2 + col;
     T* out1 = out0 + (int64_t)O2 * ncol;
     const int64_t vstride = (int64_t)nf1 * nf2;
-    const T* vp = pot + ((int64_t)(2 * sf.lo[2]) * nf2 + (2 * sf.lo[1] + py)) * nf1 +
-                  (2 * sf.lo[0] + px);
+    // no potential array: V = 0 (the confinement alone)
+    const T* vp = pot ? pot + ((int64_t)(2 * sf.lo[2]) * nf2 + (2 * sf.lo[1] + py)) * nf1 +
+                            (2 * sf.lo[0] + px)
+                      : nullptr;
     const double cdx = (double)(2 * sf.lo[0] + px - 14) * hh - sf.c[0];
     const double cdy = (double)(2 * sf.lo[1] + py - 14) * hh - sf.c[1];
     const double cxy = cdx * cdx + cdy * cdy;
@@ -261,8 +263,8 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
           if (k < 15) fo += Ct<T>(0, 2 * k + 1) * xs[sl] + Ct<T>(1, 2 * k + 1) * xd[sl];
         }
         const int p = 2 * q;
-        T ve = p < R2 ? vp[(int64_t)p * vstride] : T(0);
-        T vo = p + 1 < R2 ? vp[(int64_t)(p + 1) * vstride] : T(0);
+        T ve = (vp && p < R2) ? vp[(int64_t)p * vstride] : T(0);
+        T vo = (vp && p + 1 < R2) ? vp[(int64_t)(p + 1) * vstride] : T(0);
         if (ca != 0.0) {
           const double dze = cz0 + (double)p * hh, dzo = dze + hh;
           const double re = cxy + dze * dze, ro = cxy + dzo * dzo;

@@ -970,7 +970,7 @@ wvl_status wvl_compress(wvl_plan* P, wvl_dtype dt, const void* box, void* hpsi_c
 // checks shared by the eager and the captured apply
 static wvl_status apply_args(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
                              const void* pot, const void* hpsi_c, const void* workspace,
-                             const char* who) {
+                             const char* who, bool pot_optional = false) {
   if (!P) return fail(nullptr, WVL_EINVAL, "%s: null plan", who);
   wvl_ctx* ctx = P->ctx;
   if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
@@ -979,7 +979,8 @@ static wvl_status apply_args(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
   if (P->nsf == 0) return WVL_OK;
   if (!psi_c || !hpsi_c || !workspace)
     return fail(ctx, WVL_EINVAL, "%s: null coefficient or workspace buffer", who);
-  if ((terms & WVL_POT) && !pot) return fail(ctx, WVL_EINVAL, "%s: WVL_POT needs a potential", who);
+  if ((terms & WVL_POT) && !pot && !pot_optional)
+    return fail(ctx, WVL_EINVAL, "%s: WVL_POT needs a potential", who);
   return WVL_OK;
 }
 
@@ -1034,7 +1035,7 @@ static wvl_status apply_impl(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
                              const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
                              void* workspace, int accumulate, const char* who,
                              const double* conf = nullptr) {
-  wvl_status st = apply_args(P, dt, terms, psi_c, pot, hpsi_c, workspace, who);
+  wvl_status st = apply_args(P, dt, terms, psi_c, pot, hpsi_c, workspace, who, conf != nullptr);
   if (st != WVL_OK || P->nsf == 0) return st;
   for (size_t c = 0; c < P->lay.chunks.size(); ++c)
     if ((st = apply_chunk(P, c, dt == WVL_F64, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace,
@@ -1208,7 +1209,57 @@ wvl_status wvl_update(wvl_plan* P, wvl_dtype dt, double eta, const void* hpsi_c,
     const int n = std::min(65535, P->nsf - s0);
     WVL_LAUNCH(ctx, KK_UPDATE,
                launch_update(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt, eta, hpsi_c,
-                             pc.d_rowptr, pc.d_col, h_val, psi_c, s0, n, P->max_in_segs));
+                             pc.d_rowptr, pc.d_col, h_val, psi_c, s0, n, P->max_in_segs, 0,
+                             nullptr, nullptr));
+  }
+  return WVL_OK;
+}
+
+wvl_status wvl_precondition(wvl_plan* P, wvl_dtype dt, const void* g_c, const double* conf,
+                            const double* eps, int32_t niter, void* x_c, void* workspace,
+                            void* scratch) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_precondition: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (niter < 0) return fail(ctx, WVL_EINVAL, "wvl_precondition: niter < 0");
+  if (P->nsf == 0) return WVL_OK;
+  if (!g_c || !x_c || !workspace || !scratch || !eps)
+    return fail(ctx, WVL_EINVAL, "wvl_precondition: null buffer");
+  if (!P->in_sub_out)
+    return fail(ctx, WVL_EINVAL,
+                "wvl_precondition: an input pattern is not inside its output pattern");
+  const int f64 = dt == WVL_F64, sz = f64 ? 8 : 4;
+  char* base = (char*)scratch;
+  void* r = base;                   base += align_bytes(P->info.in_coefs * sz);
+  void* p = base;                   base += align_bytes(P->info.in_coefs * sz);
+  void* ap_in = base;               base += align_bytes(P->info.in_coefs * sz);
+  void* ap_out = base;              base += align_bytes(P->info.out_coefs * sz);
+  double* rr = (double*)base;       base += align_bytes(8ll * P->nsf);
+  double* pap = (double*)base;      base += align_bytes(8ll * P->nsf);
+  double* rrn = (double*)base;
+  const uint32_t terms = WVL_KIN | (conf ? WVL_POT : 0);
+  hipStream_t st = ctx->stream;
+  for (int s0 = 0; s0 < P->nsf; s0 += 65535) {
+    const int n = std::min(65535, P->nsf - s0);
+    WVL_LAUNCH(ctx, KK_UPDATE, launch_cg_init(f64, st, P->d_sf, g_c, x_c, r, p, s0, n));
+    WVL_LAUNCH(ctx, KK_UPDATE, launch_sf_dot(f64, st, P->d_sf, r, r, rr, s0, n));
+  }
+  for (int it = 0; it < niter; ++it) {
+    // A p = P_L (T + C) P_L p - min(eps, 0) p
+    wvl_status s = apply_impl(P, dt, terms, p, nullptr, ap_out, nullptr, nullptr, workspace, 0,
+                              "wvl_precondition", conf);
+    if (s != WVL_OK) return s;
+    for (int s0 = 0; s0 < P->nsf; s0 += 65535) {
+      const int n = std::min(65535, P->nsf - s0);
+      WVL_LAUNCH(ctx, KK_UPDATE,
+                 launch_update(f64, st, P->d_sf, P->d_seg, P->d_rt, 0.0, ap_out, nullptr, nullptr,
+                               nullptr, p, s0, n, P->max_in_segs, 1, eps, ap_in));
+      WVL_LAUNCH(ctx, KK_UPDATE, launch_sf_dot(f64, st, P->d_sf, p, ap_in, pap, s0, n));
+      WVL_LAUNCH(ctx, KK_UPDATE,
+                 launch_cg_xr(f64, st, P->d_sf, rr, pap, p, ap_in, x_c, r, s0, n));
+      WVL_LAUNCH(ctx, KK_UPDATE, launch_sf_dot(f64, st, P->d_sf, r, r, rrn, s0, n));
+      WVL_LAUNCH(ctx, KK_UPDATE, launch_cg_p(f64, st, P->d_sf, rr, rrn, r, p, s0, n));
+    }
   }
   return WVL_OK;
 }

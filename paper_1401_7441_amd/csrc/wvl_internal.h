@@ -118,7 +118,16 @@ int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int3
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
 int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                   double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
-                  const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs);
+                  const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs, int mode,
+                  const double* shift, void* out);
+int launch_sf_dot(int f64, void* stream, const SfDev* sf, const void* a, const void* b,
+                  double* out, int sf0, int nsf);
+int launch_cg_init(int f64, void* stream, const SfDev* sf, const void* g, void* x, void* r,
+                   void* p, int sf0, int nsf);
+int launch_cg_xr(int f64, void* stream, const SfDev* sf, const double* rr, const double* pap,
+                 const void* p, const void* ap, void* x, void* r, int sf0, int nsf);
+int launch_cg_p(int f64, void* stream, const SfDev* sf, double* rr, const double* rr_new,
+                const void* r, void* p, int sf0, int nsf);
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                          const int32_t* rt, const RowRun* rr, int ket_out, const void* bra,
                          const void* ket, const int32_t* row, const int32_t* col,

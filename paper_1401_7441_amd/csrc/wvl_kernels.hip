@@ -329,6 +329,8 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
 // input pattern is contained in the output pattern), so each segment maps
 // affinely into H psi; the map is found once per segment and staged in LDS.
 constexpr int kUpdSegs = 64;
+// mode 0 (update):   psi <- psi - eta (P_L hpsi - H_aa psi)      (out = psi)
+// mode 1 (restrict): out <- P_L hpsi - min(shift_a, 0) psi
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(const SfDev* __restrict__ sfs,
                                                 const wvl_seg* __restrict__ seg,
@@ -337,7 +339,9 @@ __global__ __launch_bounds__(256) void k_update(const SfDev* __restrict__ sfs,
                                                 const int64_t* __restrict__ hrow,
                                                 const int32_t* __restrict__ hcol,
                                                 const double* __restrict__ hval,
-                                                T* __restrict__ psi, int sf0) {
+                                                T* __restrict__ psi, int sf0, int mode,
+                                                const double* __restrict__ shift,
+                                                T* __restrict__ out) {
   __shared__ int s_in[kUpdSegs + 1];     // coefficient offset relative to the first segment
   __shared__ int64_t s_out[kUpdSegs];    // H psi index of the segment's first point
   __shared__ double s_diag;
@@ -373,13 +377,17 @@ __global__ __launch_bounds__(256) void k_update(const SfDev* __restrict__ sfs,
     }
     s_out[tid] = o;   // always found: the plan checks input inside output
   }
-  if (tid == 0) {     // H_aa: the diagonal entry of row a
-    int64_t lo = hrow[a], hi = hrow[a + 1] - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (hcol[mid] < a) lo = mid + 1; else hi = mid;
+  if (tid == 0) {
+    if (mode == 0) {  // H_aa: the diagonal entry of row a
+      int64_t lo = hrow[a], hi = hrow[a + 1] - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (hcol[mid] < a) lo = mid + 1; else hi = mid;
+      }
+      s_diag = hval[lo];
+    } else {
+      s_diag = shift ? fmin(shift[a], 0.0) : 0.0;
     }
-    s_diag = hval[lo];
   }
   __syncthreads();
   const int total = s_in[nseg];
@@ -397,8 +405,82 @@ __global__ __launch_bounds__(256) void k_update(const SfDev* __restrict__ sfs,
       const int64_t i = sf.cin + (c == 0 ? 0 : sf.n_c + (int64_t)(c - 1) * sf.n_f) + off0 + k;
       const int64_t o = sf.cout + (c == 0 ? 0 : sf.on_c + (int64_t)(c - 1) * sf.on_f) + oi;
       const double x = (double)psi[i];
-      psi[i] = (T)(x - eta * ((double)hpsi[o] - d * x));
+      if (mode == 0)
+        psi[i] = (T)(x - eta * ((double)hpsi[o] - d * x));
+      else
+        out[i] = (T)((double)hpsi[o] - d * x);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-function vector algebra for the preconditioner (input layout: each
+// function's coefficients are contiguous); one block per function, fixed
+// summation order
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_sf_dot(const SfDev* __restrict__ sfs,
+                                                const T* __restrict__ a,
+                                                const T* __restrict__ b, double* __restrict__ out,
+                                                int sf0) {
+  const SfDev& sf = sfs[sf0 + blockIdx.x];
+  const int64_t n = sf.n_c + 7 * sf.n_f;
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += TPB) v += (double)a[sf.cin + i] * (double)b[sf.cin + i];
+  const double r = block_sum(v);
+  if (threadIdx.x == 0) out[sf0 + blockIdx.x] = r;
+}
+
+// one conjugate-gradient step after Ap and pAp = <p|Ap> are known:
+//   al = rr / pAp (0 when pAp <= 0 or rr = 0);  x += al p;  r -= al Ap
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_cg_xr(const SfDev* __restrict__ sfs,
+                                               const double* __restrict__ rr,
+                                               const double* __restrict__ pap,
+                                               const T* __restrict__ p, const T* __restrict__ ap,
+                                               T* __restrict__ x, T* __restrict__ r, int sf0) {
+  const int a = sf0 + blockIdx.x;
+  const SfDev& sf = sfs[a];
+  const double al = (pap[a] > 0.0 && rr[a] > 0.0) ? rr[a] / pap[a] : 0.0;
+  const int64_t n = sf.n_c + 7 * sf.n_f;
+  for (int64_t i = threadIdx.x; i < n; i += TPB) {
+    const int64_t k = sf.cin + i;
+    x[k] = (T)((double)x[k] + al * (double)p[k]);
+    r[k] = (T)((double)r[k] - al * (double)ap[k]);
+  }
+}
+
+//   be = rr_new / rr (0 when rr = 0);  p = r + be p;  rr <- rr_new
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_cg_p(const SfDev* __restrict__ sfs,
+                                              double* __restrict__ rr,
+                                              const double* __restrict__ rr_new,
+                                              const T* __restrict__ r, T* __restrict__ p,
+                                              int sf0) {
+  const int a = sf0 + blockIdx.x;
+  const SfDev& sf = sfs[a];
+  const double be = rr[a] > 0.0 ? rr_new[a] / rr[a] : 0.0;
+  const int64_t n = sf.n_c + 7 * sf.n_f;
+  for (int64_t i = threadIdx.x; i < n; i += TPB) {
+    const int64_t k = sf.cin + i;
+    p[k] = (T)((double)r[k] + be * (double)p[k]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) rr[a] = rr_new[a];
+}
+
+// x = 0, r = p = -g over every function's coefficients
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_cg_init(const SfDev* __restrict__ sfs,
+                                                 const T* __restrict__ g, T* __restrict__ x,
+                                                 T* __restrict__ r, T* __restrict__ p, int sf0) {
+  const SfDev& sf = sfs[sf0 + blockIdx.x];
+  const int64_t n = sf.n_c + 7 * sf.n_f;
+  for (int64_t i = threadIdx.x; i < n; i += TPB) {
+    const int64_t k = sf.cin + i;
+    x[k] = T(0);
+    r[k] = -g[k];
+    p[k] = -g[k];
   }
 }
 
@@ -414,7 +496,8 @@ static inline dim3 grid2(int64_t maxvol, int nsf) {
 int preload_kernels() {
   const void* fns[] = {(const void*)k_finalize, (const void*)k_sparse_values<float>,
                        (const void*)k_sparse_values<double>, (const void*)k_update<float>,
-                       (const void*)k_update<double>};
+                       (const void*)k_update<double>, (const void*)k_sf_dot<float>,
+                       (const void*)k_sf_dot<double>};
   for (const void* f : fns) {
     hipFuncAttributes a;
     const hipError_t e = hipFuncGetAttributes(&a, f);
@@ -494,15 +577,66 @@ int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* 
 
 int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                   double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
-                  const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs) {
+                  const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs, int mode,
+                  const double* shift, void* out) {
   if (nsf == 0) return 0;
   const dim3 g((unsigned)(maxsegs / kUpdSegs + 2), (unsigned)nsf);
   if (f64)
     hipLaunchKernelGGL(k_update<double>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, eta,
-                       (const double*)hpsi, hrow, hcol, hval, (double*)psi, sf0);
+                       (const double*)hpsi, hrow, hcol, hval, (double*)psi, sf0, mode, shift,
+                       (double*)out);
   else
     hipLaunchKernelGGL(k_update<float>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, eta,
-                       (const float*)hpsi, hrow, hcol, hval, (float*)psi, sf0);
+                       (const float*)hpsi, hrow, hcol, hval, (float*)psi, sf0, mode, shift,
+                       (float*)out);
+  return (int)hipGetLastError();
+}
+
+int launch_sf_dot(int f64, void* stream, const SfDev* sf, const void* a, const void* b,
+                  double* out, int sf0, int nsf) {
+  if (nsf == 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(k_sf_dot<double>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf,
+                       (const double*)a, (const double*)b, out, sf0);
+  else
+    hipLaunchKernelGGL(k_sf_dot<float>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf,
+                       (const float*)a, (const float*)b, out, sf0);
+  return (int)hipGetLastError();
+}
+
+int launch_cg_init(int f64, void* stream, const SfDev* sf, const void* g, void* x, void* r,
+                   void* p, int sf0, int nsf) {
+  if (nsf == 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(k_cg_init<double>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf,
+                       (const double*)g, (double*)x, (double*)r, (double*)p, sf0);
+  else
+    hipLaunchKernelGGL(k_cg_init<float>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf,
+                       (const float*)g, (float*)x, (float*)r, (float*)p, sf0);
+  return (int)hipGetLastError();
+}
+
+int launch_cg_xr(int f64, void* stream, const SfDev* sf, const double* rr, const double* pap,
+                 const void* p, const void* ap, void* x, void* r, int sf0, int nsf) {
+  if (nsf == 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(k_cg_xr<double>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf, rr,
+                       pap, (const double*)p, (const double*)ap, (double*)x, (double*)r, sf0);
+  else
+    hipLaunchKernelGGL(k_cg_xr<float>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf, rr, pap,
+                       (const float*)p, (const float*)ap, (float*)x, (float*)r, sf0);
+  return (int)hipGetLastError();
+}
+
+int launch_cg_p(int f64, void* stream, const SfDev* sf, double* rr, const double* rr_new,
+                const void* r, void* p, int sf0, int nsf) {
+  if (nsf == 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(k_cg_p<double>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf, rr,
+                       rr_new, (const double*)r, (double*)p, sf0);
+  else
+    hipLaunchKernelGGL(k_cg_p<float>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf, rr,
+                       rr_new, (const float*)r, (float*)p, sf0);
   return (int)hipGetLastError();
 }
 

@@ -388,3 +388,35 @@ def test_confining_potential(spheres, dtype, tol):
         etol = 1e-12 * max(1.0, abs(oep)) if dtype == "f64" else 1e-6
         assert abs(gep[k] - oep) <= etol, (k, gep[k], oep)
         assert abs(gek[k] - oek) <= (1e-12 * max(1.0, abs(oek)) if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype,tol,conf", [("f64", 1e-11, True), ("f64", 1e-11, False),
+                                            ("f32", 1e-5, True)])
+def test_preconditioner(spheres, dtype, tol, conf):
+    """wvl_precondition (5 conjugate-gradient steps) against the oracle's
+    steps.  The FP64 bound is the apply's 1e-12 allowed to grow over the
+    five steps; FP32 keeps the 1e-5 of the apply."""
+    from oracle import precond as PC
+    _print(f"case: preconditioner {dtype} conf={conf}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    n = len(spheres.lrs)
+    ctx = W.Context(spheres.g.h, spheres.g.grid_n)
+    plan = W.Plan(ctx, spheres.rec, spheres.segs)
+    rng = np.random.default_rng(41)
+    g = np.concatenate([rng.standard_normal(c.size) for c in spheres.coefs])
+    eps = -0.3 - 0.1 * np.arange(n, dtype=np.float64)
+    eps[2] = 0.25                                   # taken as 0
+    a = np.linspace(0.01, 0.04, n) if conf else np.zeros(n)
+    gt = torch.tensor(g, dtype=dt, device="cuda")
+    x = torch.zeros_like(gt)
+    W.precondition(plan, gt, torch.tensor(eps, device="cuda"), 5, x,
+                   conf=torch.tensor(a, device="cuda") if conf else None)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy()
+    off = 0
+    for k in range(n):
+        m = spheres.coefs[k].size
+        want = PC.precondition(spheres.lrs[k], g[off:off + m], spheres.g.h, float(a[k]),
+                               float(eps[k]), 5)
+        assert rel_err(got[off:off + m], want) < tol, k
+        off += m

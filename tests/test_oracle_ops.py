@@ -484,3 +484,36 @@ def test_confinement_energy_of_a_gaussian():
     # E|x - d|^4 for an isotropic normal: 15 v^2 + 10 v |d|^2 + |d|^4
     exact2 = a * (15 * v * v + 10 * v * dd + dd * dd) * norm2
     assert abs(ep2 / exact2 - 1) < 1e-8, ep2 / exact2 - 1
+
+
+# P14: the preconditioner's operator is symmetric positive definite, and its
+# conjugate-gradient solve reaches the dense direct solution
+def test_preconditioner_against_a_dense_solve():
+    from oracle import precond as PC
+    h = 0.5
+    lo, dims = (3, 3, 3), (6, 6, 6)
+    m = np.ones((6, 6, 6), bool)
+    fm = np.zeros_like(m)
+    fm[2:4, 2:4, 2:4] = True
+    ext = 2
+    olo = [v - ext for v in lo]
+    om = np.ones((10, 10, 10), bool)
+    ofm = np.zeros_like(om)
+    ofm[ext + 2:ext + 4, ext + 2:ext + 4, ext + 2:ext + 4] = True
+    lr = LR.Locreg(lo=lo, dims=dims, ext=ext, cseg=LR.segments_from_mask(m, lo),
+                   fseg=LR.segments_from_mask(fm, lo), ocseg=LR.segments_from_mask(om, olo),
+                   ofseg=LR.segments_from_mask(ofm, olo), center=(3.2, 3.1, 2.9))
+    n = lr.n_c + 7 * lr.n_f
+    conf, eps = 0.02, -0.7
+    A = np.stack([PC.apply_operator(lr, np.eye(n)[i], h, conf, eps) for i in range(n)], axis=1)
+    assert np.max(np.abs(A - A.T)) < 1e-12 * np.max(np.abs(A))
+    w = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert w[0] > 0.69                       # T + C >= 0, shifted by 0.7
+    g = np.random.default_rng(3).standard_normal(n)
+    direct = np.linalg.solve(A, -g)
+    x = PC.precondition(lr, g, h, conf, eps, niter=n)
+    assert np.linalg.norm(x - direct) < 1e-8 * np.linalg.norm(direct)
+    # a positive eps is taken as 0: the operator is then T + C
+    A0 = np.stack([PC.apply_operator(lr, np.eye(n)[i], h, conf, 0.4) for i in range(n)], axis=1)
+    A1 = np.stack([PC.apply_operator(lr, np.eye(n)[i], h, conf, 0.0) for i in range(n)], axis=1)
+    assert np.array_equal(A0, A1)
