@@ -93,11 +93,12 @@ typedef struct {
  * input pattern.  Output box: the input box grown by `ext` on every side
  * (0 <= ext <= 16); the output pattern lies inside it and inside the grid.
  *
- * Compressed layout (SoA) of the input coefficients, starting at element
- * coef_off of the batch buffer: [s: n_c][d1: n_f]...[d7: n_f], where n_c and
- * n_f are the coarse and fine point counts of the input pattern; wavelet
- * component l = a1 + 2 a2 + 4 a3 (a_d = 1: wavelet along axis d).  Output
- * coefficients likewise at ocoef_off with on_c, on_f.
+ * Compressed layout of the input coefficients, starting at element coef_off
+ * of the batch buffer: [s: n_c][d: n_f][7] -- the scaling coefficients of
+ * the n_c coarse points in segment order, then for each of the n_f fine
+ * points (segment order) its seven wavelet coefficients, component
+ * l = a1 + 2 a2 + 4 a3 at position l - 1 (a_d = 1: wavelet along axis d).
+ * Output coefficients likewise at ocoef_off with on_c, on_f.
  *
  * center/radius/fine_radius describe the sphere the pattern was built from
  * (informational; radius <= 0 for patterns not built from a sphere). */

@@ -115,7 +115,8 @@ def geometry(workload, nsf=None, seed_offset=0):
 
 
 def coefficients(geom: Geometry, sf, points_c, points_f, smooth=False, normalize=True):
-    """Compressed coefficients [s: n_c][d1..d7: n_f] of support function `sf`.
+    """Compressed coefficients [s: n_c][d: n_f][7] of support function `sf`
+    (the seven wavelet coefficients of a fine point are contiguous).
 
     points_c / points_f: (n, 3) global coarse points (i1, i2, i3) of the input
     coarse / fine pattern, in segment order.  Each value is N(0,1) times the
@@ -133,8 +134,9 @@ def coefficients(geom: Geometry, sf, points_c, points_f, smooth=False, normalize
     if smooth:
         out = np.concatenate([ec, np.zeros(7 * nf)])
     else:
+        # draws per (component, point) as before; stored point-major
         out = np.concatenate([rng.standard_normal(nc) * ec,
-                              (rng.standard_normal((7, nf)) * ef[None, :]).ravel()])
+                              (rng.standard_normal((7, nf)) * ef[None, :]).T.ravel()])
     if normalize:
         nrm = math.sqrt(float(np.dot(out, out)))
         if nrm > 0:

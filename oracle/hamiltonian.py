@@ -24,8 +24,10 @@ from .locreg import Locreg, points_from_segments
 
 
 def uncompress(lr: Locreg, coef):
-    """Compressed [s: n_c][d1..d7: n_f each] in segment order -> dense
-    (8, N3, N2, N1) box; coefficients absent from the pattern are zero."""
+    """Compressed [s: n_c][d: n_f][7] (scaling coefficients of the coarse
+    points, then the seven wavelet coefficients of each fine point, points in
+    segment order) -> dense (8, N3, N2, N1) box; coefficients absent from the
+    pattern are zero."""
     coef = np.asarray(coef, np.float64)
     n_c, n_f = lr.n_c, lr.n_f
     assert coef.size == n_c + 7 * n_f
@@ -34,23 +36,23 @@ def uncompress(lr: Locreg, coef):
     pf = points_from_segments(lr.fseg)
     lo = lr.lo
     box[0, pc[:, 2] - lo[2], pc[:, 1] - lo[1], pc[:, 0] - lo[0]] = coef[:n_c]
+    fine = coef[n_c:].reshape(n_f, 7)
     for comp in range(1, 8):
-        vals = coef[n_c + (comp - 1) * n_f:n_c + comp * n_f]
-        box[comp, pf[:, 2] - lo[2], pf[:, 1] - lo[1], pf[:, 0] - lo[0]] = vals
+        box[comp, pf[:, 2] - lo[2], pf[:, 1] - lo[1], pf[:, 0] - lo[0]] = fine[:, comp - 1]
     return box
 
 
 def compress_out(lr: Locreg, box_out):
     """Dense (8, N3+2e, N2+2e, N1+2e) box on the grown L' box -> compressed
-    [s: on_c][d1..d7: on_f] at the output pattern."""
+    [s: on_c][d: on_f][7] at the output pattern."""
     e = lr.ext
     olo = (lr.lo[0] - e, lr.lo[1] - e, lr.lo[2] - e)
     pc = points_from_segments(lr.ocseg)
     pf = points_from_segments(lr.ofseg)
-    out = [box_out[0, pc[:, 2] - olo[2], pc[:, 1] - olo[1], pc[:, 0] - olo[0]]]
-    for comp in range(1, 8):
-        out.append(box_out[comp, pf[:, 2] - olo[2], pf[:, 1] - olo[1], pf[:, 0] - olo[0]])
-    return np.concatenate(out)
+    coarse = box_out[0, pc[:, 2] - olo[2], pc[:, 1] - olo[1], pc[:, 0] - olo[0]]
+    fine = np.stack([box_out[comp, pf[:, 2] - olo[2], pf[:, 1] - olo[1], pf[:, 0] - olo[0]]
+                     for comp in range(1, 8)], axis=1).reshape(-1)
+    return np.concatenate([coarse, fine])
 
 
 def potential_block(lr: Locreg, pot):

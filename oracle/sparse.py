@@ -28,10 +28,10 @@ def _dense(lr_seg_c, lr_seg_f, coef, lo, shape):
     assert coef.size == n_c + 7 * n_f
     if n_c:
         out[0, pc[:, 2] - lo[2], pc[:, 1] - lo[1], pc[:, 0] - lo[0]] = coef[:n_c]
-    for comp in range(1, 8):
-        if n_f:
-            out[comp, pf[:, 2] - lo[2], pf[:, 1] - lo[1], pf[:, 0] - lo[0]] = \
-                coef[n_c + (comp - 1) * n_f:n_c + comp * n_f]
+    if n_f:
+        fine = coef[n_c:].reshape(n_f, 7)       # [d: n_f][7]
+        for comp in range(1, 8):
+            out[comp, pf[:, 2] - lo[2], pf[:, 1] - lo[1], pf[:, 0] - lo[0]] = fine[:, comp - 1]
     return out
 
 

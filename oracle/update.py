@@ -19,8 +19,8 @@ from .locreg import Locreg, points_from_segments
 
 
 def restrict_to_input(lr: Locreg, out_coef):
-    """P_L: an output-layout vector [s: on_c][d1..d7: on_f] -> its values at
-    the input pattern's points, in the input layout [s: n_c][d1..d7: n_f]."""
+    """P_L: an output-layout vector [s: on_c][d: on_f][7] -> its values at
+    the input pattern's points, in the input layout [s: n_c][d: n_f][7]."""
     out_coef = np.asarray(out_coef, np.float64)
     e = lr.ext
     olo = (lr.lo[0] - e, lr.lo[1] - e, lr.lo[2] - e)
@@ -30,15 +30,15 @@ def restrict_to_input(lr: Locreg, out_coef):
     poc = points_from_segments(lr.ocseg)
     pof = points_from_segments(lr.ofseg)
     box[0, poc[:, 2] - olo[2], poc[:, 1] - olo[1], poc[:, 0] - olo[0]] = out_coef[:on_c]
+    ofine = out_coef[on_c:].reshape(on_f, 7)
     for comp in range(1, 8):
-        box[comp, pof[:, 2] - olo[2], pof[:, 1] - olo[1], pof[:, 0] - olo[0]] = \
-            out_coef[on_c + (comp - 1) * on_f:on_c + comp * on_f]
+        box[comp, pof[:, 2] - olo[2], pof[:, 1] - olo[1], pof[:, 0] - olo[0]] = ofine[:, comp - 1]
     pic = points_from_segments(lr.cseg)
     pif = points_from_segments(lr.fseg)
-    res = [box[0, pic[:, 2] - olo[2], pic[:, 1] - olo[1], pic[:, 0] - olo[0]]]
-    for comp in range(1, 8):
-        res.append(box[comp, pif[:, 2] - olo[2], pif[:, 1] - olo[1], pif[:, 0] - olo[0]])
-    return np.concatenate(res)
+    coarse = box[0, pic[:, 2] - olo[2], pic[:, 1] - olo[1], pic[:, 0] - olo[0]]
+    fine = np.stack([box[comp, pif[:, 2] - olo[2], pif[:, 1] - olo[1], pif[:, 0] - olo[0]]
+                     for comp in range(1, 8)], axis=1).reshape(-1)
+    return np.concatenate([coarse, fine])
 
 
 def update(lr: Locreg, psi, hpsi, h_aa, eta):

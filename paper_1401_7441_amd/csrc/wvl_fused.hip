@@ -82,7 +82,7 @@ __device__ __forceinline__ T coef_at(const SfDev& sf, const wvl_seg* __restrict_
     const wvl_seg g = seg[q];
     if (gx >= g.i1s && gx <= g.i1e) {
       const int64_t k = g.off + (gx - g.i1s);
-      return c == 0 ? psi[sf.cin + k] : psi[sf.cin + sf.n_c + (int64_t)(c - 1) * sf.n_f + k];
+      return c == 0 ? psi[sf.cin + k] : psi[sf.cin + sf.n_c + 7 * k + (c - 1)];
     }
   }
   return T(0);
@@ -701,19 +701,23 @@ __global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
   __syncthreads();
   const int total = s_off[nseg];
   const int oc = O2 * O1 * O0;
-  const int cfirst = fine ? 1 : 0, clast = fine ? 7 : 0;
-  for (int k = tid; k < total; k += 256) {
+  // coarse: one value per point; fine: the seven wavelets of each point are
+  // consecutive in the output, so thread t writes element t of the block's
+  // stretch (point t / 7, component t % 7 + 1)
+  const int per = fine ? 7 : 1;
+  const int64_t obase = sf.cout + (fine ? sf.on_c + 7 * off0 : off0);
+  for (int t = tid; t < per * total; t += 256) {
+    const int k = fine ? t / 7 : t;
+    const int c = fine ? t - 7 * k + 1 : 0;
     int lo = 0, hi = nseg - 1;   // last segment with s_off <= k
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
     }
     const int src = s_ob[lo] + (k - s_off[lo]);
-    for (int c = cfirst; c <= clast; ++c) {
-      const int64_t o = sf.cout + (c == 0 ? 0 : sf.on_c + (int64_t)(c - 1) * sf.on_f) + off0 + k;
-      const T v = ws[w.ob + (int64_t)c * oc + src];
-      out[o] = accumulate ? out[o] + v : v;
-    }
+    const T v = ws[w.ob + (int64_t)c * oc + src];
+    T* o = out + obase + t;
+    *o = accumulate ? *o + v : v;
   }
 }
 

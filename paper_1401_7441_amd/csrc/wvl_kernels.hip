@@ -57,7 +57,7 @@ __global__ __launch_bounds__(TPB) void k_gather(const SfDev* __restrict__ sfs,
     const wvl_seg g = seg[q];
     if (gx >= g.i1s && gx <= g.i1e) {
       const int64_t k = g.off + (gx - g.i1s);
-      v = c == 0 ? psi[sf.cin + k] : psi[sf.cin + sf.n_c + (int64_t)(c - 1) * sf.n_f + k];
+      v = c == 0 ? psi[sf.cin + k] : psi[sf.cin + sf.n_c + 7 * k + (c - 1)];
       break;
     }
   }
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(TPB) void k_scatter(const SfDev* __restrict__ sfs,
     const wvl_seg g = seg[q];
     if (gx >= g.i1s && gx <= g.i1e) {
       const int64_t k = g.off + (gx - g.i1s);
-      const int64_t o = c == 0 ? sf.cout + k : sf.cout + sf.on_c + (int64_t)(c - 1) * sf.on_f + k;
+      const int64_t o = c == 0 ? sf.cout + k : sf.cout + sf.on_c + 7 * k + (c - 1);
       out[o] = src[sf.box_out + idx];
       return;
     }
@@ -204,10 +204,9 @@ __global__ __launch_bounds__(64) void k_pattern(const SfDev* __restrict__ sfs,
 // partial sum and the final shuffle tree have an order fixed by the pair.
 template <typename T>
 __device__ __forceinline__ double run_dot(const T* __restrict__ pa, const T* __restrict__ pk,
-                                          int len, int nfa, int64_t nfb, int ncomp) {
+                                          int n) {
   double acc = 0.0;
-  for (int comp = 0; comp < ncomp; ++comp)
-    for (int x = 0; x < len; ++x) acc += (double)pa[comp * (int64_t)nfa + x] * (double)pk[comp * nfb + x];
+  for (int x = 0; x < n; ++x) acc += (double)pa[x] * (double)pk[x];
   return acc;
 }
 
@@ -242,7 +241,7 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
   const PatBox pb = pat_box(B, ket_out);
   const int pc = ket_out ? 2 : 0, pf = ket_out ? 3 : 1;
   const int64_t bc = ket_out ? B.cout : B.cin;
-  const int64_t bnc = ket_out ? B.on_c : B.n_c, bnf = ket_out ? B.on_f : B.n_f;
+  const int64_t bnc = ket_out ? B.on_c : B.n_c;
   const int ny = y1 - y0 + 1;
   const int nrows = (y1 >= y0 && z1 >= z0) ? ny * (z1 - z0 + 1) : 0;
   double acc = 0.0;
@@ -264,9 +263,11 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
           const int x0 = max((int)wa.x0, (int)wb.x0);
           const int x1 = min((int)wa.x0 + wa.len, (int)wb.x0 + wb.len) - 1;
           if (x0 <= x1) {
-            ea[fine][lane] = A.cin + (fine ? A.n_c : 0) + wa.off + (x0 - wa.x0);
-            eb[fine][lane] = bc + (fine ? bnc : 0) + wb.off + (x0 - wb.x0);
-            el[fine][lane] = x1 - x0 + 1;
+            // fine points hold their seven wavelets contiguously
+            const int sc = fine ? 7 : 1;
+            ea[fine][lane] = A.cin + (fine ? A.n_c : 0) + sc * (wa.off + (x0 - wa.x0));
+            eb[fine][lane] = bc + (fine ? bnc : 0) + sc * (wb.off + (x0 - wb.x0));
+            el[fine][lane] = sc * (x1 - x0 + 1);
           }
           continue;
         }
@@ -280,15 +281,16 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
           const wvl_seg sa = seg[qa], sb = seg[qb];
           const int x0 = max(sa.i1s, sb.i1s), x1 = min(sa.i1e, sb.i1e);
           if (x0 <= x1) {
-            const int64_t oa = A.cin + (fine ? A.n_c : 0) + sa.off + (x0 - sa.i1s);
-            const int64_t ob = bc + (fine ? bnc : 0) + sb.off + (x0 - sb.i1s);
+            const int sc = fine ? 7 : 1;
+            const int64_t oa = A.cin + (fine ? A.n_c : 0) + sc * (sa.off + (x0 - sa.i1s));
+            const int64_t ob = bc + (fine ? bnc : 0) + sc * (sb.off + (x0 - sb.i1s));
             if (first) {
               ea[fine][lane] = oa;
               eb[fine][lane] = ob;
-              el[fine][lane] = x1 - x0 + 1;
+              el[fine][lane] = sc * (x1 - x0 + 1);
               first = false;
             } else {
-              acc += run_dot<T>(bra + oa, ket + ob, x1 - x0 + 1, (int)A.n_f, bnf, fine ? 7 : 1);
+              acc += run_dot<T>(bra + oa, ket + ob, sc * (x1 - x0 + 1));
             }
           }
           if (sa.i1e < sb.i1e) ++qa; else ++qb;
@@ -298,21 +300,15 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
     __syncthreads();
     // phase 2
     const int nb = min(64, nrows - r0);
+    // each run (coarse, or fine with the seven wavelets of its points) is
+    // one contiguous stretch on both sides
     for (int q = grp; q < nb; q += 4) {
-      const int lc = el[0][q];
-      if (lc > 0) {
-        const T* pa = bra + ea[0][q];
-        const T* pk = ket + eb[0][q];
-        for (int x = gl; x < lc; x += 16) acc += (double)pa[x] * (double)pk[x];
-      }
-      const int lf = el[1][q];
-      if (lf > 0) {
-        const T* pa = bra + ea[1][q];
-        const T* pk = ket + eb[1][q];
-        for (int t = gl; t < 7 * lf; t += 16) {
-          const int comp = t / lf, x = t - comp * lf;
-          acc += (double)pa[comp * (int64_t)A.n_f + x] * (double)pk[comp * bnf + x];
-        }
+#pragma unroll
+      for (int fine = 0; fine < 2; ++fine) {
+        const int l = el[fine][q];
+        const T* pa = bra + ea[fine][q];
+        const T* pk = ket + eb[fine][q];
+        for (int x = gl; x < l; x += 16) acc += (double)pa[x] * (double)pk[x];
       }
     }
     __syncthreads();
@@ -402,8 +398,8 @@ __global__ __launch_bounds__(256) void k_update(const SfDev* __restrict__ sfs,
     if (s_out[lo] < 0) continue;   // not reached: the host checks input inside output
     const int64_t oi = s_out[lo] + (k - s_in[lo]);
     for (int c = cfirst; c <= clast; ++c) {
-      const int64_t i = sf.cin + (c == 0 ? 0 : sf.n_c + (int64_t)(c - 1) * sf.n_f) + off0 + k;
-      const int64_t o = sf.cout + (c == 0 ? 0 : sf.on_c + (int64_t)(c - 1) * sf.on_f) + oi;
+      const int64_t i = sf.cin + (c == 0 ? off0 + k : sf.n_c + 7 * (off0 + k) + (c - 1));
+      const int64_t o = sf.cout + (c == 0 ? oi : sf.on_c + 7 * oi + (c - 1));
       const double x = (double)psi[i];
       if (mode == 0)
         psi[i] = (T)(x - eta * ((double)hpsi[o] - d * x));

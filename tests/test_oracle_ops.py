@@ -131,10 +131,8 @@ def _full_box_locreg(n):
 def _compress_full(lr, c8):
     pc = LR.points_from_segments(lr.cseg)
     pf = LR.points_from_segments(lr.fseg)
-    out = [c8[0, pc[:, 2], pc[:, 1], pc[:, 0]]]
-    for comp in range(1, 8):
-        out.append(c8[comp, pf[:, 2], pf[:, 1], pf[:, 0]])
-    return np.concatenate(out)
+    fine = np.stack([c8[comp, pf[:, 2], pf[:, 1], pf[:, 0]] for comp in range(1, 8)], axis=1)
+    return np.concatenate([c8[0, pc[:, 2], pc[:, 1], pc[:, 0]], fine.reshape(-1)])
 
 
 def test_local_ham_gaussian_closed_forms_3d():
@@ -381,10 +379,10 @@ def _dict_of(seg_c, seg_f, coef):
     d = {}
     for i, p in enumerate(map(tuple, pc)):
         d[(p, 0)] = coef[i]
-    nc, nf = len(pc), len(pf)
-    for comp in range(1, 8):
-        for i, p in enumerate(map(tuple, pf)):
-            d[(p, comp)] = coef[nc + (comp - 1) * nf + i]
+    nc = len(pc)
+    for i, p in enumerate(map(tuple, pf)):          # [d: n_f][7]
+        for comp in range(1, 8):
+            d[(p, comp)] = coef[nc + 7 * i + (comp - 1)]
     return d
 
 
@@ -422,6 +420,13 @@ def test_sparse_matrices_against_dictionary_products():
         assert abs(S[a, a] - bra[a] @ bra[a]) < 1e-12
 
 
+def _layout(cseg, fseg):
+    """(component, point) of each compressed coefficient, in storage order:
+    coarse points (scaling), then each fine point's seven wavelets."""
+    return ([(0, p) for p in LR.points_from_segments(cseg)] +
+            [(c, p) for p in LR.points_from_segments(fseg) for c in range(1, 8)])
+
+
 # P12: the update step's projection P_L is a pointwise restriction
 def test_update_restriction_matches_pointwise_dictionary():
     from oracle import update as U
@@ -433,14 +438,12 @@ def test_update_restriction_matches_pointwise_dictionary():
         # dictionary: (component, point) -> value of the output-layout vector
         d = {}
         k = 0
-        for comp, segs in [(0, lr.ocseg)] + [(c, lr.ofseg) for c in range(1, 8)]:
-            for p in LR.points_from_segments(segs):
-                d[(comp, tuple(int(v) for v in p))] = out[k]
-                k += 1
+        for comp, p in _layout(lr.ocseg, lr.ofseg):
+            d[(comp, tuple(int(v) for v in p))] = out[k]
+            k += 1
         want = []
-        for comp, segs in [(0, lr.cseg)] + [(c, lr.fseg) for c in range(1, 8)]:
-            for p in LR.points_from_segments(segs):
-                want.append(d[(comp, tuple(int(v) for v in p))])
+        for comp, p in _layout(lr.cseg, lr.fseg):
+            want.append(d[(comp, tuple(int(v) for v in p))])
         got = U.restrict_to_input(lr, out)
         assert np.array_equal(got, np.array(want))
         psi = rng.standard_normal(lr.n_c + 7 * lr.n_f)
@@ -449,15 +452,13 @@ def test_update_restriction_matches_pointwise_dictionary():
         emb = np.zeros_like(out)
         k = 0
         inv = {}
-        for comp, segs in [(0, lr.cseg)] + [(c, lr.fseg) for c in range(1, 8)]:
-            for p in LR.points_from_segments(segs):
-                inv[(comp, tuple(int(v) for v in p))] = psi[k]
-                k += 1
+        for comp, p in _layout(lr.cseg, lr.fseg):
+            inv[(comp, tuple(int(v) for v in p))] = psi[k]
+            k += 1
         k = 0
-        for comp, segs in [(0, lr.ocseg)] + [(c, lr.ofseg) for c in range(1, 8)]:
-            for p in LR.points_from_segments(segs):
-                emb[k] = 2.5 * inv.get((comp, tuple(int(v) for v in p)), 0.0)
-                k += 1
+        for comp, p in _layout(lr.ocseg, lr.ofseg):
+            emb[k] = 2.5 * inv.get((comp, tuple(int(v) for v in p)), 0.0)
+            k += 1
         assert np.allclose(U.update(lr, psi, emb, 2.5, 0.01), psi, rtol=0, atol=1e-15)
 
 
