@@ -5,9 +5,11 @@
 // stride-2 down passes; kinetic term as the coarse two-level filters
 // K_ab = R^T a R), but the separable passes are grouped by where their data
 // can live:
-//   k_fwd_plane  one input z-plane: gather from the compressed segments into
-//                LDS, up pass x, up pass y -> fine (x, y) plane in global G1;
-//                also the dense coarse plane C8 for the kinetic kernels.
+//   k_unpack     one coarse plane of one component: uncompress through the
+//                compact row runs, write the dense box in two layouts (C8 x
+//                fastest, C8X y fastest) for the other kernels.
+//   k_fwd_plane  one input z-plane: up pass x, up pass y from C8 -> fine
+//                (x, y) plane in global G1.
 //   k_pot_column one fine (x, y) column per thread, streaming along z with
 //                register rings: up pass z, potential multiply (FP64 energy
 //                partials), down pass z -> G2.  Every input is read once.
@@ -89,6 +91,61 @@ __device__ __forceinline__ T coef_at(const SfDev& sf, const wvl_seg* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// k_unpack: block = (function, component c, input plane z)
+// ---------------------------------------------------------------------------
+// Uncompress one coarse plane of one component into LDS through the compact
+// row runs (one record per row; rows with several runs walk the segments),
+// then write it twice: C8[c][z][y][x] (x fastest) and C8X[c][z][x][y]
+// (y fastest), both with consecutive threads on consecutive addresses.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack(const SfDev* __restrict__ sfs,
+                                                const wvl_seg* __restrict__ seg,
+                                                const int32_t* __restrict__ rt,
+                                                const RowRun* __restrict__ rr,
+                                                const T* __restrict__ psi,
+                                                const SfWork* __restrict__ wk,
+                                                T* __restrict__ ws) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* pl = reinterpret_cast<T*>(smem_raw);   // [N1][N0 + 1]
+  const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
+  const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2];
+  const int c = blockIdx.x & 7, z = blockIdx.x >> 3;
+  if (z >= N2) return;   // uniform over the block
+  const int fine = c == 0 ? 0 : 1;
+  const int ld = N0 + 1;
+  const int64_t fbase = sf.cin + sf.n_c + (c - 1);   // fine point k at fbase + 7 k
+  for (int idx = threadIdx.x; idx < N0 * N1; idx += 256) {
+    const int y = idx / N0, x = idx - y * N0;
+    const int64_t r = (int64_t)z * N1 + y;
+    const RowRun run = rr[sf.rr[fine] + r];
+    T v = T(0);
+    if (run.len == kMultiRun) {
+      v = coef_at<T>(sf, seg, rt, psi, c, r, sf.lo[0] + x);
+    } else {
+      const int dx = sf.lo[0] + x - (int)run.x0;
+      if (dx >= 0 && dx < (int)run.len) {
+        const int64_t k = run.off + dx;
+        v = fine ? psi[fbase + 7 * k] : psi[sf.cin + k];
+      }
+    }
+    pl[y * ld + x] = v;
+  }
+  __syncthreads();
+  const int64_t plane = (int64_t)N0 * N1;
+  T* c8 = ws + w.c8 + ((int64_t)c * N2 + z) * plane;
+  T* c8x = ws + w.c8x + ((int64_t)c * N2 + z) * plane;
+  for (int idx = threadIdx.x; idx < N0 * N1; idx += 256) {
+    const int y = idx / N0, x = idx - y * N0;
+    c8[idx] = pl[y * ld + x];
+  }
+  for (int idx = threadIdx.x; idx < N0 * N1; idx += 256) {
+    const int x = idx / N1, y = idx - x * N1;
+    c8x[idx] = pl[y * ld + x];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_fwd_plane: block = (function, input plane z, channel a3, row tile)
 // ---------------------------------------------------------------------------
 // LDS: A[4][ny][N0] (components a1 + 2 a2 of channel a3, input rows iy0..iy1),
@@ -114,6 +171,7 @@ __global__ __launch_bounds__(256) void k_fwd_plane(const SfDev* __restrict__ sfs
   const int a3 = bx & 1;
   const int z = bx >> 1;
   if (z >= N2) return;
+  if (!up_on) return;
   const int py0 = tile * tile_rows, py1 = min(R1, py0 + tile_rows);
   const int iy0 = max(0, (py0 - 29) >> 1), iy1 = min(N1 - 1, (py1 - 1) >> 1);
   const int ny = iy1 - iy0 + 1;
@@ -121,37 +179,15 @@ __global__ __launch_bounds__(256) void k_fwd_plane(const SfDev* __restrict__ sfs
   T* B = A + 4 * ny * N0;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int64_t plane = (int64_t)N0 * N1;
-  // 1. gather components of channel a3 on rows iy0..iy1 (and, tile 0 only,
-  //    the dense coarse plane of every row for the kinetic kernels)
-  for (int idx = tid; up_on && idx < 4 * ny * N0; idx += nth) {
+  // 1. components of channel a3 on rows iy0..iy1, from the dense box (x fastest)
+  const T* c8 = ws + w.c8;
+  for (int idx = tid; idx < 4 * ny * N0; idx += nth) {
     const int x = idx % N0;
     const int t = idx / N0;
     const int yy = t % ny, c4 = t / ny;
     const int c = c4 + 4 * a3;
-    A[idx] = coef_at<T>(sf, seg, rt, psi, c, (int64_t)z * N1 + iy0 + yy, sf.lo[0] + x);
+    A[idx] = c8[((int64_t)c * N2 + z) * plane + (int64_t)(iy0 + yy) * N0 + x];
   }
-  if (tile == 0) {
-    // dense coarse plane in two layouts: x fastest (c8) and y fastest (c8x)
-    T* c8 = ws + w.c8;
-    T* c8x = ws + w.c8x;
-    for (int idx = tid; idx < 4 * N1 * N0; idx += nth) {
-      const int x = idx % N0;
-      const int t = idx / N0;
-      const int y = t % N1, c4 = t / N1;
-      const int c = c4 + 4 * a3;
-      c8[((int64_t)c * N2 + z) * plane + (int64_t)y * N0 + x] =
-          coef_at<T>(sf, seg, rt, psi, c, (int64_t)z * N1 + y, sf.lo[0] + x);
-    }
-    for (int idx = tid; idx < 4 * N1 * N0; idx += nth) {
-      const int y = idx % N1;
-      const int t = idx / N1;
-      const int x = t % N0, c4 = t / N0;
-      const int c = c4 + 4 * a3;
-      c8x[(((int64_t)c * N2 + z) * N0 + x) * N1 + y] =
-          coef_at<T>(sf, seg, rt, psi, c, (int64_t)z * N1 + y, sf.lo[0] + x);
-    }
-  }
-  if (!up_on) return;
   __syncthreads();
   // 2. up pass x: B[a2][yy][px], px = 2q (16 taps) and 2q+1 (15 taps) share
   //    the inputs i = q-15..q
@@ -731,6 +767,7 @@ __global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
 int preload_fused_kernels() {
   const void* fns[] = {
       (const void*)k_fwd_plane<float>,      (const void*)k_fwd_plane<double>,
+      (const void*)k_unpack<float>,         (const void*)k_unpack<double>,
       (const void*)k_pot_column<float>,     (const void*)k_pot_column<double>,
       (const void*)k_kin_col<float, 0>,     (const void*)k_kin_col<float, 1>,
       (const void*)k_kin_col<float, 2>,     (const void*)k_kin_col<double, 0>,
@@ -744,6 +781,20 @@ int preload_fused_kernels() {
     if (e != hipSuccess) return (int)e;
   }
   return 0;
+}
+
+int launch_unpack(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                  const RowRun* rr, const void* psi, const SfWork* wk, int nsf, int gridx,
+                  size_t lds, void* ws) {
+  if (nsf == 0 || gridx == 0) return 0;
+  const dim3 g((unsigned)gridx, (unsigned)nsf);
+  if (f64)
+    hipLaunchKernelGGL(k_unpack<double>, g, dim3(256), lds, (hipStream_t)stream, sf, seg, rt, rr,
+                       (const double*)psi, wk, (double*)ws);
+  else
+    hipLaunchKernelGGL(k_unpack<float>, g, dim3(256), lds, (hipStream_t)stream, sf, seg, rt, rr,
+                       (const float*)psi, wk, (float*)ws);
+  return (int)hipGetLastError();
 }
 
 int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,

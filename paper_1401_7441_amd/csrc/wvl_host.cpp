@@ -20,12 +20,12 @@ using namespace wvl;
 
 // kernel kinds for tracing
 enum KernelKind {
-  KK_GATHER, KK_SCATTER, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
+  KK_GATHER, KK_SCATTER, KK_UNPACK, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
   KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
   KK_UPDATE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
-    "uncompress", "compress", "fwd_plane", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
+    "uncompress", "compress", "unpack", "fwd_plane", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
     "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
@@ -677,6 +677,9 @@ static bool make_layout(const wvl_plan* P, int nbins, int tile_div, Layout* L, s
         W.oz = off;  off += align64(8 * o2 * n0 * n1);
         W.ob = off;  off += align64(8 * o0 * o1 * o2);
         ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
+        ch.grid_u = (int32_t)std::max<int64_t>(ch.grid_u, 8 * n2);
+        for (int d = 0; d < 2; ++d)
+          ch.lds_u[d] = std::max<int64_t>(ch.lds_u[d], n1 * (n0 + 1) * (d ? 8 : 4));
         ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
         ch.maxsegs_out = std::max<int64_t>(ch.maxsegs_out, P->nsegs_out[id]);
         ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
@@ -998,10 +1001,14 @@ static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, co
   const ChunkDev& ch = P->lay.chunks[c];
   const SfWork* wk = P->d_wk + ch.sf0;
   double* parts = (double*)((char*)workspace + align_bytes(P->lay.elems_span * sz));
-  WVL_LAUNCH(ctx, KK_FWD_PLANE,
-             launch_fwd_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, wk, ch.sf0, ch.nsf,
-                              ch.grid_f[d], ch.tile_f[d], (size_t)ch.lds_f[d], workspace, pot_on));
+  WVL_LAUNCH(ctx, KK_UNPACK,
+             launch_unpack(f64, st, P->d_sf, P->d_seg, P->d_rt, P->d_rr, psi_c, wk, ch.nsf,
+                           ch.grid_u, (size_t)ch.lds_u[d], workspace));
   if (pot_on) {
+    WVL_LAUNCH(ctx, KK_FWD_PLANE,
+               launch_fwd_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, wk, ch.sf0, ch.nsf,
+                                ch.grid_f[d], ch.tile_f[d], (size_t)ch.lds_f[d], workspace,
+                                pot_on));
     WVL_LAUNCH(ctx, KK_POT_COLUMN,
                launch_pot_column(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_b, workspace, pot,
                                  nf1, nf2, parts, conf, 0.5 * ctx->grid.h));

@@ -77,6 +77,8 @@ __host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2) {
 struct ChunkDev {
   int32_t sf0, nsf;                // positions [sf0, sf0 + nsf) of the processing order
   int64_t maxbox_in, maxbox_out;   // largest dense input / output box (elements)
+  int32_t grid_u;                  // k_unpack: 8 planes per input z
+  int64_t lds_u[2];
   int32_t grid_f[2], tile_f[2];    // k_fwd_plane
   int64_t lds_f[2];
   int32_t grid_b;                  // k_pot_column
@@ -97,6 +99,9 @@ int launch_gather(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, co
 int launch_scatter(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                    const void* box, void* out, int sf0, int nsf, int64_t maxvol);
 int launch_fill(int f64, void* stream, void* ptr, int64_t n);
+int launch_unpack(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                  const RowRun* rr, const void* psi, const SfWork* wk, int nsf, int gridx,
+                  size_t lds, void* ws);
 int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                      const int32_t* rt, const void* psi, const SfWork* wk, int sf0, int nsf,
                      int gridx, int tile_rows, size_t lds, void* ws, int up_on);
