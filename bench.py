@@ -89,9 +89,13 @@ def work_model(locregs, sz):
         g = r0 * r1 * r2
         g1, g2, q = 2 * n2 * r1 * r0, 2 * o2 * r1 * r0, 4 * o2 * r0 * o1
         kx, ky, kz = 8 * o0 * n1 * n2, 8 * n0 * o1 * n2, 8 * n0 * n1 * o2
-        # compressed phi -> two dense copies of the coarse box + x, y up passes
-        add("fwd_plane", sz * (nin + 2 * c8 + g1),
-            2 * 2 * 4 * n1 * n2 * _count_up(n0) + 2 * 2 * 2 * r0 * n2 * _count_up(n1))
+        gx = 4 * n2 * n1 * r0
+        # compressed phi -> two dense copies of the coarse box (x and y fastest)
+        add("unpack", sz * (nin + 2 * c8), 0)
+        # x up pass: 8 coarse components -> 4 channel pairs of x-fine rows
+        add("up_x", sz * (c8 + gx), 2 * 2 * 4 * n1 * n2 * _count_up(n0))
+        # y up pass: 4 channel pairs -> 2 (x, y)-fine planes per z
+        add("up_y", sz * (gx + g1), 2 * 2 * 2 * r0 * n2 * _count_up(n1))
         # z up pass, V multiply, e_pot partials, z down pass
         add("pot_column", sz * (g1 + g + g2),
             2 * 2 * r0 * r1 * _count_up(n2) + 3 * g + 2 * 2 * r0 * r1 * _count_down(n2, e))
@@ -424,7 +428,6 @@ def main():
         "schedule": {"timed": "graph replay" if graph is not None else "eager calls",
                      "eager_ms_per_step": eager_ms,
                      "nbins": tune["best"]["nbins"] if tune else 1,
-                     "tile_div": tune["best"]["tile_div"] if tune else 1,
                      "chunks": S["plan"].info["chunks"],
                      "autotune": tune},
         "setup": {"locregs_s": S["t_locreg"], "patterns_ms": S["t_pattern"] * 1e3},

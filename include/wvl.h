@@ -282,9 +282,10 @@ wvl_status wvl_graph_create(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const 
 wvl_status wvl_graph_launch(wvl_graph* graph);
 void wvl_graph_destroy(wvl_graph* graph);
 
-/* Autotuner over the plan's schedule: for every bin count in {1, 2, 4, 8}
- * and k_fwd_plane row-tile divisor in {1, 2, 4}, runs the apply `reps` times
- * (after one warm-up) and keeps the fastest layout.  Buffers as for wvl_apply_local_ham (hpsi_c is overwritten; the
+/* Autotuner over the plan's schedule: for every bin count in
+ * {1, 2, 3, 4, 6, 8} (functions sorted by box volume, cut into that many
+ * launches per stage), runs the apply `reps` times (after one warm-up) and
+ * keeps the fastest layout.  Buffers as for wvl_apply_local_ham (hpsi_c is overwritten; the
  * workspace is the size wvl_plan_create reported, which covers every
  * candidate).  tried (host, may be NULL) receives up to max_tried points,
  * *ntried the number timed, *best the chosen one.  Synchronous; the plan
@@ -292,7 +293,6 @@ void wvl_graph_destroy(wvl_graph* graph);
  * do not depend on the layout chosen (bitwise). */
 typedef struct {
   int32_t nbins;      /* bins of the size-sorted functions */
-  int32_t tile_div;   /* k_fwd_plane row tile = largest that fits / tile_div */
   double ms;          /* mean duration of one apply */
 } wvl_tune_point;
 wvl_status wvl_plan_autotune(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const void* psi_c,

@@ -61,7 +61,7 @@ class _Grid(ctypes.Structure):
 
 
 class _TunePoint(ctypes.Structure):
-    _fields_ = [("nbins", ctypes.c_int32), ("tile_div", ctypes.c_int32), ("ms", ctypes.c_double)]
+    _fields_ = [("nbins", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -485,7 +485,7 @@ class Graph:
 
 
 def autotune(plan: Plan, psi_c, pot, hpsi_c, workspace, reps=3, terms=KIN | POT):
-    """wvl_plan_autotune -> (best, tried): dicts {nbins, tile_div, ms}."""
+    """wvl_plan_autotune -> (best, tried): dicts {nbins, ms}."""
     _need_cuda(psi_c, pot, hpsi_c, workspace)
     dt = _dtype_code(psi_c, pot, hpsi_c)
     _check_sizes(plan, psi_c, hpsi_c, None, None, workspace, dt)
@@ -495,6 +495,6 @@ def autotune(plan: Plan, psi_c, pot, hpsi_c, workspace, reps=3, terms=KIN | POT)
     _check(lib().wvl_plan_autotune(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
                                    _ptr(hpsi_c), _ptr(workspace), int(reps), tried, 32,
                                    ctypes.byref(n), ctypes.byref(best)), plan.ctx.handle)
-    as_dict = lambda t: {"nbins": t.nbins, "tile_div": t.tile_div, "ms": t.ms}
+    as_dict = lambda t: {"nbins": t.nbins, "ms": t.ms}
     plan.info = plan._read_info()
     return as_dict(best), [as_dict(tried[i]) for i in range(n.value)]

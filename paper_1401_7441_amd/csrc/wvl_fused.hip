@@ -8,8 +8,11 @@
 //   k_unpack     one coarse plane of one component: uncompress through the
 //                compact row runs, write the dense box in two layouts (C8 x
 //                fastest, C8X y fastest) for the other kernels.
-//   k_fwd_plane  one input z-plane: up pass x, up pass y from C8 -> fine
-//                (x, y) plane in global G1.
+//   k_up_x       one coarse row per thread, streaming along x: the x up pass
+//                (synthesis and magic filter in one 31-tap filter) into GX
+//                through 32-wide LDS stages.
+//   k_up_y       one fine column per thread, streaming along y: the y up
+//                pass from GX into G1.
 //   k_pot_column one fine (x, y) column per thread, streaming along z with
 //                register rings: up pass z, potential multiply (FP64 energy
 //                partials), down pass z -> G2.  Every input is read once.
@@ -146,93 +149,121 @@ __global__ __launch_bounds__(256) void k_unpack(const SfDev* __restrict__ sfs,
 }
 
 // ---------------------------------------------------------------------------
-// k_fwd_plane: block = (function, input plane z, channel a3, row tile)
+// k_up_x: thread = one coarse row (channel pair, z, y), streaming along x
 // ---------------------------------------------------------------------------
-// LDS: A[4][ny][N0] (components a1 + 2 a2 of channel a3, input rows iy0..iy1),
-//      B[2][ny][R0] (after the x up pass, channel a2).
-// Output G1[a3][z][py][px], py in the tile [py0, py1), px in [0, R0).
+// The two components c = a1 + 2 a2 + 4 a3 (a1 = 0, 1) of channel pair
+// ch = a2 + 2 a3 are read from C8X (y across the lanes); fine points p = 2q,
+// 2q+1 (f_p = sum_i C_a1[p - 2i] x_a1(i), i = q-15..q) come out of a 16-slot
+// ring.  Every 32 fine points are staged in LDS and written to
+// GX[ch][z][y][px] (px fastest), 2 rows x 32 points per store.
+constexpr int kSPX = 66;   // stage stride: banks 2 j + row parity are distinct
 template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_plane(const SfDev* __restrict__ sfs,
-                                                   const wvl_seg* __restrict__ seg,
-                                                   const int32_t* __restrict__ rt,
-                                                   const T* __restrict__ psi,
-                                                   const SfWork* __restrict__ wk, int sf0,
-                                                   T* __restrict__ ws, int tile_rows, int up_on) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
+__global__ __launch_bounds__(64) void k_up_x(const SfDev* __restrict__ sfs,
+                                             const SfWork* __restrict__ wk,
+                                             T* __restrict__ ws) {
+  __shared__ T st[32 * kSPX];
+  const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
+  const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2];
+  const int R0 = 2 * N0 + 29;
+  const int nrow = 4 * N2 * N1;
+  const int row0 = blockIdx.x * 64;
+  if (row0 >= nrow) return;   // uniform over the block
+  const int lane = threadIdx.x;
+  const int row = row0 + lane;
+  const bool active = row < nrow;
+  const int y = active ? row % N1 : 0;
+  const int t = active ? row / N1 : 0;
+  const int z = t % N2, ch = t / N2;
+  const int64_t plane = (int64_t)N0 * N1;
+  const int c0 = 2 * (ch & 1) + 4 * (ch >> 1);
+  const T* in0 = ws + w.c8x + ((int64_t)c0 * N2 + z) * plane + y;        // [c][z][x][y]
+  const T* in1 = in0 + (int64_t)N2 * plane;                               // component c0 + 1
+  const int obase = active ? row * R0 : -1;                               // GX row start
+  T* gx = ws + w.gx;
+  T xs[16], xd[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) xs[k] = xd[k] = T(0);
+  const int qend = N0 + 14;
+  for (int q0 = 0; q0 <= qend; q0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q0 + u;
+      const bool ok = active && q < N0;
+      xs[u] = ok ? in0[(int64_t)q * N1] : T(0);
+      xd[u] = ok ? in1[(int64_t)q * N1] : T(0);
+      T fe = T(0), fo = T(0);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int sl = (u - k) & 15;
+        fe += Ct<T>(0, 2 * k) * xs[sl] + Ct<T>(1, 2 * k) * xd[sl];
+        if (k < 15) fo += Ct<T>(0, 2 * k + 1) * xs[sl] + Ct<T>(1, 2 * k + 1) * xd[sl];
+      }
+      st[(2 * u) * kSPX + lane] = fe;
+      st[(2 * u + 1) * kSPX + lane] = fo;
+    }
+    // flush px = 2 q0 + j, j = 0..31
+    __syncthreads();
+    const int j = lane & 31;
+    const int px = 2 * q0 + j;
+    const bool okp = px < R0;
+#pragma unroll 4
+    for (int it = 0; it < 32; ++it) {
+      const int rl = 2 * it + (lane >> 5);
+      const int ob = __shfl(obase, rl, 64);
+      if (okp && ob >= 0) gx[ob + px] = st[j * kSPX + rl];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_up_y: thread = one fine column (a3, z, px), streaming along y
+// ---------------------------------------------------------------------------
+// Reads GX[a2 + 2 a3][z][y][px] for a2 = 0, 1 (px across the lanes) and
+// writes G1[a3][z][py][px] for py = 2q, 2q+1 from a 16-slot ring.
+template <typename T>
+__global__ __launch_bounds__(256) void k_up_y(const SfDev* __restrict__ sfs,
+                                              const SfWork* __restrict__ wk,
+                                              T* __restrict__ ws) {
   const SfWork& w = wk[blockIdx.y];
   const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2];
   const int R0 = 2 * N0 + 29, R1 = 2 * N1 + 29;
-  const int ntile = (R1 + tile_rows - 1) / tile_rows;
-  int bx = blockIdx.x;
-  const int tile = bx % ntile;
-  bx /= ntile;
-  const int a3 = bx & 1;
-  const int z = bx >> 1;
-  if (z >= N2) return;
-  if (!up_on) return;
-  const int py0 = tile * tile_rows, py1 = min(R1, py0 + tile_rows);
-  const int iy0 = max(0, (py0 - 29) >> 1), iy1 = min(N1 - 1, (py1 - 1) >> 1);
-  const int ny = iy1 - iy0 + 1;
-  T* A = sm;
-  T* B = A + 4 * ny * N0;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int64_t plane = (int64_t)N0 * N1;
-  // 1. components of channel a3 on rows iy0..iy1, from the dense box (x fastest)
-  const T* c8 = ws + w.c8;
-  for (int idx = tid; idx < 4 * ny * N0; idx += nth) {
-    const int x = idx % N0;
-    const int t = idx / N0;
-    const int yy = t % ny, c4 = t / ny;
-    const int c = c4 + 4 * a3;
-    A[idx] = c8[((int64_t)c * N2 + z) * plane + (int64_t)(iy0 + yy) * N0 + x];
-  }
-  __syncthreads();
-  // 2. up pass x: B[a2][yy][px], px = 2q (16 taps) and 2q+1 (15 taps) share
-  //    the inputs i = q-15..q
-  const int Q0 = N0 + 15;
-  for (int idx = tid; idx < 2 * ny * Q0; idx += nth) {
-    const int q = idx % Q0;
-    const int t = idx / Q0;
-    const int yy = t % ny, a2 = t / ny;
-    const T* s = A + (2 * a2) * ny * N0 + yy * N0;
-    const T* d = s + ny * N0;
-    T fe = T(0), fo = T(0);
+  const int64_t ncol = 2ll * N2 * R0;                 // columns (a3, z, px), px fastest
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncol) return;
+  const int px = (int)(col % R0);
+  const int64_t t = col / R0;
+  const int z = (int)(t % N2), a3 = (int)(t / N2);
+  const int64_t gxc = (int64_t)N2 * N1 * R0;          // GX channel stride
+  const T* in0 = ws + w.gx + ((int64_t)(2 * a3) * N2 + z) * N1 * R0 + px;   // a2 = 0
+  const T* in1 = in0 + gxc;                                                   // a2 = 1
+  T* out = ws + w.g1 + ((int64_t)a3 * N2 + z) * ((int64_t)R1 * R0) + px;
+  // (in0, in1 and out move forward as the stream advances)
+  T xs[16], xd[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int i = q - k;
-      if (i >= 0 && i < N0) {
-        const T sv = s[i], dv = d[i];
-        fe += Ct<T>(0, 2 * k) * sv + Ct<T>(1, 2 * k) * dv;
-        if (k < 15) fo += Ct<T>(0, 2 * k + 1) * sv + Ct<T>(1, 2 * k + 1) * dv;
+  for (int k = 0; k < 16; ++k) xs[k] = xd[k] = T(0);
+  const int qend = N1 + 14;
+  const int64_t gstep = 16 * (int64_t)R0;   // pointers advance by 16 rows per block
+  for (int q0 = 0; q0 <= qend; q0 += 16, in0 += gstep, in1 += gstep, out += 2 * gstep) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q0 + u;
+      if (q <= qend) {
+        xs[u] = q < N1 ? in0[u * R0] : T(0);
+        xd[u] = q < N1 ? in1[u * R0] : T(0);
+        T fe = T(0), fo = T(0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int sl = (u - k) & 15;
+          fe += Ct<T>(0, 2 * k) * xs[sl] + Ct<T>(1, 2 * k) * xd[sl];
+          if (k < 15) fo += Ct<T>(0, 2 * k + 1) * xs[sl] + Ct<T>(1, 2 * k + 1) * xd[sl];
+        }
+        out[(2 * u) * R0] = fe;
+        if (2 * q + 1 < R1) out[(2 * u + 1) * R0] = fo;
       }
     }
-    T* o = B + a2 * ny * R0 + yy * R0;
-    o[2 * q] = fe;
-    if (2 * q + 1 < R0) o[2 * q + 1] = fo;
-  }
-  __syncthreads();
-  // 3. up pass y into global: rows py = 2q, 2q+1 of the tile
-  T* g1 = ws + w.g1 + ((int64_t)a3 * N2 + z) * ((int64_t)R0 * R1);
-  const int qy0 = py0 >> 1, qy1 = (py1 + 1) >> 1;
-  const int nq = qy1 - qy0;
-  for (int idx = tid; idx < nq * R0; idx += nth) {
-    const int px = idx % R0;
-    const int q = qy0 + idx / R0;
-    T fe = T(0), fo = T(0);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int i = q - k;
-      if (i >= iy0 && i <= iy1) {
-        const T sv = B[(i - iy0) * R0 + px], dv = B[ny * R0 + (i - iy0) * R0 + px];
-        fe += Ct<T>(0, 2 * k) * sv + Ct<T>(1, 2 * k) * dv;
-        if (k < 15) fo += Ct<T>(0, 2 * k + 1) * sv + Ct<T>(1, 2 * k + 1) * dv;
-      }
-    }
-    const int pe = 2 * q, po = 2 * q + 1;
-    if (pe >= py0 && pe < py1) g1[(int64_t)pe * R0 + px] = fe;
-    if (po >= py0 && po < py1) g1[(int64_t)po * R0 + px] = fo;
   }
 }
 
@@ -766,8 +797,9 @@ __global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
 // a stream is being captured.
 int preload_fused_kernels() {
   const void* fns[] = {
-      (const void*)k_fwd_plane<float>,      (const void*)k_fwd_plane<double>,
       (const void*)k_unpack<float>,         (const void*)k_unpack<double>,
+      (const void*)k_up_x<float>,           (const void*)k_up_x<double>,
+      (const void*)k_up_y<float>,           (const void*)k_up_y<double>,
       (const void*)k_pot_column<float>,     (const void*)k_pot_column<double>,
       (const void*)k_kin_col<float, 0>,     (const void*)k_kin_col<float, 1>,
       (const void*)k_kin_col<float, 2>,     (const void*)k_kin_col<double, 0>,
@@ -797,17 +829,22 @@ int launch_unpack(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, co
   return (int)hipGetLastError();
 }
 
-int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
-                     const int32_t* rt, const void* psi, const SfWork* wk, int sf0, int nsf,
-                     int gridx, int tile_rows, size_t lds, void* ws, int up_on) {
+int launch_up(int f64, void* stream, int axis, const SfWork* wk, const SfDev* sf, int nsf,
+              int gridx, void* ws) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
-  if (f64)
-    hipLaunchKernelGGL(k_fwd_plane<double>, g, dim3(256), lds, (hipStream_t)stream, sf, seg, rt,
-                       (const double*)psi, wk, sf0, (double*)ws, tile_rows, up_on);
-  else
-    hipLaunchKernelGGL(k_fwd_plane<float>, g, dim3(256), lds, (hipStream_t)stream, sf, seg, rt,
-                       (const float*)psi, wk, sf0, (float*)ws, tile_rows, up_on);
+  hipStream_t st = (hipStream_t)stream;
+  if (axis == 0) {
+    if (f64)
+      hipLaunchKernelGGL(k_up_x<double>, g, dim3(64), 0, st, sf, wk, (double*)ws);
+    else
+      hipLaunchKernelGGL(k_up_x<float>, g, dim3(64), 0, st, sf, wk, (float*)ws);
+  } else {
+    if (f64)
+      hipLaunchKernelGGL(k_up_y<double>, g, dim3(256), 0, st, sf, wk, (double*)ws);
+    else
+      hipLaunchKernelGGL(k_up_y<float>, g, dim3(256), 0, st, sf, wk, (float*)ws);
+  }
   return (int)hipGetLastError();
 }
 

@@ -20,12 +20,12 @@ using namespace wvl;
 
 // kernel kinds for tracing
 enum KernelKind {
-  KK_GATHER, KK_SCATTER, KK_UNPACK, KK_FWD_PLANE, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
+  KK_GATHER, KK_SCATTER, KK_UNPACK, KK_UP_X, KK_UP_Y, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
   KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
   KK_UPDATE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
-    "uncompress", "compress", "unpack", "fwd_plane", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
+    "uncompress", "compress", "unpack", "up_x", "up_y", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
     "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
@@ -151,7 +151,7 @@ struct Layout {
   std::vector<ChunkDev> chunks;
   std::vector<SfWork> wk;        // per position of the processing order
   bool disjoint = true;
-  int nbins = 1, tile_div = 1;
+  int nbins = 1;
   int64_t elems_span = 0;        // elements of the compute type before the partials
   int64_t parts_span = 0;        // doubles of energy partials
   int64_t bytes(int sz) const { return align_bytes(elems_span * sz) + parts_span * 8; }
@@ -616,7 +616,7 @@ void wvl_plan_destroy(wvl_plan* plan) {
 }
 
 // bin counts the autotuner tries (the plan's workspace covers all of them)
-static const int kTuneBins[] = {1, 2, 4, 8};
+static const int kTuneBins[] = {1, 2, 3, 4, 6, 8};
 
 static int64_t sf_elems(const SfDev& S) {
   const int64_t n0 = S.n[0], n1 = S.n[1], n2 = S.n[2], e = S.ext;
@@ -624,17 +624,16 @@ static int64_t sf_elems(const SfDev& S) {
   const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
   return 2 * align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) + align64(2 * o2 * r0 * r1) +
          align64(4 * o2 * r0 * o1) + align64(8 * n2 * o0 * n1) + align64(8 * n2 * o1 * n0) +
-         align64(8 * o2 * n0 * n1) + align64(8 * o0 * o1 * o2);
+         align64(8 * o2 * n0 * n1) + align64(8 * o0 * o1 * o2) + align64(4 * n2 * n1 * r0);
 }
 
-// Builds the layout for `nbins` bins and fwd_plane row tiles divided by
-// `tile_div`; false (with a message) when some box does not fit the LDS tiles.
-static bool make_layout(const wvl_plan* P, int nbins, int tile_div, Layout* L, std::string* err) {
+// Builds the layout for `nbins` bins; false (with a message) when a box
+// does not fit the kernels' LDS stages.
+static bool make_layout(const wvl_plan* P, int nbins, Layout* L, std::string* err) {
   const int nsf = P->nsf;
   L->chunks.clear();
   L->wk.assign(nsf, SfWork{});
   L->nbins = nbins;
-  L->tile_div = tile_div;
   L->disjoint = P->max_ws == 0;
   L->elems_span = 0;
   L->parts_span = 0;
@@ -676,8 +675,11 @@ static bool make_layout(const wvl_plan* P, int nbins, int tile_div, Layout* L, s
         W.oy = off;  off += align64(8 * n2 * o1 * n0);
         W.oz = off;  off += align64(8 * o2 * n0 * n1);
         W.ob = off;  off += align64(8 * o0 * o1 * o2);
+        W.gx = off;  off += align64(4 * n2 * n1 * r0);
         ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
         ch.grid_u = (int32_t)std::max<int64_t>(ch.grid_u, 8 * n2);
+        ch.grid_ux = (int32_t)std::max<int64_t>(ch.grid_ux, (4 * n2 * n1 + 63) / 64);
+        ch.grid_uy = (int32_t)std::max<int64_t>(ch.grid_uy, (2 * n2 * r0 + 255) / 256);
         for (int d = 0; d < 2; ++d)
           ch.lds_u[d] = std::max<int64_t>(ch.lds_u[d], n1 * (n0 + 1) * (d ? 8 : 4));
         ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
@@ -688,40 +690,6 @@ static bool make_layout(const wvl_plan* P, int nbins, int tile_div, Layout* L, s
         ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2));
         ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
         ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, ((4 * o1 + 63) / 64) * o2);
-      }
-      for (int d = 0; d < 2; ++d) {
-        const int64_t sz = d ? 8 : 4;
-        // k_fwd_plane: the largest row tile (of fine output rows) that fits,
-        // divided by tile_div
-        int64_t r1max = 0;
-        for (int q = k; q < j; ++q) r1max = std::max<int64_t>(r1max, 2 * P->h_sf[P->order[q]].n[1] + 29);
-        auto lds_f = [&](int64_t T) {
-          int64_t m = 0;
-          for (int q = k; q < j; ++q) {
-            const SfDev& S = P->h_sf[P->order[q]];
-            const int64_t ny = std::min<int64_t>(S.n[1], T / 2 + 17);
-            m = std::max<int64_t>(m, (4 * ny * S.n[0] + 2 * ny * (2 * S.n[0] + 29)) * sz);
-          }
-          return m;
-        };
-        int64_t tf = r1max;
-        while (tf > 2 && lds_f(tf) > kLdsBudget) tf = (tf + 1) / 2;
-        tf = std::max<int64_t>(2, tf / std::max(1, tile_div));
-        ch.tile_f[d] = (int32_t)tf;
-        ch.lds_f[d] = lds_f(tf);
-        int64_t gf = 0;
-        for (int q = k; q < j; ++q) {
-          const SfDev& S = P->h_sf[P->order[q]];
-          gf = std::max<int64_t>(gf, (int64_t)S.n[2] * 2 * ((2 * S.n[1] + 29 + tf - 1) / tf));
-        }
-        ch.grid_f[d] = (int32_t)gf;
-        if (ch.lds_f[d] > kLdsBudget) {
-          char buf[160];
-          snprintf(buf, sizeof buf, "functions %d..%d (processing order): boxes too large for "
-                   "the LDS tiles", k, j - 1);
-          *err = buf;
-          return false;
-        }
       }
       ch.nblk_pot = ch.grid_b;
       ch.nblk_kin = ch.grid_kx + ch.grid_ky + ch.grid_kz;
@@ -887,7 +855,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   for (int nb : kTuneBins) {
     Layout L;
     std::string err;
-    if (!make_layout(P, nb, 1, &L, &err)) {
+    if (!make_layout(P, nb, &L, &err)) {
       wvl_plan_destroy(P);
       return fail(ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
     }
@@ -1005,10 +973,8 @@ static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, co
              launch_unpack(f64, st, P->d_sf, P->d_seg, P->d_rt, P->d_rr, psi_c, wk, ch.nsf,
                            ch.grid_u, (size_t)ch.lds_u[d], workspace));
   if (pot_on) {
-    WVL_LAUNCH(ctx, KK_FWD_PLANE,
-               launch_fwd_plane(f64, st, P->d_sf, P->d_seg, P->d_rt, psi_c, wk, ch.sf0, ch.nsf,
-                                ch.grid_f[d], ch.tile_f[d], (size_t)ch.lds_f[d], workspace,
-                                pot_on));
+    WVL_LAUNCH(ctx, KK_UP_X, launch_up(f64, st, 0, wk, P->d_sf, ch.nsf, ch.grid_ux, workspace));
+    WVL_LAUNCH(ctx, KK_UP_Y, launch_up(f64, st, 1, wk, P->d_sf, ch.nsf, ch.grid_uy, workspace));
     WVL_LAUNCH(ctx, KK_POT_COLUMN,
                launch_pot_column(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_b, workspace, pot,
                                  nf1, nf2, parts, conf, 0.5 * ctx->grid.h));
@@ -1435,37 +1401,34 @@ wvl_status wvl_plan_autotune(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
     (void)hipEventDestroy(e0);
     return fail(ctx, WVL_EDEVICE, "wvl_plan_autotune: event creation failed");
   }
-  wvl_tune_point top{0, 0, 1e300};
+  wvl_tune_point top{0, 1e300};
   int n = 0;
   for (int nb : kTuneBins) {
-    for (int td : {1, 2, 4}) {
-      Layout L;
-      std::string err;
-      if (!make_layout(P, nb, td, &L, &err) || L.bytes(sz) > P->ws_cap[sz == 8]) continue;
-      if ((st = set_layout(P, std::move(L))) != WVL_OK) break;
-      // warm-up, then `reps` timed eager applies of this layout
-      if ((st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
-                           "wvl_plan_autotune")) != WVL_OK)
-        break;
-      hipError_t he = hipEventRecord(e0, ctx->stream);
-      for (int r = 0; he == hipSuccess && st == WVL_OK && r < reps; ++r)
-        st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
-                        "wvl_plan_autotune");
-      if (st != WVL_OK) break;
-      if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
-      if (he == hipSuccess) he = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      if (he != hipSuccess) {
-        st = fail(ctx, WVL_EDEVICE, "wvl_plan_autotune: %s", hipGetErrorString(he));
-        break;
-      }
-      const wvl_tune_point pt{nb, td, (double)ms / reps};
-      if (tried && n < max_tried) tried[n] = pt;
-      ++n;
-      if (pt.ms < top.ms) top = pt;
-    }
+    Layout L;
+    std::string err;
+    if (!make_layout(P, nb, &L, &err) || L.bytes(sz) > P->ws_cap[sz == 8]) continue;
+    if ((st = set_layout(P, std::move(L))) != WVL_OK) break;
+    // warm-up, then `reps` timed eager applies of this layout
+    if ((st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
+                         "wvl_plan_autotune")) != WVL_OK)
+      break;
+    hipError_t he = hipEventRecord(e0, ctx->stream);
+    for (int r = 0; he == hipSuccess && st == WVL_OK && r < reps; ++r)
+      st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
+                      "wvl_plan_autotune");
     if (st != WVL_OK) break;
+    if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      st = fail(ctx, WVL_EDEVICE, "wvl_plan_autotune: %s", hipGetErrorString(he));
+      break;
+    }
+    const wvl_tune_point pt{nb, (double)ms / reps};
+    if (tried && n < max_tried) tried[n] = pt;
+    ++n;
+    if (pt.ms < top.ms) top = pt;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1474,7 +1437,7 @@ wvl_status wvl_plan_autotune(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
   if (n == 0) return fail(ctx, WVL_EUNSUPPORTED, "wvl_plan_autotune: no candidate fits");
   Layout L;
   std::string err;
-  if (!make_layout(P, top.nbins, top.tile_div, &L, &err))
+  if (!make_layout(P, top.nbins, &L, &err))
     return fail(ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
   if ((st = set_layout(P, std::move(L))) != WVL_OK) return st;
   if (best) *best = top;

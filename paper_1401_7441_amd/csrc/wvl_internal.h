@@ -57,9 +57,10 @@ constexpr uint16_t kMultiRun = 0xFFFF;
 //   oy   y part of the kinetic term      [8][N2][N0][O1]
 //   oz   z part of the kinetic term      [8][O2][N0][N1]
 //   ob   dense output box                [8][O2][O1][O0]
+//   gx   after the x up pass             [4][N2][N1][R0]   (channel a2 + 2 a3)
 struct SfWork {
   int64_t id;         // the function's index in the plan (SfDev array, outputs)
-  int64_t c8, c8x, g1, g2, q, ox, oy, oz, ob;
+  int64_t c8, c8x, g1, g2, q, ox, oy, oz, ob, gx;
   int64_t epart;      // offset (in doubles) of its e_pot partials
   int64_t kpart;      // offset (in doubles) of its e_kin partials
   int64_t nkpart;     // number of e_kin partials: its own k_kin_col blocks
@@ -78,9 +79,8 @@ struct ChunkDev {
   int32_t sf0, nsf;                // positions [sf0, sf0 + nsf) of the processing order
   int64_t maxbox_in, maxbox_out;   // largest dense input / output box (elements)
   int32_t grid_u;                  // k_unpack: 8 planes per input z
+  int32_t grid_ux, grid_uy;        // k_up_x, k_up_y
   int64_t lds_u[2];
-  int32_t grid_f[2], tile_f[2];    // k_fwd_plane
-  int64_t lds_f[2];
   int32_t grid_b;                  // k_pot_column
   int32_t grid_kx, grid_ky, grid_kz;   // k_kin_col (x, y, z)
   int32_t grid_by;                 // k_back_y
@@ -102,9 +102,8 @@ int launch_fill(int f64, void* stream, void* ptr, int64_t n);
 int launch_unpack(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                   const RowRun* rr, const void* psi, const SfWork* wk, int nsf, int gridx,
                   size_t lds, void* ws);
-int launch_fwd_plane(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
-                     const int32_t* rt, const void* psi, const SfWork* wk, int sf0, int nsf,
-                     int gridx, int tile_rows, size_t lds, void* ws, int up_on);
+int launch_up(int f64, void* stream, int axis, const SfWork* wk, const SfDev* sf, int nsf,
+              int gridx, void* ws);
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                       int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart,
                       const double* conf, double hh);
