@@ -353,10 +353,10 @@ def main():
     fine_pts = sum(int((2 * r["dims"][0] + 29) * (2 * r["dims"][1] + 29) * (2 * r["dims"][2] + 29))
                    for r in S["lr"])
     model = work_model(S["lr"], sz)
-    # S and H values: phi (and H phi) read once, CSR indices read, values written
+    # S and H values: phi (and H phi) read once, one value per pair written
     info = S["plan"].info
-    model["sparse_s"] = (sz * info["in_coefs"] + 16.0 * S["nnz_s"], 0.0)
-    model["sparse_h"] = (sz * (info["in_coefs"] + info["out_coefs"]) + 16.0 * S["nnz_h"], 0.0)
+    model["sparse_s"] = (sz * info["in_coefs"] + 8.0 * S["nnz_s"], 0.0)
+    model["sparse_h"] = (sz * (info["in_coefs"] + info["out_coefs"]) + 8.0 * S["nnz_h"], 0.0)
     kernels = {}
     for k, (n, ms) in prof.items():
         if n:

@@ -271,6 +271,10 @@ def test_sparse_overlap_and_hamiltonian(spheres, dtype):
             for a in range(n):
                 diag = v[rp[a] + list(cl[rp[a]:rp[a + 1]]).index(a)]
                 assert abs(diag - 1.0) < (1e-13 if dtype == "f64" else 1e-6)
+        # a second call starts from cleared partials: bitwise the same values
+        _, _, val2 = W.sparse_overlap(plan, psi, hpsi if ket_out else psi, ket_out)
+        torch.cuda.synchronize()
+        assert np.array_equal(val2.cpu().numpy(), v)
 
 
 def test_repeat_runs_bitwise_deterministic(spheres):
