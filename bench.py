@@ -212,6 +212,72 @@ def step(S):
     W.sparse_overlap(S["plan"], S["psi"], S["hpsi"], True, out=S["h_out"])
 
 
+def density_section(S, reps=3):
+    """Fine-box values of every function (wvl_synthesize) and the density
+    rho = sum_ab phi_a K^ab phi_b (wvl_density) with a smooth kernel
+    K_ab = 0.5 exp(-|R_a - R_b|^2 / 18) on the overlap pattern."""
+    import numpy as np
+    import torch
+
+    import paper_1401_7441_amd as W
+    plan, psi, ctx = S["plan"], S["psi"], S["ctx"]
+    g = S["g"]
+    n = g.grid_n
+    fine = torch.empty(plan.info["fine_box"], dtype=psi.dtype, device="cuda")
+    work = torch.empty_like(fine)
+    rho = torch.empty((2 * n[0] + 29) * (2 * n[1] + 29) * (2 * n[2] + 29), dtype=psi.dtype,
+                      device="cuda")
+    rowptr, col, _ = W.sparse_overlap(plan, psi, psi, False)
+    rp = rowptr.cpu().numpy()
+    row = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    c = np.asarray(g.centers, np.float64)
+    d2 = np.sum((c[row] - c[col.cpu().numpy()]) ** 2, axis=1)
+    kval = torch.tensor(0.5 * np.exp(-d2 / 18.0), dtype=torch.float64, device="cuda")
+    W.synthesize(plan, psi, fine, S["ws"])
+    W.density(plan, fine, rowptr, col, kval, rho, work)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        W.synthesize(plan, psi, fine, S["ws"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        W.density(plan, fine, rowptr, col, kval, rho, work)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    sz = psi.element_size()
+    nfine = plan.info["fine_box"]
+    grid_pts = rho.numel()
+    # pair work: every kernel entry over the common part of the two fine boxes
+    lo = np.array([[int(v) for v in r["lo"]] for r in S["lr"]])
+    dims = np.array([[int(v) for v in r["dims"]] for r in S["lr"]])
+    a0, a1 = 2 * lo, 2 * lo + 2 * dims + 29
+    cb = col.cpu().numpy()
+    ov = np.prod(np.maximum(0, np.minimum(a1[row], a1[cb]) - np.maximum(a0[row], a0[cb])), axis=1)
+    pair_pts = float(np.sum(ov))
+    kern = {k: {"launches": v[0] // reps, "avg_ms": v[1] / v[0]} for k, v in prof.items() if v[0]}
+    pair_ms = kern.get("dens_pair", {}).get("avg_ms")
+    return {
+        "synthesize_ms": (t1 - t0) * 1e3 / reps,
+        "density_ms": (t2 - t1) * 1e3 / reps,
+        "kernels": kern,
+        "fine_box_points": nfine,
+        "grid_points": grid_pts,
+        "kernel_nnz": int(kval.numel()),
+        "pair_box_points": pair_pts,
+        # k_dens_pair: algorithmic bytes = the fine values read once and the
+        # products written once; measured against them it is the pairwise
+        # re-reading (pair_box_points values) that bounds it
+        "dens_pair_alg_gbps": (2 * nfine * sz / (pair_ms * 1e-3) / 1e9) if pair_ms else None,
+        "dens_pair_pair_gbps": (pair_pts * sz / (pair_ms * 1e-3) / 1e9) if pair_ms else None,
+        "note": "K on the overlap (S) pattern, smooth synthetic values; eager calls",
+    }
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
@@ -264,6 +330,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the request-loop measurement (p50/p99 latency)")
     ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the fine-grid values + density section")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -433,6 +501,11 @@ def main():
         "setup": {"locregs_s": S["t_locreg"], "patterns_ms": S["t_pattern"] * 1e3},
         "source_hash": source_hash(),
     }
+    if not args.no_density:
+        log("density: fine-box values and rho on the fine grid")
+        res["density"] = density_section(S)
+        log(f"density: synthesize {res['density']['synthesize_ms']:.2f} ms, "
+            f"density {res['density']['density_ms']:.2f} ms")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.workload)
     if not args.no_serve:

@@ -125,6 +125,7 @@ typedef struct {
   int64_t workspace_f32;/* workspace bytes for WVL_F32                     */
   int64_t workspace_f64;/* workspace bytes for WVL_F64                     */
   int64_t chunks;       /* support-function chunks one apply iterates     */
+  int64_t fine_box;     /* elements of all fine boxes (wvl_synthesize)    */
 } wvl_plan_info;
 
 typedef struct wvl_ctx wvl_ctx;
@@ -220,6 +221,36 @@ wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hp
 wvl_status wvl_sparse_overlap(wvl_plan* plan, const void* bra_c, int ket_is_output,
                               const void* ket_c, wvl_dtype dt, int64_t* nnz, int64_t* rowptr,
                               int32_t* col, double* val);
+
+/* Real-space values of every support function on its fine box (Sec. II.B:
+ * the two-level synthesis to the grid of spacing h/2, then the magic filter,
+ * the steps the potential term of wvl_apply_local_ham starts with).  Function
+ * k's box holds (2 N + 29)^3 points per its box dims N, stored
+ * fine[off_k + (pz (2 N1 + 29) + py) (2 N0 + 29) + px] with off_k the sum of
+ * the boxes of functions 0..k-1 (wvl_plan_info.fine_box elements in all);
+ * point p of an axis sits at global fine-grid index 2 lo + p, the grid of
+ * the potential.  psi_c: device, input layout; fine: device, dt; workspace
+ * as for wvl_apply_local_ham.  Asynchronous on the context's stream. */
+wvl_status wvl_synthesize(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* fine,
+                          void* workspace);
+
+/* Electronic density on the fine grid, Eq. (density) of Sec. II:
+ *   rho(r) = sum_ab phi_a(r) K^ab phi_b(r)
+ * with phi on the fine grid as wvl_synthesize writes it (fine) and the
+ * density kernel K in CSR form: k_rowptr (device int64[nsf + 1]), k_col
+ * (device int32[k_nnz]), k_val (device double[k_nnz]); any pattern, entries
+ * summed as given (columns outside [0, nsf) and positions outside
+ * [0, k_nnz) are skipped).  rho: device, dt, the global fine grid
+ * [2 n2 + 29][2 n1 + 29][2 n0 + 29] (z, y, x), every point written (0 where
+ * no fine box reaches).  work: device scratch of wvl_plan_info.fine_box
+ * elements of dt.  Sums run in double in an order fixed by the plan and K
+ * (row order of K per point, then increasing function index), so the
+ * result is reproducible bitwise.  The first call builds the plan's tile
+ * lists (synchronizes once).  Errors: WVL_EINVAL for null buffers or
+ * k_nnz < 0. */
+wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int64_t* k_rowptr,
+                       const int32_t* k_col, const double* k_val, int64_t k_nnz, void* rho,
+                       void* work);
 
 /* Support-function update step (the localized gradient step of Sec. III.A
  * and IV.A, reduced to a fixed step length):

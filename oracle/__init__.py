@@ -26,6 +26,8 @@ update       The support-function update step with the localized gradient
              (paper Sec. III.A and IV.A), fixed step length.
 precond      Kinetic + confinement preconditioning of the gradient (paper
              Sec. IV.A, Eq. (precond)), conjugate-gradient steps.
+density      Fine-grid values of the support functions and the density
+             rho = sum_ab phi_a K^ab phi_b (paper Sec. II, Eq. (density)).
 
 Parity status: every function here is pinned by a check that does not reuse
 its own formula (closed forms, invariants, brute force); see the tests marked

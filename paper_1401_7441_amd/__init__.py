@@ -43,7 +43,7 @@ LOCREG_DTYPE = np.dtype([
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
             "wvl_compress", "wvl_apply_local_ham", "wvl_apply_local_ham_conf", "wvl_kinetic",
-            "wvl_sparse_overlap",
+            "wvl_sparse_overlap", "wvl_synthesize", "wvl_density",
             "wvl_update", "wvl_precondition", "wvl_graph_create", "wvl_graph_launch",
             "wvl_graph_destroy",
             "wvl_plan_autotune",
@@ -66,7 +66,8 @@ class _TunePoint(ctypes.Structure):
 
 class _PlanInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("nsf", "in_coefs", "out_coefs", "in_box", "out_box",
-                                               "workspace_f32", "workspace_f64", "chunks")]
+                                               "workspace_f32", "workspace_f64", "chunks",
+                                               "fine_box")]
 
 
 def _load():
@@ -103,6 +104,8 @@ def _load():
         "wvl_kinetic": [P, ctypes.c_int, P, P, P, P],
         "wvl_apply_local_ham_conf": [P, ctypes.c_int, U32, P, P, P, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
+        "wvl_synthesize": [P, ctypes.c_int, P, P, P],
+        "wvl_density": [P, ctypes.c_int, P, P, P, P, I64, P, P],
         "wvl_update": [P, ctypes.c_int, D, P, P, P],
         "wvl_precondition": [P, ctypes.c_int, P, P, P, I32, P, P, P],
         "wvl_graph_create": [P, ctypes.c_int, U32, P, P, P, P, P, P, P, P, ctypes.POINTER(P)],
@@ -409,6 +412,44 @@ def update(plan: Plan, psi_c, hpsi_c, h_val, eta):
     if h_val.dtype.itemsize != 8 or h_val.numel() < sparse_pattern_nnz(plan, True):
         raise WvlError(WVL_EINVAL, "h_val must be float64 with the H pattern's nnz entries")
     _check(lib().wvl_update(plan._ptr, dt, float(eta), _ptr(hpsi_c), _ptr(h_val), _ptr(psi_c)),
+           plan.ctx.handle)
+
+
+def synthesize(plan: Plan, psi_c, fine, workspace=None):
+    """wvl_synthesize: every function's real-space values on its fine box,
+    concatenated in function order (plan.info["fine_box"] elements)."""
+    _need_cuda(psi_c, fine, workspace)
+    dt = _dtype_code(psi_c, fine)
+    if psi_c.numel() < plan.info["in_coefs"] or fine.numel() < plan.info["fine_box"]:
+        raise WvlError(WVL_EINVAL, "buffer smaller than the plan's layout")
+    if workspace is None:
+        workspace = plan.new_workspace(psi_c.dtype)
+    _check(lib().wvl_synthesize(plan._ptr, dt, _ptr(psi_c), _ptr(fine), _ptr(workspace)),
+           plan.ctx.handle)
+
+
+def density(plan: Plan, fine, k_rowptr, k_col, k_val, rho, work=None):
+    """wvl_density: rho (global fine grid, z, y, x) = sum_ab phi_a K^ab phi_b
+    from the fine-box values `fine` and K in CSR form (int64 rowptr, int32
+    col, float64 val, all on the device)."""
+    import torch
+    _need_cuda(fine, k_rowptr, k_col, k_val, rho, work)
+    dt = _dtype_code(fine, rho, work)
+    n = plan.ctx.grid_n
+    if rho.numel() < (2 * n[0] + 29) * (2 * n[1] + 29) * (2 * n[2] + 29):
+        raise WvlError(WVL_EINVAL, "rho smaller than the fine grid")
+    if fine.numel() < plan.info["fine_box"]:
+        raise WvlError(WVL_EINVAL, "fine smaller than the plan's fine boxes")
+    if k_rowptr.dtype != torch.int64 or k_rowptr.numel() < plan.nsf + 1 or \
+            k_col.dtype != torch.int32 or k_val.dtype != torch.float64 or \
+            k_col.numel() != k_val.numel():
+        raise WvlError(WVL_EINVAL, "K must be CSR: int64 rowptr[nsf + 1], int32 col, float64 val")
+    if work is None:
+        work = torch.empty(max(1, plan.info["fine_box"]), dtype=fine.dtype, device="cuda")
+    elif work.numel() < plan.info["fine_box"]:
+        raise WvlError(WVL_EINVAL, "work smaller than the plan's fine boxes")
+    _check(lib().wvl_density(plan._ptr, dt, _ptr(fine), _ptr(k_rowptr), _ptr(k_col),
+                             _ptr(k_val), int(k_val.numel()), _ptr(rho), _ptr(work)),
            plan.ctx.handle)
 
 

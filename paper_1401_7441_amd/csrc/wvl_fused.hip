@@ -268,6 +268,55 @@ __global__ __launch_bounds__(256) void k_up_y(const SfDev* __restrict__ sfs,
 }
 
 // ---------------------------------------------------------------------------
+// k_up_z: thread = one fine (x, y) column, streaming along z
+// ---------------------------------------------------------------------------
+// Reads G1[a3][z][py][px] for a3 = 0, 1 and writes the function's values on
+// its fine box, FINE[pz][py][px] (fine point p of an axis at global fine
+// index 2 lo + p), for pz = 2q, 2q+1 from a 16-slot ring: the last step of
+// the synthesis to real space.
+template <typename T>
+__global__ __launch_bounds__(256) void k_up_z(const SfDev* __restrict__ sfs,
+                                              const SfWork* __restrict__ wk,
+                                              const T* __restrict__ ws,
+                                              const int64_t* __restrict__ fine_off,
+                                              T* __restrict__ fine) {
+  const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
+  const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2];
+  const int R0 = 2 * N0 + 29, R1 = 2 * N1 + 29, R2 = 2 * N2 + 29;
+  const int64_t plane = (int64_t)R1 * R0;
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= plane) return;
+  const T* in0 = ws + w.g1 + col;                 // a3 = 0
+  const T* in1 = in0 + (int64_t)N2 * plane;       // a3 = 1
+  T* out = fine + fine_off[w.id] + col;
+  T xs[16], xd[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) xs[k] = xd[k] = T(0);
+  const int qend = N2 + 14;
+  for (int q0 = 0; q0 <= qend; q0 += 16, in0 += 16 * plane, in1 += 16 * plane,
+           out += 32 * plane) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q0 + u;
+      if (q <= qend) {
+        xs[u] = q < N2 ? in0[u * plane] : T(0);
+        xd[u] = q < N2 ? in1[u * plane] : T(0);
+        T fe = T(0), fo = T(0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int sl = (u - k) & 15;
+          fe += Ct<T>(0, 2 * k) * xs[sl] + Ct<T>(1, 2 * k) * xd[sl];
+          if (k < 15) fo += Ct<T>(0, 2 * k + 1) * xs[sl] + Ct<T>(1, 2 * k + 1) * xd[sl];
+        }
+        out[(2 * u) * plane] = fe;
+        if (2 * q + 1 < R2) out[(2 * u + 1) * plane] = fo;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_pot_column: thread = one fine (x, y) column of one function
 // ---------------------------------------------------------------------------
 // Streaming over coarse z index q: input pair x(q) arrives, fine points
@@ -798,6 +847,7 @@ __global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
 int preload_fused_kernels() {
   const void* fns[] = {
       (const void*)k_unpack<float>,         (const void*)k_unpack<double>,
+      (const void*)k_up_z<float>,           (const void*)k_up_z<double>,
       (const void*)k_up_x<float>,           (const void*)k_up_x<double>,
       (const void*)k_up_y<float>,           (const void*)k_up_y<double>,
       (const void*)k_pot_column<float>,     (const void*)k_pot_column<double>,
@@ -845,6 +895,19 @@ int launch_up(int f64, void* stream, int axis, const SfWork* wk, const SfDev* sf
     else
       hipLaunchKernelGGL(k_up_y<float>, g, dim3(256), 0, st, sf, wk, (float*)ws);
   }
+  return (int)hipGetLastError();
+}
+
+int launch_up_z(int f64, void* stream, const SfWork* wk, const SfDev* sf, int nsf, int gridx,
+                const void* ws, const int64_t* fine_off, void* fine) {
+  if (nsf == 0) return 0;
+  const dim3 g((unsigned)gridx, (unsigned)nsf);
+  if (f64)
+    hipLaunchKernelGGL(k_up_z<double>, g, dim3(256), 0, (hipStream_t)stream, sf, wk,
+                       (const double*)ws, fine_off, (double*)fine);
+  else
+    hipLaunchKernelGGL(k_up_z<float>, g, dim3(256), 0, (hipStream_t)stream, sf, wk,
+                       (const float*)ws, fine_off, (float*)fine);
   return (int)hipGetLastError();
 }
 

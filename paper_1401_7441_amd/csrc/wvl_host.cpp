@@ -22,11 +22,12 @@ using namespace wvl;
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_UNPACK, KK_UP_X, KK_UP_Y, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
   KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
-  KK_UPDATE, KK_COUNT
+  KK_UPDATE, KK_UP_Z, KK_DENS_PAIR, KK_DENS_GATHER, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "unpack", "up_x", "up_y", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
-    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update"};
+    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update",
+    "up_z", "dens_pair", "dens_gather"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -183,6 +184,10 @@ struct wvl_plan {
   int32_t* d_rt = nullptr;
   RowRun* d_rr = nullptr;
   SfWork* d_wk = nullptr;
+  int64_t* d_foff = nullptr;          // fine-box offsets (wvl_synthesize), function order
+  int64_t max_fine = 0;               // largest fine box (elements)
+  int64_t* d_cptr = nullptr;          // density: functions meeting each k_dens_gather tile
+  int32_t* d_csf = nullptr;
   wvl_plan_info info{};
   PatternCache pat[2];
 };
@@ -606,6 +611,9 @@ void wvl_plan_destroy(wvl_plan* plan) {
   if (!plan) return;
   if (plan->d_sf) (void)hipFree(plan->d_sf);
   if (plan->d_seg) (void)hipFree(plan->d_seg);
+  if (plan->d_foff) (void)hipFree(plan->d_foff);
+  if (plan->d_cptr) (void)hipFree(plan->d_cptr);
+  if (plan->d_csf) (void)hipFree(plan->d_csf);
   if (plan->d_rt) (void)hipFree(plan->d_rt);
   if (plan->d_rr) (void)hipFree(plan->d_rr);
   if (plan->d_wk) (void)hipFree(plan->d_wk);
@@ -872,11 +880,20 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   P->info.workspace_f32 = best_f32;
   P->info.workspace_f64 = best_f64;
   P->info.chunks = (int64_t)P->lay.chunks.size();
+  std::vector<int64_t> foff(nsf + 1, 0);
+  for (int k = 0; k < nsf; ++k) {
+    const SfDev& S = P->h_sf[k];
+    const int64_t v = (int64_t)(2 * S.n[0] + 29) * (2 * S.n[1] + 29) * (2 * S.n[2] + 29);
+    foff[k + 1] = foff[k] + v;
+    P->max_fine = std::max(P->max_fine, v);
+  }
+  P->info.fine_box = foff[nsf];
   if ((st = upload(ctx, &P->d_sf, P->h_sf.data(), sizeof(SfDev) * nsf)) != WVL_OK ||
       (st = upload(ctx, &P->d_seg, segs, sizeof(wvl_seg) * nsegs)) != WVL_OK ||
       (st = upload(ctx, &P->d_rt, rt.data(), sizeof(int32_t) * rt.size())) != WVL_OK ||
       (st = upload(ctx, &P->d_rr, rr.data(), sizeof(RowRun) * rr.size())) != WVL_OK ||
-      (st = upload(ctx, &P->d_wk, P->lay.wk.data(), sizeof(SfWork) * nsf)) != WVL_OK) {
+      (st = upload(ctx, &P->d_wk, P->lay.wk.data(), sizeof(SfWork) * nsf)) != WVL_OK ||
+      (st = upload(ctx, &P->d_foff, foff.data(), sizeof(int64_t) * (nsf + 1))) != WVL_OK) {
     wvl_plan_destroy(P);
     return st;
   }
@@ -1162,6 +1179,112 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
                                     P->d_rr, ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col,
                                     pc.d_order, pc.nnz, val));
   }
+  return WVL_OK;
+}
+
+wvl_status wvl_synthesize(wvl_plan* P, wvl_dtype dt, const void* psi_c, void* fine,
+                          void* workspace) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_synthesize: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (P->nsf == 0) return WVL_OK;
+  if (!psi_c || !fine || !workspace) return fail(ctx, WVL_EINVAL, "wvl_synthesize: null buffer");
+  const int f64 = dt == WVL_F64 ? 1 : 0;
+  for (size_t c = 0; c < P->lay.chunks.size(); ++c) {
+    const ChunkDev& ch = P->lay.chunks[c];
+    const SfWork* wk = P->d_wk + ch.sf0;
+    hipStream_t st = ctx->stream;
+    WVL_LAUNCH(ctx, KK_UNPACK,
+               launch_unpack(f64, st, P->d_sf, P->d_seg, P->d_rt, P->d_rr, psi_c, wk, ch.nsf,
+                             ch.grid_u, (size_t)ch.lds_u[f64], workspace));
+    WVL_LAUNCH(ctx, KK_UP_X, launch_up(f64, st, 0, wk, P->d_sf, ch.nsf, ch.grid_ux, workspace));
+    WVL_LAUNCH(ctx, KK_UP_Y, launch_up(f64, st, 1, wk, P->d_sf, ch.nsf, ch.grid_uy, workspace));
+    WVL_LAUNCH(ctx, KK_UP_Z, launch_up_z(f64, st, wk, P->d_sf, ch.nsf, ch.grid_b, workspace,
+                                         P->d_foff, fine));
+  }
+  return WVL_OK;
+}
+
+// functions whose fine box meets each k_dens_gather tile, increasing index
+static wvl_status ensure_cover(wvl_plan* P) {
+  if (P->d_cptr) return WVL_OK;
+  wvl_ctx* ctx = P->ctx;
+  int gf[3], nt[3];
+  for (int a = 0; a < 3; ++a) {
+    gf[a] = 2 * ctx->grid.n[a] + 29;
+    nt[a] = (gf[a] + kDensTile[a] - 1) / kDensTile[a];
+  }
+  const int64_t ntile = (int64_t)nt[0] * nt[1] * nt[2];
+  if (ntile > INT32_MAX) return fail(ctx, WVL_EUNSUPPORTED, "density: fine grid too large");
+  std::vector<int64_t> cptr(ntile + 1, 0);
+  std::vector<int32_t> csf;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int64_t> pos;
+    if (pass == 1) {
+      for (int64_t t = 0; t < ntile; ++t) cptr[t + 1] += cptr[t];
+      pos.assign(cptr.begin(), cptr.end() - 1);
+      csf.resize(cptr[ntile]);
+    }
+    for (int k = 0; k < P->nsf; ++k) {
+      const SfDev& S = P->h_sf[k];
+      int t0[3], t1[3];
+      for (int a = 0; a < 3; ++a) {
+        t0[a] = (2 * S.lo[a]) / kDensTile[a];
+        t1[a] = (2 * S.lo[a] + 2 * S.n[a] + 28) / kDensTile[a];
+      }
+      for (int z = t0[2]; z <= t1[2]; ++z)
+        for (int y = t0[1]; y <= t1[1]; ++y)
+          for (int x = t0[0]; x <= t1[0]; ++x) {
+            const int64_t t = ((int64_t)z * nt[1] + y) * nt[0] + x;
+            if (pass == 0)
+              ++cptr[t + 1];
+            else
+              csf[pos[t]++] = k;
+          }
+    }
+  }
+  wvl_status st;
+  if ((st = upload(ctx, &P->d_cptr, cptr.data(), sizeof(int64_t) * cptr.size())) != WVL_OK)
+    return st;
+  if ((st = upload(ctx, &P->d_csf, csf.data(), sizeof(int32_t) * csf.size())) != WVL_OK) {
+    (void)hipFree(P->d_cptr);
+    P->d_cptr = nullptr;
+    return st;
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    (void)hipFree(P->d_cptr);
+    if (P->d_csf) (void)hipFree(P->d_csf);
+    P->d_cptr = nullptr;
+    P->d_csf = nullptr;
+    return fail(ctx, WVL_EDEVICE, "density tile lists upload failed");
+  }
+  return WVL_OK;
+}
+
+wvl_status wvl_density(wvl_plan* P, wvl_dtype dt, const void* fine, const int64_t* k_rowptr,
+                       const int32_t* k_col, const double* k_val, int64_t k_nnz, void* rho,
+                       void* work) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_density: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (k_nnz < 0) return fail(ctx, WVL_EINVAL, "wvl_density: k_nnz < 0");
+  if (!rho) return fail(ctx, WVL_EINVAL, "wvl_density: null rho");
+  if (P->nsf > 0 && (!fine || !k_rowptr || !work || (k_nnz > 0 && (!k_col || !k_val))))
+    return fail(ctx, WVL_EINVAL, "wvl_density: null buffer");
+  wvl_status st = ensure_cover(P);
+  if (st != WVL_OK) return st;
+  const int f64 = dt == WVL_F64 ? 1 : 0;
+  for (int s0 = 0; s0 < P->nsf; s0 += 65535) {
+    const int n = std::min(65535, P->nsf - s0);
+    WVL_LAUNCH(ctx, KK_DENS_PAIR,
+               launch_dens_pair(f64, ctx->stream, P->d_sf, P->nsf, P->d_foff, fine, k_rowptr,
+                                k_col, k_val, k_nnz, s0, n, P->max_fine, work));
+  }
+  int gf[3];
+  for (int a = 0; a < 3; ++a) gf[a] = 2 * ctx->grid.n[a] + 29;
+  WVL_LAUNCH(ctx, KK_DENS_GATHER,
+             launch_dens_gather(f64, ctx->stream, P->d_sf, P->d_foff, work, P->d_cptr, P->d_csf,
+                                gf, rho));
   return WVL_OK;
 }
 

@@ -104,6 +104,17 @@ int launch_unpack(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, co
                   size_t lds, void* ws);
 int launch_up(int f64, void* stream, int axis, const SfWork* wk, const SfDev* sf, int nsf,
               int gridx, void* ws);
+int launch_up_z(int f64, void* stream, const SfWork* wk, const SfDev* sf, int nsf, int gridx,
+                const void* ws, const int64_t* fine_off, void* fine);
+int launch_dens_pair(int f64, void* stream, const SfDev* sf, int nsf, const int64_t* foff,
+                     const void* fine, const int64_t* krow, const int32_t* kcol,
+                     const double* kval, int64_t knnz, int sf0, int nrows, int64_t maxvol,
+                     void* prod);
+// tile of k_dens_gather (x, y, z fine points; 256 points) and its launch
+constexpr int kDensTile[3] = {32, 4, 2};
+int launch_dens_gather(int f64, void* stream, const SfDev* sf, const int64_t* foff,
+                       const void* prod, const int64_t* cptr, const int32_t* csf, const int* gf,
+                       void* rho);
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                       int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart,
                       const double* conf, double hh);

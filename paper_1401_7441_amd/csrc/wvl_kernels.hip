@@ -318,6 +318,75 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// density rho(r) = sum_ab phi_a(r) K^ab phi_b(r) on the fine grid
+// ---------------------------------------------------------------------------
+// Step 1 (k_dens_pair): thread = one fine point r of function a's box;
+// P_a(r) = phi_a(r) sum_q K[q] phi_b(r) over the kernel's row a (b = col[q]),
+// phi_b(r) = 0 outside b's fine box.  The row is walked in its stored order,
+// so each point is a fixed sum.  Columns outside [0, nsf) and positions
+// outside [0, knnz) are skipped.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dens_pair(const SfDev* __restrict__ sfs, int nsf,
+                                                   const int64_t* __restrict__ foff,
+                                                   const T* __restrict__ fine,
+                                                   const int64_t* __restrict__ krow,
+                                                   const int32_t* __restrict__ kcol,
+                                                   const double* __restrict__ kval, int64_t knnz,
+                                                   int sf0, T* __restrict__ prod) {
+  const int a = sf0 + blockIdx.y;
+  const SfDev& A = sfs[a];
+  const int R0 = 2 * A.n[0] + 29, R1 = 2 * A.n[1] + 29, R2 = 2 * A.n[2] + 29;
+  const int64_t vol = (int64_t)R0 * R1 * R2;
+  const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= vol) return;
+  const int px = (int)(idx % R0);
+  const int64_t t = idx / R0;
+  const int py = (int)(t % R1), pz = (int)(t / R1);
+  const int gx = 2 * A.lo[0] + px, gy = 2 * A.lo[1] + py, gz = 2 * A.lo[2] + pz;
+  const int64_t q0 = max((int64_t)0, krow[a]), q1 = min(knnz, krow[a + 1]);
+  double acc = 0.0;
+  for (int64_t q = q0; q < q1; ++q) {
+    const int b = kcol[q];
+    if (b < 0 || b >= nsf) continue;
+    const SfDev& B = sfs[b];
+    const int bx = gx - 2 * B.lo[0], by = gy - 2 * B.lo[1], bz = gz - 2 * B.lo[2];
+    const int S0 = 2 * B.n[0] + 29, S1 = 2 * B.n[1] + 29, S2 = 2 * B.n[2] + 29;
+    if (bx < 0 || bx >= S0 || by < 0 || by >= S1 || bz < 0 || bz >= S2) continue;
+    acc += kval[q] * (double)fine[foff[b] + ((int64_t)bz * S1 + by) * S0 + bx];
+  }
+  prod[foff[a] + idx] = (T)((double)fine[foff[a] + idx] * acc);
+}
+
+// Step 2 (k_dens_gather): block = one tile of 32 x 4 x 2 fine-grid points;
+// rho(r) = sum of P_a(r) over the functions whose fine box meets the tile,
+// in increasing function index (a fixed sum); 0 where no box reaches.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dens_gather(const SfDev* __restrict__ sfs,
+                                                     const int64_t* __restrict__ foff,
+                                                     const T* __restrict__ prod,
+                                                     const int64_t* __restrict__ cptr,
+                                                     const int32_t* __restrict__ csf, int tx,
+                                                     int ty, int g0, int g1, int g2,
+                                                     T* __restrict__ rho) {
+  const int tile = blockIdx.x;
+  const int ix = tile % tx, iy = (tile / tx) % ty, iz = tile / (tx * ty);
+  const int gx = ix * kDensTile[0] + (threadIdx.x & 31);
+  const int gy = iy * kDensTile[1] + ((threadIdx.x >> 5) & 3);
+  const int gz = iz * kDensTile[2] + (threadIdx.x >> 7);
+  if (gx >= g0 || gy >= g1 || gz >= g2) return;
+  double acc = 0.0;
+  for (int64_t i = cptr[tile]; i < cptr[tile + 1]; ++i) {
+    const int a = csf[i];
+    const SfDev& A = sfs[a];
+    const int px = gx - 2 * A.lo[0], py = gy - 2 * A.lo[1], pz = gz - 2 * A.lo[2];
+    const int R0 = 2 * A.n[0] + 29, R1 = 2 * A.n[1] + 29, R2 = 2 * A.n[2] + 29;
+    if (px < 0 || px >= R0 || py < 0 || py >= R1 || pz < 0 || pz >= R2) continue;
+    acc += (double)prod[foff[a] + ((int64_t)pz * R1 + py) * R0 + px];
+  }
+  rho[((int64_t)gz * g1 + gy) * g0 + gx] = (T)acc;
+}
+
+// ---------------------------------------------------------------------------
 // support-function update: psi <- psi - eta (P_L hpsi - H_aa psi)
 // ---------------------------------------------------------------------------
 // Block = 64 consecutive input segments of one function (coarse blocks, then
@@ -493,7 +562,9 @@ int preload_kernels() {
   const void* fns[] = {(const void*)k_finalize, (const void*)k_sparse_values<float>,
                        (const void*)k_sparse_values<double>, (const void*)k_update<float>,
                        (const void*)k_update<double>, (const void*)k_sf_dot<float>,
-                       (const void*)k_sf_dot<double>};
+                       (const void*)k_sf_dot<double>, (const void*)k_dens_pair<float>,
+                       (const void*)k_dens_pair<double>, (const void*)k_dens_gather<float>,
+                       (const void*)k_dens_gather<double>};
   for (const void* f : fns) {
     hipFuncAttributes a;
     const hipError_t e = hipFuncGetAttributes(&a, f);
@@ -568,6 +639,39 @@ int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* 
     hipLaunchKernelGGL(k_sparse_values<float>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
                        seg, rt, rr, ket_out, (const float*)bra, (const float*)ket, row, col,
                        order, nnz, val);
+  return (int)hipGetLastError();
+}
+
+int launch_dens_pair(int f64, void* stream, const SfDev* sf, int nsf, const int64_t* foff,
+                     const void* fine, const int64_t* krow, const int32_t* kcol,
+                     const double* kval, int64_t knnz, int sf0, int nrows, int64_t maxvol,
+                     void* prod) {
+  if (nrows == 0 || maxvol == 0) return 0;
+  const dim3 g((unsigned)((maxvol + TPB - 1) / TPB), (unsigned)nrows);
+  if (f64)
+    hipLaunchKernelGGL(k_dens_pair<double>, g, dim3(TPB), 0, (hipStream_t)stream, sf, nsf, foff,
+                       (const double*)fine, krow, kcol, kval, knnz, sf0, (double*)prod);
+  else
+    hipLaunchKernelGGL(k_dens_pair<float>, g, dim3(TPB), 0, (hipStream_t)stream, sf, nsf, foff,
+                       (const float*)fine, krow, kcol, kval, knnz, sf0, (float*)prod);
+  return (int)hipGetLastError();
+}
+
+int launch_dens_gather(int f64, void* stream, const SfDev* sf, const int64_t* foff,
+                       const void* prod, const int64_t* cptr, const int32_t* csf, const int* gf,
+                       void* rho) {
+  const int tx = (gf[0] + kDensTile[0] - 1) / kDensTile[0];
+  const int ty = (gf[1] + kDensTile[1] - 1) / kDensTile[1];
+  const int tz = (gf[2] + kDensTile[2] - 1) / kDensTile[2];
+  const dim3 g((unsigned)((int64_t)tx * ty * tz));
+  if (f64)
+    hipLaunchKernelGGL(k_dens_gather<double>, g, dim3(TPB), 0, (hipStream_t)stream, sf, foff,
+                       (const double*)prod, cptr, csf, tx, ty, gf[0], gf[1], gf[2],
+                       (double*)rho);
+  else
+    hipLaunchKernelGGL(k_dens_gather<float>, g, dim3(TPB), 0, (hipStream_t)stream, sf, foff,
+                       (const float*)prod, cptr, csf, tx, ty, gf[0], gf[1], gf[2],
+                       (float*)rho);
   return (int)hipGetLastError();
 }
 

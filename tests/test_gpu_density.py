@@ -1,0 +1,141 @@
+"""Fine-grid values and density rho = sum_ab phi_a K^ab phi_b (paper Sec. II,
+Eq. (density)) through the C ABI, against the oracle.
+
+Tolerances: FP64 1e-12 and FP32 1e-5, relative to the largest magnitude of
+the array compared (the values and products are sums of many terms of both
+signs, so an elementwise relative bound has no meaning near zeros)."""
+import numpy as np
+import pytest
+
+from oracle import density as D
+from tests.test_gpu_batching import _mixed_case
+from tests.test_gpu_parity import _print, _sphere_case
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_1401_7441_amd as W
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def spheres():
+    return _sphere_case(nsf=5, seed_shift=3)
+
+
+def _fine_offsets(lrs):
+    sizes = [int(np.prod(D.fine_box_shape(lr))) for lr in lrs]
+    return np.concatenate([[0], np.cumsum(sizes)])
+
+
+def _synth(case, dt):
+    ctx = W.Context(case.g.h, case.g.grid_n)
+    plan = W.Plan(ctx, case.rec, case.segs)
+    psi = torch.tensor(case.psi, dtype=dt, device="cuda")
+    fine = torch.full((plan.info["fine_box"],), float("nan"), dtype=dt, device="cuda")
+    W.synthesize(plan, psi, fine)
+    torch.cuda.synchronize()
+    return plan, psi, fine
+
+
+def _kernel_on_s_pattern(plan, psi, nsf, seed):
+    """K = sum_i f_i c_i c_i^T (three orbitals) kept on the overlap pattern."""
+    rowptr, col, _ = W.sparse_overlap(plan, psi, psi, False)
+    rp, cl = rowptr.cpu().numpy(), col.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((3, nsf))
+    f = rng.uniform(0.2, 2.0, 3)
+    K = sum(f[i] * np.outer(c[i], c[i]) for i in range(3))
+    val = np.array([K[a, cl[q]] for a in range(nsf) for q in range(rp[a], rp[a + 1])])
+    return rp, cl, val
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fine_values_against_oracle(spheres, dtype):
+    _print(f"case: fine-box values, {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    _, _, fine = _synth(spheres, dt)
+    got = fine.cpu().numpy().astype(np.float64)
+    off = _fine_offsets(spheres.lrs)
+    assert off[-1] == got.size
+    for k, lr in enumerate(spheres.lrs):
+        want = D.fine_values(lr, spheres.coefs[k]).ravel()
+        g = got[off[k]:off[k + 1]]
+        assert np.all(np.isfinite(g)), k
+        assert np.max(np.abs(g - want)) <= TOL[dtype] * np.max(np.abs(want)), k
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_density_against_oracle(spheres, dtype):
+    _print(f"case: density, {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    plan, psi, fine = _synth(spheres, dt)
+    nsf = len(spheres.lrs)
+    rp, cl, val = _kernel_on_s_pattern(plan, psi, nsf, seed=7)
+    n = spheres.g.grid_n
+    rho = torch.full(((2 * n[2] + 29) * (2 * n[1] + 29) * (2 * n[0] + 29),), float("nan"),
+                     dtype=dt, device="cuda")
+    args = (torch.tensor(rp, dtype=torch.int64, device="cuda"),
+            torch.tensor(cl, dtype=torch.int32, device="cuda"),
+            torch.tensor(val, dtype=torch.float64, device="cuda"))
+    W.density(plan, fine, *args, rho)
+    torch.cuda.synchronize()
+    got = rho.cpu().numpy().astype(np.float64)
+    want = D.density(spheres.lrs, spheres.coefs, (rp, cl, val), n).ravel()
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - want)) <= TOL[dtype] * np.max(np.abs(want))
+    # a second call: bitwise the same
+    rho2 = torch.empty_like(rho)
+    W.density(plan, fine, *args, rho2)
+    torch.cuda.synchronize()
+    assert np.array_equal(rho2.cpu().numpy(), rho.cpu().numpy())
+
+
+def test_density_kernel_edge_cases(spheres):
+    """Empty rows, a duplicated entry (summed) and out-of-range columns
+    (skipped), against the oracle on the same entries minus the skipped."""
+    _print("case: density, kernel edge cases")
+    plan, psi, fine = _synth(spheres, torch.float64)
+    nsf = len(spheres.lrs)
+    rows = {0: [(0, 1.0), (2, 0.5), (2, 0.25), (nsf, 9.0)], 1: [], 2: [(0, 0.75), (-1, 3.0)],
+            3: [(3, 2.0)], 4: []}
+    rp = np.zeros(nsf + 1, np.int64)
+    cl, val = [], []
+    for a in range(nsf):
+        for b, v in rows.get(a, []):
+            cl.append(b)
+            val.append(v)
+        rp[a + 1] = len(cl)
+    n = spheres.g.grid_n
+    rho = torch.empty((2 * n[2] + 29) * (2 * n[1] + 29) * (2 * n[0] + 29), dtype=torch.float64,
+                      device="cuda")
+    W.density(plan, fine, torch.tensor(rp, device="cuda"),
+              torch.tensor(np.array(cl, np.int32), device="cuda"),
+              torch.tensor(np.array(val), device="cuda"), rho)
+    torch.cuda.synchronize()
+    keep = [(a, b, v) for a in range(nsf) for b, v in rows.get(a, []) if 0 <= b < nsf]
+    K = np.zeros((nsf, nsf))
+    for a, b, v in keep:
+        K[a, b] += v
+    want = D.density(spheres.lrs, spheres.coefs, K, n).ravel()
+    got = rho.cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_density_on_uneven_boxes():
+    """Boxes of very different sizes in one plan (FP64)."""
+    _print("case: density, mixed box sizes")
+    case = _mixed_case(nsf=6, seed=11)
+    plan, psi, fine = _synth(case, torch.float64)
+    nsf = len(case.lrs)
+    rp, cl, val = _kernel_on_s_pattern(plan, psi, nsf, seed=8)
+    n = case.g.grid_n
+    rho = torch.empty((2 * n[2] + 29) * (2 * n[1] + 29) * (2 * n[0] + 29), dtype=torch.float64,
+                      device="cuda")
+    W.density(plan, fine, torch.tensor(rp, device="cuda"), torch.tensor(cl, device="cuda"),
+              torch.tensor(val, device="cuda"), rho)
+    torch.cuda.synchronize()
+    want = D.density(case.lrs, case.coefs, (rp, cl, val), n).ravel()
+    assert np.max(np.abs(rho.cpu().numpy() - want)) <= 1e-12 * np.max(np.abs(want))
