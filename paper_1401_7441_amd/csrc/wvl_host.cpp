@@ -188,6 +188,8 @@ struct wvl_plan {
   int64_t max_fine = 0;               // largest fine box (elements)
   int64_t* d_cptr = nullptr;          // density: functions meeting each k_dens_gather tile
   int32_t* d_csf = nullptr;
+  int32_t* d_planes = nullptr;        // density: (function, box plane) by global plane
+  int64_t nplanes = 0;
   wvl_plan_info info{};
   PatternCache pat[2];
 };
@@ -614,6 +616,7 @@ void wvl_plan_destroy(wvl_plan* plan) {
   if (plan->d_foff) (void)hipFree(plan->d_foff);
   if (plan->d_cptr) (void)hipFree(plan->d_cptr);
   if (plan->d_csf) (void)hipFree(plan->d_csf);
+  if (plan->d_planes) (void)hipFree(plan->d_planes);
   if (plan->d_rt) (void)hipFree(plan->d_rt);
   if (plan->d_rr) (void)hipFree(plan->d_rr);
   if (plan->d_wk) (void)hipFree(plan->d_wk);
@@ -1243,21 +1246,39 @@ static wvl_status ensure_cover(wvl_plan* P) {
           }
     }
   }
+  // k_dens_pair blocks: (function, plane of its box), by global plane
+  std::vector<int32_t> planes;
+  for (int gz = 0; gz < gf[2]; ++gz)
+    for (int k = 0; k < P->nsf; ++k) {
+      const SfDev& S = P->h_sf[k];
+      const int pz = gz - 2 * S.lo[2];
+      if (pz >= 0 && pz < 2 * S.n[2] + 29) {
+        planes.push_back(k);
+        planes.push_back(pz);
+      }
+    }
+  if (planes.size() / 2 > (size_t)UINT32_MAX)
+    return fail(ctx, WVL_EUNSUPPORTED, "density: too many box planes");
+  auto drop = [&]() {
+    for (void** p : {(void**)&P->d_cptr, (void**)&P->d_csf, (void**)&P->d_planes})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+  };
   wvl_status st;
-  if ((st = upload(ctx, &P->d_cptr, cptr.data(), sizeof(int64_t) * cptr.size())) != WVL_OK)
-    return st;
-  if ((st = upload(ctx, &P->d_csf, csf.data(), sizeof(int32_t) * csf.size())) != WVL_OK) {
-    (void)hipFree(P->d_cptr);
-    P->d_cptr = nullptr;
+  if ((st = upload(ctx, &P->d_cptr, cptr.data(), sizeof(int64_t) * cptr.size())) != WVL_OK ||
+      (st = upload(ctx, &P->d_csf, csf.data(), sizeof(int32_t) * csf.size())) != WVL_OK ||
+      (st = upload(ctx, &P->d_planes, planes.data(), sizeof(int32_t) * planes.size())) !=
+          WVL_OK) {
+    drop();
     return st;
   }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
-    (void)hipFree(P->d_cptr);
-    if (P->d_csf) (void)hipFree(P->d_csf);
-    P->d_cptr = nullptr;
-    P->d_csf = nullptr;
+    drop();
     return fail(ctx, WVL_EDEVICE, "density tile lists upload failed");
   }
+  P->nplanes = (int64_t)planes.size() / 2;
   return WVL_OK;
 }
 
@@ -1274,12 +1295,9 @@ wvl_status wvl_density(wvl_plan* P, wvl_dtype dt, const void* fine, const int64_
   wvl_status st = ensure_cover(P);
   if (st != WVL_OK) return st;
   const int f64 = dt == WVL_F64 ? 1 : 0;
-  for (int s0 = 0; s0 < P->nsf; s0 += 65535) {
-    const int n = std::min(65535, P->nsf - s0);
-    WVL_LAUNCH(ctx, KK_DENS_PAIR,
-               launch_dens_pair(f64, ctx->stream, P->d_sf, P->nsf, P->d_foff, fine, k_rowptr,
-                                k_col, k_val, k_nnz, s0, n, P->max_fine, work));
-  }
+  WVL_LAUNCH(ctx, KK_DENS_PAIR,
+             launch_dens_pair(f64, ctx->stream, P->d_sf, P->nsf, P->d_foff, fine, k_rowptr,
+                              k_col, k_val, k_nnz, P->d_planes, P->nplanes, work));
   int gf[3];
   for (int a = 0; a < 3; ++a) gf[a] = 2 * ctx->grid.n[a] + 29;
   WVL_LAUNCH(ctx, KK_DENS_GATHER,

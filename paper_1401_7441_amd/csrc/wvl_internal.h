@@ -106,9 +106,11 @@ int launch_up(int f64, void* stream, int axis, const SfWork* wk, const SfDev* sf
               int gridx, void* ws);
 int launch_up_z(int f64, void* stream, const SfWork* wk, const SfDev* sf, int nsf, int gridx,
                 const void* ws, const int64_t* fine_off, void* fine);
+// planes: (function, fine z-plane of its box) pairs as int32 pairs, by
+// global plane then function
 int launch_dens_pair(int f64, void* stream, const SfDev* sf, int nsf, const int64_t* foff,
                      const void* fine, const int64_t* krow, const int32_t* kcol,
-                     const double* kval, int64_t knnz, int sf0, int nrows, int64_t maxvol,
+                     const double* kval, int64_t knnz, const int32_t* planes, int64_t nplanes,
                      void* prod);
 // tile of k_dens_gather (x, y, z fine points; 256 points) and its launch
 constexpr int kDensTile[3] = {32, 4, 2};

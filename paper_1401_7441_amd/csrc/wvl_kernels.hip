@@ -320,11 +320,20 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
 // ---------------------------------------------------------------------------
 // density rho(r) = sum_ab phi_a(r) K^ab phi_b(r) on the fine grid
 // ---------------------------------------------------------------------------
-// Step 1 (k_dens_pair): thread = one fine point r of function a's box;
-// P_a(r) = phi_a(r) sum_q K[q] phi_b(r) over the kernel's row a (b = col[q]),
-// phi_b(r) = 0 outside b's fine box.  The row is walked in its stored order,
-// so each point is a fixed sum.  Columns outside [0, nsf) and positions
-// outside [0, knnz) are skipped.
+// Step 1 (k_dens_pair): block = one fine z-plane pz of function a's box
+// (blocks enumerated by global plane, so that the blocks in flight read the
+// same planes of the neighbouring boxes from the caches);
+// P_a(r) = phi_a(r) sum_q K[q] phi_b(r) over the kernel's row a
+// (b = col[q]), phi_b(r) = 0 outside b's fine box.  The entries whose box
+// holds the plane are staged in LDS in row order, so each point is a fixed
+// sum.  Columns outside [0, nsf) and positions outside [0, knnz) are skipped.
+struct DensEnt {
+  int32_t x0, y0;         // global fine x, y of the box's first point
+  int32_t s0, s1;         // box points along x, y
+  int64_t base;           // element of (x0, y0) on this plane in `fine`
+  double k;               // K^ab
+};
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_dens_pair(const SfDev* __restrict__ sfs, int nsf,
                                                    const int64_t* __restrict__ foff,
@@ -332,29 +341,85 @@ __global__ __launch_bounds__(TPB) void k_dens_pair(const SfDev* __restrict__ sfs
                                                    const int64_t* __restrict__ krow,
                                                    const int32_t* __restrict__ kcol,
                                                    const double* __restrict__ kval, int64_t knnz,
-                                                   int sf0, T* __restrict__ prod) {
-  const int a = sf0 + blockIdx.y;
+                                                   const int2* __restrict__ planes,
+                                                   T* __restrict__ prod) {
+  __shared__ DensEnt ent[TPB];
+  __shared__ int wcount[TPB / 64];
+  const int2 ap = planes[blockIdx.x];
+  const int a = ap.x, pz = ap.y;
   const SfDev& A = sfs[a];
-  const int R0 = 2 * A.n[0] + 29, R1 = 2 * A.n[1] + 29, R2 = 2 * A.n[2] + 29;
-  const int64_t vol = (int64_t)R0 * R1 * R2;
-  const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (idx >= vol) return;
-  const int px = (int)(idx % R0);
-  const int64_t t = idx / R0;
-  const int py = (int)(t % R1), pz = (int)(t / R1);
-  const int gx = 2 * A.lo[0] + px, gy = 2 * A.lo[1] + py, gz = 2 * A.lo[2] + pz;
+  const int R0 = 2 * A.n[0] + 29, R1 = 2 * A.n[1] + 29;
+  const int gz = 2 * A.lo[2] + pz;
+  const int gx0 = 2 * A.lo[0], gy0 = 2 * A.lo[1];
+  const int npts = R0 * R1;
+  const int64_t outp = foff[a] + (int64_t)pz * npts;
   const int64_t q0 = max((int64_t)0, krow[a]), q1 = min(knnz, krow[a + 1]);
-  double acc = 0.0;
-  for (int64_t q = q0; q < q1; ++q) {
-    const int b = kcol[q];
-    if (b < 0 || b >= nsf) continue;
-    const SfDev& B = sfs[b];
-    const int bx = gx - 2 * B.lo[0], by = gy - 2 * B.lo[1], bz = gz - 2 * B.lo[2];
-    const int S0 = 2 * B.n[0] + 29, S1 = 2 * B.n[1] + 29, S2 = 2 * B.n[2] + 29;
-    if (bx < 0 || bx >= S0 || by < 0 || by >= S1 || bz < 0 || bz >= S2) continue;
-    acc += kval[q] * (double)fine[foff[b] + ((int64_t)bz * S1 + by) * S0 + bx];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool one_pass = q1 - q0 <= TPB;   // the row is staged once
+  int nent = 0;
+  for (int p0 = 0; p0 < npts; p0 += TPB) {
+    const int p = p0 + threadIdx.x;
+    const bool inside = p < npts;
+    const int py = inside ? p / R0 : 0, px = inside ? p - py * R0 : 0;
+    const int gx = gx0 + px, gy = gy0 + py;
+    double acc = 0.0;
+    for (int64_t c0 = q0; c0 < q1; c0 += TPB) {
+      if (!one_pass || p0 == 0) {
+        // stage the entries whose box holds plane gz, in row order
+        __syncthreads();
+        const int64_t q = c0 + threadIdx.x;
+        DensEnt e{};
+        bool keep = false;
+        if (q < q1) {
+          const int bb = kcol[q];
+          if (bb >= 0 && bb < nsf) {
+            const SfDev& B = sfs[bb];
+            const int bz = gz - 2 * B.lo[2];
+            if (bz >= 0 && bz < 2 * B.n[2] + 29) {
+              keep = true;
+              e.x0 = 2 * B.lo[0];
+              e.y0 = 2 * B.lo[1];
+              e.s0 = 2 * B.n[0] + 29;
+              e.s1 = 2 * B.n[1] + 29;
+              e.base = foff[bb] + (int64_t)bz * e.s1 * e.s0;
+              e.k = kval[q];
+            }
+          }
+        }
+        const unsigned long long m = __ballot(keep);
+        if (lane == 0) wcount[wave] = __popcll(m);
+        __syncthreads();
+        int before = __popcll(m & ((1ull << lane) - 1ull));
+        nent = 0;
+        for (int w = 0; w < TPB / 64; ++w) {
+          if (w < wave) before += wcount[w];
+          nent += wcount[w];
+        }
+        if (keep) ent[before] = e;
+        __syncthreads();
+      }
+      // eight loads in flight at a time; the sum keeps the row order
+      for (int j0 = 0; j0 < nent; j0 += 8) {
+        int64_t at[8];
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          at[u] = -1;
+          if (j0 + u < nent) {
+            const DensEnt& e = ent[j0 + u];
+            const unsigned bx = (unsigned)(gx - e.x0), by = (unsigned)(gy - e.y0);
+            if (inside && bx < (unsigned)e.s0 && by < (unsigned)e.s1)
+              at[u] = e.base + (int64_t)(by * e.s0 + bx);
+          }
+          v[u] = at[u] >= 0 ? fine[at[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (at[u] >= 0) acc += ent[j0 + u].k * (double)v[u];
+      }
+    }
+    if (inside) prod[outp + p] = (T)((double)fine[outp + p] * acc);
   }
-  prod[foff[a] + idx] = (T)((double)fine[foff[a] + idx] * acc);
 }
 
 // Step 2 (k_dens_gather): block = one tile of 32 x 4 x 2 fine-grid points;
@@ -644,16 +709,17 @@ int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* 
 
 int launch_dens_pair(int f64, void* stream, const SfDev* sf, int nsf, const int64_t* foff,
                      const void* fine, const int64_t* krow, const int32_t* kcol,
-                     const double* kval, int64_t knnz, int sf0, int nrows, int64_t maxvol,
+                     const double* kval, int64_t knnz, const int32_t* planes, int64_t nplanes,
                      void* prod) {
-  if (nrows == 0 || maxvol == 0) return 0;
-  const dim3 g((unsigned)((maxvol + TPB - 1) / TPB), (unsigned)nrows);
+  if (nplanes == 0) return 0;
+  const dim3 g((unsigned)nplanes);
+  const int2* pl = reinterpret_cast<const int2*>(planes);
   if (f64)
     hipLaunchKernelGGL(k_dens_pair<double>, g, dim3(TPB), 0, (hipStream_t)stream, sf, nsf, foff,
-                       (const double*)fine, krow, kcol, kval, knnz, sf0, (double*)prod);
+                       (const double*)fine, krow, kcol, kval, knnz, pl, (double*)prod);
   else
     hipLaunchKernelGGL(k_dens_pair<float>, g, dim3(TPB), 0, (hipStream_t)stream, sf, nsf, foff,
-                       (const float*)fine, krow, kcol, kval, knnz, sf0, (float*)prod);
+                       (const float*)fine, krow, kcol, kval, knnz, pl, (float*)prod);
   return (int)hipGetLastError();
 }
 
