@@ -278,6 +278,40 @@ def density_section(S, reps=3):
     }
 
 
+def foe_section(S, npl=100, delta=1.0, reps=2):
+    """Density kernel by the Fermi operator expansion on the step's S and H
+    (overlap pattern, Gershgorin bounds, half the functions occupied)."""
+    import torch
+
+    import paper_1401_7441_amd as W
+    plan, ctx = S["plan"], S["ctx"]
+    psi, hpsi = S["psi"], S["hpsi"]
+    _, _, sv = W.sparse_overlap(plan, psi, psi, False)
+    _, _, hv = W.sparse_overlap(plan, psi, hpsi, True)
+    nsf = plan.nsf
+    W.foe(plan, sv, hv, npl, delta, 0.5 * nsf)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, mu, ebs = W.foe(plan, sv, hv, npl, delta, 0.5 * nsf)
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kern = {k: {"launches": v[0] // reps, "avg_ms": v[1] / v[0]} for k, v in prof.items() if v[0]}
+    nnz = int(sv.numel())
+    mm = kern.get("foe_mm", {})
+    return {"ms": ms, "npl": npl, "delta": delta, "n_occ": 0.5 * nsf, "nnz": nnz, "mu": mu,
+            "e_bs": ebs, "kernels": kern,
+            # one truncated product reads the two operands and the third
+            # term once and writes the result (plus the pattern): per entry
+            # 4 doubles and 12 bytes of indices
+            "foe_mm_alg_gbps": (nnz * 44 / (mm["avg_ms"] * 1e-3) / 1e9) if mm else None,
+            "note": "S and H of the timed step; 2 npl truncated products (traces, then the "
+                    "kernel) plus the transforms; the call synchronizes"}
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
@@ -332,6 +366,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--no-density", action="store_true",
                     help="skip the fine-grid values + density section")
+    ap.add_argument("--no-foe", action="store_true",
+                    help="skip the Fermi-operator-expansion section")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -506,6 +542,10 @@ def main():
         res["density"] = density_section(S)
         log(f"density: synthesize {res['density']['synthesize_ms']:.2f} ms, "
             f"density {res['density']['density_ms']:.2f} ms")
+    if not args.no_foe:
+        log("foe: density kernel by the Fermi operator expansion")
+        res["foe"] = foe_section(S)
+        log(f"foe: {res['foe']['ms']:.1f} ms")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.workload)
     if not args.no_serve:

@@ -252,6 +252,42 @@ wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int
                        const int32_t* k_col, const double* k_val, int64_t k_nnz, void* rho,
                        void* work);
 
+/* Density kernel by the Fermi operator expansion (Sec. IV.B and App. B),
+ * on the overlap pattern P of the plan (the pattern wvl_sparse_overlap
+ * reports with ket_is_output = 0; every matrix below lives on P, each
+ * product truncated to P):
+ *   S, H      symmetric parts of the given S (on P) and H (on the H
+ *             pattern, taken at P's entries);
+ *   S^-1/2    ~ (3 I - S) / 2, the first-order Taylor expansion;
+ *   H~ = sigma (H - tau S), sigma = 2 / (eps_max - eps_min),
+ *             tau = (eps_min + eps_max) / 2;
+ *   H~' = S^-1/2 H~ S^-1/2;  K' = c_0/2 I + sum_{i=1..npl} c_i T^i(H~'),
+ *             T^i by the Chebyshev recursion, c_i the Chebyshev coefficients
+ *             on [-1, 1] of f = (1 - erf((eps - mu) / delta)) / 2;
+ *   mu        such that Tr K' = n_occ (bisection: the traces of the T^i are
+ *             taken once, then the matrices are formed again with the final
+ *             coefficients);
+ *   K = S^-1/2 K' S^-1/2;  E_BS = Tr(K H~) / sigma + tau Tr(K S).
+ * The symmetric part is taken after each two-sided product, since the
+ * truncation breaks the symmetry the exact product has.
+ *   s_val:   device double[nnz of P], S values (wvl_sparse_overlap order)
+ *   h_val:   device double[nnz of the H pattern], H values
+ *   npl:     expansion degree (>= 1); delta: width of the Fermi function
+ *            (> 0); n_occ: the target trace, in (0, nsf)
+ *   eps_min, eps_max: spectral bounds of H c = eps S c; eps_min >= eps_max
+ *            asks for Gershgorin bounds of S^-1/2 H S^-1/2
+ *   k_val:   device double[nnz of P], the kernel K
+ *   mu, e_bs: host, the chemical potential and the band-structure energy
+ *            (either may be NULL)
+ *   scratch: device, at least 8 (9 nnz + npl + 5) bytes
+ * All arithmetic is in double, sums in fixed orders (bitwise reproducible).
+ * Synchronizes (the traces and bounds come back to the host).  Errors:
+ * WVL_EINVAL for bad parameters or null buffers; WVL_EUNSUPPORTED when P is
+ * not symmetric or not inside the H pattern. */
+wvl_status wvl_foe(wvl_plan* plan, const double* s_val, const double* h_val, int32_t npl,
+                   double delta, double n_occ, double eps_min, double eps_max, double* k_val,
+                   double* mu, double* e_bs, void* scratch);
+
 /* Support-function update step (the localized gradient step of Sec. III.A
  * and IV.A, reduced to a fixed step length):
  *   psi_a <- psi_a - eta (P_La (H psi)_a - H_aa psi_a)

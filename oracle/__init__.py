@@ -28,6 +28,8 @@ precond      Kinetic + confinement preconditioning of the gradient (paper
              Sec. IV.A, Eq. (precond)), conjugate-gradient steps.
 density      Fine-grid values of the support functions and the density
              rho = sum_ab phi_a K^ab phi_b (paper Sec. II, Eq. (density)).
+foe          Density kernel by the Fermi operator expansion (paper Sec. IV.B,
+             App. B): Chebyshev recursion on truncated sparse matrices.
 
 Parity status: every function here is pinned by a check that does not reuse
 its own formula (closed forms, invariants, brute force); see the tests marked

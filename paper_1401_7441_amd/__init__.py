@@ -43,7 +43,7 @@ LOCREG_DTYPE = np.dtype([
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
             "wvl_compress", "wvl_apply_local_ham", "wvl_apply_local_ham_conf", "wvl_kinetic",
-            "wvl_sparse_overlap", "wvl_synthesize", "wvl_density",
+            "wvl_sparse_overlap", "wvl_synthesize", "wvl_density", "wvl_foe",
             "wvl_update", "wvl_precondition", "wvl_graph_create", "wvl_graph_launch",
             "wvl_graph_destroy",
             "wvl_plan_autotune",
@@ -105,6 +105,7 @@ def _load():
         "wvl_apply_local_ham_conf": [P, ctypes.c_int, U32, P, P, P, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
         "wvl_synthesize": [P, ctypes.c_int, P, P, P],
+        "wvl_foe": [P, P, P, I32, D, D, D, D, P, ctypes.POINTER(D), ctypes.POINTER(D), P],
         "wvl_density": [P, ctypes.c_int, P, P, P, P, I64, P, P],
         "wvl_update": [P, ctypes.c_int, D, P, P, P],
         "wvl_precondition": [P, ctypes.c_int, P, P, P, I32, P, P, P],
@@ -451,6 +452,31 @@ def density(plan: Plan, fine, k_rowptr, k_col, k_val, rho, work=None):
     _check(lib().wvl_density(plan._ptr, dt, _ptr(fine), _ptr(k_rowptr), _ptr(k_col),
                              _ptr(k_val), int(k_val.numel()), _ptr(rho), _ptr(work)),
            plan.ctx.handle)
+
+
+def foe(plan: Plan, s_val, h_val, npl, delta, n_occ, eps_min=0.0, eps_max=0.0, k_val=None,
+        scratch=None):
+    """wvl_foe: density kernel K on the overlap pattern by the Fermi operator
+    expansion; returns (k_val, mu, e_bs).  s_val / h_val: float64 device
+    values on the S / H patterns.  eps_min >= eps_max: Gershgorin bounds."""
+    import torch
+    _need_cuda(s_val, h_val, k_val, scratch)
+    nnz_s, nnz_h = sparse_pattern_nnz(plan, False), sparse_pattern_nnz(plan, True)
+    if s_val.dtype != torch.float64 or h_val.dtype != torch.float64 or \
+            s_val.numel() < nnz_s or h_val.numel() < nnz_h:
+        raise WvlError(WVL_EINVAL, "s_val / h_val must be float64 on the S / H patterns")
+    if k_val is None:
+        k_val = torch.empty(max(1, nnz_s), dtype=torch.float64, device="cuda")
+    need = 8 * (9 * nnz_s + int(npl) + 5)
+    if scratch is None:
+        scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+    elif scratch.numel() * scratch.element_size() < need:
+        raise WvlError(WVL_EINVAL, "scratch smaller than wvl_foe needs")
+    mu, ebs = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().wvl_foe(plan._ptr, _ptr(s_val), _ptr(h_val), int(npl), float(delta),
+                         float(n_occ), float(eps_min), float(eps_max), _ptr(k_val),
+                         ctypes.byref(mu), ctypes.byref(ebs), _ptr(scratch)), plan.ctx.handle)
+    return k_val, mu.value, ebs.value
 
 
 def precondition_scratch_bytes(plan: Plan, dtype_code):

@@ -22,12 +22,12 @@ using namespace wvl;
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_UNPACK, KK_UP_X, KK_UP_Y, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
   KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
-  KK_UPDATE, KK_UP_Z, KK_DENS_PAIR, KK_DENS_GATHER, KK_COUNT
+  KK_UPDATE, KK_UP_Z, KK_DENS_PAIR, KK_DENS_GATHER, KK_FOE_MM, KK_FOE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "unpack", "up_x", "up_y", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
     "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update",
-    "up_z", "dens_pair", "dens_gather"};
+    "up_z", "dens_pair", "dens_gather", "foe_mm", "foe"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -125,6 +125,11 @@ struct PatternCache {
   int32_t* d_col = nullptr;
   int32_t* d_row = nullptr;
   int32_t* d_order = nullptr;   // processing order of the pairs (CSR positions)
+  // S pattern only (Fermi operator expansion): position of the transposed
+  // entry, and of the entry and its transpose in the H pattern
+  int64_t* d_tpos = nullptr;
+  int64_t* d_hpos = nullptr;
+  int64_t* d_htpos = nullptr;
 };
 
 // 3D Morton code of a non-negative grid point (10 bits per axis)
@@ -606,6 +611,9 @@ static void free_pattern(PatternCache& p) {
   if (p.d_col) (void)hipFree(p.d_col);
   if (p.d_row) (void)hipFree(p.d_row);
   if (p.d_order) (void)hipFree(p.d_order);
+  if (p.d_tpos) (void)hipFree(p.d_tpos);
+  if (p.d_hpos) (void)hipFree(p.d_hpos);
+  if (p.d_htpos) (void)hipFree(p.d_htpos);
   p = PatternCache{};
 }
 
@@ -1303,6 +1311,214 @@ wvl_status wvl_density(wvl_plan* P, wvl_dtype dt, const void* fine, const int64_
   WVL_LAUNCH(ctx, KK_DENS_GATHER,
              launch_dens_gather(f64, ctx->stream, P->d_sf, P->d_foff, work, P->d_cptr, P->d_csf,
                                 gf, rho));
+  return WVL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fermi operator expansion (Sec. IV.B, App. B)
+// ---------------------------------------------------------------------------
+
+// transpose positions in the S pattern, and the S entries' positions (and
+// their transposes') in the H pattern
+static wvl_status ensure_foe_maps(wvl_plan* P) {
+  PatternCache& S = P->pat[0];
+  if (S.d_tpos) return WVL_OK;
+  wvl_ctx* ctx = P->ctx;
+  const PatternCache& Hp = P->pat[1];
+  const int n = P->nsf;
+  std::vector<int64_t> srp(n + 1), hrp(n + 1);
+  std::vector<int32_t> scol(S.nnz), hcol(Hp.nnz);
+  WVL_HIP(ctx, hipMemcpyAsync(srp.data(), S.d_rowptr, sizeof(int64_t) * (n + 1),
+                              hipMemcpyDeviceToHost, ctx->stream));
+  WVL_HIP(ctx, hipMemcpyAsync(hrp.data(), Hp.d_rowptr, sizeof(int64_t) * (n + 1),
+                              hipMemcpyDeviceToHost, ctx->stream));
+  if (S.nnz)
+    WVL_HIP(ctx, hipMemcpyAsync(scol.data(), S.d_col, sizeof(int32_t) * S.nnz,
+                                hipMemcpyDeviceToHost, ctx->stream));
+  if (Hp.nnz)
+    WVL_HIP(ctx, hipMemcpyAsync(hcol.data(), Hp.d_col, sizeof(int32_t) * Hp.nnz,
+                                hipMemcpyDeviceToHost, ctx->stream));
+  WVL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  auto find = [](const std::vector<int64_t>& rp, const std::vector<int32_t>& cl, int i,
+                 int j) -> int64_t {
+    const auto b = cl.begin() + rp[i], e = cl.begin() + rp[i + 1];
+    const auto it = std::lower_bound(b, e, j);
+    return (it != e && *it == j) ? (int64_t)(it - cl.begin()) : -1;
+  };
+  std::vector<int64_t> tpos(S.nnz), hpos(S.nnz), htpos(S.nnz);
+  for (int i = 0; i < n; ++i)
+    for (int64_t p = srp[i]; p < srp[i + 1]; ++p) {
+      const int j = scol[p];
+      tpos[p] = find(srp, scol, j, i);
+      hpos[p] = find(hrp, hcol, i, j);
+      htpos[p] = find(hrp, hcol, j, i);
+      if (tpos[p] < 0 || hpos[p] < 0 || htpos[p] < 0)
+        return fail(ctx, WVL_EUNSUPPORTED,
+                    "wvl_foe: overlap pattern not symmetric or not inside the H pattern");
+    }
+  wvl_status st;
+  if ((st = upload(ctx, &S.d_tpos, tpos.data(), sizeof(int64_t) * tpos.size())) != WVL_OK ||
+      (st = upload(ctx, &S.d_hpos, hpos.data(), sizeof(int64_t) * hpos.size())) != WVL_OK ||
+      (st = upload(ctx, &S.d_htpos, htpos.data(), sizeof(int64_t) * htpos.size())) != WVL_OK)
+    return st;
+  WVL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return WVL_OK;
+}
+
+// Chebyshev coefficients c_0..c_npl on [-1, 1] of
+// f(x) = erfc((x / sigma + tau - mu) / delta) / 2, by the defining integral
+// c_i = (2 / pi) int_0^pi f(cos t) cos(i t) dt on m midpoints (exact for the
+// cosine series up to degree 2m - 1)
+struct FoeCoef {
+  int npl, m;
+  std::vector<double> x, cs;   // nodes cos t_k; cos(i t_k), [k][i]
+  explicit FoeCoef(int npl_) : npl(npl_), m(std::max(8 * npl_, 2048)) {
+    const double pi = 3.14159265358979323846;
+    x.resize(m);
+    cs.resize((size_t)m * (npl + 1));
+    for (int k = 0; k < m; ++k) {
+      const double t = pi * (k + 0.5) / m;
+      x[k] = std::cos(t);
+      for (int i = 0; i <= npl; ++i) cs[(size_t)k * (npl + 1) + i] = std::cos(i * t);
+    }
+  }
+  void operator()(double sigma, double tau, double mu, double delta, std::vector<double>* c) {
+    c->assign(npl + 1, 0.0);
+    for (int k = 0; k < m; ++k) {
+      const double f = 0.5 * std::erfc((x[k] / sigma + tau - mu) / delta);
+      const double* row = &cs[(size_t)k * (npl + 1)];
+      for (int i = 0; i <= npl; ++i) (*c)[i] += f * row[i];
+    }
+    for (int i = 0; i <= npl; ++i) (*c)[i] *= 2.0 / m;
+  }
+};
+
+wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_t npl,
+                   double delta, double n_occ, double eps_min, double eps_max, double* k_val,
+                   double* mu_out, double* e_bs_out, void* scratch) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_foe: null plan");
+  wvl_ctx* ctx = P->ctx;
+  const int n = P->nsf;
+  if (npl < 1) return fail(ctx, WVL_EINVAL, "wvl_foe: npl < 1");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(ctx, WVL_EINVAL, "wvl_foe: delta");
+  if (!(n_occ > 0.0) || !(n_occ < n)) return fail(ctx, WVL_EINVAL, "wvl_foe: n_occ not in (0, nsf)");
+  if (!s_val || !h_val || !k_val || !scratch)
+    return fail(ctx, WVL_EINVAL, "wvl_foe: null buffer");
+  if (!std::isfinite(eps_min) || !std::isfinite(eps_max))
+    return fail(ctx, WVL_EINVAL, "wvl_foe: spectral bounds not finite");
+  wvl_status st;
+  if ((st = ensure_pattern(P, 0)) != WVL_OK || (st = ensure_pattern(P, 1)) != WVL_OK ||
+      (st = ensure_foe_maps(P)) != WVL_OK)
+    return st;
+  const PatternCache& pc = P->pat[0];
+  const int64_t nnz = pc.nnz;
+  hipStream_t s = ctx->stream;
+  const int64_t* rp = pc.d_rowptr;
+  const int32_t* cl = pc.d_col;
+  const int32_t* rw = pc.d_row;
+  const int64_t* tp = pc.d_tpos;
+  double* w = (double*)scratch;
+  double *Ss = w, *Sh = w + nnz, *Hs = w + 2 * nnz, *X = w + 3 * nnz, *Ht = w + 4 * nnz;
+  double *T[3] = {w + 5 * nnz, w + 6 * nnz, w + 7 * nnz};
+  double* Kp = w + 8 * nnz;
+  double* tr = w + 9 * nnz;
+  double* red = tr + npl + 1;
+  auto mm = [&](double al, const double* A, const double* B, double be, const double* D,
+                double* C) { return launch_foe_mm(s, rp, cl, rw, tp, nnz, al, A, B, be, D, C); };
+  auto axpby = [&](double a, const double* x, double b, const double* y, double d, double* o) {
+    return launch_foe_axpby(s, nnz, a, x, b, y, rw, cl, d, o);
+  };
+  // S and H on the overlap pattern, symmetric parts (they are symmetric in
+  // exact arithmetic); S^-1/2 ~ (3 I - S) / 2, the first-order Taylor form
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, s_val, Ss));
+  WVL_LAUNCH(ctx, KK_FOE, axpby(-0.5, Ss, 0.0, nullptr, 1.5, Sh));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_gather(s, nnz, pc.d_hpos, h_val, X));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_gather(s, nnz, pc.d_htpos, h_val, Ht));
+  WVL_LAUNCH(ctx, KK_FOE, axpby(0.5, X, 0.5, Ht, 0.0, Hs));
+  // spectral bounds: Gershgorin discs of S^-1/2 H S^-1/2 unless given
+  if (eps_min >= eps_max) {
+    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
+    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0]));
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], Ht));
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_gersh(s, n, rp, cl, Ht, red));
+    double b[2];
+    WVL_HIP(ctx, hipMemcpyAsync(b, red, sizeof b, hipMemcpyDeviceToHost, s));
+    WVL_HIP(ctx, hipStreamSynchronize(s));
+    eps_min = b[0];
+    eps_max = b[1];
+    if (!(eps_max > eps_min)) eps_max = eps_min + 1.0;
+  }
+  const double sigma = 2.0 / (eps_max - eps_min), tau = 0.5 * (eps_min + eps_max);
+  // H~ = sigma (H - tau S), then H~' = S^-1/2 H~ S^-1/2 (symmetric part)
+  WVL_LAUNCH(ctx, KK_FOE, axpby(sigma, Hs, -sigma * tau, Ss, 0.0, Hs));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0]));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], Ht));
+  // pass 1: traces of the Chebyshev matrices T^0 .. T^npl
+  WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, T[0]));
+  WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, T[1]));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[0], nullptr, tr, 0));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[1], nullptr, tr, 1));
+  int a = 0, b = 1, c = 2;
+  for (int j = 1; j < npl; ++j) {
+    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, T[b], -1.0, T[a], T[c]));
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[c], nullptr, tr, j + 1));
+    const int t = a;
+    a = b;
+    b = c;
+    c = t;
+  }
+  std::vector<double> trh(npl + 1);
+  WVL_HIP(ctx, hipMemcpyAsync(trh.data(), tr, sizeof(double) * (npl + 1), hipMemcpyDeviceToHost,
+                              s));
+  WVL_HIP(ctx, hipStreamSynchronize(s));
+  // chemical potential: Tr K'(mu) = c_0/2 Tr T^0 + sum_i c_i Tr T^i = n_occ,
+  // increasing in mu; bisection
+  std::vector<double> coef;
+  FoeCoef coefficients(npl);
+  auto trace_at = [&](double mu) {
+    coefficients(sigma, tau, mu, delta, &coef);
+    double v = 0.5 * coef[0] * trh[0];
+    for (int i = 1; i <= npl; ++i) v += coef[i] * trh[i];
+    return v;
+  };
+  double lo = eps_min - 20.0 * delta, hi = eps_max + 20.0 * delta;
+  for (int it = 0; it < 200 && hi - lo > 1e-13 * std::max(1.0, std::fabs(lo) + std::fabs(hi));
+       ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (trace_at(mid) < n_occ)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const double mu = 0.5 * (lo + hi);
+  coefficients(sigma, tau, mu, delta, &coef);
+  // pass 2: K' = c_0/2 I + sum_i c_i T^i(H~')
+  WVL_LAUNCH(ctx, KK_FOE, axpby(coef[1], Ht, 0.0, nullptr, 0.5 * coef[0], Kp));
+  WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, T[0]));
+  WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, T[1]));
+  a = 0;
+  b = 1;
+  c = 2;
+  for (int j = 1; j < npl; ++j) {
+    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, T[b], -1.0, T[a], T[c]));
+    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Kp, coef[j + 1], T[c], 0.0, Kp));
+    const int t = a;
+    a = b;
+    b = c;
+    c = t;
+  }
+  // K = S^-1/2 K' S^-1/2 (symmetric part); E_BS = Tr(K H~) / sigma + tau Tr(K S)
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Kp, 0.0, nullptr, X));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0]));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], k_val));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, k_val, Hs, red, 2));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, k_val, Ss, red, 3));
+  double e2[2];
+  WVL_HIP(ctx, hipMemcpyAsync(e2, red + 2, sizeof e2, hipMemcpyDeviceToHost, s));
+  WVL_HIP(ctx, hipStreamSynchronize(s));
+  if (mu_out) *mu_out = mu;
+  if (e_bs_out) *e_bs_out = e2[0] / sigma + tau * e2[1];
   return WVL_OK;
 }
 

@@ -133,6 +133,21 @@ int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const doub
                     int which, int nblk, double* out);
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
+// Fermi operator expansion on a symmetric CSR pattern (row: row of each
+// entry, tpos: position of the transposed entry)
+int launch_foe_mm(void* stream, const int64_t* rowptr, const int32_t* col, const int32_t* row,
+                  const int64_t* tpos, int64_t nnz, double alpha, const double* A,
+                  const double* B, double beta, const double* D, double* C);
+int launch_foe_axpby(void* stream, int64_t nnz, double a, const double* X, double b,
+                     const double* Y, const int32_t* row, const int32_t* col, double d,
+                     double* out);
+int launch_foe_sym(void* stream, int64_t nnz, const int64_t* tpos, const double* X, double* out);
+int launch_foe_gather(void* stream, int64_t nnz, const int64_t* qpos, const double* X,
+                      double* out);
+int launch_foe_dot(void* stream, int64_t nnz, const int32_t* row, const int32_t* col,
+                   const double* X, const double* Y, double* out, int slot);
+int launch_foe_gersh(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
+                     const double* X, double* out);
 int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                   double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
                   const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs, int mode,

@@ -452,6 +452,131 @@ __global__ __launch_bounds__(TPB) void k_dens_gather(const SfDev* __restrict__ s
 }
 
 // ---------------------------------------------------------------------------
+// Fermi operator expansion: matrices on one symmetric pattern P (CSR, sorted
+// columns, diagonal present), values in double
+// ---------------------------------------------------------------------------
+
+// C = alpha (A B)|_P + beta D, one thread per entry (i, j) of P:
+// (A B)_ij = sum_k A_ik B_kj over the k in both row i and row j of P (the
+// pattern is symmetric, so B_kj sits at the transpose position of (j, k)),
+// summed in increasing k.  D may be NULL (beta ignored).
+__global__ __launch_bounds__(TPB) void k_foe_mm(const int64_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col,
+                                                const int32_t* __restrict__ row,
+                                                const int64_t* __restrict__ tpos, int64_t nnz,
+                                                double alpha, const double* __restrict__ A,
+                                                const double* __restrict__ B, double beta,
+                                                const double* __restrict__ D,
+                                                double* __restrict__ C) {
+  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (p >= nnz) return;
+  const int i = row[p], j = col[p];
+  int64_t qa = rowptr[i], qb = rowptr[j];
+  const int64_t ea = rowptr[i + 1], eb = rowptr[j + 1];
+  double acc = 0.0;
+  while (qa < ea && qb < eb) {
+    const int ka = col[qa], kb = col[qb];
+    if (ka < kb) {
+      ++qa;
+    } else if (kb < ka) {
+      ++qb;
+    } else {
+      acc += A[qa] * B[tpos[qb]];
+      ++qa;
+      ++qb;
+    }
+  }
+  C[p] = D ? alpha * acc + beta * D[p] : alpha * acc;
+}
+
+// elementwise on P: out = a X + b Y (+ d on the diagonal when diag != NULL)
+__global__ __launch_bounds__(TPB) void k_foe_axpby(int64_t nnz, double a,
+                                                   const double* __restrict__ X, double b,
+                                                   const double* __restrict__ Y,
+                                                   const int32_t* __restrict__ row,
+                                                   const int32_t* __restrict__ col, double d,
+                                                   double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (p >= nnz) return;
+  double v = 0.0;
+  if (X) v += a * X[p];
+  if (Y) v += b * Y[p];
+  if (row && row[p] == col[p]) v += d;
+  out[p] = v;
+}
+
+// symmetric part on P: out = (X + X^T) / 2
+__global__ __launch_bounds__(TPB) void k_foe_sym(int64_t nnz, const int64_t* __restrict__ tpos,
+                                                 const double* __restrict__ X,
+                                                 double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (p >= nnz) return;
+  out[p] = 0.5 * (X[p] + X[tpos[p]]);
+}
+
+// out = values of X (on pattern Q) at the positions qpos of P's entries
+__global__ __launch_bounds__(TPB) void k_foe_gather(int64_t nnz, const int64_t* __restrict__ qpos,
+                                                    const double* __restrict__ X,
+                                                    double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (p >= nnz) return;
+  out[p] = X[qpos[p]];
+}
+
+// one block: out[slot] = sum_p X[p] Y[p] over P (Y NULL: the trace of X,
+// i.e. the diagonal entries), in a fixed order
+__global__ __launch_bounds__(TPB) void k_foe_dot(int64_t nnz, const int32_t* __restrict__ row,
+                                                 const int32_t* __restrict__ col,
+                                                 const double* __restrict__ X,
+                                                 const double* __restrict__ Y,
+                                                 double* __restrict__ out, int slot) {
+  double v = 0.0;
+  for (int64_t p = threadIdx.x; p < nnz; p += TPB) {
+    if (Y)
+      v += X[p] * Y[p];
+    else if (row[p] == col[p])
+      v += X[p];
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) out[slot] = s;
+}
+
+// one block: Gershgorin bounds of X (min_i X_ii - r_i, max_i X_ii + r_i with
+// r_i the absolute off-diagonal row sum), out[0], out[1]
+__global__ __launch_bounds__(TPB) void k_foe_gersh(int nrow, const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ out) {
+  __shared__ double lo[TPB], hi[TPB];
+  double l = 1e300, h = -1e300;
+  for (int i = threadIdx.x; i < nrow; i += TPB) {
+    double dgl = 0.0, r = 0.0;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      if (col[q] == i)
+        dgl = X[q];
+      else
+        r += fabs(X[q]);
+    }
+    l = fmin(l, dgl - r);
+    h = fmax(h, dgl + r);
+  }
+  lo[threadIdx.x] = l;
+  hi[threadIdx.x] = h;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + s]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = lo[0];
+    out[1] = hi[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // support-function update: psi <- psi - eta (P_L hpsi - H_aa psi)
 // ---------------------------------------------------------------------------
 // Block = 64 consecutive input segments of one function (coarse blocks, then
@@ -738,6 +863,54 @@ int launch_dens_gather(int f64, void* stream, const SfDev* sf, const int64_t* fo
     hipLaunchKernelGGL(k_dens_gather<float>, g, dim3(TPB), 0, (hipStream_t)stream, sf, foff,
                        (const float*)prod, cptr, csf, tx, ty, gf[0], gf[1], gf[2],
                        (float*)rho);
+  return (int)hipGetLastError();
+}
+
+static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + TPB - 1) / TPB)); }
+
+int launch_foe_mm(void* stream, const int64_t* rowptr, const int32_t* col, const int32_t* row,
+                  const int64_t* tpos, int64_t nnz, double alpha, const double* A,
+                  const double* B, double beta, const double* D, double* C) {
+  if (nnz == 0) return 0;
+  hipLaunchKernelGGL(k_foe_mm, grid1(nnz), dim3(TPB), 0, (hipStream_t)stream, rowptr, col, row,
+                     tpos, nnz, alpha, A, B, beta, D, C);
+  return (int)hipGetLastError();
+}
+
+int launch_foe_axpby(void* stream, int64_t nnz, double a, const double* X, double b,
+                     const double* Y, const int32_t* row, const int32_t* col, double d,
+                     double* out) {
+  if (nnz == 0) return 0;
+  hipLaunchKernelGGL(k_foe_axpby, grid1(nnz), dim3(TPB), 0, (hipStream_t)stream, nnz, a, X, b, Y,
+                     row, col, d, out);
+  return (int)hipGetLastError();
+}
+
+int launch_foe_sym(void* stream, int64_t nnz, const int64_t* tpos, const double* X, double* out) {
+  if (nnz == 0) return 0;
+  hipLaunchKernelGGL(k_foe_sym, grid1(nnz), dim3(TPB), 0, (hipStream_t)stream, nnz, tpos, X, out);
+  return (int)hipGetLastError();
+}
+
+int launch_foe_gather(void* stream, int64_t nnz, const int64_t* qpos, const double* X,
+                      double* out) {
+  if (nnz == 0) return 0;
+  hipLaunchKernelGGL(k_foe_gather, grid1(nnz), dim3(TPB), 0, (hipStream_t)stream, nnz, qpos, X,
+                     out);
+  return (int)hipGetLastError();
+}
+
+int launch_foe_dot(void* stream, int64_t nnz, const int32_t* row, const int32_t* col,
+                   const double* X, const double* Y, double* out, int slot) {
+  hipLaunchKernelGGL(k_foe_dot, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nnz, row, col, X, Y,
+                     out, slot);
+  return (int)hipGetLastError();
+}
+
+int launch_foe_gersh(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
+                     const double* X, double* out) {
+  hipLaunchKernelGGL(k_foe_gersh, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nrow, rowptr, col,
+                     X, out);
   return (int)hipGetLastError();
 }
 
