@@ -227,7 +227,7 @@ def density_section(S, reps=3):
     work = torch.empty_like(fine)
     rho = torch.empty((2 * n[0] + 29) * (2 * n[1] + 29) * (2 * n[2] + 29), dtype=psi.dtype,
                       device="cuda")
-    rowptr, col, _ = W.sparse_overlap(plan, psi, psi, False)
+    rowptr, col, _ = W.sparse_overlap(plan, psi, psi, False, values=False)
     rp = rowptr.cpu().numpy()
     row = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
     c = np.asarray(g.centers, np.float64)

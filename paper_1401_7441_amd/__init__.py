@@ -380,9 +380,10 @@ def sparse_pattern_nnz(plan: Plan, ket_is_output: bool):
     return n.value
 
 
-def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None):
+def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None, values=True):
     """wvl_sparse_overlap -> (rowptr int64[nsf+1], col int32[nnz], val float64[nnz]),
-    device tensors.  `out` may hold preallocated (rowptr, col, val)."""
+    device tensors.  `out` may hold preallocated (rowptr, col, val); with
+    values=False only the pattern is written (val is returned unfilled)."""
     import torch
     _need_cuda(bra_c, ket_c)
     dt = _dtype_code(bra_c, ket_c)
@@ -398,7 +399,8 @@ def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None):
         rowptr, col, val = out
     n = ctypes.c_int64(0)
     _check(lib().wvl_sparse_overlap(plan._ptr, _ptr(bra_c), int(bool(ket_is_output)), _ptr(ket_c),
-                                   dt, ctypes.byref(n), _ptr(rowptr), _ptr(col), _ptr(val)),
+                                   dt, ctypes.byref(n), _ptr(rowptr), _ptr(col),
+                                   _ptr(val) if values else None),
            plan.ctx.handle)
     return rowptr, col[:nnz], val[:nnz]
 

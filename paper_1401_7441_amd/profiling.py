@@ -72,6 +72,7 @@ def stats_markdown(trace_csv: str, command: str) -> str:
     rows = _rows(trace_csv)
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     per = {}
+    cfg = {}
     nsparse = 0
     for r in rows:
         k = kind_of(r["Kernel_Name"])
@@ -83,6 +84,8 @@ def stats_markdown(trace_csv: str, command: str) -> str:
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
         per.setdefault(k, {"name": re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", ""),
                            "ms": []})["ms"].append(d)
+        cfg.setdefault(k, {}).setdefault((r.get("Grid_Size_X"), r.get("Grid_Size_Y")),
+                                         []).append(d)
     tot = sum(sum(v["ms"]) for v in per.values())
     out = ["Command:", "", "```", command, "```", "",
            "| kind | kernel | dispatches | avg ms | min ms | max ms | total ms | % of library time |",
@@ -91,6 +94,15 @@ def stats_markdown(trace_csv: str, command: str) -> str:
         ms = v["ms"]
         out.append(f"| {k} | `{v['name']}` | {len(ms)} | {sum(ms) / len(ms):.3f} | {min(ms):.3f} | "
                    f"{max(ms):.3f} | {sum(ms):.3f} | {100 * sum(ms) / tot:.1f} |")
+    # per launch configuration: a kind launches once per bin with its own
+    # grid; configurations seen at least 5 times are the timed layout (the
+    # others are autotuner candidates or side runs)
+    out += ["", "Launch configurations seen at least 5 times (grid x, y; the timed layout):", "",
+            "| kind | grid | dispatches | avg ms |", "|---|---|---|---|"]
+    for k in sorted(cfg):
+        for g, ms in sorted(cfg[k].items(), key=lambda kv: -len(kv[1])):
+            if len(ms) >= 5:
+                out.append(f"| {k} | {g[0]} x {g[1]} | {len(ms)} | {sum(ms) / len(ms):.3f} |")
     return "\n".join(out) + "\n"
 
 
