@@ -279,7 +279,7 @@ wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int
  *   k_val:   device double[nnz of P], the kernel K
  *   mu, e_bs: host, the chemical potential and the band-structure energy
  *            (either may be NULL)
- *   scratch: device, at least 8 (9 nnz + npl + 5) bytes
+ *   scratch: device, at least 8 (13 nnz + npl + 5) bytes
  * All arithmetic is in double, sums in fixed orders (bitwise reproducible).
  * Synchronizes (the traces and bounds come back to the host).  Errors:
  * WVL_EINVAL for bad parameters or null buffers; WVL_EUNSUPPORTED when P is

@@ -469,7 +469,7 @@ def foe(plan: Plan, s_val, h_val, npl, delta, n_occ, eps_min=0.0, eps_max=0.0, k
         raise WvlError(WVL_EINVAL, "s_val / h_val must be float64 on the S / H patterns")
     if k_val is None:
         k_val = torch.empty(max(1, nnz_s), dtype=torch.float64, device="cuda")
-    need = 8 * (9 * nnz_s + int(npl) + 5)
+    need = 8 * (13 * nnz_s + int(npl) + 5)
     if scratch is None:
         scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
     elif scratch.numel() * scratch.element_size() < need:

@@ -1069,6 +1069,9 @@ wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hp
                     "wvl_kinetic");
 }
 
+// rows whose S/H pairs are interleaved by ket (see ensure_pattern)
+constexpr int kPairGroup = 8;
+
 static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
   wvl_ctx* ctx = P->ctx;
   PatternCache& pc = P->pat[ket_out];
@@ -1130,9 +1133,11 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
       return fail(ctx, WVL_EDEVICE, "pattern upload failed: %s", hipGetErrorString(e));
     }
   }
-  // Value pairs are processed row by row in the Morton order of the rows'
-  // box centres, so that concurrently running pairs share bra and ket data
-  // in the caches (the values land at their CSR positions regardless).
+  // Value pairs are processed in groups of kPairGroup rows, the rows in the
+  // Morton order of their box centres and the pairs of a group ordered by
+  // ket: concurrently running pairs then share the bra rows and each ket's
+  // overlap in the caches (the values land at their CSR positions
+  // regardless, each summed in the same order).
   if (nnz > 0) {
     if (nnz > INT32_MAX) {
       free_pattern(pc);
@@ -1145,11 +1150,28 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
                         (uint32_t)(S.lo[2] + S.n[2] / 2)), a};
     }
     std::sort(key.begin(), key.end());
+    std::vector<int32_t> col(nnz);
+    hipError_t ce = hipMemcpyAsync(col.data(), pc.d_col, sizeof(int32_t) * nnz,
+                                   hipMemcpyDeviceToHost, ctx->stream);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(ctx->stream);
+    if (ce != hipSuccess) {
+      free_pattern(pc);
+      return fail(ctx, WVL_EDEVICE, "pattern columns: %s", hipGetErrorString(ce));
+    }
     std::vector<int32_t> order;
     order.reserve(nnz);
-    for (const auto& kv : key)
-      for (int64_t q = rowptr[kv.second]; q < rowptr[kv.second + 1]; ++q)
-        order.push_back((int32_t)q);
+    std::vector<std::pair<int32_t, int32_t>> grp;   // (ket, CSR position)
+    for (int c0 = 0; c0 < nsf; c0 += kPairGroup) {
+      grp.clear();
+      for (int c = c0; c < std::min(nsf, c0 + kPairGroup); ++c) {
+        const int a = key[c].second;
+        for (int64_t q = rowptr[a]; q < rowptr[a + 1]; ++q) grp.emplace_back(col[q], (int32_t)q);
+      }
+      std::stable_sort(grp.begin(), grp.end(),
+                       [](const std::pair<int32_t, int32_t>& x,
+                          const std::pair<int32_t, int32_t>& y) { return x.first < y.first; });
+      for (const auto& e : grp) order.push_back(e.second);
+    }
     if ((st = upload(ctx, &pc.d_order, order.data(), sizeof(int32_t) * nnz)) != WVL_OK) {
       free_pattern(pc);
       return st;
@@ -1418,13 +1440,20 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   const int32_t* rw = pc.d_row;
   const int64_t* tp = pc.d_tpos;
   double* w = (double*)scratch;
+  // matrices on P; Tt[] and Kpt hold the transposes (right operands of the
+  // products are read transposed)
   double *Ss = w, *Sh = w + nnz, *Hs = w + 2 * nnz, *X = w + 3 * nnz, *Ht = w + 4 * nnz;
-  double *T[3] = {w + 5 * nnz, w + 6 * nnz, w + 7 * nnz};
+  double* T[3] = {w + 5 * nnz, w + 6 * nnz, w + 7 * nnz};
   double* Kp = w + 8 * nnz;
-  double* tr = w + 9 * nnz;
+  double* Tt[3] = {w + 9 * nnz, w + 10 * nnz, w + 11 * nnz};
+  double* Kpt = w + 12 * nnz;
+  double* tr = w + 13 * nnz;
   double* red = tr + npl + 1;
-  auto mm = [&](double al, const double* A, const double* B, double be, const double* D,
-                double* C) { return launch_foe_mm(s, rp, cl, rw, tp, nnz, al, A, B, be, D, C); };
+  // C = al A B (+ be D), B given transposed; Ct: C transposed as well
+  auto mm = [&](double al, const double* A, const double* Bt, double be, const double* D,
+                double* C, double* Ct) {
+    return launch_foe_mm(s, rp, cl, rw, tp, nnz, al, A, Bt, be, D, C, Ct);
+  };
   auto axpby = [&](double a, const double* x, double b, const double* y, double d, double* o) {
     return launch_foe_axpby(s, nnz, a, x, b, y, rw, cl, d, o);
   };
@@ -1436,9 +1465,10 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_gather(s, nnz, pc.d_htpos, h_val, Ht));
   WVL_LAUNCH(ctx, KK_FOE, axpby(0.5, X, 0.5, Ht, 0.0, Hs));
   // spectral bounds: Gershgorin discs of S^-1/2 H S^-1/2 unless given
+  // (Sh and Hs are symmetric: they are their own transposes)
   if (eps_min >= eps_max) {
-    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
-    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0]));
+    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X, nullptr));
+    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0], nullptr));
     WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], Ht));
     WVL_LAUNCH(ctx, KK_FOE, launch_foe_gersh(s, n, rp, cl, Ht, red));
     double b[2];
@@ -1451,17 +1481,23 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   const double sigma = 2.0 / (eps_max - eps_min), tau = 0.5 * (eps_min + eps_max);
   // H~ = sigma (H - tau S), then H~' = S^-1/2 H~ S^-1/2 (symmetric part)
   WVL_LAUNCH(ctx, KK_FOE, axpby(sigma, Hs, -sigma * tau, Ss, 0.0, Hs));
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0]));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X, nullptr));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0], nullptr));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], Ht));
   // pass 1: traces of the Chebyshev matrices T^0 .. T^npl
-  WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, T[0]));
-  WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, T[1]));
+  auto start = [&]() -> wvl_status {
+    WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, T[0]));
+    WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, Tt[0]));
+    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, T[1]));
+    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, Tt[1]));
+    return WVL_OK;
+  };
+  if ((st = start()) != WVL_OK) return st;
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[0], nullptr, tr, 0));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[1], nullptr, tr, 1));
   int a = 0, b = 1, c = 2;
   for (int j = 1; j < npl; ++j) {
-    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, T[b], -1.0, T[a], T[c]));
+    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, Tt[b], -1.0, T[a], T[c], Tt[c]));
     WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[c], nullptr, tr, j + 1));
     const int t = a;
     a = b;
@@ -1493,24 +1529,25 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   }
   const double mu = 0.5 * (lo + hi);
   coefficients(sigma, tau, mu, delta, &coef);
-  // pass 2: K' = c_0/2 I + sum_i c_i T^i(H~')
+  // pass 2: K' = c_0/2 I + sum_i c_i T^i(H~'), and its transpose
   WVL_LAUNCH(ctx, KK_FOE, axpby(coef[1], Ht, 0.0, nullptr, 0.5 * coef[0], Kp));
-  WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, T[0]));
-  WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, T[1]));
+  WVL_LAUNCH(ctx, KK_FOE, axpby(coef[1], Ht, 0.0, nullptr, 0.5 * coef[0], Kpt));
+  if ((st = start()) != WVL_OK) return st;
   a = 0;
   b = 1;
   c = 2;
   for (int j = 1; j < npl; ++j) {
-    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, T[b], -1.0, T[a], T[c]));
+    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, Tt[b], -1.0, T[a], T[c], Tt[c]));
     WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Kp, coef[j + 1], T[c], 0.0, Kp));
+    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Kpt, coef[j + 1], Tt[c], 0.0, Kpt));
     const int t = a;
     a = b;
     b = c;
     c = t;
   }
   // K = S^-1/2 K' S^-1/2 (symmetric part); E_BS = Tr(K H~) / sigma + tau Tr(K S)
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Kp, 0.0, nullptr, X));
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0]));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Kpt, 0.0, nullptr, X, nullptr));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0], nullptr));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], k_val));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, k_val, Hs, red, 2));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, k_val, Ss, red, 3));

@@ -134,10 +134,11 @@ int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const doub
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
 // Fermi operator expansion on a symmetric CSR pattern (row: row of each
-// entry, tpos: position of the transposed entry)
+// entry, tpos: position of the transposed entry).  foe_mm takes its right
+// operand transposed (Bt) and can write its result transposed too (Ct).
 int launch_foe_mm(void* stream, const int64_t* rowptr, const int32_t* col, const int32_t* row,
                   const int64_t* tpos, int64_t nnz, double alpha, const double* A,
-                  const double* B, double beta, const double* D, double* C);
+                  const double* Bt, double beta, const double* D, double* C, double* Ct);
 int launch_foe_axpby(void* stream, int64_t nnz, double a, const double* X, double b,
                      const double* Y, const int32_t* row, const int32_t* col, double d,
                      double* out);

@@ -457,17 +457,19 @@ __global__ __launch_bounds__(TPB) void k_dens_gather(const SfDev* __restrict__ s
 // ---------------------------------------------------------------------------
 
 // C = alpha (A B)|_P + beta D, one thread per entry (i, j) of P:
-// (A B)_ij = sum_k A_ik B_kj over the k in both row i and row j of P (the
-// pattern is symmetric, so B_kj sits at the transpose position of (j, k)),
-// summed in increasing k.  D may be NULL (beta ignored).
+// (A B)_ij = sum_k A_ik B_kj over the k in both row i and row j of P, summed
+// in increasing k.  The pattern is symmetric, and B comes transposed (Bt:
+// B_kj stored at the position of (j, k)), so both operands are read along
+// rows.  D may be NULL (beta ignored); when Ct is given, C is also written
+// transposed (Ct at the position of (j, i)).
 __global__ __launch_bounds__(TPB) void k_foe_mm(const int64_t* __restrict__ rowptr,
                                                 const int32_t* __restrict__ col,
                                                 const int32_t* __restrict__ row,
                                                 const int64_t* __restrict__ tpos, int64_t nnz,
                                                 double alpha, const double* __restrict__ A,
-                                                const double* __restrict__ B, double beta,
+                                                const double* __restrict__ Bt, double beta,
                                                 const double* __restrict__ D,
-                                                double* __restrict__ C) {
+                                                double* __restrict__ C, double* __restrict__ Ct) {
   const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (p >= nnz) return;
   const int i = row[p], j = col[p];
@@ -481,12 +483,14 @@ __global__ __launch_bounds__(TPB) void k_foe_mm(const int64_t* __restrict__ rowp
     } else if (kb < ka) {
       ++qb;
     } else {
-      acc += A[qa] * B[tpos[qb]];
+      acc += A[qa] * Bt[qb];
       ++qa;
       ++qb;
     }
   }
-  C[p] = D ? alpha * acc + beta * D[p] : alpha * acc;
+  const double c = D ? alpha * acc + beta * D[p] : alpha * acc;
+  C[p] = c;
+  if (Ct) Ct[tpos[p]] = c;
 }
 
 // elementwise on P: out = a X + b Y (+ d on the diagonal when diag != NULL)
@@ -870,10 +874,10 @@ static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + TPB - 1) / TPB
 
 int launch_foe_mm(void* stream, const int64_t* rowptr, const int32_t* col, const int32_t* row,
                   const int64_t* tpos, int64_t nnz, double alpha, const double* A,
-                  const double* B, double beta, const double* D, double* C) {
+                  const double* Bt, double beta, const double* D, double* C, double* Ct) {
   if (nnz == 0) return 0;
   hipLaunchKernelGGL(k_foe_mm, grid1(nnz), dim3(TPB), 0, (hipStream_t)stream, rowptr, col, row,
-                     tpos, nnz, alpha, A, B, beta, D, C);
+                     tpos, nnz, alpha, A, Bt, beta, D, C, Ct);
   return (int)hipGetLastError();
 }
 
