@@ -388,12 +388,12 @@ def percentile(xs, q):
 
 
 def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_requests=4,
-              baseline_budget_s=60.0, log=print):
+              baseline_budget_s=60.0, log=print, loads=(0.5, 0.95)):
     """Serving measurement: (1) saturated throughput with every request
     queued at t = 0; (2) Poisson arrivals at `load` x that request rate, p50
-    and p99 latency; (3) the per-function FP64 baseline on the first
-    `baseline_requests` requests of the same arrival trace (one at a time).
-    Returns a dict of the figures."""
+    and p99 latency (and at each of `loads` as well); (3) the per-function
+    FP64 baseline on the first `baseline_requests` requests of the `load`
+    arrival trace (one at a time).  Returns a dict of the figures."""
     import torch
     t0 = time.perf_counter()
     base_reqs = make_requests(n_requests, seed=seed, fast=True)
@@ -415,20 +415,25 @@ def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_re
            "ticks": eng.ticks}
     log(f"serving: saturated {t_sat:.2f} s, {mu:.2f} requests/s, "
         f"{eng.sf_steps / t_sat:.0f} support-function steps/s")
-    rate = load * mu
-    rng = np.random.default_rng(9000 + seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
-    reqs2 = [r.fresh(float(a)) for r, a in zip(base_reqs, arrivals)]
-    eng2 = Engine(dtype=dtype, steps=steps)
-    t2 = time.perf_counter()
-    done = eng2.run(reqs2)
-    t_run = time.perf_counter() - t2
-    lat = [r.latency for r in done]
-    served = {"offered_requests_per_s": rate, "load": load, "seconds": t_run,
-              "requests_per_s": len(done) / t_run, "sf_steps_per_s": eng2.sf_steps / t_run,
-              "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
-              "max_s": max(lat), "rejected": len(eng2.rejected)}
-    log(f"serving: load {load}: p50 {served['p50_s']:.3f} s, p99 {served['p99_s']:.3f} s")
+    def poisson(ld):
+        rate = ld * mu
+        rng = np.random.default_rng(9000 + seed)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+        reqs2 = [r.fresh(float(a)) for r, a in zip(base_reqs, arrivals)]
+        eng2 = Engine(dtype=dtype, steps=steps)
+        t2 = time.perf_counter()
+        done = eng2.run(reqs2)
+        t_run = time.perf_counter() - t2
+        lat = [r.latency for r in done]
+        res = {"offered_requests_per_s": rate, "load": ld, "seconds": t_run,
+               "requests_per_s": len(done) / t_run, "sf_steps_per_s": eng2.sf_steps / t_run,
+               "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+               "max_s": max(lat), "rejected": len(eng2.rejected)}
+        log(f"serving: load {ld}: p50 {res['p50_s']:.3f} s, p99 {res['p99_s']:.3f} s")
+        return res, arrivals, lat
+
+    served, arrivals, lat = poisson(load)
+    others = [poisson(ld)[0] for ld in loads if ld != load]
     base = None
     if baseline_requests:
         breqs = [r.fresh(float(a)) for r, a in zip(base_reqs[:baseline_requests], arrivals)]
@@ -442,5 +447,6 @@ def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_re
         log(f"serving: per-function FP64 baseline p50 {base['p50_s']:.3f} s, "
             f"p99 {base['p99_s']:.3f} s over its {baseline_requests} requests")
     return {"requests": n_requests, "functions": sum(sizes), "steps": steps, "dtype": dtype,
-            "saturated": sat, "poisson": served, "per_function_fp64": base,
+            "saturated": sat, "poisson": served,
+            "poisson_other_loads": others, "per_function_fp64": base,
             "latency_note": "arrival -> end of the last step, host clock"}
