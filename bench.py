@@ -224,7 +224,7 @@ def density_section(S, reps=3):
     g = S["g"]
     n = g.grid_n
     fine = torch.empty(plan.info["fine_box"], dtype=psi.dtype, device="cuda")
-    work = torch.empty_like(fine)
+    work = None
     rho = torch.empty((2 * n[0] + 29) * (2 * n[1] + 29) * (2 * n[2] + 29), dtype=psi.dtype,
                       device="cuda")
     rowptr, col, _ = W.sparse_overlap(plan, psi, psi, False, values=False)
@@ -260,7 +260,7 @@ def density_section(S, reps=3):
     ov = np.prod(np.maximum(0, np.minimum(a1[row], a1[cb]) - np.maximum(a0[row], a0[cb])), axis=1)
     pair_pts = float(np.sum(ov))
     kern = {k: {"launches": v[0] // reps, "avg_ms": v[1] / v[0]} for k, v in prof.items() if v[0]}
-    pair_ms = kern.get("dens_pair", {}).get("avg_ms")
+    tile_ms = kern.get("dens_tile", {}).get("avg_ms")
     return {
         "synthesize_ms": (t1 - t0) * 1e3 / reps,
         "density_ms": (t2 - t1) * 1e3 / reps,
@@ -269,11 +269,12 @@ def density_section(S, reps=3):
         "grid_points": grid_pts,
         "kernel_nnz": int(kval.numel()),
         "pair_box_points": pair_pts,
-        # k_dens_pair: algorithmic bytes = the fine values read once and the
-        # products written once; measured against them it is the pairwise
-        # re-reading (pair_box_points values) that bounds it
-        "dens_pair_alg_gbps": (2 * nfine * sz / (pair_ms * 1e-3) / 1e9) if pair_ms else None,
-        "dens_pair_pair_gbps": (pair_pts * sz / (pair_ms * 1e-3) / 1e9) if pair_ms else None,
+        # k_dens_tile: algorithmic bytes = the fine values read once and rho
+        # written once; flops = a multiply-add per kernel entry and common
+        # fine point (pair_box_points of them)
+        "dens_tile_alg_gbps": ((nfine + grid_pts) * sz / (tile_ms * 1e-3) / 1e9)
+        if tile_ms else None,
+        "dens_tile_tflops": (2 * pair_pts / (tile_ms * 1e-3) / 1e12) if tile_ms else None,
         "note": "K on the overlap (S) pattern, smooth synthetic values; eager calls",
     }
 

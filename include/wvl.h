@@ -242,12 +242,13 @@ wvl_status wvl_synthesize(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void*
  * summed as given (columns outside [0, nsf) and positions outside
  * [0, k_nnz) are skipped).  rho: device, dt, the global fine grid
  * [2 n2 + 29][2 n1 + 29][2 n0 + 29] (z, y, x), every point written (0 where
- * no fine box reaches).  work: device scratch of wvl_plan_info.fine_box
- * elements of dt.  Sums run in double in an order fixed by the plan and K
- * (row order of K per point, then increasing function index), so the
+ * no fine box reaches).  work: unused (may be NULL).  Sums run in double
+ * in an order fixed by the plan and K (per point: the functions meeting its
+ * tile in increasing index, each with its row of K in stored order), so the
  * result is reproducible bitwise.  The first call builds the plan's tile
  * lists (synchronizes once).  Errors: WVL_EINVAL for null buffers or
- * k_nnz < 0. */
+ * k_nnz < 0; WVL_EUNSUPPORTED when more than 1024 fine boxes meet one tile
+ * of 16 x 4 x 1 fine-grid points. */
 wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int64_t* k_rowptr,
                        const int32_t* k_col, const double* k_val, int64_t k_nnz, void* rho,
                        void* work);

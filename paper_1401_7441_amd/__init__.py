@@ -434,7 +434,7 @@ def synthesize(plan: Plan, psi_c, fine, workspace=None):
 def density(plan: Plan, fine, k_rowptr, k_col, k_val, rho, work=None):
     """wvl_density: rho (global fine grid, z, y, x) = sum_ab phi_a K^ab phi_b
     from the fine-box values `fine` and K in CSR form (int64 rowptr, int32
-    col, float64 val, all on the device)."""
+    col, float64 val, all on the device).  `work` is not used."""
     import torch
     _need_cuda(fine, k_rowptr, k_col, k_val, rho, work)
     dt = _dtype_code(fine, rho, work)
@@ -447,10 +447,6 @@ def density(plan: Plan, fine, k_rowptr, k_col, k_val, rho, work=None):
             k_col.dtype != torch.int32 or k_val.dtype != torch.float64 or \
             k_col.numel() != k_val.numel():
         raise WvlError(WVL_EINVAL, "K must be CSR: int64 rowptr[nsf + 1], int32 col, float64 val")
-    if work is None:
-        work = torch.empty(max(1, plan.info["fine_box"]), dtype=fine.dtype, device="cuda")
-    elif work.numel() < plan.info["fine_box"]:
-        raise WvlError(WVL_EINVAL, "work smaller than the plan's fine boxes")
     _check(lib().wvl_density(plan._ptr, dt, _ptr(fine), _ptr(k_rowptr), _ptr(k_col),
                              _ptr(k_val), int(k_val.numel()), _ptr(rho), _ptr(work)),
            plan.ctx.handle)

@@ -22,12 +22,12 @@ using namespace wvl;
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_UNPACK, KK_UP_X, KK_UP_Y, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
   KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
-  KK_UPDATE, KK_UP_Z, KK_DENS_PAIR, KK_DENS_GATHER, KK_FOE_MM, KK_FOE, KK_COUNT
+  KK_UPDATE, KK_UP_Z, KK_DENS_TILE, KK_FOE_MM, KK_FOE, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "unpack", "up_x", "up_y", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
     "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update",
-    "up_z", "dens_pair", "dens_gather", "foe_mm", "foe"};
+    "up_z", "dens_tile", "foe_mm", "foe"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -191,10 +191,8 @@ struct wvl_plan {
   SfWork* d_wk = nullptr;
   int64_t* d_foff = nullptr;          // fine-box offsets (wvl_synthesize), function order
   int64_t max_fine = 0;               // largest fine box (elements)
-  int64_t* d_cptr = nullptr;          // density: functions meeting each k_dens_gather tile
+  int64_t* d_cptr = nullptr;          // density: functions meeting each k_dens_tile tile
   int32_t* d_csf = nullptr;
-  int32_t* d_planes = nullptr;        // density: (function, box plane) by global plane
-  int64_t nplanes = 0;
   wvl_plan_info info{};
   PatternCache pat[2];
 };
@@ -624,7 +622,6 @@ void wvl_plan_destroy(wvl_plan* plan) {
   if (plan->d_foff) (void)hipFree(plan->d_foff);
   if (plan->d_cptr) (void)hipFree(plan->d_cptr);
   if (plan->d_csf) (void)hipFree(plan->d_csf);
-  if (plan->d_planes) (void)hipFree(plan->d_planes);
   if (plan->d_rt) (void)hipFree(plan->d_rt);
   if (plan->d_rr) (void)hipFree(plan->d_rr);
   if (plan->d_wk) (void)hipFree(plan->d_wk);
@@ -1238,7 +1235,7 @@ wvl_status wvl_synthesize(wvl_plan* P, wvl_dtype dt, const void* psi_c, void* fi
   return WVL_OK;
 }
 
-// functions whose fine box meets each k_dens_gather tile, increasing index
+// functions whose fine box meets each k_dens_tile tile, increasing index
 static wvl_status ensure_cover(wvl_plan* P) {
   if (P->d_cptr) return WVL_OK;
   wvl_ctx* ctx = P->ctx;
@@ -1276,21 +1273,14 @@ static wvl_status ensure_cover(wvl_plan* P) {
           }
     }
   }
-  // k_dens_pair blocks: (function, plane of its box), by global plane
-  std::vector<int32_t> planes;
-  for (int gz = 0; gz < gf[2]; ++gz)
-    for (int k = 0; k < P->nsf; ++k) {
-      const SfDev& S = P->h_sf[k];
-      const int pz = gz - 2 * S.lo[2];
-      if (pz >= 0 && pz < 2 * S.n[2] + 29) {
-        planes.push_back(k);
-        planes.push_back(pz);
-      }
-    }
-  if (planes.size() / 2 > (size_t)UINT32_MAX)
-    return fail(ctx, WVL_EUNSUPPORTED, "density: too many box planes");
+  int64_t maxc = 0;
+  for (int64_t t = 0; t < ntile; ++t) maxc = std::max(maxc, cptr[t + 1] - cptr[t]);
+  if (maxc > kDensMaxCover)
+    return fail(ctx, WVL_EUNSUPPORTED,
+                "density: %lld fine boxes meet one tile (at most %d are supported)",
+                (long long)maxc, kDensMaxCover);
   auto drop = [&]() {
-    for (void** p : {(void**)&P->d_cptr, (void**)&P->d_csf, (void**)&P->d_planes})
+    for (void** p : {(void**)&P->d_cptr, (void**)&P->d_csf})
       if (*p) {
         (void)hipFree(*p);
         *p = nullptr;
@@ -1298,9 +1288,7 @@ static wvl_status ensure_cover(wvl_plan* P) {
   };
   wvl_status st;
   if ((st = upload(ctx, &P->d_cptr, cptr.data(), sizeof(int64_t) * cptr.size())) != WVL_OK ||
-      (st = upload(ctx, &P->d_csf, csf.data(), sizeof(int32_t) * csf.size())) != WVL_OK ||
-      (st = upload(ctx, &P->d_planes, planes.data(), sizeof(int32_t) * planes.size())) !=
-          WVL_OK) {
+      (st = upload(ctx, &P->d_csf, csf.data(), sizeof(int32_t) * csf.size())) != WVL_OK) {
     drop();
     return st;
   }
@@ -1308,7 +1296,6 @@ static wvl_status ensure_cover(wvl_plan* P) {
     drop();
     return fail(ctx, WVL_EDEVICE, "density tile lists upload failed");
   }
-  P->nplanes = (int64_t)planes.size() / 2;
   return WVL_OK;
 }
 
@@ -1320,19 +1307,17 @@ wvl_status wvl_density(wvl_plan* P, wvl_dtype dt, const void* fine, const int64_
   if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
   if (k_nnz < 0) return fail(ctx, WVL_EINVAL, "wvl_density: k_nnz < 0");
   if (!rho) return fail(ctx, WVL_EINVAL, "wvl_density: null rho");
-  if (P->nsf > 0 && (!fine || !k_rowptr || !work || (k_nnz > 0 && (!k_col || !k_val))))
+  (void)work;
+  if (P->nsf > 0 && (!fine || !k_rowptr || (k_nnz > 0 && (!k_col || !k_val))))
     return fail(ctx, WVL_EINVAL, "wvl_density: null buffer");
   wvl_status st = ensure_cover(P);
   if (st != WVL_OK) return st;
   const int f64 = dt == WVL_F64 ? 1 : 0;
-  WVL_LAUNCH(ctx, KK_DENS_PAIR,
-             launch_dens_pair(f64, ctx->stream, P->d_sf, P->nsf, P->d_foff, fine, k_rowptr,
-                              k_col, k_val, k_nnz, P->d_planes, P->nplanes, work));
   int gf[3];
   for (int a = 0; a < 3; ++a) gf[a] = 2 * ctx->grid.n[a] + 29;
-  WVL_LAUNCH(ctx, KK_DENS_GATHER,
-             launch_dens_gather(f64, ctx->stream, P->d_sf, P->d_foff, work, P->d_cptr, P->d_csf,
-                                gf, rho));
+  WVL_LAUNCH(ctx, KK_DENS_TILE,
+             launch_dens_tile(f64, ctx->stream, P->d_sf, P->d_foff, fine, k_rowptr, k_col, k_val,
+                              k_nnz, P->d_cptr, P->d_csf, gf, rho));
   return WVL_OK;
 }
 

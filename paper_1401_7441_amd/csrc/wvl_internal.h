@@ -106,17 +106,14 @@ int launch_up(int f64, void* stream, int axis, const SfWork* wk, const SfDev* sf
               int gridx, void* ws);
 int launch_up_z(int f64, void* stream, const SfWork* wk, const SfDev* sf, int nsf, int gridx,
                 const void* ws, const int64_t* fine_off, void* fine);
-// planes: (function, fine z-plane of its box) pairs as int32 pairs, by
-// global plane then function
-int launch_dens_pair(int f64, void* stream, const SfDev* sf, int nsf, const int64_t* foff,
+// density: tiles of 16 x 4 x 1 fine-grid points (one 64-lane workgroup each)
+// with the functions whose fine box meets them (at most kDensMaxCover)
+constexpr int kDensTile[3] = {16, 4, 1};
+constexpr int kDensMaxCover = 1024;
+int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff,
                      const void* fine, const int64_t* krow, const int32_t* kcol,
-                     const double* kval, int64_t knnz, const int32_t* planes, int64_t nplanes,
-                     void* prod);
-// tile of k_dens_gather (x, y, z fine points; 256 points) and its launch
-constexpr int kDensTile[3] = {32, 4, 2};
-int launch_dens_gather(int f64, void* stream, const SfDev* sf, const int64_t* foff,
-                       const void* prod, const int64_t* cptr, const int32_t* csf, const int* gf,
-                       void* rho);
+                     const double* kval, int64_t knnz, const int64_t* cptr, const int32_t* csf,
+                     const int* gf, void* rho);
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                       int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart,
                       const double* conf, double hh);

@@ -320,135 +320,119 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
 // ---------------------------------------------------------------------------
 // density rho(r) = sum_ab phi_a(r) K^ab phi_b(r) on the fine grid
 // ---------------------------------------------------------------------------
-// Step 1 (k_dens_pair): block = one fine z-plane pz of function a's box
-// (blocks enumerated by global plane, so that the blocks in flight read the
-// same planes of the neighbouring boxes from the caches);
-// P_a(r) = phi_a(r) sum_q K[q] phi_b(r) over the kernel's row a
-// (b = col[q]), phi_b(r) = 0 outside b's fine box.  The entries whose box
-// holds the plane are staged in LDS in row order, so each point is a fixed
-// sum.  Columns outside [0, nsf) and positions outside [0, knnz) are skipped.
-struct DensEnt {
-  int32_t x0, y0;         // global fine x, y of the box's first point
-  int32_t s0, s1;         // box points along x, y
-  int64_t base;           // element of (x0, y0) on this plane in `fine`
-  double k;               // K^ab
-};
+// One workgroup of eight waves per tile of 16 x 4 x 1 fine-grid points (lane =
+// point in every wave).  The functions whose fine box meets the tile (its
+// cover, increasing index) are taken in chunks of C: the values phi_a(r) of
+// an i-chunk and a j-chunk are staged in LDS (0 outside a box).  Wave w takes
+// the functions a = i-chunk entries w, w + 8, ...: it scans the kernel row a
+// for the columns b in the j-chunk (binary search in the cover), kept in row
+// order, and accumulates
+//   rho_w(r) += phi_a(r) sum_{b in row a, j-chunk} K[q] phi_b(r);
+// rho(r) is then rho_0 + rho_1 + ... + rho_7.  The order of every sum is
+// fixed by the tile's cover and K.  Columns outside [0, nsf) never match;
+// positions outside [0, knnz) are skipped.
+constexpr int kDensWaves = 8;
 
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_dens_pair(const SfDev* __restrict__ sfs, int nsf,
-                                                   const int64_t* __restrict__ foff,
-                                                   const T* __restrict__ fine,
-                                                   const int64_t* __restrict__ krow,
-                                                   const int32_t* __restrict__ kcol,
-                                                   const double* __restrict__ kval, int64_t knnz,
-                                                   const int2* __restrict__ planes,
-                                                   T* __restrict__ prod) {
-  __shared__ DensEnt ent[TPB];
-  __shared__ int wcount[TPB / 64];
-  const int2 ap = planes[blockIdx.x];
-  const int a = ap.x, pz = ap.y;
-  const SfDev& A = sfs[a];
-  const int R0 = 2 * A.n[0] + 29, R1 = 2 * A.n[1] + 29;
-  const int gz = 2 * A.lo[2] + pz;
-  const int gx0 = 2 * A.lo[0], gy0 = 2 * A.lo[1];
-  const int npts = R0 * R1;
-  const int64_t outp = foff[a] + (int64_t)pz * npts;
-  const int64_t q0 = max((int64_t)0, krow[a]), q1 = min(knnz, krow[a + 1]);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool one_pass = q1 - q0 <= TPB;   // the row is staged once
-  int nent = 0;
-  for (int p0 = 0; p0 < npts; p0 += TPB) {
-    const int p = p0 + threadIdx.x;
-    const bool inside = p < npts;
-    const int py = inside ? p / R0 : 0, px = inside ? p - py * R0 : 0;
-    const int gx = gx0 + px, gy = gy0 + py;
-    double acc = 0.0;
-    for (int64_t c0 = q0; c0 < q1; c0 += TPB) {
-      if (!one_pass || p0 == 0) {
-        // stage the entries whose box holds plane gz, in row order
-        __syncthreads();
-        const int64_t q = c0 + threadIdx.x;
-        DensEnt e{};
-        bool keep = false;
-        if (q < q1) {
-          const int bb = kcol[q];
-          if (bb >= 0 && bb < nsf) {
-            const SfDev& B = sfs[bb];
-            const int bz = gz - 2 * B.lo[2];
-            if (bz >= 0 && bz < 2 * B.n[2] + 29) {
-              keep = true;
-              e.x0 = 2 * B.lo[0];
-              e.y0 = 2 * B.lo[1];
-              e.s0 = 2 * B.n[0] + 29;
-              e.s1 = 2 * B.n[1] + 29;
-              e.base = foff[bb] + (int64_t)bz * e.s1 * e.s0;
-              e.k = kval[q];
-            }
-          }
-        }
-        const unsigned long long m = __ballot(keep);
-        if (lane == 0) wcount[wave] = __popcll(m);
-        __syncthreads();
-        int before = __popcll(m & ((1ull << lane) - 1ull));
-        nent = 0;
-        for (int w = 0; w < TPB / 64; ++w) {
-          if (w < wave) before += wcount[w];
-          nent += wcount[w];
-        }
-        if (keep) ent[before] = e;
-        __syncthreads();
-      }
-      // eight loads in flight at a time; the sum keeps the row order
-      for (int j0 = 0; j0 < nent; j0 += 8) {
-        int64_t at[8];
-        T v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          at[u] = -1;
-          if (j0 + u < nent) {
-            const DensEnt& e = ent[j0 + u];
-            const unsigned bx = (unsigned)(gx - e.x0), by = (unsigned)(gy - e.y0);
-            if (inside && bx < (unsigned)e.s0 && by < (unsigned)e.s1)
-              at[u] = e.base + (int64_t)(by * e.s0 + bx);
-          }
-          v[u] = at[u] >= 0 ? fine[at[u]] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (at[u] >= 0) acc += ent[j0 + u].k * (double)v[u];
-      }
-    }
-    if (inside) prod[outp + p] = (T)((double)fine[outp + p] * acc);
-  }
+// orders a wave's LDS writes before its other lanes' reads (and the reads
+// before the next writes)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-// Step 2 (k_dens_gather): block = one tile of 32 x 4 x 2 fine-grid points;
-// rho(r) = sum of P_a(r) over the functions whose fine box meets the tile,
-// in increasing function index (a fixed sum); 0 where no box reaches.
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_dens_gather(const SfDev* __restrict__ sfs,
-                                                     const int64_t* __restrict__ foff,
-                                                     const T* __restrict__ prod,
-                                                     const int64_t* __restrict__ cptr,
-                                                     const int32_t* __restrict__ csf, int tx,
-                                                     int ty, int g0, int g1, int g2,
-                                                     T* __restrict__ rho) {
+__global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
+    const SfDev* __restrict__ sfs, const int64_t* __restrict__ foff, const T* __restrict__ fine,
+    const int64_t* __restrict__ krow, const int32_t* __restrict__ kcol,
+    const double* __restrict__ kval, int64_t knnz, const int64_t* __restrict__ cptr,
+    const int32_t* __restrict__ csf, int tx, int ty, int g0, int g1, int g2,
+    T* __restrict__ rho) {
+  constexpr int C = sizeof(T) == 4 ? 128 : 64;    // functions per staged chunk
+  __shared__ T vi[C * 64], vj[C * 64];
+  __shared__ int32_t cov[kDensMaxCover];
+  __shared__ int32_t lj[kDensWaves][64];
+  __shared__ double lk[kDensWaves][64];
+  __shared__ double red[kDensWaves][64];
   const int tile = blockIdx.x;
   const int ix = tile % tx, iy = (tile / tx) % ty, iz = tile / (tx * ty);
-  const int gx = ix * kDensTile[0] + (threadIdx.x & 31);
-  const int gy = iy * kDensTile[1] + ((threadIdx.x >> 5) & 3);
-  const int gz = iz * kDensTile[2] + (threadIdx.x >> 7);
-  if (gx >= g0 || gy >= g1 || gz >= g2) return;
-  double acc = 0.0;
-  for (int64_t i = cptr[tile]; i < cptr[tile + 1]; ++i) {
-    const int a = csf[i];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int gx = ix * kDensTile[0] + (lane & 15);
+  const int gy = iy * kDensTile[1] + (lane >> 4);
+  const int gz = iz;
+  const bool inside = gx < g0 && gy < g1 && gz < g2;
+  const int64_t c0 = cptr[tile];
+  const int m = (int)(cptr[tile + 1] - c0);
+  for (int i = tid; i < m; i += 64 * kDensWaves) cov[i] = csf[c0 + i];
+  // phi_a at this lane's point, 0 outside a's fine box
+  auto value = [&](int a) -> T {
     const SfDev& A = sfs[a];
     const int px = gx - 2 * A.lo[0], py = gy - 2 * A.lo[1], pz = gz - 2 * A.lo[2];
     const int R0 = 2 * A.n[0] + 29, R1 = 2 * A.n[1] + 29, R2 = 2 * A.n[2] + 29;
-    if (px < 0 || px >= R0 || py < 0 || py >= R1 || pz < 0 || pz >= R2) continue;
-    acc += (double)prod[foff[a] + ((int64_t)pz * R1 + py) * R0 + px];
+    if (!inside || px < 0 || px >= R0 || py < 0 || py >= R1 || pz < 0 || pz >= R2) return T(0);
+    return fine[foff[a] + ((int64_t)pz * R1 + py) * R0 + px];
+  };
+  double acc = 0.0;
+  __syncthreads();
+  for (int ic = 0; ic < m; ic += C) {
+    const int ni = min(C, m - ic);
+    for (int i = wave; i < ni; i += kDensWaves) vi[i * 64 + lane] = value(cov[ic + i]);
+    for (int jc = 0; jc < m; jc += C) {
+      const int nj = min(C, m - jc);
+      const T* vb = vi;
+      if (jc != ic) {
+        __syncthreads();   // vj no longer read
+        for (int j = wave; j < nj; j += kDensWaves) vj[j * 64 + lane] = value(cov[jc + j]);
+        vb = vj;
+      }
+      __syncthreads();
+      const int blo = cov[jc], bhi = cov[jc + nj - 1];
+      for (int i = wave; i < ni; i += kDensWaves) {
+        const int a = cov[ic + i];
+        const int64_t q0 = max((int64_t)0, krow[a]), q1 = min(knnz, krow[a + 1]);
+        double u = 0.0;
+        for (int64_t qq = q0; qq < q1; qq += 64) {
+          const int64_t q = qq + lane;
+          int j = -1;
+          double kq = 0.0;
+          if (q < q1) {
+            const int b = kcol[q];
+            if (b >= blo && b <= bhi) {   // binary search in the j-chunk
+              int lo = 0, hi = nj - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (cov[jc + mid] < b) lo = mid + 1; else hi = mid;
+              }
+              if (cov[jc + lo] == b) {
+                j = lo;
+                kq = kval[q];
+              }
+            }
+          }
+          const unsigned long long hit = __ballot(j >= 0);
+          if (j >= 0) {
+            const int pos = __popcll(hit & ((1ull << lane) - 1ull));
+            lj[wave][pos] = j;
+            lk[wave][pos] = kq;
+          }
+          wave_sync();
+          const int cnt = __popcll(hit);
+#pragma unroll 4
+          for (int t = 0; t < cnt; ++t) u += lk[wave][t] * (double)vb[lj[wave][t] * 64 + lane];
+          wave_sync();
+        }
+        acc += (double)vi[i * 64 + lane] * u;
+      }
+      __syncthreads();   // vi / vj no longer read
+    }
   }
-  rho[((int64_t)gz * g1 + gy) * g0 + gx] = (T)acc;
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && inside) {
+    double r = red[0][lane];
+    for (int w = 1; w < kDensWaves; ++w) r += red[w][lane];
+    rho[((int64_t)gz * g1 + gy) * g0 + gx] = (T)r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -756,9 +740,8 @@ int preload_kernels() {
   const void* fns[] = {(const void*)k_finalize, (const void*)k_sparse_values<float>,
                        (const void*)k_sparse_values<double>, (const void*)k_update<float>,
                        (const void*)k_update<double>, (const void*)k_sf_dot<float>,
-                       (const void*)k_sf_dot<double>, (const void*)k_dens_pair<float>,
-                       (const void*)k_dens_pair<double>, (const void*)k_dens_gather<float>,
-                       (const void*)k_dens_gather<double>};
+                       (const void*)k_sf_dot<double>, (const void*)k_dens_tile<float>,
+                       (const void*)k_dens_tile<double>};
   for (const void* f : fns) {
     hipFuncAttributes a;
     const hipError_t e = hipFuncGetAttributes(&a, f);
@@ -836,37 +819,24 @@ int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* 
   return (int)hipGetLastError();
 }
 
-int launch_dens_pair(int f64, void* stream, const SfDev* sf, int nsf, const int64_t* foff,
+int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff,
                      const void* fine, const int64_t* krow, const int32_t* kcol,
-                     const double* kval, int64_t knnz, const int32_t* planes, int64_t nplanes,
-                     void* prod) {
-  if (nplanes == 0) return 0;
-  const dim3 g((unsigned)nplanes);
-  const int2* pl = reinterpret_cast<const int2*>(planes);
-  if (f64)
-    hipLaunchKernelGGL(k_dens_pair<double>, g, dim3(TPB), 0, (hipStream_t)stream, sf, nsf, foff,
-                       (const double*)fine, krow, kcol, kval, knnz, pl, (double*)prod);
-  else
-    hipLaunchKernelGGL(k_dens_pair<float>, g, dim3(TPB), 0, (hipStream_t)stream, sf, nsf, foff,
-                       (const float*)fine, krow, kcol, kval, knnz, pl, (float*)prod);
-  return (int)hipGetLastError();
-}
-
-int launch_dens_gather(int f64, void* stream, const SfDev* sf, const int64_t* foff,
-                       const void* prod, const int64_t* cptr, const int32_t* csf, const int* gf,
-                       void* rho) {
+                     const double* kval, int64_t knnz, const int64_t* cptr, const int32_t* csf,
+                     const int* gf, void* rho) {
   const int tx = (gf[0] + kDensTile[0] - 1) / kDensTile[0];
   const int ty = (gf[1] + kDensTile[1] - 1) / kDensTile[1];
   const int tz = (gf[2] + kDensTile[2] - 1) / kDensTile[2];
   const dim3 g((unsigned)((int64_t)tx * ty * tz));
   if (f64)
-    hipLaunchKernelGGL(k_dens_gather<double>, g, dim3(TPB), 0, (hipStream_t)stream, sf, foff,
-                       (const double*)prod, cptr, csf, tx, ty, gf[0], gf[1], gf[2],
-                       (double*)rho);
+    hipLaunchKernelGGL(k_dens_tile<double>, g, dim3(64 * kDensWaves), 0, (hipStream_t)stream, sf,
+                       foff,
+                       (const double*)fine, krow, kcol, kval, knnz, cptr, csf, tx, ty, gf[0],
+                       gf[1], gf[2], (double*)rho);
   else
-    hipLaunchKernelGGL(k_dens_gather<float>, g, dim3(TPB), 0, (hipStream_t)stream, sf, foff,
-                       (const float*)prod, cptr, csf, tx, ty, gf[0], gf[1], gf[2],
-                       (float*)rho);
+    hipLaunchKernelGGL(k_dens_tile<float>, g, dim3(64 * kDensWaves), 0, (hipStream_t)stream, sf,
+                       foff,
+                       (const float*)fine, krow, kcol, kval, knnz, cptr, csf, tx, ty, gf[0],
+                       gf[1], gf[2], (float*)rho);
   return (int)hipGetLastError();
 }
 
