@@ -130,6 +130,7 @@ struct PatternCache {
   int64_t* d_tpos = nullptr;
   int64_t* d_hpos = nullptr;
   int64_t* d_htpos = nullptr;
+  int64_t* d_dpos = nullptr;    // diagonal entry of every row
 };
 
 // 3D Morton code of a non-negative grid point (10 bits per axis)
@@ -612,6 +613,7 @@ static void free_pattern(PatternCache& p) {
   if (p.d_tpos) (void)hipFree(p.d_tpos);
   if (p.d_hpos) (void)hipFree(p.d_hpos);
   if (p.d_htpos) (void)hipFree(p.d_htpos);
+  if (p.d_dpos) (void)hipFree(p.d_dpos);
   p = PatternCache{};
 }
 
@@ -1352,7 +1354,13 @@ static wvl_status ensure_foe_maps(wvl_plan* P) {
     const auto it = std::lower_bound(b, e, j);
     return (it != e && *it == j) ? (int64_t)(it - cl.begin()) : -1;
   };
-  std::vector<int64_t> tpos(S.nnz), hpos(S.nnz), htpos(S.nnz);
+  std::vector<int64_t> tpos(S.nnz), hpos(S.nnz), htpos(S.nnz), dpos(n);
+  for (int i = 0; i < n; ++i) {
+    dpos[i] = find(srp, scol, i, i);
+    if (dpos[i] < 0)
+      return fail(ctx, WVL_EUNSUPPORTED, "wvl_foe: row %d of the overlap pattern has no diagonal",
+                  i);
+  }
   for (int i = 0; i < n; ++i)
     for (int64_t p = srp[i]; p < srp[i + 1]; ++p) {
       const int j = scol[p];
@@ -1366,7 +1374,8 @@ static wvl_status ensure_foe_maps(wvl_plan* P) {
   wvl_status st;
   if ((st = upload(ctx, &S.d_tpos, tpos.data(), sizeof(int64_t) * tpos.size())) != WVL_OK ||
       (st = upload(ctx, &S.d_hpos, hpos.data(), sizeof(int64_t) * hpos.size())) != WVL_OK ||
-      (st = upload(ctx, &S.d_htpos, htpos.data(), sizeof(int64_t) * htpos.size())) != WVL_OK)
+      (st = upload(ctx, &S.d_htpos, htpos.data(), sizeof(int64_t) * htpos.size())) != WVL_OK ||
+      (st = upload(ctx, &S.d_dpos, dpos.data(), sizeof(int64_t) * dpos.size())) != WVL_OK)
     return st;
   WVL_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return WVL_OK;
@@ -1478,12 +1487,12 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
     return WVL_OK;
   };
   if ((st = start()) != WVL_OK) return st;
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[0], nullptr, tr, 0));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[1], nullptr, tr, 1));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_trace(s, n, pc.d_dpos, T[0], tr, 0));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_trace(s, n, pc.d_dpos, T[1], tr, 1));
   int a = 0, b = 1, c = 2;
   for (int j = 1; j < npl; ++j) {
     WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, Tt[b], -1.0, T[a], T[c], Tt[c]));
-    WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, T[c], nullptr, tr, j + 1));
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_trace(s, n, pc.d_dpos, T[c], tr, j + 1));
     const int t = a;
     a = b;
     b = c;
@@ -1534,8 +1543,8 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Kpt, 0.0, nullptr, X, nullptr));
   WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0], nullptr));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], k_val));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, k_val, Hs, red, 2));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, rw, cl, k_val, Ss, red, 3));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Hs, red, 2));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Ss, red, 3));
   double e2[2];
   WVL_HIP(ctx, hipMemcpyAsync(e2, red + 2, sizeof e2, hipMemcpyDeviceToHost, s));
   WVL_HIP(ctx, hipStreamSynchronize(s));

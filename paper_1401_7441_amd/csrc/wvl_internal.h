@@ -142,8 +142,10 @@ int launch_foe_axpby(void* stream, int64_t nnz, double a, const double* X, doubl
 int launch_foe_sym(void* stream, int64_t nnz, const int64_t* tpos, const double* X, double* out);
 int launch_foe_gather(void* stream, int64_t nnz, const int64_t* qpos, const double* X,
                       double* out);
-int launch_foe_dot(void* stream, int64_t nnz, const int32_t* row, const int32_t* col,
-                   const double* X, const double* Y, double* out, int slot);
+int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, double* out,
+                   int slot);
+int launch_foe_trace(void* stream, int n, const int64_t* dpos, const double* X, double* out,
+                     int slot);
 int launch_foe_gersh(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
                      const double* X, double* out);
 int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,

@@ -511,20 +511,23 @@ __global__ __launch_bounds__(TPB) void k_foe_gather(int64_t nnz, const int64_t* 
   out[p] = X[qpos[p]];
 }
 
-// one block: out[slot] = sum_p X[p] Y[p] over P (Y NULL: the trace of X,
-// i.e. the diagonal entries), in a fixed order
-__global__ __launch_bounds__(TPB) void k_foe_dot(int64_t nnz, const int32_t* __restrict__ row,
-                                                 const int32_t* __restrict__ col,
-                                                 const double* __restrict__ X,
+// one block: out[slot] = sum_p X[p] Y[p] over P, in a fixed order
+__global__ __launch_bounds__(TPB) void k_foe_dot(int64_t nnz, const double* __restrict__ X,
                                                  const double* __restrict__ Y,
                                                  double* __restrict__ out, int slot) {
   double v = 0.0;
-  for (int64_t p = threadIdx.x; p < nnz; p += TPB) {
-    if (Y)
-      v += X[p] * Y[p];
-    else if (row[p] == col[p])
-      v += X[p];
-  }
+  for (int64_t p = threadIdx.x; p < nnz; p += TPB) v += X[p] * Y[p];
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) out[slot] = s;
+}
+
+// one block: out[slot] = trace of X, its diagonal entries at dpos[0..n), in
+// a fixed order
+__global__ __launch_bounds__(TPB) void k_foe_trace(int n, const int64_t* __restrict__ dpos,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ out, int slot) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += TPB) v += X[dpos[i]];
   const double s = block_sum(v);
   if (threadIdx.x == 0) out[slot] = s;
 }
@@ -874,10 +877,16 @@ int launch_foe_gather(void* stream, int64_t nnz, const int64_t* qpos, const doub
   return (int)hipGetLastError();
 }
 
-int launch_foe_dot(void* stream, int64_t nnz, const int32_t* row, const int32_t* col,
-                   const double* X, const double* Y, double* out, int slot) {
-  hipLaunchKernelGGL(k_foe_dot, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nnz, row, col, X, Y,
-                     out, slot);
+int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, double* out,
+                   int slot) {
+  hipLaunchKernelGGL(k_foe_dot, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nnz, X, Y, out, slot);
+  return (int)hipGetLastError();
+}
+
+int launch_foe_trace(void* stream, int n, const int64_t* dpos, const double* X, double* out,
+                     int slot) {
+  hipLaunchKernelGGL(k_foe_trace, dim3(1), dim3(TPB), 0, (hipStream_t)stream, n, dpos, X, out,
+                     slot);
   return (int)hipGetLastError();
 }
 
