@@ -309,8 +309,9 @@ def foe_section(S, npl=100, delta=1.0, reps=2):
             # term once and writes the result (plus the pattern): per entry
             # 4 doubles and 12 bytes of indices
             "foe_mm_alg_gbps": (nnz * 44 / (mm["avg_ms"] * 1e-3) / 1e9) if mm else None,
-            "note": "S and H of the timed step; 2 npl truncated products (traces, then the "
-                    "kernel) plus the transforms; the call synchronizes"}
+            "note": "S and H of the timed step; npl - 1 truncated products of the Chebyshev "
+                    "recursion (every T^i kept, the traces and the kernel summed from them) "
+                    "plus the transforms; the call synchronizes"}
 
 
 # ---------------------------------------------------------------------------

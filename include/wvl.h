@@ -266,8 +266,8 @@ wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int
  *             T^i by the Chebyshev recursion, c_i the Chebyshev coefficients
  *             on [-1, 1] of f = (1 - erf((eps - mu) / delta)) / 2;
  *   mu        such that Tr K' = n_occ (bisection: the traces of the T^i are
- *             taken once, then the matrices are formed again with the final
- *             coefficients);
+ *             taken once; K' then sums the kept T^i with the final
+ *             coefficients, or, in the smaller scratch, forms them again);
  *   K = S^-1/2 K' S^-1/2;  E_BS = Tr(K H~) / sigma + tau Tr(K S).
  * The symmetric part is taken after each two-sided product, since the
  * truncation breaks the symmetry the exact product has.
@@ -280,14 +280,19 @@ wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int
  *   k_val:   device double[nnz of P], the kernel K
  *   mu, e_bs: host, the chemical potential and the band-structure energy
  *            (either may be NULL)
- *   scratch: device, at least 8 (13 nnz + npl + 5) bytes
+ *   scratch, scratch_bytes: device buffer and its size: at least
+ *            8 ((npl + 7) nnz + 2 npl + 6) bytes keeps every T^i (one
+ *            recursion); at least 8 (9 nnz + npl + 5) bytes runs the
+ *            recursion twice.  Both give the same values, bit for bit.
  * All arithmetic is in double, sums in fixed orders (bitwise reproducible).
  * Synchronizes (the traces and bounds come back to the host).  Errors:
- * WVL_EINVAL for bad parameters or null buffers; WVL_EUNSUPPORTED when P is
- * not symmetric or not inside the H pattern. */
+ * WVL_EINVAL for bad parameters, null buffers or a scratch below the smaller
+ * size; WVL_EUNSUPPORTED when P is
+ * not symmetric, not inside the H pattern, lacks a diagonal entry, has a
+ * row of more than 1024 entries, or the plan has more than 2^21 functions. */
 wvl_status wvl_foe(wvl_plan* plan, const double* s_val, const double* h_val, int32_t npl,
                    double delta, double n_occ, double eps_min, double eps_max, double* k_val,
-                   double* mu, double* e_bs, void* scratch);
+                   double* mu, double* e_bs, void* scratch, size_t scratch_bytes);
 
 /* Support-function update step (the localized gradient step of Sec. III.A
  * and IV.A, reduced to a fixed step length):

@@ -105,7 +105,8 @@ def _load():
         "wvl_apply_local_ham_conf": [P, ctypes.c_int, U32, P, P, P, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
         "wvl_synthesize": [P, ctypes.c_int, P, P, P],
-        "wvl_foe": [P, P, P, I32, D, D, D, D, P, ctypes.POINTER(D), ctypes.POINTER(D), P],
+        "wvl_foe": [P, P, P, I32, D, D, D, D, P, ctypes.POINTER(D), ctypes.POINTER(D), P,
+                    ctypes.c_size_t],
         "wvl_density": [P, ctypes.c_int, P, P, P, P, I64, P, P],
         "wvl_update": [P, ctypes.c_int, D, P, P, P],
         "wvl_precondition": [P, ctypes.c_int, P, P, P, I32, P, P, P],
@@ -452,11 +453,22 @@ def density(plan: Plan, fine, k_rowptr, k_col, k_val, rho, work=None):
            plan.ctx.handle)
 
 
+def foe_scratch_bytes(plan: Plan, npl, keep=True):
+    """Scratch bytes of wvl_foe: with every Chebyshev matrix kept (one
+    recursion), or the smaller size that runs the recursion twice."""
+    nnz_s = sparse_pattern_nnz(plan, False)
+    npl = int(npl)
+    return 8 * ((npl + 7) * nnz_s + 2 * npl + 6) if keep else 8 * (9 * nnz_s + npl + 5)
+
+
 def foe(plan: Plan, s_val, h_val, npl, delta, n_occ, eps_min=0.0, eps_max=0.0, k_val=None,
-        scratch=None):
+        scratch=None, keep=True):
     """wvl_foe: density kernel K on the overlap pattern by the Fermi operator
     expansion; returns (k_val, mu, e_bs).  s_val / h_val: float64 device
-    values on the S / H patterns.  eps_min >= eps_max: Gershgorin bounds."""
+    values on the S / H patterns.  eps_min >= eps_max: Gershgorin bounds.
+    Without a scratch buffer, one of foe_scratch_bytes(plan, npl, keep) is
+    allocated; the library keeps the Chebyshev matrices when the buffer has
+    room for them."""
     import torch
     _need_cuda(s_val, h_val, k_val, scratch)
     nnz_s, nnz_h = sparse_pattern_nnz(plan, False), sparse_pattern_nnz(plan, True)
@@ -465,15 +477,14 @@ def foe(plan: Plan, s_val, h_val, npl, delta, n_occ, eps_min=0.0, eps_max=0.0, k
         raise WvlError(WVL_EINVAL, "s_val / h_val must be float64 on the S / H patterns")
     if k_val is None:
         k_val = torch.empty(max(1, nnz_s), dtype=torch.float64, device="cuda")
-    need = 8 * (13 * nnz_s + int(npl) + 5)
     if scratch is None:
-        scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
-    elif scratch.numel() * scratch.element_size() < need:
-        raise WvlError(WVL_EINVAL, "scratch smaller than wvl_foe needs")
+        scratch = torch.empty(foe_scratch_bytes(plan, npl, keep), dtype=torch.uint8,
+                              device="cuda")
     mu, ebs = ctypes.c_double(0.0), ctypes.c_double(0.0)
     _check(lib().wvl_foe(plan._ptr, _ptr(s_val), _ptr(h_val), int(npl), float(delta),
                          float(n_occ), float(eps_min), float(eps_max), _ptr(k_val),
-                         ctypes.byref(mu), ctypes.byref(ebs), _ptr(scratch)), plan.ctx.handle)
+                         ctypes.byref(mu), ctypes.byref(ebs), _ptr(scratch),
+                         scratch.numel() * scratch.element_size()), plan.ctx.handle)
     return k_val, mu.value, ebs.value
 
 

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "wvl_internal.h"
@@ -131,6 +132,7 @@ struct PatternCache {
   int64_t* d_hpos = nullptr;
   int64_t* d_htpos = nullptr;
   int64_t* d_dpos = nullptr;    // diagonal entry of every row
+  int maxdeg = 0;               // longest row
 };
 
 // 3D Morton code of a non-negative grid point (10 bits per axis)
@@ -172,6 +174,55 @@ struct wvl_graph {
   std::vector<hipEvent_t> events;   // fork/join events of the capture, kept with the graph
 };
 
+// Chebyshev coefficients c_0..c_npl on [-1, 1] of
+// f(x) = erfc((x / sigma + tau - mu) / delta) / 2, by the defining integral
+// c_i = (2 / pi) int_0^pi f(cos t) cos(i t) dt on m midpoints (exact for the
+// cosine series up to degree 2m - 1).  The node table is kept with the plan.
+struct FoeCoef {
+  int npl, m;
+  std::vector<double> x, cs;   // nodes cos t_k; cos(i t_k), [k][i]
+  explicit FoeCoef(int npl_) : npl(npl_), m(std::max(8 * npl_, 2048)) {
+    const double pi = 3.14159265358979323846;
+    x.resize(m);
+    cs.resize((size_t)m * (npl + 1));
+    for (int k = 0; k < m; ++k) {
+      const double t = pi * (k + 0.5) / m;
+      x[k] = std::cos(t);
+      for (int i = 0; i <= npl; ++i) cs[(size_t)k * (npl + 1) + i] = std::cos(i * t);
+    }
+  }
+  double f(int k, double sigma, double tau, double mu, double delta) const {
+    return 0.5 * std::erfc((x[k] / sigma + tau - mu) / delta);
+  }
+  void operator()(double sigma, double tau, double mu, double delta,
+                  std::vector<double>* c) const {
+    c->assign(npl + 1, 0.0);
+    for (int k = 0; k < m; ++k) {
+      const double fk = f(k, sigma, tau, mu, delta);
+      const double* row = &cs[(size_t)k * (npl + 1)];
+      for (int i = 0; i <= npl; ++i) (*c)[i] += fk * row[i];
+    }
+    for (int i = 0; i <= npl; ++i) (*c)[i] *= 2.0 / m;
+  }
+  // c_0 / 2 tr_0 + sum_i c_i tr_i = (2 / m) sum_k f(x_k) g_k with
+  // g_k = tr_0 / 2 + sum_i cos(i t_k) tr_i: the node weights of the traces
+  void weights(const std::vector<double>& tr, std::vector<double>* g) const {
+    g->resize(m);
+    for (int k = 0; k < m; ++k) {
+      const double* row = &cs[(size_t)k * (npl + 1)];
+      double v = 0.5 * row[0] * tr[0];
+      for (int i = 1; i <= npl; ++i) v += row[i] * tr[i];
+      (*g)[k] = v;
+    }
+  }
+  double trace(const std::vector<double>& g, double sigma, double tau, double mu,
+               double delta) const {
+    double v = 0.0;
+    for (int k = 0; k < m; ++k) v += f(k, sigma, tau, mu, delta) * g[k];
+    return v * (2.0 / m);
+  }
+};
+
 struct wvl_plan {
   wvl_ctx* ctx = nullptr;
   int nsf = 0;
@@ -196,6 +247,7 @@ struct wvl_plan {
   int32_t* d_csf = nullptr;
   wvl_plan_info info{};
   PatternCache pat[2];
+  std::unique_ptr<FoeCoef> foe_coef;  // Chebyshev node table of the last wvl_foe degree
 };
 
 namespace {
@@ -1355,6 +1407,13 @@ static wvl_status ensure_foe_maps(wvl_plan* P) {
     return (it != e && *it == j) ? (int64_t)(it - cl.begin()) : -1;
   };
   std::vector<int64_t> tpos(S.nnz), hpos(S.nnz), htpos(S.nnz), dpos(n);
+  int maxdeg = 0;
+  for (int i = 0; i < n; ++i) maxdeg = std::max(maxdeg, (int)(srp[i + 1] - srp[i]));
+  if (maxdeg > kFoeMaxDeg || S.nnz > INT32_MAX || n > kFoeMaxCol)
+    return fail(ctx, WVL_EUNSUPPORTED,
+                "wvl_foe: overlap pattern with %d entries in a row (at most %d), %lld in all or "
+                "%d rows (at most %d)",
+                maxdeg, kFoeMaxDeg, (long long)S.nnz, n, kFoeMaxCol);
   for (int i = 0; i < n; ++i) {
     dpos[i] = find(srp, scol, i, i);
     if (dpos[i] < 0)
@@ -1378,40 +1437,20 @@ static wvl_status ensure_foe_maps(wvl_plan* P) {
       (st = upload(ctx, &S.d_dpos, dpos.data(), sizeof(int64_t) * dpos.size())) != WVL_OK)
     return st;
   WVL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  S.maxdeg = maxdeg;
   return WVL_OK;
 }
 
-// Chebyshev coefficients c_0..c_npl on [-1, 1] of
-// f(x) = erfc((x / sigma + tau - mu) / delta) / 2, by the defining integral
-// c_i = (2 / pi) int_0^pi f(cos t) cos(i t) dt on m midpoints (exact for the
-// cosine series up to degree 2m - 1)
-struct FoeCoef {
-  int npl, m;
-  std::vector<double> x, cs;   // nodes cos t_k; cos(i t_k), [k][i]
-  explicit FoeCoef(int npl_) : npl(npl_), m(std::max(8 * npl_, 2048)) {
-    const double pi = 3.14159265358979323846;
-    x.resize(m);
-    cs.resize((size_t)m * (npl + 1));
-    for (int k = 0; k < m; ++k) {
-      const double t = pi * (k + 0.5) / m;
-      x[k] = std::cos(t);
-      for (int i = 0; i <= npl; ++i) cs[(size_t)k * (npl + 1) + i] = std::cos(i * t);
-    }
-  }
-  void operator()(double sigma, double tau, double mu, double delta, std::vector<double>* c) {
-    c->assign(npl + 1, 0.0);
-    for (int k = 0; k < m; ++k) {
-      const double f = 0.5 * std::erfc((x[k] / sigma + tau - mu) / delta);
-      const double* row = &cs[(size_t)k * (npl + 1)];
-      for (int i = 0; i <= npl; ++i) (*c)[i] += f * row[i];
-    }
-    for (int i = 0; i <= npl; ++i) (*c)[i] *= 2.0 / m;
-  }
-};
+// wvl_foe scratch: 9 matrices on P (or 7 + npl with every T^i kept), the
+// traces, four reduction slots (and the coefficients)
+static size_t foe_scratch_bytes(int64_t nnz, int npl, bool keep) {
+  return keep ? 8 * ((size_t)(npl + 7) * nnz + 2 * (size_t)npl + 6)
+              : 8 * ((size_t)9 * nnz + (size_t)npl + 5);
+}
 
 wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_t npl,
                    double delta, double n_occ, double eps_min, double eps_max, double* k_val,
-                   double* mu_out, double* e_bs_out, void* scratch) {
+                   double* mu_out, double* e_bs_out, void* scratch, size_t scratch_bytes) {
   if (!P) return fail(nullptr, WVL_EINVAL, "wvl_foe: null plan");
   wvl_ctx* ctx = P->ctx;
   const int n = P->nsf;
@@ -1428,25 +1467,33 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
     return st;
   const PatternCache& pc = P->pat[0];
   const int64_t nnz = pc.nnz;
+  if (scratch_bytes < foe_scratch_bytes(nnz, npl, false))
+    return fail(ctx, WVL_EINVAL, "wvl_foe: scratch of %zu bytes, at least %zu needed",
+                scratch_bytes, foe_scratch_bytes(nnz, npl, false));
+  // with room for every T^i, pass 2 sums the kept matrices instead of
+  // running the recursion again
+  const bool keep = scratch_bytes >= foe_scratch_bytes(nnz, npl, true);
   hipStream_t s = ctx->stream;
   const int64_t* rp = pc.d_rowptr;
   const int32_t* cl = pc.d_col;
   const int32_t* rw = pc.d_row;
   const int64_t* tp = pc.d_tpos;
   double* w = (double*)scratch;
-  // matrices on P; Tt[] and Kpt hold the transposes (right operands of the
-  // products are read transposed)
+  // matrices on P: six, then T^0 .. T^npl (kept) or three T^i in turn; the
+  // traces, four reduction slots, the coefficients (kept)
   double *Ss = w, *Sh = w + nnz, *Hs = w + 2 * nnz, *X = w + 3 * nnz, *Ht = w + 4 * nnz;
-  double* T[3] = {w + 5 * nnz, w + 6 * nnz, w + 7 * nnz};
-  double* Kp = w + 8 * nnz;
-  double* Tt[3] = {w + 9 * nnz, w + 10 * nnz, w + 11 * nnz};
-  double* Kpt = w + 12 * nnz;
-  double* tr = w + 13 * nnz;
+  double* Kp = w + 5 * nnz;
+  double* Tall = w + 6 * nnz;
+  double* tr = w + (keep ? npl + 7 : 9) * nnz;
   double* red = tr + npl + 1;
-  // C = al A B (+ be D), B given transposed; Ct: C transposed as well
-  auto mm = [&](double al, const double* A, const double* Bt, double be, const double* D,
-                double* C, double* Ct) {
-    return launch_foe_mm(s, rp, cl, rw, tp, nnz, al, A, Bt, be, D, C, Ct);
+  double* cf = red + 4;
+  auto Tm = [&](int i) { return Tall + (keep ? i : i % 3) * nnz; };
+  int lognb = 5;
+  while ((1 << lognb) < 2 * pc.maxdeg) ++lognb;
+  // C = al (A B)|_P (+ be D)
+  auto mm = [&](double al, const double* A, const double* B, double be, const double* D,
+                double* C) {
+    return launch_foe_mm(s, n, rp, cl, al, A, B, be, D, C, lognb, pc.maxdeg);
   };
   auto axpby = [&](double a, const double* x, double b, const double* y, double d, double* o) {
     return launch_foe_axpby(s, nnz, a, x, b, y, rw, cl, d, o);
@@ -1461,9 +1508,9 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   // spectral bounds: Gershgorin discs of S^-1/2 H S^-1/2 unless given
   // (Sh and Hs are symmetric: they are their own transposes)
   if (eps_min >= eps_max) {
-    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X, nullptr));
-    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0], nullptr));
-    WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], Ht));
+    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
+    WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, Tm(0)));
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, Tm(0), Ht));
     WVL_LAUNCH(ctx, KK_FOE, launch_foe_gersh(s, n, rp, cl, Ht, red));
     double b[2];
     WVL_HIP(ctx, hipMemcpyAsync(b, red, sizeof b, hipMemcpyDeviceToHost, s));
@@ -1475,43 +1522,40 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   const double sigma = 2.0 / (eps_max - eps_min), tau = 0.5 * (eps_min + eps_max);
   // H~ = sigma (H - tau S), then H~' = S^-1/2 H~ S^-1/2 (symmetric part)
   WVL_LAUNCH(ctx, KK_FOE, axpby(sigma, Hs, -sigma * tau, Ss, 0.0, Hs));
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X, nullptr));
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0], nullptr));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], Ht));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, Tm(0)));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, Tm(0), Ht));
   // pass 1: traces of the Chebyshev matrices T^0 .. T^npl
   auto start = [&]() -> wvl_status {
-    WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, T[0]));
-    WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, Tt[0]));
-    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, T[1]));
-    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, Tt[1]));
+    WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, Tm(0)));
+    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Ht, 0.0, nullptr, 0.0, Tm(1)));
     return WVL_OK;
   };
+  auto trace = [&](int i) { return launch_foe_trace(s, n, pc.d_dpos, Tm(i), 0, 1, tr, i); };
   if ((st = start()) != WVL_OK) return st;
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_trace(s, n, pc.d_dpos, T[0], tr, 0));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_trace(s, n, pc.d_dpos, T[1], tr, 1));
-  int a = 0, b = 1, c = 2;
-  for (int j = 1; j < npl; ++j) {
-    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, Tt[b], -1.0, T[a], T[c], Tt[c]));
-    WVL_LAUNCH(ctx, KK_FOE, launch_foe_trace(s, n, pc.d_dpos, T[c], tr, j + 1));
-    const int t = a;
-    a = b;
-    b = c;
-    c = t;
+  if (!keep) {
+    WVL_LAUNCH(ctx, KK_FOE, trace(0));
+    WVL_LAUNCH(ctx, KK_FOE, trace(1));
   }
+  for (int j = 1; j < npl; ++j) {
+    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, Tm(j), -1.0, Tm(j - 1), Tm(j + 1)));
+    if (!keep) WVL_LAUNCH(ctx, KK_FOE, trace(j + 1));
+  }
+  if (keep) WVL_LAUNCH(ctx, KK_FOE, launch_foe_trace(s, n, pc.d_dpos, Tall, nnz, npl + 1, tr, 0));
   std::vector<double> trh(npl + 1);
   WVL_HIP(ctx, hipMemcpyAsync(trh.data(), tr, sizeof(double) * (npl + 1), hipMemcpyDeviceToHost,
                               s));
   WVL_HIP(ctx, hipStreamSynchronize(s));
   // chemical potential: Tr K'(mu) = c_0/2 Tr T^0 + sum_i c_i Tr T^i = n_occ,
   // increasing in mu; bisection
-  std::vector<double> coef;
-  FoeCoef coefficients(npl);
-  auto trace_at = [&](double mu) {
-    coefficients(sigma, tau, mu, delta, &coef);
-    double v = 0.5 * coef[0] * trh[0];
-    for (int i = 1; i <= npl; ++i) v += coef[i] * trh[i];
-    return v;
-  };
+  if (!P->foe_coef || P->foe_coef->npl != npl) {
+    P->foe_coef.reset(new (std::nothrow) FoeCoef(npl));
+    if (!P->foe_coef) return fail(ctx, WVL_ENOMEM, "wvl_foe: host allocation failed");
+  }
+  const FoeCoef& coefficients = *P->foe_coef;
+  std::vector<double> coef, g;
+  coefficients.weights(trh, &g);
+  auto trace_at = [&](double mu) { return coefficients.trace(g, sigma, tau, mu, delta); };
   double lo = eps_min - 20.0 * delta, hi = eps_max + 20.0 * delta;
   for (int it = 0; it < 200 && hi - lo > 1e-13 * std::max(1.0, std::fabs(lo) + std::fabs(hi));
        ++it) {
@@ -1523,26 +1567,23 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   }
   const double mu = 0.5 * (lo + hi);
   coefficients(sigma, tau, mu, delta, &coef);
-  // pass 2: K' = c_0/2 I + sum_i c_i T^i(H~'), and its transpose
-  WVL_LAUNCH(ctx, KK_FOE, axpby(coef[1], Ht, 0.0, nullptr, 0.5 * coef[0], Kp));
-  WVL_LAUNCH(ctx, KK_FOE, axpby(coef[1], Ht, 0.0, nullptr, 0.5 * coef[0], Kpt));
-  if ((st = start()) != WVL_OK) return st;
-  a = 0;
-  b = 1;
-  c = 2;
-  for (int j = 1; j < npl; ++j) {
-    WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, Tt[b], -1.0, T[a], T[c], Tt[c]));
-    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Kp, coef[j + 1], T[c], 0.0, Kp));
-    WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Kpt, coef[j + 1], Tt[c], 0.0, Kpt));
-    const int t = a;
-    a = b;
-    b = c;
-    c = t;
+  // pass 2: K' = c_0/2 I + sum_i c_i T^i(H~')
+  if (keep) {
+    WVL_HIP(ctx, hipMemcpyAsync(cf, coef.data(), sizeof(double) * (npl + 1),
+                                hipMemcpyHostToDevice, s));
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_series(s, nnz, npl, cf, Tall, rw, cl, Kp));
+  } else {
+    WVL_LAUNCH(ctx, KK_FOE, axpby(coef[1], Ht, 0.0, nullptr, 0.5 * coef[0], Kp));
+    if ((st = start()) != WVL_OK) return st;
+    for (int j = 1; j < npl; ++j) {
+      WVL_LAUNCH(ctx, KK_FOE_MM, mm(2.0, Ht, Tm(j), -1.0, Tm(j - 1), Tm(j + 1)));
+      WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Kp, coef[j + 1], Tm(j + 1), 0.0, Kp));
+    }
   }
   // K = S^-1/2 K' S^-1/2 (symmetric part); E_BS = Tr(K H~) / sigma + tau Tr(K S)
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Kpt, 0.0, nullptr, X, nullptr));
-  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, T[0], nullptr));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, T[0], k_val));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Kp, 0.0, nullptr, X));
+  WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, Tm(0)));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, Tm(0), k_val));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Hs, red, 2));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Ss, red, 3));
   double e2[2];

@@ -131,11 +131,16 @@ int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const doub
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
 // Fermi operator expansion on a symmetric CSR pattern (row: row of each
-// entry, tpos: position of the transposed entry).  foe_mm takes its right
-// operand transposed (Bt) and can write its result transposed too (Ct).
-int launch_foe_mm(void* stream, const int64_t* rowptr, const int32_t* col, const int32_t* row,
-                  const int64_t* tpos, int64_t nnz, double alpha, const double* A,
-                  const double* Bt, double beta, const double* D, double* C, double* Ct);
+// entry, tpos: position of the transposed entry).  foe_mm: one workgroup per
+// row, 8 waves for rows of at most kFoeMaxDeg / 2 entries, else 2; rows of
+// at most kFoeMaxDeg entries, columns below kFoeMaxCol, entries addressed
+// with 32-bit offsets; 2^lognb hash buckets of 16 bytes, at least twice the
+// longest row (maxdeg) and at least 32 (at most 64 KiB of LDS in all).
+constexpr int kFoeMaxDeg = 1024;
+constexpr int kFoeMaxCol = 1 << 21;
+int launch_foe_mm(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
+                  double alpha, const double* A, const double* B, double beta, const double* D,
+                  double* C, int lognb, int maxdeg);
 int launch_foe_axpby(void* stream, int64_t nnz, double a, const double* X, double b,
                      const double* Y, const int32_t* row, const int32_t* col, double d,
                      double* out);
@@ -144,8 +149,10 @@ int launch_foe_gather(void* stream, int64_t nnz, const int64_t* qpos, const doub
                       double* out);
 int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, double* out,
                    int slot);
-int launch_foe_trace(void* stream, int n, const int64_t* dpos, const double* X, double* out,
-                     int slot);
+int launch_foe_trace(void* stream, int n, const int64_t* dpos, const double* X, int64_t stride,
+                     int count, double* out, int slot);
+int launch_foe_series(void* stream, int64_t nnz, int npl, const double* c, const double* T,
+                      const int32_t* row, const int32_t* col, double* out);
 int launch_foe_gersh(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
                      const double* X, double* out);
 int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,

@@ -440,44 +440,176 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
 // columns, diagonal present), values in double
 // ---------------------------------------------------------------------------
 
-// C = alpha (A B)|_P + beta D, one thread per entry (i, j) of P:
-// (A B)_ij = sum_k A_ik B_kj over the k in both row i and row j of P, summed
-// in increasing k.  The pattern is symmetric, and B comes transposed (Bt:
-// B_kj stored at the position of (j, k)), so both operands are read along
-// rows.  D may be NULL (beta ignored); when Ct is given, C is also written
-// transposed (Ct at the position of (j, i)).
-__global__ __launch_bounds__(TPB) void k_foe_mm(const int64_t* __restrict__ rowptr,
-                                                const int32_t* __restrict__ col,
-                                                const int32_t* __restrict__ row,
-                                                const int64_t* __restrict__ tpos, int64_t nnz,
-                                                double alpha, const double* __restrict__ A,
-                                                const double* __restrict__ Bt, double beta,
-                                                const double* __restrict__ D,
-                                                double* __restrict__ C, double* __restrict__ Ct) {
-  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (p >= nnz) return;
-  const int i = row[p], j = col[p];
-  int64_t qa = rowptr[i], qb = rowptr[j];
-  const int64_t ea = rowptr[i + 1], eb = rowptr[j + 1];
-  double acc = 0.0;
-  while (qa < ea && qb < eb) {
-    const int ka = col[qa], kb = col[qb];
-    if (ka < kb) {
-      ++qa;
-    } else if (kb < ka) {
-      ++qb;
-    } else {
-      acc += A[qa] * Bt[qb];
-      ++qa;
-      ++qb;
+// C = alpha (A B)|_P + beta D, one workgroup of W waves per row i of P.
+// Row i's columns go into an LDS hash table of 2^lognb buckets of four
+// 32-bit slots, each slot (column << 10 | position in the row); a bucket
+// fills from its first slot, and a full one spills into the next.  Wave w
+// takes the k of row i with index t = w, w + W, .. in increasing order; its
+// lanes walk row k of B, 256 entries at a time, and add A_ik B_kj to the
+// wave's own accumulator of j when j is in row i.  The next batch of B is
+// loaded while the current one is added.  The waves' accumulators are summed
+// in wave order at the end, so every entry's sum has a fixed order.  D may be
+// NULL (beta ignored).  Needs columns below 2^21 and rows of at most 1024
+// entries; LDS: W + 2 doubles per row entry (maxdeg) and 16 bytes per
+// bucket.
+constexpr uint32_t kFoeEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int foe_bucket(int j, int lognb) {
+  return (int)(((uint32_t)j * 2654435761u) >> (32 - lognb));
+}
+
+// position of column j in a bucket, or -1
+__device__ __forceinline__ int foe_match(uint4 v, int j) {
+  const uint32_t uj = (uint32_t)j;
+  int p = -1;
+  if ((v.x >> 10) == uj) p = (int)(v.x & 1023u);
+  if ((v.y >> 10) == uj) p = (int)(v.y & 1023u);
+  if ((v.z >> 10) == uj) p = (int)(v.z & 1023u);
+  if ((v.w >> 10) == uj) p = (int)(v.w & 1023u);
+  return p;
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_foe_mm(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, double alpha,
+    const double* __restrict__ A, const double* __restrict__ B, double beta,
+    const double* __restrict__ D, double* __restrict__ C, int lognb, int maxdeg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);   // [W][maxdeg]
+  double* av = acc + (size_t)W * maxdeg;                // A_ik, [maxdeg]
+  int* kst = reinterpret_cast<int*>(av + maxdeg);       // start of row k in B
+  int* kdg = kst + maxdeg;                              // length of row k
+  uint4* bucket = reinterpret_cast<uint4*>(kdg + maxdeg);   // [nb]
+  uint32_t* slot = reinterpret_cast<uint32_t*>(bucket);
+  constexpr int nt = 64 * W;
+  const int nb = 1 << lognb;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t r0 = rowptr[blockIdx.x];
+  const int deg = (int)(rowptr[blockIdx.x + 1] - r0);
+  for (int h = tid; h < 4 * nb; h += nt) slot[h] = kFoeEmpty;
+  for (int p = tid; p < deg; p += nt) {
+    const int k = col[r0 + p];
+    const int64_t k0 = rowptr[k];
+    kst[p] = (int)k0;
+    kdg[p] = (int)(rowptr[k + 1] - k0);
+    av[p] = A[r0 + p];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[(size_t)w * maxdeg + p] = 0.0;
+  }
+  __syncthreads();
+  // 4 nb slots > deg: every insertion finds a free slot
+  for (int p = tid; p < deg; p += nt) {
+    const int j = col[r0 + p];
+    const uint32_t key = ((uint32_t)j << 10) | (uint32_t)p;
+    for (int b = foe_bucket(j, lognb);; b = (b + 1) & (nb - 1)) {
+      int c = 0;
+      while (c < 4 && atomicCAS(&slot[4 * b + c], kFoeEmpty, key) != kFoeEmpty) ++c;
+      if (c < 4) break;
     }
   }
-  const double c = D ? alpha * acc + beta * D[p] : alpha * acc;
-  C[p] = c;
-  if (Ct) Ct[tpos[p]] = c;
+  __syncthreads();
+  double* my = acc + (size_t)wave * maxdeg;
+  // entries q0 + lane, q0 + 64 + lane, .. of row k (column -1: none)
+  auto load = [&](int k0, int kd, int q0, int (&jj)[4], double (&bb)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + 64 * u + lane;
+      jj[u] = q < kd ? col[k0 + q] : -1;
+      bb[u] = q < kd ? B[k0 + q] : 0.0;
+    }
+  };
+  // the four lookups, the four accumulator reads and the four writes are
+  // issued together: the columns of one row of B are distinct, so are the
+  // positions they hit
+  auto add = [&](const int (&jj)[4], const double (&bb)[4], double a) {
+    int b[4];
+    uint4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      b[u] = foe_bucket(jj[u], lognb);
+      v[u] = bucket[b[u]];
+    }
+    int p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      p[u] = foe_match(v[u], jj[u]);
+      while (p[u] < 0 && jj[u] >= 0 && v[u].w != kFoeEmpty) {
+        b[u] = (b[u] + 1) & (nb - 1);
+        v[u] = bucket[b[u]];
+        p[u] = foe_match(v[u], jj[u]);
+      }
+    }
+    double o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o[u] = my[p[u] >= 0 ? p[u] : 0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (p[u] >= 0) my[p[u]] = o[u] + a * bb[u];
+  };
+  int t = wave;
+  int k0 = 0, kd = 0;
+  double a = 0.0;
+  int jj[4];
+  double bb[4];
+  if (t < deg) {
+    k0 = kst[t];
+    kd = kdg[t];
+    a = av[t];
+    load(k0, kd, 0, jj, bb);
+  }
+  while (t < deg) {
+    const int tn = t + W;
+    int k0n = 0, kdn = 0;
+    double an = 0.0;
+    if (tn < deg) {
+      k0n = kst[tn];
+      kdn = kdg[tn];
+      an = av[tn];
+    }
+    for (int q0 = 0;; q0 += 256) {
+      const bool more = q0 + 256 < kd;
+      int jn[4];
+      double bn[4];
+      if (more)
+        load(k0, kd, q0 + 256, jn, bn);
+      else
+        load(k0n, kdn, 0, jn, bn);
+      add(jj, bb, a);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        jj[u] = jn[u];
+        bb[u] = bn[u];
+      }
+      if (!more) break;
+    }
+    t = tn;
+    k0 = k0n;
+    kd = kdn;
+    a = an;
+  }
+  __syncthreads();
+  for (int p = tid; p < deg; p += nt) {
+    double v = acc[p];
+#pragma unroll
+    for (int w = 1; w < W; ++w) v += acc[(size_t)w * maxdeg + p];
+    C[r0 + p] = D ? alpha * v + beta * D[r0 + p] : alpha * v;
+  }
 }
 
 // elementwise on P: out = a X + b Y (+ d on the diagonal when diag != NULL)
+// v = a x + b y (+ d on the diagonal), each term only when present; the one
+// expression both k_foe_axpby and k_foe_series evaluate
+__device__ __forceinline__ double foe_lin(bool hx, double a, double x, bool hy, double b,
+                                          double y, bool diag, double d) {
+  double v = 0.0;
+  if (hx) v += a * x;
+  if (hy) v += b * y;
+  if (diag) v += d;
+  return v;
+}
+
 __global__ __launch_bounds__(TPB) void k_foe_axpby(int64_t nnz, double a,
                                                    const double* __restrict__ X, double b,
                                                    const double* __restrict__ Y,
@@ -486,10 +618,26 @@ __global__ __launch_bounds__(TPB) void k_foe_axpby(int64_t nnz, double a,
                                                    double* __restrict__ out) {
   const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (p >= nnz) return;
-  double v = 0.0;
-  if (X) v += a * X[p];
-  if (Y) v += b * Y[p];
-  if (row && row[p] == col[p]) v += d;
+  out[p] = foe_lin(X != nullptr, a, X ? X[p] : 0.0, Y != nullptr, b, Y ? Y[p] : 0.0,
+                   row && row[p] == col[p], d);
+}
+
+// the Chebyshev series on P from the kept matrices T^0 .. T^npl (T^j at
+// T + j nnz): out = c_0 / 2 I + c_1 T^1, then out += c_j T^j for j = 2 ..
+// npl, term by term as k_foe_axpby adds them when the matrices are
+// recomputed (same values, bit for bit)
+__global__ __launch_bounds__(TPB) void k_foe_series(int64_t nnz, int npl,
+                                                    const double* __restrict__ c,
+                                                    const double* __restrict__ T,
+                                                    const int32_t* __restrict__ row,
+                                                    const int32_t* __restrict__ col,
+                                                    double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (p >= nnz) return;
+  const bool diag = row[p] == col[p];
+  double v = foe_lin(true, c[1], T[nnz + p], false, 0.0, 0.0, diag, 0.5 * c[0]);
+  for (int j = 2; j <= npl; ++j)
+    v = foe_lin(true, 1.0, v, true, c[j], T[(int64_t)j * nnz + p], diag, 0.0);
   out[p] = v;
 }
 
@@ -521,15 +669,16 @@ __global__ __launch_bounds__(TPB) void k_foe_dot(int64_t nnz, const double* __re
   if (threadIdx.x == 0) out[slot] = s;
 }
 
-// one block: out[slot] = trace of X, its diagonal entries at dpos[0..n), in
-// a fixed order
+// block b: out[slot + b] = trace of X + b stride, its diagonal entries at
+// dpos[0..n), in a fixed order
 __global__ __launch_bounds__(TPB) void k_foe_trace(int n, const int64_t* __restrict__ dpos,
-                                                   const double* __restrict__ X,
+                                                   const double* __restrict__ X, int64_t stride,
                                                    double* __restrict__ out, int slot) {
+  const double* Xb = X + (int64_t)blockIdx.x * stride;
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += TPB) v += X[dpos[i]];
+  for (int i = threadIdx.x; i < n; i += TPB) v += Xb[dpos[i]];
   const double s = block_sum(v);
-  if (threadIdx.x == 0) out[slot] = s;
+  if (threadIdx.x == 0) out[slot + blockIdx.x] = s;
 }
 
 // one block: Gershgorin bounds of X (min_i X_ii - r_i, max_i X_ii + r_i with
@@ -845,12 +994,18 @@ int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff
 
 static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + TPB - 1) / TPB)); }
 
-int launch_foe_mm(void* stream, const int64_t* rowptr, const int32_t* col, const int32_t* row,
-                  const int64_t* tpos, int64_t nnz, double alpha, const double* A,
-                  const double* Bt, double beta, const double* D, double* C, double* Ct) {
-  if (nnz == 0) return 0;
-  hipLaunchKernelGGL(k_foe_mm, grid1(nnz), dim3(TPB), 0, (hipStream_t)stream, rowptr, col, row,
-                     tpos, nnz, alpha, A, Bt, beta, D, C, Ct);
+int launch_foe_mm(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
+                  double alpha, const double* A, const double* B, double beta, const double* D,
+                  double* C, int lognb, int maxdeg) {
+  if (nrow == 0) return 0;
+  const int w = maxdeg <= kFoeMaxDeg / 2 ? 8 : 2;
+  const size_t lds = (size_t)maxdeg * 8 * (w + 2) + ((size_t)16 << lognb);
+  if (w == 8)
+    hipLaunchKernelGGL(k_foe_mm<8>, dim3((unsigned)nrow), dim3(64 * 8), lds, (hipStream_t)stream,
+                       rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
+  else
+    hipLaunchKernelGGL(k_foe_mm<2>, dim3((unsigned)nrow), dim3(64 * 2), lds, (hipStream_t)stream,
+                       rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
   return (int)hipGetLastError();
 }
 
@@ -883,10 +1038,19 @@ int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, 
   return (int)hipGetLastError();
 }
 
-int launch_foe_trace(void* stream, int n, const int64_t* dpos, const double* X, double* out,
-                     int slot) {
-  hipLaunchKernelGGL(k_foe_trace, dim3(1), dim3(TPB), 0, (hipStream_t)stream, n, dpos, X, out,
-                     slot);
+int launch_foe_trace(void* stream, int n, const int64_t* dpos, const double* X, int64_t stride,
+                     int count, double* out, int slot) {
+  if (count == 0) return 0;
+  hipLaunchKernelGGL(k_foe_trace, dim3((unsigned)count), dim3(TPB), 0, (hipStream_t)stream, n,
+                     dpos, X, stride, out, slot);
+  return (int)hipGetLastError();
+}
+
+int launch_foe_series(void* stream, int64_t nnz, int npl, const double* c, const double* T,
+                      const int32_t* row, const int32_t* col, double* out) {
+  if (nnz == 0) return 0;
+  hipLaunchKernelGGL(k_foe_series, grid1(nnz), dim3(TPB), 0, (hipStream_t)stream, nnz, npl, c, T,
+                     row, col, out);
   return (int)hipGetLastError();
 }
 

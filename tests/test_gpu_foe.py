@@ -8,7 +8,9 @@ import numpy as np
 import pytest
 
 from oracle import foe as F
+from oracle import locreg as LR
 from oracle import sparse as SP
+from tests.abi_helpers import to_abi
 from tests.test_gpu_parity import _print, _sphere_case
 
 torch = pytest.importorskip("torch")
@@ -60,10 +62,68 @@ def test_foe_against_oracle(system, bounds):
     assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want))
     assert abs(gmu - mu) <= 1e-9
     assert abs(gebs - ebs) <= 1e-9 * max(1.0, abs(ebs))
-    # bitwise reproducible
-    kv2, mu2, ebs2 = W.foe(plan, torch.tensor(sv, device="cuda"), torch.tensor(hv, device="cuda"),
-                           npl, delta, nocc, emin or 0.0, emax or 0.0)
-    assert np.array_equal(kv2.cpu().numpy(), got) and mu2 == gmu and ebs2 == gebs
+    # bitwise reproducible, and the same bits when the Chebyshev matrices are
+    # formed twice (smaller scratch) instead of kept
+    for keep in (True, False):
+        kv2, mu2, ebs2 = W.foe(plan, torch.tensor(sv, device="cuda"),
+                               torch.tensor(hv, device="cuda"), npl, delta, nocc, emin or 0.0,
+                               emax or 0.0, keep=keep)
+        assert np.array_equal(kv2.cpu().numpy(), got) and mu2 == gmu and ebs2 == gebs, keep
+
+
+def _cluster_plan(m):
+    """Three clusters of m identical boxes (11 x 7 x 7 coarse points, output =
+    input) at x = 0, 8 and 16: boxes of clusters c and c' share points iff
+    |c - c'| <= 1, so the overlap pattern is known in closed form.  Rows of
+    the outer clusters miss the columns of the far cluster that rows of the
+    middle one hold."""
+    lrs = []
+    for c in range(3):
+        for _ in range(m):
+            lrs.append(LR.box_locreg((8 * c, 0, 0), (11, 7, 7), (8 * c + 3, 2, 2),
+                                     (8 * c + 6, 4, 4)))
+    ctx = W.Context(0.45, (32, 16, 16))
+    rec, segs = to_abi(lrs)
+    plan = W.Plan(ctx, rec, segs)
+    cl = np.repeat(np.arange(3), m)
+    mask = np.abs(cl[:, None] - cl[None, :]) <= 1
+    return ctx, plan, mask
+
+
+@pytest.mark.parametrize("m", [150, 250])
+def test_foe_on_long_rows(m):
+    """Rows of 300 / 450 entries (m = 150: eight waves per row) and 500 / 750
+    (m = 250: two waves per row), each longer than one 256-entry batch of the
+    product kernel; seeded S = I + small symmetric part and H = spread
+    diagonal + symmetric part, on the closed-form pattern."""
+    n = 3 * m
+    _print(f"case: FOE on three clusters of {m} boxes ({n} functions)")
+    ctx, plan, mask = _cluster_plan(m)
+    zin = torch.zeros(max(1, plan.info["in_coefs"]), dtype=torch.float64, device="cuda")
+    zout = torch.zeros(max(1, plan.info["out_coefs"]), dtype=torch.float64, device="cuda")
+    rows, cols = np.nonzero(mask)
+    rp = np.concatenate([[0], np.cumsum(mask.sum(1))])
+    for ket_out in (False, True):
+        prp, pcl, _ = W.sparse_overlap(plan, zin, zout if ket_out else zin, ket_out,
+                                       values=False)
+        assert np.array_equal(prp.cpu().numpy(), rp) and np.array_equal(pcl.cpu().numpy(), cols)
+    rng = np.random.default_rng(4100 + m)
+    R1, R2 = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    S = (np.eye(n) + 0.2 / np.sqrt(n) * (R1 + R1.T)) * mask
+    H = (np.diag(np.linspace(-1.0, 1.0, n)) + 0.5 / np.sqrt(n) * (R2 + R2.T)) * mask
+    npl, delta, nocc = 40, 0.3, 0.5 * n
+    K, mu, ebs, _ = F.foe(S, H, mask, npl, delta, nocc)
+    sv = torch.tensor(S[rows, cols], device="cuda")
+    hv = torch.tensor(H[rows, cols], device="cuda")
+    want = K[rows, cols]
+    res = []
+    for keep in (True, False):
+        kv, gmu, gebs = W.foe(plan, sv, hv, npl, delta, nocc, keep=keep)
+        got = kv.cpu().numpy()
+        assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want)), keep
+        assert abs(gmu - mu) <= 1e-9 and abs(gebs - ebs) <= 1e-9 * max(1.0, abs(ebs)), keep
+        res.append((got, gmu, gebs))
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
 
 
 def test_foe_rejects_bad_parameters(system):
@@ -76,3 +136,7 @@ def test_foe_rejects_bad_parameters(system):
     for args in ((0, 0.2, 3.0), (10, 0.0, 3.0), (10, 0.2, 0.0), (10, 0.2, float(n))):
         with pytest.raises(W.WvlError):
             W.foe(plan, s, h, *args)
+    small = torch.empty(W.foe_scratch_bytes(plan, 10, keep=False) - 8, dtype=torch.uint8,
+                        device="cuda")
+    with pytest.raises(W.WvlError):
+        W.foe(plan, s, h, 10, 0.2, 3.0, scratch=small)
