@@ -132,6 +132,7 @@ struct PatternCache {
   int64_t* d_hpos = nullptr;
   int64_t* d_htpos = nullptr;
   int64_t* d_dpos = nullptr;    // diagonal entry of every row
+  int32_t* d_foe_rows = nullptr;   // rows by decreasing product work
   int maxdeg = 0;               // longest row
 };
 
@@ -666,6 +667,7 @@ static void free_pattern(PatternCache& p) {
   if (p.d_hpos) (void)hipFree(p.d_hpos);
   if (p.d_htpos) (void)hipFree(p.d_htpos);
   if (p.d_dpos) (void)hipFree(p.d_dpos);
+  if (p.d_foe_rows) (void)hipFree(p.d_foe_rows);
   p = PatternCache{};
 }
 
@@ -1383,7 +1385,7 @@ wvl_status wvl_density(wvl_plan* P, wvl_dtype dt, const void* fine, const int64_
 // their transposes') in the H pattern
 static wvl_status ensure_foe_maps(wvl_plan* P) {
   PatternCache& S = P->pat[0];
-  if (S.d_tpos) return WVL_OK;
+  if (S.maxdeg > 0) return WVL_OK;   // set once every map is on the device
   wvl_ctx* ctx = P->ctx;
   const PatternCache& Hp = P->pat[1];
   const int n = P->nsf;
@@ -1430,8 +1432,28 @@ static wvl_status ensure_foe_maps(wvl_plan* P) {
         return fail(ctx, WVL_EUNSUPPORTED,
                     "wvl_foe: overlap pattern not symmetric or not inside the H pattern");
     }
+  // product work of row i: the entries of the rows k it holds
+  std::vector<int64_t> work(n, 0);
+  std::vector<int32_t> rows(n);
+  for (int i = 0; i < n; ++i) {
+    rows[i] = i;
+    for (int64_t p = srp[i]; p < srp[i + 1]; ++p) work[i] += srp[scol[p] + 1] - srp[scol[p]];
+  }
+  std::stable_sort(rows.begin(), rows.end(),
+                   [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+  // buffers of an earlier call that failed part way
+  auto drop = [](auto*& q) {
+    if (q) (void)hipFree(q);
+    q = nullptr;
+  };
+  drop(S.d_foe_rows);
+  drop(S.d_tpos);
+  drop(S.d_hpos);
+  drop(S.d_htpos);
+  drop(S.d_dpos);
   wvl_status st;
-  if ((st = upload(ctx, &S.d_tpos, tpos.data(), sizeof(int64_t) * tpos.size())) != WVL_OK ||
+  if ((st = upload(ctx, &S.d_foe_rows, rows.data(), sizeof(int32_t) * rows.size())) != WVL_OK ||
+      (st = upload(ctx, &S.d_tpos, tpos.data(), sizeof(int64_t) * tpos.size())) != WVL_OK ||
       (st = upload(ctx, &S.d_hpos, hpos.data(), sizeof(int64_t) * hpos.size())) != WVL_OK ||
       (st = upload(ctx, &S.d_htpos, htpos.data(), sizeof(int64_t) * htpos.size())) != WVL_OK ||
       (st = upload(ctx, &S.d_dpos, dpos.data(), sizeof(int64_t) * dpos.size())) != WVL_OK)
@@ -1489,11 +1511,11 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   double* cf = red + 4;
   auto Tm = [&](int i) { return Tall + (keep ? i : i % 3) * nnz; };
   int lognb = 5;
-  while ((1 << lognb) < 2 * pc.maxdeg) ++lognb;
+  while ((1 << lognb) < pc.maxdeg) ++lognb;
   // C = al (A B)|_P (+ be D)
   auto mm = [&](double al, const double* A, const double* B, double be, const double* D,
                 double* C) {
-    return launch_foe_mm(s, n, rp, cl, al, A, B, be, D, C, lognb, pc.maxdeg);
+    return launch_foe_mm(s, n, pc.d_foe_rows, rp, cl, al, A, B, be, D, C, lognb, pc.maxdeg);
   };
   auto axpby = [&](double a, const double* x, double b, const double* y, double d, double* o) {
     return launch_foe_axpby(s, nnz, a, x, b, y, rw, cl, d, o);

@@ -132,15 +132,16 @@ int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int3
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
 // Fermi operator expansion on a symmetric CSR pattern (row: row of each
 // entry, tpos: position of the transposed entry).  foe_mm: one workgroup per
-// row, 8 waves for rows of at most kFoeMaxDeg / 2 entries, else 2; rows of
-// at most kFoeMaxDeg entries, columns below kFoeMaxCol, entries addressed
-// with 32-bit offsets; 2^lognb hash buckets of 16 bytes, at least twice the
-// longest row (maxdeg) and at least 32 (at most 64 KiB of LDS in all).
+// row, 8 waves when no row has more than kFoeMaxDeg / 2 entries, else 4;
+// rows of at most kFoeMaxDeg entries, columns below kFoeMaxCol, entries
+// addressed with 32-bit offsets; 2^lognb hash buckets of 16 bytes, at least
+// as many as the longest row has entries (maxdeg) and at least 32 (at most
+// 64 KiB of LDS in all).
 constexpr int kFoeMaxDeg = 1024;
 constexpr int kFoeMaxCol = 1 << 21;
-int launch_foe_mm(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
-                  double alpha, const double* A, const double* B, double beta, const double* D,
-                  double* C, int lognb, int maxdeg);
+int launch_foe_mm(void* stream, int nrow, const int32_t* rows, const int64_t* rowptr,
+                  const int32_t* col, double alpha, const double* A, const double* B, double beta,
+                  const double* D, double* C, int lognb, int maxdeg);
 int launch_foe_axpby(void* stream, int64_t nnz, double a, const double* X, double b,
                      const double* Y, const int32_t* row, const int32_t* col, double d,
                      double* out);

@@ -440,8 +440,8 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
 // columns, diagonal present), values in double
 // ---------------------------------------------------------------------------
 
-// C = alpha (A B)|_P + beta D, one workgroup of W waves per row i of P.
-// Row i's columns go into an LDS hash table of 2^lognb buckets of four
+// C = alpha (A B)|_P + beta D, one workgroup of W waves per row i of P,
+// rows taken in the order `rows` gives (longest work first).  Row i's columns go into an LDS hash table of 2^lognb buckets of four
 // 32-bit slots, each slot (column << 10 | position in the row); a bucket
 // fills from its first slot, and a full one spills into the next.  Wave w
 // takes the k of row i with index t = w, w + W, .. in increasing order; its
@@ -471,7 +471,8 @@ __device__ __forceinline__ int foe_match(uint4 v, int j) {
 
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_foe_mm(
-    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col, double alpha,
+    const int32_t* __restrict__ rows, const int64_t* __restrict__ rowptr,
+    const int32_t* __restrict__ col, double alpha,
     const double* __restrict__ A, const double* __restrict__ B, double beta,
     const double* __restrict__ D, double* __restrict__ C, int lognb, int maxdeg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -486,8 +487,9 @@ __global__ __launch_bounds__(64 * W) void k_foe_mm(
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t r0 = rowptr[blockIdx.x];
-  const int deg = (int)(rowptr[blockIdx.x + 1] - r0);
+  const int i = rows[blockIdx.x];
+  const int64_t r0 = rowptr[i];
+  const int deg = (int)(rowptr[i + 1] - r0);
   for (int h = tid; h < 4 * nb; h += nt) slot[h] = kFoeEmpty;
   for (int p = tid; p < deg; p += nt) {
     const int k = col[r0 + p];
@@ -499,7 +501,8 @@ __global__ __launch_bounds__(64 * W) void k_foe_mm(
     for (int w = 0; w < W; ++w) acc[(size_t)w * maxdeg + p] = 0.0;
   }
   __syncthreads();
-  // 4 nb slots > deg: every insertion finds a free slot
+  // 4 nb slots > deg: every insertion finds a free slot, every lookup a
+  // bucket that is not full
   for (int p = tid; p < deg; p += nt) {
     const int j = col[r0 + p];
     const uint32_t key = ((uint32_t)j << 10) | (uint32_t)p;
@@ -994,18 +997,18 @@ int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff
 
 static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + TPB - 1) / TPB)); }
 
-int launch_foe_mm(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
-                  double alpha, const double* A, const double* B, double beta, const double* D,
-                  double* C, int lognb, int maxdeg) {
+int launch_foe_mm(void* stream, int nrow, const int32_t* rows, const int64_t* rowptr,
+                  const int32_t* col, double alpha, const double* A, const double* B, double beta,
+                  const double* D, double* C, int lognb, int maxdeg) {
   if (nrow == 0) return 0;
-  const int w = maxdeg <= kFoeMaxDeg / 2 ? 8 : 2;
+  const int w = maxdeg <= kFoeMaxDeg / 2 ? 8 : 4;
   const size_t lds = (size_t)maxdeg * 8 * (w + 2) + ((size_t)16 << lognb);
   if (w == 8)
     hipLaunchKernelGGL(k_foe_mm<8>, dim3((unsigned)nrow), dim3(64 * 8), lds, (hipStream_t)stream,
-                       rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
+                       rows, rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
   else
-    hipLaunchKernelGGL(k_foe_mm<2>, dim3((unsigned)nrow), dim3(64 * 2), lds, (hipStream_t)stream,
-                       rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
+    hipLaunchKernelGGL(k_foe_mm<4>, dim3((unsigned)nrow), dim3(64 * 4), lds, (hipStream_t)stream,
+                       rows, rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
   return (int)hipGetLastError();
 }
 

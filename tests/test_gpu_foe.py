@@ -93,7 +93,7 @@ def _cluster_plan(m):
 @pytest.mark.parametrize("m", [150, 250])
 def test_foe_on_long_rows(m):
     """Rows of 300 / 450 entries (m = 150: eight waves per row) and 500 / 750
-    (m = 250: two waves per row), each longer than one 256-entry batch of the
+    (m = 250: four waves per row), each longer than one 256-entry batch of the
     product kernel; seeded S = I + small symmetric part and H = spread
     diagonal + symmetric part, on the closed-form pattern."""
     n = 3 * m
