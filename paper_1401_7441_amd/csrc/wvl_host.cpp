@@ -1533,7 +1533,8 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
     WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
     WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, Tm(0)));
     WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, Tm(0), Ht));
-    WVL_LAUNCH(ctx, KK_FOE, launch_foe_gersh(s, n, rp, cl, Ht, red));
+    // X and T^0 are free here, and each holds nnz >= n doubles
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_gersh(s, n, rp, cl, Ht, X, Tm(0), red));
     double b[2];
     WVL_HIP(ctx, hipMemcpyAsync(b, red, sizeof b, hipMemcpyDeviceToHost, s));
     WVL_HIP(ctx, hipStreamSynchronize(s));
@@ -1606,8 +1607,8 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Kp, 0.0, nullptr, X));
   WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, Tm(0)));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, Tm(0), k_val));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Hs, red, 2));
-  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Ss, red, 3));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Hs, X, red, 2));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_dot(s, nnz, k_val, Ss, X, red, 3));
   double e2[2];
   WVL_HIP(ctx, hipMemcpyAsync(e2, red + 2, sizeof e2, hipMemcpyDeviceToHost, s));
   WVL_HIP(ctx, hipStreamSynchronize(s));

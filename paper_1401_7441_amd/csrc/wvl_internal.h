@@ -148,14 +148,16 @@ int launch_foe_axpby(void* stream, int64_t nnz, double a, const double* X, doubl
 int launch_foe_sym(void* stream, int64_t nnz, const int64_t* tpos, const double* X, double* out);
 int launch_foe_gather(void* stream, int64_t nnz, const int64_t* qpos, const double* X,
                       double* out);
-int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, double* out,
-                   int slot);
+// dot: part needs min(256, ceil(nnz / 2048)) doubles (at most nnz)
+int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, double* part,
+                   double* out, int slot);
 int launch_foe_trace(void* stream, int n, const int64_t* dpos, const double* X, int64_t stride,
                      int count, double* out, int slot);
 int launch_foe_series(void* stream, int64_t nnz, int npl, const double* c, const double* T,
                       const int32_t* row, const int32_t* col, double* out);
+// Gershgorin bounds: lo, hi hold nrow doubles each
 int launch_foe_gersh(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
-                     const double* X, double* out);
+                     const double* X, double* lo, double* hi, double* out);
 int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                   double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
                   const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs, int mode,

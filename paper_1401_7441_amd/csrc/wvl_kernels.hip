@@ -663,11 +663,25 @@ __global__ __launch_bounds__(TPB) void k_foe_gather(int64_t nnz, const int64_t* 
 }
 
 // one block: out[slot] = sum_p X[p] Y[p] over P, in a fixed order
-__global__ __launch_bounds__(TPB) void k_foe_dot(int64_t nnz, const double* __restrict__ X,
+// block b of nblk: part[b] = sum of X[p] Y[p] over its contiguous chunk of
+// the entries; then one block: out[slot] = part[0] + .. + part[nblk - 1]
+// (both sums in fixed orders)
+__global__ __launch_bounds__(TPB) void k_foe_dot(int64_t nnz, int64_t chunk,
+                                                 const double* __restrict__ X,
                                                  const double* __restrict__ Y,
+                                                 double* __restrict__ part) {
+  const int64_t p0 = (int64_t)blockIdx.x * chunk;
+  const int64_t p1 = min(nnz, p0 + chunk);
+  double v = 0.0;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += TPB) v += X[p] * Y[p];
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(TPB) void k_foe_sum(int n, const double* __restrict__ part,
                                                  double* __restrict__ out, int slot) {
   double v = 0.0;
-  for (int64_t p = threadIdx.x; p < nnz; p += TPB) v += X[p] * Y[p];
+  for (int i = threadIdx.x; i < n; i += TPB) v += part[i];
   const double s = block_sum(v);
   if (threadIdx.x == 0) out[slot] = s;
 }
@@ -684,38 +698,58 @@ __global__ __launch_bounds__(TPB) void k_foe_trace(int n, const int64_t* __restr
   if (threadIdx.x == 0) out[slot + blockIdx.x] = s;
 }
 
-// one block: Gershgorin bounds of X (min_i X_ii - r_i, max_i X_ii + r_i with
-// r_i the absolute off-diagonal row sum), out[0], out[1]
-__global__ __launch_bounds__(TPB) void k_foe_gersh(int nrow, const int64_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col,
-                                                   const double* __restrict__ X,
+// Gershgorin discs of X: one wave per row i (four rows per block) sums
+// r_i = sum_{j != i} |X_ij| over the lanes in a fixed tree and writes
+// lo[i] = X_ii - r_i, hi[i] = X_ii + r_i
+__global__ __launch_bounds__(TPB) void k_foe_gersh_rows(int nrow,
+                                                        const int64_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ X,
+                                                        double* __restrict__ lo,
+                                                        double* __restrict__ hi) {
+  const int i = blockIdx.x * (TPB / 64) + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nrow) return;
+  double dgl = 0.0, r = 0.0;
+  for (int64_t q = rowptr[i] + lane; q < rowptr[i + 1]; q += 64) {
+    if (col[q] == i)
+      dgl = X[q];
+    else
+      r += fabs(X[q]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    r += __shfl_xor(r, o, 64);
+    dgl += __shfl_xor(dgl, o, 64);   // one lane holds the diagonal, the others 0
+  }
+  if (lane == 0) {
+    lo[i] = dgl - r;
+    hi[i] = dgl + r;
+  }
+}
+
+// one block: out[0] = min_i lo[i], out[1] = max_i hi[i]
+__global__ __launch_bounds__(TPB) void k_foe_gersh(int nrow, const double* __restrict__ lo,
+                                                   const double* __restrict__ hi,
                                                    double* __restrict__ out) {
-  __shared__ double lo[TPB], hi[TPB];
+  __shared__ double sl[TPB], sh[TPB];
   double l = 1e300, h = -1e300;
   for (int i = threadIdx.x; i < nrow; i += TPB) {
-    double dgl = 0.0, r = 0.0;
-    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-      if (col[q] == i)
-        dgl = X[q];
-      else
-        r += fabs(X[q]);
-    }
-    l = fmin(l, dgl - r);
-    h = fmax(h, dgl + r);
+    l = fmin(l, lo[i]);
+    h = fmax(h, hi[i]);
   }
-  lo[threadIdx.x] = l;
-  hi[threadIdx.x] = h;
+  sl[threadIdx.x] = l;
+  sh[threadIdx.x] = h;
   __syncthreads();
   for (int s = TPB / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
-      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + s]);
-      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + s]);
+      sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + s]);
+      sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = lo[0];
-    out[1] = hi[0];
+    out[0] = sl[0];
+    out[1] = sh[0];
   }
 }
 
@@ -1035,9 +1069,13 @@ int launch_foe_gather(void* stream, int64_t nnz, const int64_t* qpos, const doub
   return (int)hipGetLastError();
 }
 
-int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, double* out,
-                   int slot) {
-  hipLaunchKernelGGL(k_foe_dot, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nnz, X, Y, out, slot);
+int launch_foe_dot(void* stream, int64_t nnz, const double* X, const double* Y, double* part,
+                   double* out, int slot) {
+  const int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (nnz + 2047) / 2048));
+  const int64_t chunk = (nnz + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_foe_dot, dim3(nblk), dim3(TPB), 0, (hipStream_t)stream, nnz, chunk, X, Y,
+                     part);
+  hipLaunchKernelGGL(k_foe_sum, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nblk, part, out, slot);
   return (int)hipGetLastError();
 }
 
@@ -1058,9 +1096,12 @@ int launch_foe_series(void* stream, int64_t nnz, int npl, const double* c, const
 }
 
 int launch_foe_gersh(void* stream, int nrow, const int64_t* rowptr, const int32_t* col,
-                     const double* X, double* out) {
-  hipLaunchKernelGGL(k_foe_gersh, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nrow, rowptr, col,
-                     X, out);
+                     const double* X, double* lo, double* hi, double* out) {
+  if (nrow == 0) return 0;
+  const int rows = TPB / 64;
+  hipLaunchKernelGGL(k_foe_gersh_rows, dim3((unsigned)((nrow + rows - 1) / rows)), dim3(TPB), 0,
+                     (hipStream_t)stream, nrow, rowptr, col, X, lo, hi);
+  hipLaunchKernelGGL(k_foe_gersh, dim3(1), dim3(TPB), 0, (hipStream_t)stream, nrow, lo, hi, out);
   return (int)hipGetLastError();
 }
 
