@@ -217,7 +217,10 @@ wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hp
  * the device, cached in the plan, *nnz set (the call synchronizes the
  * stream).  Otherwise rowptr (device int64[nsf+1]), col (device int32[nnz])
  * and val (device double[nnz]) are filled, each optional; values are dot
- * products accumulated in double in an order fixed per pair. */
+ * products accumulated in double in an order fixed per pair.  For S with
+ * bra_c == ket_c the pairs a <= b are summed and each value written to
+ * (a, b) and (b, a); a pair's sum does not depend on which side is the bra,
+ * so the values are those of the full computation, bit for bit. */
 wvl_status wvl_sparse_overlap(wvl_plan* plan, const void* bra_c, int ket_is_output,
                               const void* ket_c, wvl_dtype dt, int64_t* nnz, int64_t* rowptr,
                               int32_t* col, double* val);

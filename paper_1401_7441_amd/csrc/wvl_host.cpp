@@ -126,6 +126,11 @@ struct PatternCache {
   int32_t* d_col = nullptr;
   int32_t* d_row = nullptr;
   int32_t* d_order = nullptr;   // processing order of the pairs (CSR positions)
+  // S pattern, bra = ket: the pairs a <= b in processing order, and for each
+  // the position of (b, a) (-1 on the diagonal); empty when not symmetric
+  int32_t* d_order_u = nullptr;
+  int32_t* d_mirror_u = nullptr;
+  int64_t nnz_u = 0;
   // S pattern only (Fermi operator expansion): position of the transposed
   // entry, and of the entry and its transpose in the H pattern
   int64_t* d_tpos = nullptr;
@@ -663,6 +668,8 @@ static void free_pattern(PatternCache& p) {
   if (p.d_col) (void)hipFree(p.d_col);
   if (p.d_row) (void)hipFree(p.d_row);
   if (p.d_order) (void)hipFree(p.d_order);
+  if (p.d_order_u) (void)hipFree(p.d_order_u);
+  if (p.d_mirror_u) (void)hipFree(p.d_mirror_u);
   if (p.d_tpos) (void)hipFree(p.d_tpos);
   if (p.d_hpos) (void)hipFree(p.d_hpos);
   if (p.d_htpos) (void)hipFree(p.d_htpos);
@@ -1229,6 +1236,37 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
       free_pattern(pc);
       return st;
     }
+    // the overlap of a function with itself: S_ab = S_ba, so only the pairs
+    // a <= b are summed and each value is written to both positions
+    if (!ket_out) {
+      std::vector<int32_t> ou, mu;
+      ou.reserve(nnz / 2 + nsf);
+      mu.reserve(nnz / 2 + nsf);
+      bool sym = true;
+      for (int64_t s = 0; s < nnz && sym; ++s) {
+        const int32_t k = order[s], a = row[k], b = col[k];
+        if (a > b) continue;
+        int32_t m = -1;
+        if (a != b) {
+          const auto e = col.begin() + rowptr[b + 1];
+          const auto it = std::lower_bound(col.begin() + rowptr[b], e, a);
+          if (it == e || *it != a)
+            sym = false;
+          else
+            m = (int32_t)(it - col.begin());
+        }
+        ou.push_back(k);
+        mu.push_back(m);
+      }
+      if (sym && (st = upload(ctx, &pc.d_order_u, ou.data(), sizeof(int32_t) * ou.size())) ==
+                     WVL_OK)
+        st = upload(ctx, &pc.d_mirror_u, mu.data(), sizeof(int32_t) * mu.size());
+      if (st != WVL_OK) {
+        free_pattern(pc);
+        return st;
+      }
+      pc.nnz_u = sym ? (int64_t)ou.size() : 0;
+    }
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
       free_pattern(pc);
@@ -1260,10 +1298,13 @@ wvl_status wvl_sparse_overlap(wvl_plan* P, const void* bra_c, int ket_is_output,
                                 ctx->stream));
   if (val && pc.nnz) {
     if (!bra_c || !ket_c) return fail(ctx, WVL_EINVAL, "wvl_sparse_overlap: null bra or ket");
+    const bool half = !ket_is_output && bra_c == ket_c && pc.nnz_u > 0;
     WVL_LAUNCH(ctx, ket_is_output ? KK_SPARSE_H : KK_SPARSE_S,
                launch_sparse_values(dt == WVL_F64, ctx->stream, P->d_sf, P->d_seg, P->d_rt,
                                     P->d_rr, ket_is_output, bra_c, ket_c, pc.d_row, pc.d_col,
-                                    pc.d_order, pc.nnz, val));
+                                    half ? pc.d_order_u : pc.d_order,
+                                    half ? pc.d_mirror_u : nullptr, half ? pc.nnz_u : pc.nnz,
+                                    val));
   }
   return WVL_OK;
 }
@@ -1754,9 +1795,13 @@ static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const 
       double* val = ket_out ? h_val : s_val;
       const PatternCache& pc = P->pat[ket_out];
       if (!val || pc.nnz == 0) continue;
+      // S = <psi|psi> is symmetric: half the pairs, each written twice
+      const bool half = !ket_out && pc.nnz_u > 0;
       const int e = launch_sparse_values(f64, cs, P->d_sf, P->d_seg, P->d_rt, P->d_rr, ket_out,
                                          psi_c, ket_out ? hpsi_c : psi_c, pc.d_row, pc.d_col,
-                                         pc.d_order, pc.nnz, val);
+                                         half ? pc.d_order_u : pc.d_order,
+                                         half ? pc.d_mirror_u : nullptr,
+                                         half ? pc.nnz_u : pc.nnz, val);
       if (e != 0) st = fail(ctx, WVL_EDEVICE, "capture of sparse values failed");
     }
   }

@@ -173,6 +173,6 @@ int launch_cg_p(int f64, void* stream, const SfDev* sf, double* rr, const double
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                          const int32_t* rt, const RowRun* rr, int ket_out, const void* bra,
                          const void* ket, const int32_t* row, const int32_t* col,
-                         const int32_t* order, int64_t nnz, double* val);
+                         const int32_t* order, const int32_t* mirror, int64_t nnz, double* val);
 
 }  // namespace wvl

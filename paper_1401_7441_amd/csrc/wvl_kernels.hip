@@ -202,6 +202,9 @@ __global__ __launch_bounds__(64) void k_pattern(const SfDev* __restrict__ sfs,
 // patterns never produce, are summed by that lane directly.  Phase 2: four
 // 16-lane groups stream the kept runs with contiguous loads.  Every lane's
 // partial sum and the final shuffle tree have an order fixed by the pair.
+// mirror (may be NULL): for the pair at processing position s, the CSR
+// position that receives the same value as well (the transposed pair of a
+// symmetric matrix), or -1.
 template <typename T>
 __device__ __forceinline__ double run_dot(const T* __restrict__ pa, const T* __restrict__ pk,
                                           int n) {
@@ -220,6 +223,7 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
                                                       const int32_t* __restrict__ rowi,
                                                       const int32_t* __restrict__ coli,
                                                       const int32_t* __restrict__ order,
+                                                      const int32_t* __restrict__ mirror,
                                                       int64_t nnz, double* __restrict__ val) {
   __shared__ int64_t ea[2][64], eb[2][64];   // run start offsets (bra, ket) per kind
   __shared__ int32_t el[2][64];              // run lengths (0: none)
@@ -314,7 +318,10 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
     __syncthreads();
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (lane == 0) val[k] = acc;
+  if (lane == 0) {
+    val[k] = acc;
+    if (mirror != nullptr && mirror[s] >= 0) val[mirror[s]] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -994,17 +1001,17 @@ int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int3
 int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
                          const int32_t* rt, const RowRun* rr, int ket_out, const void* bra,
                          const void* ket, const int32_t* row, const int32_t* col,
-                         const int32_t* order, int64_t nnz, double* val) {
+                         const int32_t* order, const int32_t* mirror, int64_t nnz, double* val) {
   if (nnz == 0) return 0;
   const unsigned nblk = (unsigned)(8 * ((nnz + 7) / 8));
   if (f64)
     hipLaunchKernelGGL(k_sparse_values<double>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
                        seg, rt, rr, ket_out, (const double*)bra, (const double*)ket, row, col,
-                       order, nnz, val);
+                       order, mirror, nnz, val);
   else
     hipLaunchKernelGGL(k_sparse_values<float>, dim3(nblk), dim3(64), 0, (hipStream_t)stream, sf,
                        seg, rt, rr, ket_out, (const float*)bra, (const float*)ket, row, col,
-                       order, nnz, val);
+                       order, mirror, nnz, val);
   return (int)hipGetLastError();
 }
 

@@ -275,6 +275,12 @@ def test_sparse_overlap_and_hamiltonian(spheres, dtype):
         _, _, val2 = W.sparse_overlap(plan, psi, hpsi if ket_out else psi, ket_out)
         torch.cuda.synchronize()
         assert np.array_equal(val2.cpu().numpy(), v)
+        if not ket_out:
+            # S with bra == ket sums each pair once and mirrors it; a copy of
+            # psi as the ket takes every pair: the same bits
+            _, _, val3 = W.sparse_overlap(plan, psi, psi.clone(), False)
+            torch.cuda.synchronize()
+            assert np.array_equal(val3.cpu().numpy(), v)
 
 
 def test_repeat_runs_bitwise_deterministic(spheres):
