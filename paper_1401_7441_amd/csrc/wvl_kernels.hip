@@ -312,7 +312,22 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
         const int l = el[fine][q];
         const T* pa = bra + ea[fine][q];
         const T* pk = ket + eb[fine][q];
-        for (int x = gl; x < l; x += 16) acc += (double)pa[x] * (double)pk[x];
+        // FP64: four positions of the lane loaded before they are added, in
+        // the order x, x + 16, x + 32, x + 48 (the order of the plain loop);
+        // FP32 runs faster with one (fewer requests in flight per CU)
+        constexpr int U = sizeof(T) == 8 ? 4 : 1;
+        for (int x = gl; x < l; x += 16 * U) {
+          T va[U], vk[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const bool in = x + 16 * u < l;
+            va[u] = in ? pa[x + 16 * u] : T(0);
+            vk[u] = in ? pk[x + 16 * u] : T(0);
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (x + 16 * u < l) acc += (double)va[u] * (double)vk[u];
+        }
       }
     }
     __syncthreads();
