@@ -1633,8 +1633,10 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   coefficients(sigma, tau, mu, delta, &coef);
   // pass 2: K' = c_0/2 I + sum_i c_i T^i(H~')
   if (keep) {
+    // the host vector must outlive the copy: wait for it before going on
     WVL_HIP(ctx, hipMemcpyAsync(cf, coef.data(), sizeof(double) * (npl + 1),
                                 hipMemcpyHostToDevice, s));
+    WVL_HIP(ctx, hipStreamSynchronize(s));
     WVL_LAUNCH(ctx, KK_FOE, launch_foe_series(s, nnz, npl, cf, Tall, rw, cl, Kp));
   } else {
     WVL_LAUNCH(ctx, KK_FOE, axpby(coef[1], Ht, 0.0, nullptr, 0.5 * coef[0], Kp));
