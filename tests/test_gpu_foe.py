@@ -126,6 +126,44 @@ def test_foe_on_long_rows(m):
     assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
 
 
+def test_foe_full_size_lattice():
+    """The bench's FOE configuration (1,000 functions, npl = 100, delta = 1,
+    n_occ = n/2, Gershgorin bounds) on a 10 x 10 x 10 lattice of 11^3 boxes
+    spaced 4 points apart: boxes meet iff their lattice indices differ by at
+    most 2 along every axis, so the overlap pattern (27 to 125 entries per
+    row) is known in closed form and checked bit for bit.  Seeded S and H as
+    in the cluster test; the oracle runs the dense masked recursion."""
+    _print("case: FOE full size, 1,000 functions on a lattice, npl 100")
+    L = 10
+    idx = np.array([(i, j, k) for k in range(L) for j in range(L) for i in range(L)])
+    lrs = [LR.box_locreg((4 * i, 4 * j, 4 * k), (11, 11, 11), (4 * i + 4, 4 * j + 4, 4 * k + 4),
+                         (4 * i + 6, 4 * j + 6, 4 * k + 6)) for i, j, k in idx]
+    ctx = W.Context(0.45, (48, 48, 48))
+    rec, segs = to_abi(lrs)
+    plan = W.Plan(ctx, rec, segs)
+    n = len(lrs)
+    mask = np.all(np.abs(idx[:, None, :] - idx[None, :, :]) <= 2, axis=2)
+    rows, cols = np.nonzero(mask)
+    rp = np.concatenate([[0], np.cumsum(mask.sum(1))])
+    zin = torch.zeros(plan.info["in_coefs"], dtype=torch.float64, device="cuda")
+    zout = torch.zeros(plan.info["out_coefs"], dtype=torch.float64, device="cuda")
+    for ket_out in (False, True):
+        prp, pcl, _ = W.sparse_overlap(plan, zin, zout if ket_out else zin, ket_out,
+                                       values=False)
+        assert np.array_equal(prp.cpu().numpy(), rp) and np.array_equal(pcl.cpu().numpy(), cols)
+    rng = np.random.default_rng(4300)
+    R1, R2 = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    S = (np.eye(n) + 0.02 * (R1 + R1.T)) * mask
+    H = (np.diag(np.linspace(-1.0, 1.0, n)) + 0.05 * (R2 + R2.T)) * mask
+    npl, delta, nocc = 100, 1.0, 0.5 * n
+    K, mu, ebs, _ = F.foe(S, H, mask, npl, delta, nocc)
+    kv, gmu, gebs = W.foe(plan, torch.tensor(S[rows, cols], device="cuda"),
+                          torch.tensor(H[rows, cols], device="cuda"), npl, delta, nocc)
+    want = K[rows, cols]
+    assert np.max(np.abs(kv.cpu().numpy() - want)) <= 1e-9 * np.max(np.abs(want))
+    assert abs(gmu - mu) <= 1e-9 and abs(gebs - ebs) <= 1e-9 * max(1.0, abs(ebs))
+
+
 def test_foe_rejects_bad_parameters(system):
     _print("case: FOE parameter checks")
     case, (srp, scl, sv), (hrp, hcl, hv) = system
