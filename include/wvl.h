@@ -251,7 +251,7 @@ wvl_status wvl_synthesize(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void*
  * result is reproducible bitwise.  The first call builds the plan's tile
  * lists (synchronizes once).  Errors: WVL_EINVAL for null buffers or
  * k_nnz < 0; WVL_EUNSUPPORTED when more than 1024 fine boxes meet one tile
- * of 16 x 4 x 1 fine-grid points. */
+ * of 16 x 4 x 1 fine-grid points, or the plan has 2^24 or more functions. */
 wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int64_t* k_rowptr,
                        const int32_t* k_col, const double* k_val, int64_t k_nnz, void* rho,
                        void* work);

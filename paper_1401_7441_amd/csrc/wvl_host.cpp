@@ -1376,6 +1376,8 @@ static wvl_status ensure_cover(wvl_plan* P) {
     return fail(ctx, WVL_EUNSUPPORTED,
                 "density: %lld fine boxes meet one tile (at most %d are supported)",
                 (long long)maxc, kDensMaxCover);
+  if (P->nsf >= (1 << 24))   // the tile kernel's lookup keys hold 24-bit indices
+    return fail(ctx, WVL_EUNSUPPORTED, "density: more than 2^24 - 1 functions");
   auto drop = [&]() {
     for (void** p : {(void**)&P->d_cptr, (void**)&P->d_csf})
       if (*p) {

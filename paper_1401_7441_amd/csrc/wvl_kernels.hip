@@ -362,6 +362,22 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+__device__ __forceinline__ int dens_bucket(int b) {
+  return (int)(((uint32_t)b * 2654435761u) >> 24);
+}
+
+// position of function b in a bucket of (function << 8 | position), or -1
+__device__ __forceinline__ int dens_match(uint4 v, int b) {
+  const uint32_t ub = (uint32_t)b;
+  int p = -1;
+  if ((v.x >> 8) == ub) p = (int)(v.x & 255u);
+  if ((v.y >> 8) == ub) p = (int)(v.y & 255u);
+  if ((v.z >> 8) == ub) p = (int)(v.z & 255u);
+  if ((v.w >> 8) == ub) p = (int)(v.w & 255u);
+  return p;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
     const SfDev* __restrict__ sfs, const int64_t* __restrict__ foff, const T* __restrict__ fine,
@@ -374,7 +390,15 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
   __shared__ int32_t cov[kDensMaxCover];
   __shared__ int32_t lj[kDensWaves][64];
   __shared__ double lk[kDensWaves][64];
-  __shared__ double red[kDensWaves][64];
+  // the j-chunk's functions by index: 256 buckets of four slots
+  // (function << 8 | position in the chunk); the final reduction reuses the
+  // space
+  __shared__ __align__(16) unsigned char hraw[kDensWaves * 64 * sizeof(double)];
+  uint4* hb = reinterpret_cast<uint4*>(hraw);
+  uint32_t* hslot = reinterpret_cast<uint32_t*>(hraw);
+  double (*red)[64] = reinterpret_cast<double (*)[64]>(hraw);
+  static_assert(kDensWaves * 64 * sizeof(double) == 256 * sizeof(uint4), "hash size");
+  static_assert(C <= 256, "chunk positions need 8 bits");
   const int tile = blockIdx.x;
   const int ix = tile % tx, iy = (tile / tx) % ty, iz = tile / (tx * ty);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -403,9 +427,21 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
       const int nj = min(C, m - jc);
       const T* vb = vi;
       if (jc != ic) {
-        __syncthreads();   // vj no longer read
         for (int j = wave; j < nj; j += kDensWaves) vj[j * 64 + lane] = value(cov[jc + j]);
         vb = vj;
+      }
+      for (int h = tid; h < 4 * 256; h += 64 * kDensWaves) hslot[h] = 0xFFFFFFFFu;
+      __syncthreads();
+      // 1024 slots > nj: every insertion finds a free slot, every lookup a
+      // bucket that is not full
+      if (tid < nj) {
+        const int b = cov[jc + tid];
+        const uint32_t key = ((uint32_t)b << 8) | (uint32_t)tid;
+        for (int bk = dens_bucket(b);; bk = (bk + 1) & 255) {
+          int c = 0;
+          while (c < 4 && atomicCAS(&hslot[4 * bk + c], 0xFFFFFFFFu, key) != 0xFFFFFFFFu) ++c;
+          if (c < 4) break;
+        }
       }
       __syncthreads();
       const int blo = cov[jc], bhi = cov[jc + nj - 1];
@@ -419,14 +455,17 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
           double kq = 0.0;
           if (q < q1) {
             const int b = kcol[q];
-            if (b >= blo && b <= bhi) {   // binary search in the j-chunk
-              int lo = 0, hi = nj - 1;
-              while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (cov[jc + mid] < b) lo = mid + 1; else hi = mid;
+            if (b >= blo && b <= bhi) {   // b's position in the j-chunk, if any
+              int bk = dens_bucket(b);
+              uint4 v = hb[bk];
+              int p = dens_match(v, b);
+              while (p < 0 && v.w != 0xFFFFFFFFu) {
+                bk = (bk + 1) & 255;
+                v = hb[bk];
+                p = dens_match(v, b);
               }
-              if (cov[jc + lo] == b) {
-                j = lo;
+              if (p >= 0) {
+                j = p;
                 kq = kval[q];
               }
             }
@@ -445,7 +484,7 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
         }
         acc += (double)vi[i * 64 + lane] * u;
       }
-      __syncthreads();   // vi / vj no longer read
+      __syncthreads();   // vi / vj and the hash no longer read
     }
   }
   red[wave][lane] = acc;
@@ -463,15 +502,16 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
 // ---------------------------------------------------------------------------
 
 // C = alpha (A B)|_P + beta D, one workgroup of W waves per row i of P,
-// rows taken in the order `rows` gives (longest work first).  Row i's columns go into an LDS hash table of 2^lognb buckets of four
-// 32-bit slots, each slot (column << 10 | position in the row); a bucket
-// fills from its first slot, and a full one spills into the next.  Wave w
-// takes the k of row i with index t = w, w + W, .. in increasing order; its
-// lanes walk row k of B, 256 entries at a time, and add A_ik B_kj to the
-// wave's own accumulator of j when j is in row i.  The next batch of B is
-// loaded while the current one is added.  The waves' accumulators are summed
-// in wave order at the end, so every entry's sum has a fixed order.  D may be
-// NULL (beta ignored).  Needs columns below 2^21 and rows of at most 1024
+// rows taken in the order `rows` gives (longest work first).  Row i's
+// columns go into an LDS hash table of 2^lognb buckets of four 32-bit slots,
+// each slot (column << 10 | position in the row); a bucket fills from its
+// first slot, and a full one spills into the next.  Wave w takes the k of
+// row i with index t = w, w + W, .. in increasing order; its lanes walk row
+// k of B, 256 entries at a time, and add A_ik B_kj to the wave's own
+// accumulator of j when j is in row i.  The next batch of B is loaded while
+// the current one is added.  The waves' accumulators are summed in wave
+// order at the end, so every entry's sum has a fixed order.  D may be NULL
+// (beta ignored).  Needs columns below 2^21 and rows of at most 1024
 // entries; LDS: W + 2 doubles per row entry (maxdeg) and 16 bytes per
 // bucket.
 constexpr uint32_t kFoeEmpty = 0xFFFFFFFFu;
