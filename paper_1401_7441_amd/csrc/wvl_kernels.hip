@@ -445,29 +445,54 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
       }
       __syncthreads();
       const int blo = cov[jc], bhi = cov[jc + nj - 1];
-      for (int i = wave; i < ni; i += kDensWaves) {
+      // the wave's rows i = wave, wave + 8, ..; the next row's bounds and
+      // the next 64 kernel entries are loaded while the current ones are
+      // used (the sums keep their order)
+      int i = wave;
+      int64_t q0 = 0, q1 = 0;
+      if (i < ni) {
         const int a = cov[ic + i];
-        const int64_t q0 = max((int64_t)0, krow[a]), q1 = min(knnz, krow[a + 1]);
+        q0 = max((int64_t)0, krow[a]);
+        q1 = min(knnz, krow[a + 1]);
+      }
+      while (i < ni) {
+        const int inx = i + kDensWaves;
+        int64_t n0 = 0, n1 = 0;
+        if (inx < ni) {
+          const int an = cov[ic + inx];
+          n0 = krow[an];
+          n1 = krow[an + 1];
+        }
         double u = 0.0;
+        int bn = -1;
+        double kn = 0.0;
+        if (q0 + lane < q1) {
+          bn = kcol[q0 + lane];
+          kn = kval[q0 + lane];
+        }
         for (int64_t qq = q0; qq < q1; qq += 64) {
-          const int64_t q = qq + lane;
+          const int b = bn;
+          const double kb = kn;
+          bn = -1;
+          kn = 0.0;
+          if (qq + 64 + lane < q1) {
+            bn = kcol[qq + 64 + lane];
+            kn = kval[qq + 64 + lane];
+          }
           int j = -1;
           double kq = 0.0;
-          if (q < q1) {
-            const int b = kcol[q];
-            if (b >= blo && b <= bhi) {   // b's position in the j-chunk, if any
-              int bk = dens_bucket(b);
-              uint4 v = hb[bk];
-              int p = dens_match(v, b);
-              while (p < 0 && v.w != 0xFFFFFFFFu) {
-                bk = (bk + 1) & 255;
-                v = hb[bk];
-                p = dens_match(v, b);
-              }
-              if (p >= 0) {
-                j = p;
-                kq = kval[q];
-              }
+          if (b >= blo && b <= bhi) {   // b's position in the j-chunk, if any
+            int bk = dens_bucket(b);
+            uint4 v = hb[bk];
+            int p = dens_match(v, b);
+            while (p < 0 && v.w != 0xFFFFFFFFu) {
+              bk = (bk + 1) & 255;
+              v = hb[bk];
+              p = dens_match(v, b);
+            }
+            if (p >= 0) {
+              j = p;
+              kq = kb;
             }
           }
           const unsigned long long hit = __ballot(j >= 0);
@@ -483,6 +508,9 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
           wave_sync();
         }
         acc += (double)vi[i * 64 + lane] * u;
+        i = inx;
+        q0 = max((int64_t)0, n0);
+        q1 = min(knnz, n1);
       }
       __syncthreads();   // vi / vj and the hash no longer read
     }
