@@ -197,8 +197,14 @@ struct FoeCoef {
       for (int i = 0; i <= npl; ++i) cs[(size_t)k * (npl + 1) + i] = std::cos(i * t);
     }
   }
+  // erfc(z) rounds to 2 for z <= -6 and to 0 for z >= 28 in double, so the
+  // call is needed only in between (most nodes lie outside when delta is
+  // small against the spectral range)
   double f(int k, double sigma, double tau, double mu, double delta) const {
-    return 0.5 * std::erfc((x[k] / sigma + tau - mu) / delta);
+    const double z = (x[k] / sigma + tau - mu) / delta;
+    if (z <= -6.0) return 1.0;
+    if (z >= 28.0) return 0.0;
+    return 0.5 * std::erfc(z);
   }
   void operator()(double sigma, double tau, double mu, double delta,
                   std::vector<double>* c) const {
