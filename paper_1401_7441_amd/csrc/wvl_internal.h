@@ -132,7 +132,8 @@ int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int3
                    int ket_out, int64_t* count, const int64_t* rowptr, int32_t* col);
 // Fermi operator expansion on a symmetric CSR pattern (row: row of each
 // entry, tpos: position of the transposed entry).  foe_mm: one workgroup per
-// row, 8 waves when no row has more than kFoeMaxDeg / 2 entries, else 4;
+// row, 8 waves when no row has more than kFoeMaxDeg / 2 entries, else 4
+// (and two rows of B a step when none has more than kFoeMaxDeg / 4);
 // rows of at most kFoeMaxDeg entries, columns below kFoeMaxCol, entries
 // addressed with 32-bit offsets; 2^lognb hash buckets of 16 bytes, at least
 // as many as the longest row has entries (maxdeg) and at least 32 (at most

@@ -535,12 +535,13 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
 // each slot (column << 10 | position in the row); a bucket fills from its
 // first slot, and a full one spills into the next.  Wave w takes the k of
 // row i with index t = w, w + W, .. in increasing order; its lanes walk row
-// k of B, 256 entries at a time, and add A_ik B_kj to the wave's own
-// accumulator of j when j is in row i.  The next batch of B is loaded while
-// the current one is added.  The waves' accumulators are summed in wave
-// order at the end, so every entry's sum has a fixed order.  D may be NULL
+// k of B in parts of 256 / NH entries, NH parts a step, and add A_ik B_kj to
+// the wave's accumulator of that part's slot when j is in row i.  The next
+// step's entries of B are loaded while the current ones are added.  The
+// accumulators are summed in (wave, slot) order at the end, so every entry's
+// sum has a fixed order.  D may be NULL
 // (beta ignored).  Needs columns below 2^21 and rows of at most 1024
-// entries; LDS: W + 2 doubles per row entry (maxdeg) and 16 bytes per
+// entries; LDS: W NH + 2 doubles per row entry (maxdeg) and 16 bytes per
 // bucket.
 constexpr uint32_t kFoeEmpty = 0xFFFFFFFFu;
 
@@ -559,20 +560,22 @@ __device__ __forceinline__ int foe_match(uint4 v, int j) {
   return p;
 }
 
-template <int W>
+template <int W, int NH>
 __global__ __launch_bounds__(64 * W) void k_foe_mm(
     const int32_t* __restrict__ rows, const int64_t* __restrict__ rowptr,
     const int32_t* __restrict__ col, double alpha,
     const double* __restrict__ A, const double* __restrict__ B, double beta,
     const double* __restrict__ D, double* __restrict__ C, int lognb, int maxdeg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* acc = reinterpret_cast<double*>(smem_raw);   // [W][maxdeg]
-  double* av = acc + (size_t)W * maxdeg;                // A_ik, [maxdeg]
+  double* acc = reinterpret_cast<double*>(smem_raw);   // [W][NH][maxdeg]
+  double* av = acc + (size_t)W * NH * maxdeg;           // A_ik, [maxdeg]
   int* kst = reinterpret_cast<int*>(av + maxdeg);       // start of row k in B
   int* kdg = kst + maxdeg;                              // length of row k
   uint4* bucket = reinterpret_cast<uint4*>(kdg + maxdeg);   // [nb]
   uint32_t* slot = reinterpret_cast<uint32_t*>(bucket);
   constexpr int nt = 64 * W;
+  constexpr int QW = 256 / NH;   // entries of a row k per part
+  constexpr int UH = 4 / NH;     // 64-lane slots per part
   const int nb = 1 << lognb;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -588,7 +591,7 @@ __global__ __launch_bounds__(64 * W) void k_foe_mm(
     kdg[p] = (int)(rowptr[k + 1] - k0);
     av[p] = A[r0 + p];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[(size_t)w * maxdeg + p] = 0.0;
+    for (int w = 0; w < W * NH; ++w) acc[(size_t)w * maxdeg + p] = 0.0;
   }
   __syncthreads();
   // 4 nb slots > deg: every insertion finds a free slot, every lookup a
@@ -603,20 +606,44 @@ __global__ __launch_bounds__(64 * W) void k_foe_mm(
     }
   }
   __syncthreads();
-  double* my = acc + (size_t)wave * maxdeg;
-  // entries q0 + lane, q0 + 64 + lane, .. of row k (column -1: none)
-  auto load = [&](int k0, int kd, int q0, int (&jj)[4], double (&bb)[4]) {
+  double* my = acc + (size_t)wave * NH * maxdeg;   // the wave's NH accumulators
+  // the wave's parts in order: (t, q0) for t = wave, wave + W, .. and
+  // q0 = 0, QW, .. below the length of row k; a step takes NH parts, part h
+  // on the 64-lane slots h UH .. h UH + UH - 1 and into accumulator h
+  int qt = wave, qq = 0;
+  auto next = [&](int& k0, int& kd, int& q0, double& a) {
+    if (qt >= deg) {
+      k0 = 0;
+      kd = 0;
+      q0 = 0;
+      a = 0.0;
+      return;
+    }
+    k0 = kst[qt];
+    kd = kdg[qt];
+    q0 = qq;
+    a = av[qt];
+    qq += QW;
+    if (qq >= kd) {
+      qt += W;
+      qq = 0;
+    }
+  };
+  // column -1: none
+  auto load = [&](const int (&k0)[NH], const int (&kd)[NH], const int (&q0)[NH], int (&jj)[4],
+                  double (&bb)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int q = q0 + 64 * u + lane;
-      jj[u] = q < kd ? col[k0 + q] : -1;
-      bb[u] = q < kd ? B[k0 + q] : 0.0;
+      const int h = u / UH;
+      const int q = q0[h] + 64 * (u % UH) + lane;
+      jj[u] = q < kd[h] ? col[k0[h] + q] : -1;
+      bb[u] = q < kd[h] ? B[k0[h] + q] : 0.0;
     }
   };
   // the four lookups, the four accumulator reads and the four writes are
-  // issued together: the columns of one row of B are distinct, so are the
-  // positions they hit
-  auto add = [&](const int (&jj)[4], const double (&bb)[4], double a) {
+  // issued together: within a part the columns (one row of B) are distinct,
+  // and parts add into accumulators of their own
+  auto add = [&](const int (&jj)[4], const double (&bb)[4], const double (&a)[NH]) {
     int b[4];
     uint4 v[4];
 #pragma unroll
@@ -636,62 +663,47 @@ __global__ __launch_bounds__(64 * W) void k_foe_mm(
     }
     double o[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) o[u] = my[p[u] >= 0 ? p[u] : 0];
+    for (int u = 0; u < 4; ++u) o[u] = my[(size_t)(u / UH) * maxdeg + (p[u] >= 0 ? p[u] : 0)];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (p[u] >= 0) my[p[u]] = o[u] + a * bb[u];
+      if (p[u] >= 0) my[(size_t)(u / UH) * maxdeg + p[u]] = o[u] + a[u / UH] * bb[u];
   };
-  int t = wave;
-  int k0 = 0, kd = 0;
-  double a = 0.0;
+  int steps = 0;
+  for (int t = wave; t < deg; t += W) steps += (kdg[t] + QW - 1) / QW;
+  steps = (steps + NH - 1) / NH;
+  int k0[NH], kd[NH], q0[NH];
+  double a[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) next(k0[h], kd[h], q0[h], a[h]);
   int jj[4];
   double bb[4];
-  if (t < deg) {
-    k0 = kst[t];
-    kd = kdg[t];
-    a = av[t];
-    load(k0, kd, 0, jj, bb);
-  }
-  while (t < deg) {
-    const int tn = t + W;
-    int k0n = 0, kdn = 0;
-    double an = 0.0;
-    if (tn < deg) {
-      k0n = kst[tn];
-      kdn = kdg[tn];
-      an = av[tn];
-    }
-    for (int q0 = 0;; q0 += 256) {
-      const bool more = q0 + 256 < kd;
-      int jn[4];
-      double bn[4];
-      if (more)
-        load(k0, kd, q0 + 256, jn, bn);
-      else
-        load(k0n, kdn, 0, jn, bn);
-      add(jj, bb, a);
+  load(k0, kd, q0, jj, bb);
+  // the next step's entries of B load while the current ones are added
+  for (; steps > 0; --steps) {
+    double an[NH];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        jj[u] = jn[u];
-        bb[u] = bn[u];
-      }
-      if (!more) break;
+    for (int h = 0; h < NH; ++h) next(k0[h], kd[h], q0[h], an[h]);
+    int jn[4];
+    double bn[4];
+    load(k0, kd, q0, jn, bn);
+    add(jj, bb, a);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      jj[u] = jn[u];
+      bb[u] = bn[u];
     }
-    t = tn;
-    k0 = k0n;
-    kd = kdn;
-    a = an;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) a[h] = an[h];
   }
   __syncthreads();
   for (int p = tid; p < deg; p += nt) {
     double v = acc[p];
 #pragma unroll
-    for (int w = 1; w < W; ++w) v += acc[(size_t)w * maxdeg + p];
+    for (int w = 1; w < W * NH; ++w) v += acc[(size_t)w * maxdeg + p];
     C[r0 + p] = D ? alpha * v + beta * D[r0 + p] : alpha * v;
   }
 }
 
-// elementwise on P: out = a X + b Y (+ d on the diagonal when diag != NULL)
 // v = a x + b y (+ d on the diagonal), each term only when present; the one
 // expression both k_foe_axpby and k_foe_series evaluate
 __device__ __forceinline__ double foe_lin(bool hx, double a, double x, bool hy, double b,
@@ -703,6 +715,7 @@ __device__ __forceinline__ double foe_lin(bool hx, double a, double x, bool hy, 
   return v;
 }
 
+// elementwise on P: out = a X + b Y (+ d on the diagonal when row != NULL)
 __global__ __launch_bounds__(TPB) void k_foe_axpby(int64_t nnz, double a,
                                                    const double* __restrict__ X, double b,
                                                    const double* __restrict__ Y,
@@ -1125,14 +1138,21 @@ int launch_foe_mm(void* stream, int nrow, const int32_t* rows, const int64_t* ro
                   const int32_t* col, double alpha, const double* A, const double* B, double beta,
                   const double* D, double* C, int lognb, int maxdeg) {
   if (nrow == 0) return 0;
+  // rows of at most 256 entries: two rows of B (128 entries each) per step
   const int w = maxdeg <= kFoeMaxDeg / 2 ? 8 : 4;
-  const size_t lds = (size_t)maxdeg * 8 * (w + 2) + ((size_t)16 << lognb);
-  if (w == 8)
-    hipLaunchKernelGGL(k_foe_mm<8>, dim3((unsigned)nrow), dim3(64 * 8), lds, (hipStream_t)stream,
-                       rows, rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
+  const int nh = maxdeg <= kFoeMaxDeg / 4 ? 2 : 1;
+  const size_t lds = (size_t)maxdeg * 8 * (w * nh + 2) + ((size_t)16 << lognb);
+  const dim3 g((unsigned)nrow), blk(64 * w);
+  hipStream_t st = (hipStream_t)stream;
+  if (nh == 2)
+    hipLaunchKernelGGL((k_foe_mm<8, 2>), g, blk, lds, st, rows, rowptr, col, alpha, A, B, beta,
+                       D, C, lognb, maxdeg);
+  else if (w == 8)
+    hipLaunchKernelGGL((k_foe_mm<8, 1>), g, blk, lds, st, rows, rowptr, col, alpha, A, B, beta,
+                       D, C, lognb, maxdeg);
   else
-    hipLaunchKernelGGL(k_foe_mm<4>, dim3((unsigned)nrow), dim3(64 * 4), lds, (hipStream_t)stream,
-                       rows, rowptr, col, alpha, A, B, beta, D, C, lognb, maxdeg);
+    hipLaunchKernelGGL((k_foe_mm<4, 1>), g, blk, lds, st, rows, rowptr, col, alpha, A, B, beta,
+                       D, C, lognb, maxdeg);
   return (int)hipGetLastError();
 }
 
