@@ -257,6 +257,8 @@ struct wvl_plan {
   int64_t max_fine = 0;               // largest fine box (elements)
   int64_t* d_cptr = nullptr;          // density: functions meeting each k_dens_tile tile
   int32_t* d_csf = nullptr;
+  int32_t* d_tord[2] = {nullptr, nullptr};   // tiles, one-chunk ones first (FP32, FP64)
+  int64_t dens_one[2] = {0, 0};              // how many of them have one chunk
   wvl_plan_info info{};
   PatternCache pat[2];
   std::unique_ptr<FoeCoef> foe_coef;  // Chebyshev node table of the last wvl_foe degree
@@ -691,6 +693,8 @@ void wvl_plan_destroy(wvl_plan* plan) {
   if (plan->d_foff) (void)hipFree(plan->d_foff);
   if (plan->d_cptr) (void)hipFree(plan->d_cptr);
   if (plan->d_csf) (void)hipFree(plan->d_csf);
+  for (int d = 0; d < 2; ++d)
+    if (plan->d_tord[d]) (void)hipFree(plan->d_tord[d]);
   if (plan->d_rt) (void)hipFree(plan->d_rt);
   if (plan->d_rr) (void)hipFree(plan->d_rr);
   if (plan->d_wk) (void)hipFree(plan->d_wk);
@@ -1384,16 +1388,39 @@ static wvl_status ensure_cover(wvl_plan* P) {
                 (long long)maxc, kDensMaxCover);
   if (P->nsf >= (1 << 24))   // the tile kernel's lookup keys hold 24-bit indices
     return fail(ctx, WVL_EUNSUPPORTED, "density: more than 2^24 - 1 functions");
+  // FP32: the tiles that fit one staged chunk first (a launch of their own,
+  // with less LDS per workgroup), then the others.  FP64 (chunks of 64, so
+  // about half the tiles need two) runs all tiles in one launch, which
+  // measured faster.
+  std::vector<int32_t> tord[2];
+  for (int d = 0; d < 2; ++d) {
+    tord[d].reserve(ntile);
+    P->dens_one[d] = 0;
+    if (d == 1) {
+      for (int64_t t = 0; t < ntile; ++t) tord[d].push_back((int32_t)t);
+      continue;
+    }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int64_t t = 0; t < ntile; ++t)
+        if ((cptr[t + 1] - cptr[t] <= kDensChunk[d]) == (pass == 0)) tord[d].push_back((int32_t)t);
+    for (int64_t t = 0; t < ntile; ++t) P->dens_one[d] += cptr[t + 1] - cptr[t] <= kDensChunk[d];
+  }
   auto drop = [&]() {
-    for (void** p : {(void**)&P->d_cptr, (void**)&P->d_csf})
+    for (void** p : {(void**)&P->d_cptr, (void**)&P->d_csf, (void**)&P->d_tord[0],
+                     (void**)&P->d_tord[1]})
       if (*p) {
         (void)hipFree(*p);
         *p = nullptr;
       }
   };
   wvl_status st;
-  if ((st = upload(ctx, &P->d_cptr, cptr.data(), sizeof(int64_t) * cptr.size())) != WVL_OK ||
-      (st = upload(ctx, &P->d_csf, csf.data(), sizeof(int32_t) * csf.size())) != WVL_OK) {
+  // d_cptr last: it marks the lists as ready
+  if ((st = upload(ctx, &P->d_csf, csf.data(), sizeof(int32_t) * csf.size())) != WVL_OK ||
+      (st = upload(ctx, &P->d_tord[0], tord[0].data(), sizeof(int32_t) * tord[0].size())) !=
+          WVL_OK ||
+      (st = upload(ctx, &P->d_tord[1], tord[1].data(), sizeof(int32_t) * tord[1].size())) !=
+          WVL_OK ||
+      (st = upload(ctx, &P->d_cptr, cptr.data(), sizeof(int64_t) * cptr.size())) != WVL_OK) {
     drop();
     return st;
   }
@@ -1422,7 +1449,8 @@ wvl_status wvl_density(wvl_plan* P, wvl_dtype dt, const void* fine, const int64_
   for (int a = 0; a < 3; ++a) gf[a] = 2 * ctx->grid.n[a] + 29;
   WVL_LAUNCH(ctx, KK_DENS_TILE,
              launch_dens_tile(f64, ctx->stream, P->d_sf, P->d_foff, fine, k_rowptr, k_col, k_val,
-                              k_nnz, P->d_cptr, P->d_csf, gf, rho));
+                              k_nnz, P->d_cptr, P->d_csf, P->d_tord[f64], P->dens_one[f64], gf,
+                              rho));
   return WVL_OK;
 }
 

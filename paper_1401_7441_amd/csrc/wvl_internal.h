@@ -108,12 +108,16 @@ int launch_up_z(int f64, void* stream, const SfWork* wk, const SfDev* sf, int ns
                 const void* ws, const int64_t* fine_off, void* fine);
 // density: tiles of 16 x 4 x 1 fine-grid points (one 64-lane workgroup each)
 // with the functions whose fine box meets them (at most kDensMaxCover)
+// with the functions whose fine box meets them (at most kDensMaxCover),
+// staged kDensChunk[FP32, FP64] functions at a time.  tord lists the tiles:
+// first the n_one with at most one chunk, then the others.
 constexpr int kDensTile[3] = {16, 4, 1};
 constexpr int kDensMaxCover = 1024;
+constexpr int kDensChunk[2] = {128, 64};
 int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff,
                      const void* fine, const int64_t* krow, const int32_t* kcol,
                      const double* kval, int64_t knnz, const int64_t* cptr, const int32_t* csf,
-                     const int* gf, void* rho);
+                     const int32_t* tord, int64_t n_one, const int* gf, void* rho);
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                       int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart,
                       const double* conf, double hh);

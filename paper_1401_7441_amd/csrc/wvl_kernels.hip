@@ -378,15 +378,17 @@ __device__ __forceinline__ int dens_match(uint4 v, int b) {
   return p;
 }
 
-template <typename T>
+// ONE: every tile of the launch has at most C functions (one chunk), and the
+// second chunk buffer is left out (more workgroups fit in a CU's LDS)
+template <typename T, bool ONE>
 __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
     const SfDev* __restrict__ sfs, const int64_t* __restrict__ foff, const T* __restrict__ fine,
     const int64_t* __restrict__ krow, const int32_t* __restrict__ kcol,
     const double* __restrict__ kval, int64_t knnz, const int64_t* __restrict__ cptr,
-    const int32_t* __restrict__ csf, int tx, int ty, int g0, int g1, int g2,
-    T* __restrict__ rho) {
-  constexpr int C = sizeof(T) == 4 ? 128 : 64;    // functions per staged chunk
-  __shared__ T vi[C * 64], vj[C * 64];
+    const int32_t* __restrict__ csf, const int32_t* __restrict__ tord, int64_t tbase, int tx,
+    int ty, int g0, int g1, int g2, T* __restrict__ rho) {
+  constexpr int C = kDensChunk[sizeof(T) == 4 ? 0 : 1];   // functions per staged chunk
+  __shared__ T vi[C * 64], vj[ONE ? 1 : C * 64];
   __shared__ int32_t cov[kDensMaxCover];
   __shared__ int32_t lj[kDensWaves][64];
   __shared__ double lk[kDensWaves][64];
@@ -399,7 +401,7 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
   double (*red)[64] = reinterpret_cast<double (*)[64]>(hraw);
   static_assert(kDensWaves * 64 * sizeof(double) == 256 * sizeof(uint4), "hash size");
   static_assert(C <= 256, "chunk positions need 8 bits");
-  const int tile = blockIdx.x;
+  const int tile = tord[tbase + blockIdx.x];
   const int ix = tile % tx, iy = (tile / tx) % ty, iz = tile / (tx * ty);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
     for (int jc = 0; jc < m; jc += C) {
       const int nj = min(C, m - jc);
       const T* vb = vi;
-      if (jc != ic) {
+      if (!ONE && jc != ic) {
         for (int j = wave; j < nj; j += kDensWaves) vj[j * 64 + lane] = value(cov[jc + j]);
         vb = vj;
       }
@@ -1032,8 +1034,10 @@ int preload_kernels() {
   const void* fns[] = {(const void*)k_finalize, (const void*)k_sparse_values<float>,
                        (const void*)k_sparse_values<double>, (const void*)k_update<float>,
                        (const void*)k_update<double>, (const void*)k_sf_dot<float>,
-                       (const void*)k_sf_dot<double>, (const void*)k_dens_tile<float>,
-                       (const void*)k_dens_tile<double>};
+                       (const void*)k_sf_dot<double>, (const void*)k_dens_tile<float, true>,
+                       (const void*)k_dens_tile<float, false>,
+                       (const void*)k_dens_tile<double, true>,
+                       (const void*)k_dens_tile<double, false>};
   for (const void* f : fns) {
     hipFuncAttributes a;
     const hipError_t e = hipFuncGetAttributes(&a, f);
@@ -1114,21 +1118,34 @@ int launch_sparse_values(int f64, void* stream, const SfDev* sf, const wvl_seg* 
 int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff,
                      const void* fine, const int64_t* krow, const int32_t* kcol,
                      const double* kval, int64_t knnz, const int64_t* cptr, const int32_t* csf,
-                     const int* gf, void* rho) {
+                     const int32_t* tord, int64_t n_one, const int* gf, void* rho) {
   const int tx = (gf[0] + kDensTile[0] - 1) / kDensTile[0];
   const int ty = (gf[1] + kDensTile[1] - 1) / kDensTile[1];
   const int tz = (gf[2] + kDensTile[2] - 1) / kDensTile[2];
-  const dim3 g((unsigned)((int64_t)tx * ty * tz));
-  if (f64)
-    hipLaunchKernelGGL(k_dens_tile<double>, g, dim3(64 * kDensWaves), 0, (hipStream_t)stream, sf,
-                       foff,
-                       (const double*)fine, krow, kcol, kval, knnz, cptr, csf, tx, ty, gf[0],
-                       gf[1], gf[2], (double*)rho);
-  else
-    hipLaunchKernelGGL(k_dens_tile<float>, g, dim3(64 * kDensWaves), 0, (hipStream_t)stream, sf,
-                       foff,
-                       (const float*)fine, krow, kcol, kval, knnz, cptr, csf, tx, ty, gf[0],
-                       gf[1], gf[2], (float*)rho);
+  const int64_t ntile = (int64_t)tx * ty * tz;
+  const dim3 blk(64 * kDensWaves);
+  hipStream_t st = (hipStream_t)stream;
+  for (int one = 1; one >= 0; --one) {
+    const int64_t base = one ? 0 : n_one, n = one ? n_one : ntile - n_one;
+    if (n == 0) continue;
+    const dim3 g((unsigned)n);
+    if (f64 && one)
+      hipLaunchKernelGGL((k_dens_tile<double, true>), g, blk, 0, st, sf, foff,
+                         (const double*)fine, krow, kcol, kval, knnz, cptr, csf, tord, base, tx,
+                         ty, gf[0], gf[1], gf[2], (double*)rho);
+    else if (f64)
+      hipLaunchKernelGGL((k_dens_tile<double, false>), g, blk, 0, st, sf, foff,
+                         (const double*)fine, krow, kcol, kval, knnz, cptr, csf, tord, base, tx,
+                         ty, gf[0], gf[1], gf[2], (double*)rho);
+    else if (one)
+      hipLaunchKernelGGL((k_dens_tile<float, true>), g, blk, 0, st, sf, foff,
+                         (const float*)fine, krow, kcol, kval, knnz, cptr, csf, tord, base, tx,
+                         ty, gf[0], gf[1], gf[2], (float*)rho);
+    else
+      hipLaunchKernelGGL((k_dens_tile<float, false>), g, blk, 0, st, sf, foff,
+                         (const float*)fine, krow, kcol, kval, knnz, cptr, csf, tord, base, tx,
+                         ty, gf[0], gf[1], gf[2], (float*)rho);
+  }
   return (int)hipGetLastError();
 }
 
