@@ -1388,8 +1388,8 @@ static wvl_status ensure_cover(wvl_plan* P) {
                 (long long)maxc, kDensMaxCover);
   if (P->nsf >= (1 << 24))   // the tile kernel's lookup keys hold 24-bit indices
     return fail(ctx, WVL_EUNSUPPORTED, "density: more than 2^24 - 1 functions");
-  // FP32: the tiles that fit one staged chunk first (a launch of their own,
-  // with less LDS per workgroup), then the others.  FP64 (chunks of 64, so
+  // FP32: the tiles of at most kDensChunkOne functions first (a launch of
+  // their own, with less LDS per workgroup), then the others.  FP64 (chunks of 64, so
   // about half the tiles need two) runs all tiles in one launch, which
   // measured faster.
   std::vector<int32_t> tord[2];
@@ -1402,8 +1402,8 @@ static wvl_status ensure_cover(wvl_plan* P) {
     }
     for (int pass = 0; pass < 2; ++pass)
       for (int64_t t = 0; t < ntile; ++t)
-        if ((cptr[t + 1] - cptr[t] <= kDensChunk[d]) == (pass == 0)) tord[d].push_back((int32_t)t);
-    for (int64_t t = 0; t < ntile; ++t) P->dens_one[d] += cptr[t + 1] - cptr[t] <= kDensChunk[d];
+        if ((cptr[t + 1] - cptr[t] <= kDensChunkOne) == (pass == 0)) tord[d].push_back((int32_t)t);
+    for (int64_t t = 0; t < ntile; ++t) P->dens_one[d] += cptr[t + 1] - cptr[t] <= kDensChunkOne;
   }
   auto drop = [&]() {
     for (void** p : {(void**)&P->d_cptr, (void**)&P->d_csf, (void**)&P->d_tord[0],

@@ -110,10 +110,12 @@ int launch_up_z(int f64, void* stream, const SfWork* wk, const SfDev* sf, int ns
 // with the functions whose fine box meets them (at most kDensMaxCover)
 // with the functions whose fine box meets them (at most kDensMaxCover),
 // staged kDensChunk[FP32, FP64] functions at a time.  tord lists the tiles:
-// first the n_one with at most one chunk, then the others.
+// first the n_one with at most kDensChunkOne functions (FP32), then the
+// others.
 constexpr int kDensTile[3] = {16, 4, 1};
 constexpr int kDensMaxCover = 1024;
 constexpr int kDensChunk[2] = {128, 64};
+constexpr int kDensChunkOne = 120;   // FP32 tiles of one chunk (four workgroups per CU)
 int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff,
                      const void* fine, const int64_t* krow, const int32_t* kcol,
                      const double* kval, int64_t knnz, const int64_t* cptr, const int32_t* csf,

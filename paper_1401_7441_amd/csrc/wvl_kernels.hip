@@ -363,8 +363,9 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <int LNB>
 __device__ __forceinline__ int dens_bucket(int b) {
-  return (int)(((uint32_t)b * 2654435761u) >> 24);
+  return (int)(((uint32_t)b * 2654435761u) >> (32 - LNB));
 }
 
 // position of function b in a bucket of (function << 8 | position), or -1
@@ -378,8 +379,9 @@ __device__ __forceinline__ int dens_match(uint4 v, int b) {
   return p;
 }
 
-// ONE: every tile of the launch has at most C functions (one chunk), and the
-// second chunk buffer is left out (more workgroups fit in a CU's LDS)
+// ONE: every tile of the launch has at most C functions (one chunk; in FP32
+// kDensChunkOne), and the second chunk buffer is left out, the cover list and
+// the hash sized to one chunk (more workgroups fit in a CU's LDS)
 template <typename T, bool ONE>
 __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
     const SfDev* __restrict__ sfs, const int64_t* __restrict__ foff, const T* __restrict__ fine,
@@ -387,20 +389,20 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
     const double* __restrict__ kval, int64_t knnz, const int64_t* __restrict__ cptr,
     const int32_t* __restrict__ csf, const int32_t* __restrict__ tord, int64_t tbase, int tx,
     int ty, int g0, int g1, int g2, T* __restrict__ rho) {
-  constexpr int C = kDensChunk[sizeof(T) == 4 ? 0 : 1];   // functions per staged chunk
+  // functions per staged chunk
+  constexpr int C = ONE && sizeof(T) == 4 ? kDensChunkOne : kDensChunk[sizeof(T) == 4 ? 0 : 1];
+  constexpr int LNB = ONE ? 7 : 8;   // log2 of the hash buckets
+  constexpr int NBK = 1 << LNB;
   __shared__ T vi[C * 64], vj[ONE ? 1 : C * 64];
-  __shared__ int32_t cov[kDensMaxCover];
+  __shared__ int32_t cov[ONE ? C : kDensMaxCover];
   __shared__ int32_t lj[kDensWaves][64];
   __shared__ double lk[kDensWaves][64];
-  // the j-chunk's functions by index: 256 buckets of four slots
-  // (function << 8 | position in the chunk); the final reduction reuses the
-  // space
-  __shared__ __align__(16) unsigned char hraw[kDensWaves * 64 * sizeof(double)];
-  uint4* hb = reinterpret_cast<uint4*>(hraw);
-  uint32_t* hslot = reinterpret_cast<uint32_t*>(hraw);
-  double (*red)[64] = reinterpret_cast<double (*)[64]>(hraw);
-  static_assert(kDensWaves * 64 * sizeof(double) == 256 * sizeof(uint4), "hash size");
-  static_assert(C <= 256, "chunk positions need 8 bits");
+  // the j-chunk's functions by index: NBK buckets of four slots
+  // (function << 8 | position in the chunk)
+  __shared__ uint4 hb[NBK];
+  uint32_t* hslot = reinterpret_cast<uint32_t*>(hb);
+  double (*red)[64] = lk;   // the final reduction reuses lk
+  static_assert(C <= 256 && 4 * NBK >= 2 * C, "chunk positions need 8 bits, the hash room");
   const int tile = tord[tbase + blockIdx.x];
   const int ix = tile % tx, iy = (tile / tx) % ty, iz = tile / (tx * ty);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -432,14 +434,14 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
         for (int j = wave; j < nj; j += kDensWaves) vj[j * 64 + lane] = value(cov[jc + j]);
         vb = vj;
       }
-      for (int h = tid; h < 4 * 256; h += 64 * kDensWaves) hslot[h] = 0xFFFFFFFFu;
+      for (int h = tid; h < 4 * NBK; h += 64 * kDensWaves) hslot[h] = 0xFFFFFFFFu;
       __syncthreads();
-      // 1024 slots > nj: every insertion finds a free slot, every lookup a
+      // 4 NBK slots > nj: every insertion finds a free slot, every lookup a
       // bucket that is not full
       if (tid < nj) {
         const int b = cov[jc + tid];
         const uint32_t key = ((uint32_t)b << 8) | (uint32_t)tid;
-        for (int bk = dens_bucket(b);; bk = (bk + 1) & 255) {
+        for (int bk = dens_bucket<LNB>(b);; bk = (bk + 1) & (NBK - 1)) {
           int c = 0;
           while (c < 4 && atomicCAS(&hslot[4 * bk + c], 0xFFFFFFFFu, key) != 0xFFFFFFFFu) ++c;
           if (c < 4) break;
@@ -484,11 +486,11 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
           int j = -1;
           double kq = 0.0;
           if (b >= blo && b <= bhi) {   // b's position in the j-chunk, if any
-            int bk = dens_bucket(b);
+            int bk = dens_bucket<LNB>(b);
             uint4 v = hb[bk];
             int p = dens_match(v, b);
             while (p < 0 && v.w != 0xFFFFFFFFu) {
-              bk = (bk + 1) & 255;
+              bk = (bk + 1) & (NBK - 1);
               v = hb[bk];
               p = dens_match(v, b);
             }
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(64 * kDensWaves) void k_dens_tile(
         q0 = max((int64_t)0, n0);
         q1 = min(knnz, n1);
       }
-      __syncthreads();   // vi / vj and the hash no longer read
+      __syncthreads();   // vi / vj, the hash and lk no longer read
     }
   }
   red[wave][lane] = acc;
