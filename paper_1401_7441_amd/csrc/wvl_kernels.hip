@@ -347,7 +347,7 @@ __global__ __launch_bounds__(64) void k_sparse_values(const SfDev* __restrict__ 
 // cover, increasing index) are taken in chunks of C: the values phi_a(r) of
 // an i-chunk and a j-chunk are staged in LDS (0 outside a box).  Wave w takes
 // the functions a = i-chunk entries w, w + 8, ...: it scans the kernel row a
-// for the columns b in the j-chunk (binary search in the cover), kept in row
+// for the columns b in the j-chunk (an LDS hash of the chunk), kept in row
 // order, and accumulates
 //   rho_w(r) += phi_a(r) sum_{b in row a, j-chunk} K[q] phi_b(r);
 // rho(r) is then rho_0 + rho_1 + ... + rho_7.  The order of every sum is
