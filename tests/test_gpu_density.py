@@ -4,12 +4,17 @@ Eq. (density)) through the C ABI, against the oracle.
 Tolerances: FP64 1e-12 and FP32 1e-5, relative to the largest magnitude of
 the array compared (the values and products are sums of many terms of both
 signs, so an elementwise relative bound has no meaning near zeros)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
+import inputs
 from oracle import density as D
+from oracle import locreg as LR
+from oracle import sparse as SP
 from tests.test_gpu_batching import _mixed_case
-from tests.test_gpu_parity import _print, _sphere_case
+from tests.test_gpu_parity import Case, _print, _sphere_case
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -40,10 +45,11 @@ def _synth(case, dt):
     return plan, psi, fine
 
 
-def _kernel_on_s_pattern(plan, psi, nsf, seed):
-    """K = sum_i f_i c_i c_i^T (three orbitals) kept on the overlap pattern."""
-    rowptr, col, _ = W.sparse_overlap(plan, psi, psi, False)
-    rp, cl = rowptr.cpu().numpy(), col.cpu().numpy()
+def _kernel_on_s_pattern(lrs, nsf, seed):
+    """K = sum_i f_i c_i c_i^T (three orbitals) kept on the overlap pattern
+    (the oracle's)."""
+    rp, cl = SP.pattern(lrs, False)
+    cl = cl.astype(np.int32)
     rng = np.random.default_rng(seed)
     c = rng.standard_normal((3, nsf))
     f = rng.uniform(0.2, 2.0, 3)
@@ -73,7 +79,7 @@ def test_density_against_oracle(spheres, dtype):
     dt = torch.float64 if dtype == "f64" else torch.float32
     plan, psi, fine = _synth(spheres, dt)
     nsf = len(spheres.lrs)
-    rp, cl, val = _kernel_on_s_pattern(plan, psi, nsf, seed=7)
+    rp, cl, val = _kernel_on_s_pattern(spheres.lrs, nsf, seed=7)
     n = spheres.g.grid_n
     rho = torch.full(((2 * n[2] + 29) * (2 * n[1] + 29) * (2 * n[0] + 29),), float("nan"),
                      dtype=dt, device="cuda")
@@ -130,7 +136,7 @@ def test_density_on_uneven_boxes():
     case = _mixed_case(nsf=6, seed=11)
     plan, psi, fine = _synth(case, torch.float64)
     nsf = len(case.lrs)
-    rp, cl, val = _kernel_on_s_pattern(plan, psi, nsf, seed=8)
+    rp, cl, val = _kernel_on_s_pattern(case.lrs, nsf, seed=8)
     n = case.g.grid_n
     rho = torch.empty((2 * n[2] + 29) * (2 * n[1] + 29) * (2 * n[0] + 29), dtype=torch.float64,
                       device="cuda")
@@ -139,3 +145,42 @@ def test_density_on_uneven_boxes():
     torch.cuda.synchronize()
     want = D.density(case.lrs, case.coefs, (rp, cl, val), n).ravel()
     assert np.max(np.abs(rho.cpu().numpy() - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.fixture(scope="module")
+def many():
+    """130 identical 4^3 boxes (grid 20^3), seeded coefficients, K dense (all
+    pairs), and the oracle's rho (computed once for both types)."""
+    n = 130
+    lrs = [LR.box_locreg((8, 8, 8), (4, 4, 4), (9, 9, 9), (10, 10, 10)) for _ in range(n)]
+    g1 = inputs.geometry("single")   # grid 20^3, its centre inside the boxes
+    geo = dataclasses.replace(g1, centers=np.repeat(g1.centers, n, axis=0),
+                              radii=np.repeat(g1.radii, n), fine_radii=np.repeat(g1.fine_radii, n),
+                              envelope_sigma=np.repeat(g1.envelope_sigma, n))
+    case = Case(geo, lrs)
+    rng = np.random.default_rng(12)
+    c = rng.standard_normal((3, n))
+    K = sum(f * np.outer(ci, ci) for f, ci in zip(rng.uniform(0.2, 2.0, 3), c))
+    want = D.density(case.lrs, case.coefs, K, case.g.grid_n).ravel()
+    return case, K, want
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_density_many_functions_per_tile(many, dtype):
+    """Every tile of the boxes' fine region is met by 130 functions, more
+    than one staged chunk (64 in FP64, 120 and 128 in FP32), so the
+    multi-chunk path runs."""
+    _print(f"case: density, 130 functions per tile, {dtype}")
+    case, K, want = many
+    n = len(case.lrs)
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    plan, psi, fine = _synth(case, dt)
+    g = case.g.grid_n
+    rho = torch.empty((2 * g[2] + 29) * (2 * g[1] + 29) * (2 * g[0] + 29), dtype=dt,
+                      device="cuda")
+    W.density(plan, fine, torch.arange(0, n * n + 1, n, device="cuda"),
+              torch.arange(n, dtype=torch.int32, device="cuda").repeat(n),
+              torch.tensor(K.ravel(), device="cuda"), rho)
+    torch.cuda.synchronize()
+    got = rho.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - want)) <= TOL[dtype] * np.max(np.abs(want))
