@@ -457,7 +457,7 @@ def foe_scratch_bytes(plan: Plan, npl, keep=True):
     """Scratch bytes of wvl_foe: with every Chebyshev matrix kept (one
     recursion), or the smaller size that runs the recursion twice."""
     nnz_s = sparse_pattern_nnz(plan, False)
-    npl = int(npl)
+    npl = max(1, int(npl))   # wvl_foe itself rejects npl < 1
     return 8 * ((npl + 7) * nnz_s + 2 * npl + 6) if keep else 8 * (9 * nnz_s + npl + 5)
 
 
