@@ -8,7 +8,7 @@ H matrix values on their (resident) sparsity patterns.  Inputs are resident
 in HBM before the timed region starts; patterns are built once at set-up and
 timed separately (the localization regions do not change between steps).
 
-    python bench.py [--steps K] [--warmup W] [--workload batch1k|gpu16k|single]
+    python bench.py [--steps K] [--warmup W] [--workload gpu16k|batch1k|sweep2k]
                     [--dtype f32|f64] [--no-cpu-baseline]
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
@@ -126,7 +126,8 @@ def path_bytes(locregs, sz):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("wvl_kernels.hip", "wvl_fused.hip", "wvl_host.cpp", "wvl_internal.h", "wvl_filters.h"):
+    for f in ("wvl_kernels.hip", "wvl_fused.hip", "wvl_host.cpp", "wvl_internal.h",
+              "wvl_filters.h"):
         with open(os.path.join(ROOT, "paper_1401_7441_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -318,32 +319,128 @@ def foe_section(S, npl=100, delta=1.0, reps=2):
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
 
-def cpu_baseline(workload, budget_s=20.0, max_sf=64):
+_ORACLE = {}
+
+
+def _usable_cores():
+    """Host cores this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the share of the host given to a job)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_prepare(workload):
+    """Oracle set-up for the CPU baseline, done before the GPU is touched so
+    that the worker processes forked here hold no GPU state: the geometry,
+    the oracle's sphere sets (fine-set union included) and the potential
+    in FP64.  Returns the pool of workers (one per usable core)."""
+    import multiprocessing as mp
+
+    import inputs
+    from oracle import locreg
+    t0 = time.perf_counter()
+    g = inputs.geometry(workload)
+    _ORACLE["g"] = g
+    _ORACLE["spheres"] = locreg.SphereSet(g.h, g.grid_n, g.centers, g.radii, g.fine_radii,
+                                          g.ext)
+    _ORACLE["pot"] = inputs.potential(g).numpy()
+    cores = _usable_cores()
+    pool = mp.get_context("fork").Pool(cores, initializer=_oracle_worker_init)
+    log(f"cpu baseline: oracle set-up {time.perf_counter() - t0:.1f} s, {cores} workers")
+    return pool, cores
+
+
+def _oracle_worker_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        _ORACLE["limits"] = threadpool_limits(1)     # one core per worker
+    except ImportError:
+        pass
+
+
+def _oracle_task(task):
+    """One function: the oracle's FP64 local-H apply (timed), then its error
+    against the GPU's output of the timed step.  Skipped (None) once the
+    shared deadline has passed."""
     import numpy as np
 
     import inputs
     from oracle import hamiltonian, locreg
-    g = inputs.geometry(workload)
-    t0 = time.perf_counter()
-    lrs = locreg.sphere_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
-    pot = inputs.potential(g).numpy()
-    log(f"cpu baseline: oracle set-up {time.perf_counter() - t0:.1f} s")
-    done = 0
-    elapsed = 0.0
-    pts = 0
-    while done < max_sf and (elapsed < budget_s or done < 2):
-        l = lrs[done]
-        c = inputs.coefficients(g, done, locreg.points_from_segments(l.cseg),
-                                locreg.points_from_segments(l.fseg))
-        t = time.perf_counter()
-        hamiltonian.apply_local_ham(l, c, pot, g.h)
-        elapsed += time.perf_counter() - t
-        pts += int(np.prod([2 * d + 29 for d in l.dims]))
-        done += 1
-    return {"value": done / elapsed, "unit": "SF H-applies/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {len(lrs)} support functions of {workload}, local H "
-                      f"apply only (no S/H), FP64 numpy oracle, {elapsed:.1f} s",
-            "fine_grid_pts_per_s": pts / elapsed}
+    k, deadline, got, ek, ep = task
+    if time.time() > deadline:
+        return None
+    g = _ORACLE["g"]
+    l = _ORACLE["spheres"].locreg(k)
+    c = inputs.coefficients(g, k, locreg.points_from_segments(l.cseg),
+                            locreg.points_from_segments(l.fseg))
+    t = time.perf_counter()
+    ref, rk, rp = hamiltonian.apply_local_ham(l, c, _ORACLE["pot"], g.h)
+    dt = time.perf_counter() - t
+    err = float(np.linalg.norm(got.astype(np.float64) - ref) / np.linalg.norm(ref))
+    return k, dt, int(np.prod([2 * d + 29 for d in l.dims])), err, abs(ek - rk), abs(ep - rp)
+
+
+def cpu_baseline_submit(pool, S, cores, deadline_s=20.0, per_core=48, seed=7441):
+    """Starts the oracle on a seeded random sample of the workload's functions
+    (at most per_core per worker; the GPU's outputs of the timed step, copied
+    to the host here, go with each task); returns the pending result."""
+    import numpy as np
+    import torch
+    nsf = len(S["lr"])
+    order = [int(k) for k in np.random.default_rng(seed).permutation(nsf)[:per_core * cores]]
+    ek = S["ek"].cpu().numpy()
+    ep = S["ep"].cpu().numpy()
+    spans = []
+    for k in order:
+        r = S["lr"][k]
+        spans.append((int(r["ocoef_off"]), int(r["on_c"]) + 7 * int(r["on_f"])))
+    flat = torch.cat([S["hpsi"][o:o + n] for o, n in spans]).cpu().numpy()
+    ends = np.cumsum([n for _, n in spans])
+    deadline = time.time() + deadline_s
+    tasks = [(k, deadline, flat[e - n:e], float(ek[k]), float(ep[k]))
+             for k, (_, n), e in zip(order, spans, ends)]
+    return pool.imap_unordered(_oracle_task, tasks), deadline_s
+
+
+def cpu_baseline_collect(pending, cores, workload, pool):
+    results, deadline_s = pending
+    done = [r for r in results if r is not None]
+    pool.close()
+    pool.join()
+    if not done:
+        return None, None
+    t_apply = sum(r[1] for r in done)
+    pts = sum(r[2] for r in done)
+    rate = len(done) / (t_apply / cores)
+    base = {"value": rate, "unit": "SF H-applies/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(done)} of the workload's support functions in a seeded random "
+                      f"order, local H apply only (no S/H), FP64 numpy oracle, one function "
+                      f"per worker process at a time on {cores} cores for about "
+                      f"{deadline_s:.0f} s; rate = functions / (summed apply time / cores)",
+            "fine_grid_pts_per_s": pts / (t_apply / cores),
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+    acc = {"n_sf": len(done), "workload": workload,
+           "hpsi_rel_max": max(r[3] for r in done),
+           "e_kin_abs_max_ha": max(r[4] for r in done),
+           "e_pot_abs_max_ha": max(r[5] for r in done),
+           "note": "GPU output of the timed step against the FP64 oracle on the sampled "
+                   "functions (each normalized): H|phi> per-function relative 2-norm error, "
+                   "energies absolute per function"}
+    return base, acc
 
 
 # ---------------------------------------------------------------------------
@@ -353,7 +450,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch1k", choices=["batch1k", "gpu16k", "sweep2k"])
+    ap.add_argument("--workload", default="gpu16k", choices=["batch1k", "gpu16k", "sweep2k"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true",
@@ -378,6 +475,10 @@ def main():
               "sharding of this path is a design in the notes, not part of this build",
               file=sys.stderr)
         sys.exit(2)
+    pool = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the workers are forked here
+        pool, cores = cpu_baseline_prepare(args.workload)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     import paper_1401_7441_amd as W  # noqa: F401  (fails loudly without libwvl.so)
@@ -415,6 +516,9 @@ def main():
         run()
     torch.cuda.synchronize()
     dt_s = time.perf_counter() - t0
+    # the oracle on a sample of the functions runs on the host cores while
+    # the sections below use the GPU; the timed step's outputs go with it
+    pending = cpu_baseline_submit(pool, S, cores) if pool is not None else None
     # per-kernel times: library events around every launch of K eager steps
     ctx = S["ctx"]
     prof = {}
@@ -548,8 +652,11 @@ def main():
         log("foe: density kernel by the Fermi operator expansion")
         res["foe"] = foe_section(S)
         log(f"foe: {res['foe']['ms']:.1f} ms")
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.workload)
+    if pending is not None:
+        res["cpu_baseline"], res["accuracy"] = cpu_baseline_collect(pending, cores,
+                                                                    args.workload, pool)
+        log(f"cpu baseline: {res['cpu_baseline']}")
+        log(f"accuracy: {res['accuracy']}")
     if not args.no_serve:
         # free the batch before the serving run takes its HBM budget
         if graph is not None:

@@ -73,9 +73,10 @@ typedef struct {
 } wvl_grid;
 
 /* One segment: the coarse points i1 = i1s..i1e (inclusive) at fixed (i2, i3),
- * in global coarse indices.  `off` is the position of point i1s in the
- * compressed component array the segment belongs to (scaling coefficients
- * for coarse segments, each wavelet component for fine segments). */
+ * in global coarse indices.  `off` is the position of point i1s among the
+ * points of its list: in the compressed layout (see wvl_locreg) the scaling
+ * coefficient of coarse point i1s sits at coef_off + off, and the seven
+ * wavelet coefficients of fine point i1s at coef_off + n_c + 7 off .. + 6. */
 typedef struct {
   int32_t i1s, i1e, i2, i3;
   int64_t off;
@@ -273,7 +274,13 @@ wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int
  *             coefficients, or, in the smaller scratch, forms them again);
  *   K = S^-1/2 K' S^-1/2;  E_BS = Tr(K H~) / sigma + tau Tr(K S).
  * The symmetric part is taken after each two-sided product, since the
- * truncation breaks the symmetry the exact product has.
+ * truncation breaks the symmetry the exact product has.  Spectrum guard:
+ * with the Taylor S^-1/2, H~' can reach outside [-1, 1] even for exact
+ * bounds (the recursion would then grow without bound); when the Gershgorin
+ * discs [a, b] of H~' do, the recursion runs on (H~' - c I) / r with
+ * [c - r, c + r] = [min(a, -1), max(b, 1)] and f is taken at
+ * (r x + c) / sigma + tau, which leaves p an approximation of f(H~' / sigma
+ * + tau).  Inside [-1, 1] nothing changes.
  *   s_val:   device double[nnz of P], S values (wvl_sparse_overlap order)
  *   h_val:   device double[nnz of the H pattern], H values
  *   npl:     expansion degree (>= 1); delta: width of the Fermi function
@@ -289,8 +296,8 @@ wvl_status wvl_density(wvl_plan* plan, wvl_dtype dt, const void* fine, const int
  *            recursion twice.  Both give the same values, bit for bit.
  * All arithmetic is in double, sums in fixed orders (bitwise reproducible).
  * Synchronizes (the traces and bounds come back to the host).  Errors:
- * WVL_EINVAL for bad parameters, null buffers or a scratch below the smaller
- * size; WVL_EUNSUPPORTED when P is
+ * WVL_EINVAL for bad parameters, null buffers, a scratch below the smaller
+ * size, or S and H that make H~' not finite; WVL_EUNSUPPORTED when P is
  * not symmetric, not inside the H pattern, lacks a diagonal entry, has a
  * row of more than 1024 entries, or the plan has more than 2^21 functions. */
 wvl_status wvl_foe(wvl_plan* plan, const double* s_val, const double* h_val, int32_t npl,

@@ -16,11 +16,20 @@ localization of the matrices; here the overlap pattern):
 Readings (listed in the design notes): S and H enter through their
 symmetric parts, H read at P's entries; the symmetric part is taken after
 each two-sided product (truncation breaks the symmetry); spectral bounds,
-when not given, are the Gershgorin discs of S^-1/2 H S^-1/2.
+when not given, are the Gershgorin discs of S^-1/2 H S^-1/2.  Spectrum
+guard: with the Taylor S^-1/2, S^-1/2 S S^-1/2 is not I, so H~' can reach
+outside [-1, 1] even for exact bounds, where T^i grows like
+cosh(i acosh|x|).  The Gershgorin discs of H~' are therefore checked; when
+they reach outside, the recursion runs on X = (H~' - c I) / r, with [c - r,
+c + r] = [min(a, -1), max(b, 1)] for the discs [a, b], and f is taken at
+eps(x) = (r x + c) / sigma + tau, so that p(X) still approximates
+f(H~' / sigma + tau).  Inside [-1, 1] (c = 0, r = 1) nothing changes.
 
 Parity: pinned by eigendecompositions (tests/test_oracle_foe.py): with S = I
 and no truncation, K = f(H) to the expansion error; with a general S and no
-truncation, K = S^-1/2 f(H~') S^-1/2 evaluated through eigh.
+truncation, K = S^-1/2 f(H~') S^-1/2 evaluated through eigh, also when the
+guard rescales; the truncated recursion against the column form of App. B
+(each column t_l^j truncated to column l of the pattern after every step).
 """
 from __future__ import annotations
 
@@ -49,10 +58,17 @@ def fermi(eps, mu, delta):
     return 0.5 * erfc((eps - mu) / delta)
 
 
-def foe(S, H, mask, npl, delta, n_occ, eps_min=None, eps_max=None):
+def gershgorin(A):
+    """Smallest and largest end of the Gershgorin discs of the rows of A."""
+    r = np.sum(np.abs(A), axis=1) - np.abs(np.diag(A))
+    return float(np.min(np.diag(A) - r)), float(np.max(np.diag(A) + r))
+
+
+def foe(S, H, mask, npl, delta, n_occ, eps_min=None, eps_max=None, guard=True):
     """Returns (K, mu, E_BS, (eps_min, eps_max)).  S, H dense (n, n); mask
     boolean (n, n), symmetric, holding the diagonal; products truncated to
-    it after every multiplication."""
+    it after every multiplication.  guard=False leaves out the spectrum
+    guard (for tests that show what it prevents)."""
     m = mask.astype(np.float64)
     S = 0.5 * (S + S.T) * m
     H = 0.5 * (H + H.T) * m
@@ -61,25 +77,33 @@ def foe(S, H, mask, npl, delta, n_occ, eps_min=None, eps_max=None):
     sym = lambda A: 0.5 * (A + A.T)
     if eps_min is None or eps_max is None or eps_min >= eps_max:
         Hp = sym(((Sh @ H) * m @ Sh) * m)
-        r = np.sum(np.abs(Hp), axis=1) - np.abs(np.diag(Hp))
-        eps_min, eps_max = float(np.min(np.diag(Hp) - r)), float(np.max(np.diag(Hp) + r))
+        eps_min, eps_max = gershgorin(Hp)
         if not eps_max > eps_min:
             eps_max = eps_min + 1.0
     sigma = 2.0 / (eps_max - eps_min)
     tau = 0.5 * (eps_min + eps_max)
     Htil = sigma * (H - tau * S)                                   # step 1
     Htp = sym(((Sh @ Htil) * m @ Sh) * m)                          # step 2
+    c0, r0 = 0.0, 1.0                                              # spectrum guard
+    if guard:
+        a, b = gershgorin(Htp)
+        if a < -1.0 or b > 1.0:
+            glo, ghi = min(a, -1.0), max(b, 1.0)
+            c0, r0 = 0.5 * (glo + ghi), 0.5 * (ghi - glo)
+            Htp = (Htp - c0 * np.eye(n)) / r0
     T = chebyshev_matrices(Htp, npl, m)                            # step 3
     traces = np.array([np.trace(t) for t in T])
 
     def coef(mu):
-        return chebyshev_coefficients(lambda x: fermi(x / sigma + tau, mu, delta), npl)
+        return chebyshev_coefficients(
+            lambda x: fermi((r0 * x + c0) / sigma + tau, mu, delta), npl)
 
     def trace_kp(mu):
         c = coef(mu)
         return 0.5 * c[0] * traces[0] + float(np.dot(c[1:], traces[1:]))
 
-    lo, hi = eps_min - 20.0 * delta, eps_max + 20.0 * delta        # step 4
+    lo = (c0 - r0) / sigma + tau - 20.0 * delta                    # step 4
+    hi = (c0 + r0) / sigma + tau + 20.0 * delta
     for _ in range(200):
         if hi - lo <= 1e-13 * max(1.0, abs(lo) + abs(hi)):
             break

@@ -121,52 +121,75 @@ def _ball(h, c, r, grid_n, box_lo, box_hi):
     return _dist2(h, c, i1, i2, i3) <= r2, lo
 
 
-def sphere_locregs(h, grid_n, centers, radii, fine_radii, ext):
-    """Locregs of spheres: coarse set radius R, fine set radius r_f, L' radius
-    R + ext*h (see module docstring for the exact rules)."""
-    nsf = len(centers)
-    coarse = []
-    for k in range(nsf):
-        c = [float(v) for v in centers[k]]
-        R = float(radii[k])
-        cand_lo = [int(np.floor((c[a] - R) / h)) - 1 for a in range(3)]
-        cand_hi = [int(np.ceil((c[a] + R) / h)) + 1 for a in range(3)]
-        m, mlo = _ball(h, c, R, grid_n, cand_lo, cand_hi)
-        if not m.any():
-            raise ValueError(f"support function {k}: empty localization region")
-        zz, yy, xx = np.nonzero(m)
-        lo = (mlo[0] + int(xx.min()), mlo[1] + int(yy.min()), mlo[2] + int(zz.min()))
-        hi = (mlo[0] + int(xx.max()), mlo[1] + int(yy.max()), mlo[2] + int(zz.max()))
-        m = m[lo[2] - mlo[2]:hi[2] - mlo[2] + 1, lo[1] - mlo[1]:hi[1] - mlo[1] + 1,
-              lo[0] - mlo[0]:hi[0] - mlo[0] + 1]
-        coarse.append((lo, hi, m))
-    # input fine sets and their union F
-    F = np.zeros((grid_n[2], grid_n[1], grid_n[0]), bool)
-    fine = []
-    for k, (lo, hi, m) in enumerate(coarse):
-        c = [float(v) for v in centers[k]]
-        fm, flo = _ball(h, c, float(fine_radii[k]), grid_n, lo, hi)
-        fm = fm & m
-        fine.append(fm)
-        F[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] |= fm
-    out = []
-    for k, (lo, hi, m) in enumerate(coarse):
-        c = [float(v) for v in centers[k]]
-        Rp = float(radii[k]) + ext * h
-        olo = [lo[a] - ext for a in range(3)]
-        ohi = [hi[a] + ext for a in range(3)]
-        om, omlo = _ball(h, c, Rp, grid_n, olo, ohi)
+class SphereSet:
+    """Coarse and fine sets of spheres (coarse radius R, fine radius r_f) and
+    the union F of the fine sets; locreg(k) builds function k's Locreg with
+    L' radius R + ext*h (see the module docstring for the exact rules)."""
+
+    def __init__(self, h, grid_n, centers, radii, fine_radii, ext):
+        self.h, self.grid_n, self.ext = h, grid_n, ext
+        self.centers, self.radii = centers, radii
+        nsf = len(centers)
+        self.coarse = []
+        for k in range(nsf):
+            c = [float(v) for v in centers[k]]
+            R = float(radii[k])
+            cand_lo = [int(np.floor((c[a] - R) / h)) - 1 for a in range(3)]
+            cand_hi = [int(np.ceil((c[a] + R) / h)) + 1 for a in range(3)]
+            m, mlo = _ball(h, c, R, grid_n, cand_lo, cand_hi)
+            if not m.any():
+                raise ValueError(f"support function {k}: empty localization region")
+            zz, yy, xx = np.nonzero(m)
+            lo = (mlo[0] + int(xx.min()), mlo[1] + int(yy.min()), mlo[2] + int(zz.min()))
+            hi = (mlo[0] + int(xx.max()), mlo[1] + int(yy.max()), mlo[2] + int(zz.max()))
+            m = m[lo[2] - mlo[2]:hi[2] - mlo[2] + 1, lo[1] - mlo[1]:hi[1] - mlo[1] + 1,
+                  lo[0] - mlo[0]:hi[0] - mlo[0] + 1]
+            self.coarse.append((lo, hi, m))
+        # input fine sets and their union F
+        self.F = np.zeros((grid_n[2], grid_n[1], grid_n[0]), bool)
+        self.fine = []
+        for k, (lo, hi, m) in enumerate(self.coarse):
+            c = [float(v) for v in centers[k]]
+            fm, flo = _ball(h, c, float(fine_radii[k]), grid_n, lo, hi)
+            fm = fm & m
+            self.fine.append(fm)
+            self.F[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] |= fm
+
+    def coarse_set(self, k, output=False):
+        """(mask[z, y, x], origin (x, y, z)) of function k's input coarse set,
+        or of its output (L') coarse set."""
+        if not output:
+            lo, hi, m = self.coarse[k]
+            return m, tuple(lo)
+        lo, hi, m = self.coarse[k]
+        c = [float(v) for v in self.centers[k]]
+        Rp = float(self.radii[k]) + self.ext * self.h
+        om, omlo = _ball(self.h, c, Rp, self.grid_n, [lo[a] - self.ext for a in range(3)],
+                         [hi[a] + self.ext for a in range(3)])
+        return om, tuple(omlo)
+
+    def locreg(self, k):
+        h, grid_n, ext, F = self.h, self.grid_n, self.ext, self.F
+        lo, hi, m = self.coarse[k]
+        c = [float(v) for v in self.centers[k]]
+        om, omlo = self.coarse_set(k, output=True)
         if om.size:
             ofm = om & F[omlo[2]:omlo[2] + om.shape[0], omlo[1]:omlo[1] + om.shape[1],
                          omlo[0]:omlo[0] + om.shape[2]]
         else:
             ofm = om
-        out.append(Locreg(
+        return Locreg(
             lo=tuple(lo), dims=tuple(hi[a] - lo[a] + 1 for a in range(3)), ext=int(ext),
-            cseg=segments_from_mask(m, lo), fseg=segments_from_mask(fine[k], lo),
+            cseg=segments_from_mask(m, lo), fseg=segments_from_mask(self.fine[k], lo),
             ocseg=segments_from_mask(om, omlo), ofseg=segments_from_mask(ofm, omlo),
-            center=tuple(float(v) for v in centers[k]), radius=float(radii[k])))
-    return out
+            center=tuple(c), radius=float(self.radii[k]))
+
+
+def sphere_locregs(h, grid_n, centers, radii, fine_radii, ext):
+    """Locregs of spheres: coarse set radius R, fine set radius r_f, L' radius
+    R + ext*h (see module docstring for the exact rules)."""
+    s = SphereSet(h, grid_n, centers, radii, fine_radii, ext)
+    return [s.locreg(k) for k in range(len(centers))]
 
 
 def box_locreg(lo, dims, fine_lo, fine_hi, ext=0):

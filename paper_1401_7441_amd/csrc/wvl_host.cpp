@@ -1625,6 +1625,29 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   WVL_LAUNCH(ctx, KK_FOE, mm(1.0, Sh, Hs, 0.0, nullptr, X));
   WVL_LAUNCH(ctx, KK_FOE, mm(1.0, X, Sh, 0.0, nullptr, Tm(0)));
   WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, tp, Tm(0), Ht));
+  // Spectrum guard: with the Taylor S^-1/2, S^-1/2 S S^-1/2 is not I, so
+  // H~' can reach outside [-1, 1] even for exact bounds, and T^i then grows
+  // like cosh(i acosh|x|).  When its Gershgorin discs [a, b] do, the
+  // recursion runs on X = (H~' - c I) / r with [c - r, c + r] =
+  // [min(a, -1), max(b, 1)], and f is taken at (r x + c) / sigma + tau:
+  // the effective scale sigma / r and shift tau + c / sigma.
+  double gc = 0.0, gr = 1.0;
+  {
+    WVL_LAUNCH(ctx, KK_FOE, launch_foe_gersh(s, n, rp, cl, Ht, X, Tm(0), red));
+    double b[2];
+    WVL_HIP(ctx, hipMemcpyAsync(b, red, sizeof b, hipMemcpyDeviceToHost, s));
+    WVL_HIP(ctx, hipStreamSynchronize(s));
+    if (!std::isfinite(b[0]) || !std::isfinite(b[1]))
+      return fail(ctx, WVL_EINVAL, "wvl_foe: S or H holds values that are not finite");
+    if (b[0] < -1.0 || b[1] > 1.0) {
+      const double glo = std::min(b[0], -1.0), ghi = std::max(b[1], 1.0);
+      gc = 0.5 * (glo + ghi);
+      gr = 0.5 * (ghi - glo);
+      WVL_LAUNCH(ctx, KK_FOE, axpby(1.0 / gr, Ht, 0.0, nullptr, -gc / gr, Tm(0)));
+      WVL_LAUNCH(ctx, KK_FOE, axpby(1.0, Tm(0), 0.0, nullptr, 0.0, Ht));
+    }
+  }
+  const double sig_f = sigma / gr, tau_f = tau + gc / sigma;
   // pass 1: traces of the Chebyshev matrices T^0 .. T^npl
   auto start = [&]() -> wvl_status {
     WVL_LAUNCH(ctx, KK_FOE, axpby(0.0, nullptr, 0.0, nullptr, 1.0, Tm(0)));
@@ -1655,8 +1678,8 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   const FoeCoef& coefficients = *P->foe_coef;
   std::vector<double> coef, g;
   coefficients.weights(trh, &g);
-  auto trace_at = [&](double mu) { return coefficients.trace(g, sigma, tau, mu, delta); };
-  double lo = eps_min - 20.0 * delta, hi = eps_max + 20.0 * delta;
+  auto trace_at = [&](double mu) { return coefficients.trace(g, sig_f, tau_f, mu, delta); };
+  double lo = (gc - gr) / sigma + tau - 20.0 * delta, hi = (gc + gr) / sigma + tau + 20.0 * delta;
   for (int it = 0; it < 200 && hi - lo > 1e-13 * std::max(1.0, std::fabs(lo) + std::fabs(hi));
        ++it) {
     const double mid = 0.5 * (lo + hi);
@@ -1666,7 +1689,7 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
       hi = mid;
   }
   const double mu = 0.5 * (lo + hi);
-  coefficients(sigma, tau, mu, delta, &coef);
+  coefficients(sig_f, tau_f, mu, delta, &coef);
   // pass 2: K' = c_0/2 I + sum_i c_i T^i(H~')
   if (keep) {
     // the host vector must outlive the copy: wait for it before going on

@@ -59,6 +59,8 @@ def test_foe_against_oracle(system, bounds):
                           npl, delta, nocc, emin or 0.0, emax or 0.0)
     got = kv.cpu().numpy()
     want = np.array([K[a, scl[q]] for a in range(n) for q in range(srp[a], srp[a + 1])])
+    _print(f"  K err {np.max(np.abs(got - want)):.2e} of max |K| {np.max(np.abs(want)):.2f}, "
+           f"mu err {abs(gmu - mu):.2e}, E_BS err {abs(gebs - ebs):.2e}")
     assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want))
     assert abs(gmu - mu) <= 1e-9
     assert abs(gebs - ebs) <= 1e-9 * max(1.0, abs(ebs))
@@ -120,6 +122,9 @@ def test_foe_on_long_rows(m):
     for keep in (True, False):
         kv, gmu, gebs = W.foe(plan, sv, hv, npl, delta, nocc, keep=keep)
         got = kv.cpu().numpy()
+        _print(f"  keep {keep}: K err {np.max(np.abs(got - want)):.2e} of max |K| "
+               f"{np.max(np.abs(want)):.2f}, mu err {abs(gmu - mu):.2e}, "
+               f"E_BS err {abs(gebs - ebs):.2e}")
         assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want)), keep
         assert abs(gmu - mu) <= 1e-9 and abs(gebs - ebs) <= 1e-9 * max(1.0, abs(ebs)), keep
         res.append((got, gmu, gebs))
@@ -160,6 +165,8 @@ def test_foe_full_size_lattice():
     kv, gmu, gebs = W.foe(plan, torch.tensor(S[rows, cols], device="cuda"),
                           torch.tensor(H[rows, cols], device="cuda"), npl, delta, nocc)
     want = K[rows, cols]
+    _print(f"  K err {np.max(np.abs(kv.cpu().numpy() - want)):.2e} of max |K| "
+           f"{np.max(np.abs(want)):.2f}, mu err {abs(gmu - mu):.2e}, E_BS err {abs(gebs - ebs):.2e}")
     assert np.max(np.abs(kv.cpu().numpy() - want)) <= 1e-9 * np.max(np.abs(want))
     assert abs(gmu - mu) <= 1e-9 and abs(gebs - ebs) <= 1e-9 * max(1.0, abs(ebs))
 
@@ -178,3 +185,36 @@ def test_foe_rejects_bad_parameters(system):
                         device="cuda")
     with pytest.raises(W.WvlError):
         W.foe(plan, s, h, 10, 0.2, 3.0, scratch=small)
+
+
+def test_foe_spectrum_guard():
+    """Tight Gershgorin bounds with the Taylor S^-1/2: S = I plus 0.4 on the
+    pairs (2k, 2k + 1) of one cluster, H = -8 I plus a small symmetric part,
+    on the three-cluster pattern.  H~' then has eigenvalues near -1.354; the
+    guard of both sides rescales it, and the oracle without the guard is
+    shown to diverge on the same input."""
+    m = 10
+    n = 3 * m
+    _print(f"case: FOE spectrum guard, {n} functions")
+    ctx, plan, mask = _cluster_plan(m)
+    rng = np.random.default_rng(4200)
+    S = np.eye(n)
+    for k in range(0, n - 1, 2):
+        if mask[k, k + 1]:
+            S[k, k + 1] = S[k + 1, k] = 0.4
+    R = rng.standard_normal((n, n))
+    H = (-8.0 * np.eye(n) + 1e-3 * (R + R.T)) * mask
+    rows, cols = np.nonzero(mask)
+    # half an electron above the lower 15 states: mu sits on the upper,
+    # nearly degenerate level, where Tr K'(mu) is steep and mu well defined
+    npl, delta, nocc = 120, 0.5, 0.5 * n + 0.5
+    K, mu, ebs, _ = F.foe(S, H, mask, npl, delta, nocc)
+    assert np.max(np.abs(F.foe(S, H, mask, npl, delta, nocc, guard=False)[0])) > 1e3
+    want = K[rows, cols]
+    assert np.max(np.abs(want)) < 2.0
+    kv, gmu, gebs = W.foe(plan, torch.tensor(S[rows, cols], device="cuda"),
+                          torch.tensor(H[rows, cols], device="cuda"), npl, delta, nocc)
+    err = np.max(np.abs(kv.cpu().numpy() - want))
+    _print(f"  K err {err:.2e} (max |K| {np.max(np.abs(want)):.2f}), mu err {abs(gmu - mu):.2e}")
+    assert err <= 1e-9 * np.max(np.abs(want))
+    assert abs(gmu - mu) <= 1e-9 and abs(gebs - ebs) <= 1e-9 * max(1.0, abs(ebs))

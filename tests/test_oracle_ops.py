@@ -518,3 +518,21 @@ def test_preconditioner_against_a_dense_solve():
     A0 = np.stack([PC.apply_operator(lr, np.eye(n)[i], h, conf, 0.4) for i in range(n)], axis=1)
     A1 = np.stack([PC.apply_operator(lr, np.eye(n)[i], h, conf, 0.0) for i in range(n)], axis=1)
     assert np.array_equal(A0, A1)
+
+
+def test_sphere_set_coarse_sets_match_segments():
+    """SphereSet.coarse_set (the masks the sampled full-size tests intersect
+    to find pattern rows) equals the locreg's own segment lists, input and
+    output, and one function's locreg does not depend on which others are
+    built."""
+    import inputs
+    g = inputs.geometry("batch1k", nsf=6)
+    S = LR.SphereSet(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
+    full = LR.sphere_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
+    for k in (4, 1):
+        l = S.locreg(k)
+        for a, b in ((l.cseg, full[k].cseg), (l.ocseg, full[k].ocseg), (l.ofseg, full[k].ofseg)):
+            assert np.array_equal(a, b)
+        for out, seg in ((False, l.cseg), (True, l.ocseg)):
+            m, lo = S.coarse_set(k, out)
+            assert np.array_equal(LR.mask_from_segments(seg, lo, m.shape), m)
