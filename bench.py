@@ -460,9 +460,21 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's default schedule (one bin, largest row tiles)")
     ap.add_argument("--autotune-reps", type=int, default=2)
+    ap.add_argument("--schedule", default=None, metavar="NBINS,KIN_MFMA",
+                    help="set this schedule instead of autotuning (e.g. 8,1: eight bins, "
+                         "kinetic z part on the matrix cores)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the request-loop measurement (p50/p99 latency)")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the Poisson trace at 0.8 of the saturated rate")
+    ap.add_argument("--serve-pool", type=int, default=32,
+                    help="distinct systems the serving requests are drawn from")
+    ap.add_argument("--serve-other", type=int, default=100,
+                    help="requests at the other offered loads (0.5, 0.95)")
+    ap.add_argument("--serve-saturated", type=int, default=100,
+                    help="requests of the saturated run")
+    ap.add_argument("--serve-baseline", type=int, default=4,
+                    help="requests of the per-function FP64 baseline")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the fine-grid values + density section")
     ap.add_argument("--no-foe", action="store_true",
@@ -497,7 +509,12 @@ def main():
         f"{S['t_pattern'] * 1e3:.1f} ms (S nnz {S['nnz_s']}, H nnz {S['nnz_h']}), "
         f"workspace {S['ws'].numel() / 2**30:.2f} GiB")
     tune = None
-    if not args.no_autotune:
+    if args.schedule:
+        nb, km = (int(v) for v in args.schedule.split(","))
+        W.set_schedule(S["plan"], nb, km)
+        tune = {"set": {"nbins": nb, "kin_mfma": km}}
+        log(f"schedule set: {nb} bins, kin_mfma {km}")
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         best, tried = W.autotune(S["plan"], S["psi"], S["pot"], S["hpsi"], S["ws"],
                                  reps=args.autotune_reps)
@@ -637,7 +654,10 @@ def main():
             "note": "all functions, one apply (kinetic + confinement) per step"},
         "schedule": {"timed": "graph replay" if graph is not None else "eager calls",
                      "eager_ms_per_step": eager_ms,
-                     "nbins": tune["best"]["nbins"] if tune else 1,
+                     "nbins": (tune["best"] if tune and "best" in tune else
+                               tune["set"] if tune else {"nbins": 1})["nbins"],
+                     "kin_mfma": (tune["best"] if tune and "best" in tune else
+                                  tune["set"] if tune else {"kin_mfma": 0})["kin_mfma"],
                      "chunks": S["plan"].info["chunks"],
                      "autotune": tune},
         "setup": {"locregs_s": S["t_locreg"], "patterns_ms": S["t_pattern"] * 1e3},
@@ -667,6 +687,9 @@ def main():
         torch.cuda.empty_cache()
         from paper_1401_7441_amd import serve
         res["serving"] = serve.benchmark(n_requests=args.serve_requests, dtype=args.dtype,
+                                         pool_size=args.serve_pool, n_other=args.serve_other,
+                                         n_saturated=args.serve_saturated,
+                                         baseline_requests=args.serve_baseline,
                                          log=log)
     print(json.dumps(res), flush=True)
 

@@ -304,6 +304,32 @@ wvl_status wvl_foe(wvl_plan* plan, const double* s_val, const double* h_val, int
                    double delta, double n_occ, double eps_min, double eps_max, double* k_val,
                    double* mu, double* e_bs, void* scratch, size_t scratch_bytes);
 
+/* Gradient of the support functions, Eq. (gradient) of Sec. IV.A, in the
+ * energy mode (band-structure energy Omega = sum_ab K^ab H_ab, K fixed),
+ * localized as in Sec. III.A (g_a <- L^a g_a):
+ *   g_a = L^a [ sum_d A_ad H|phi_d> - sum_d M_ad |phi_d> ],
+ *   A = S K,  M = 1/2 S^-1 (Lambda + Lambda^T),  Lambda = H K S,
+ * with S^-1 taken by its first-order Taylor expansion 2 I - S, every matrix on
+ * the overlap pattern P (the pattern wvl_sparse_overlap reports with
+ * ket_is_output = 0; H read at P's entries; S by its symmetric part), every
+ * product truncated to P, and the sums over the functions d of row a of P.
+ *   s_val:  device double[nnz of P], S values
+ *   h_val:  device double[nnz of the H pattern], H values
+ *   k_val:  device double[nnz of P], the density kernel (e.g. from wvl_foe)
+ *   psi_c:  device, input layout; hpsi_c: device, output layout (the result
+ *           of wvl_apply_local_ham)
+ *   g_c:    device, input layout, overwritten with the gradients
+ *   scratch, scratch_bytes: device buffer of at least 56 nnz(P) bytes
+ * Matrix arithmetic in double; each gradient element summed over its row's
+ * functions in CSR order in double and rounded once (rows of more than 256
+ * entries: once per 256).  Asynchronous, except that the first call builds
+ * the patterns and their maps (synchronizes).  Errors: WVL_EINVAL for null
+ * buffers or a small scratch; WVL_EUNSUPPORTED as wvl_foe for patterns it
+ * cannot take. */
+wvl_status wvl_gradient(wvl_plan* plan, wvl_dtype dt, const double* s_val, const double* h_val,
+                        const double* k_val, const void* psi_c, const void* hpsi_c, void* g_c,
+                        void* scratch, size_t scratch_bytes);
+
 /* Support-function update step (the localized gradient step of Sec. III.A
  * and IV.A, reduced to a fixed step length):
  *   psi_a <- psi_a - eta (P_La (H psi)_a - H_aa psi_a)
@@ -367,21 +393,35 @@ void wvl_graph_destroy(wvl_graph* graph);
 
 /* Autotuner over the plan's schedule: for every bin count in
  * {1, 2, 3, 4, 6, 8} (functions sorted by box volume, cut into that many
- * launches per stage), runs the apply `reps` times (after one warm-up) and
- * keeps the fastest layout.  Buffers as for wvl_apply_local_ham (hpsi_c is overwritten; the
+ * launches per stage) and both forms of the kinetic term's z part (the
+ * register-window stencil on the vector units, or banded-Toeplitz products
+ * on the FP64 matrix cores), runs the apply `reps` times (after one warm-up)
+ * and keeps the fastest layout.  Buffers as for wvl_apply_local_ham (hpsi_c is overwritten; the
  * workspace is the size wvl_plan_create reported, which covers every
  * candidate).  tried (host, may be NULL) receives up to max_tried points,
  * *ntried the number timed, *best the chosen one.  Synchronous; the plan
- * must not be in use on another stream meanwhile.  Results of later calls
- * do not depend on the layout chosen (bitwise). */
+ * must not be in use on another stream meanwhile.  A change of bin count
+ * alone leaves later results bitwise unchanged; the matrix-core z part sums
+ * in another order and agrees with the vector form to the parity
+ * tolerances. */
 typedef struct {
   int32_t nbins;      /* bins of the size-sorted functions */
+  int32_t kin_mfma;   /* 1: z part of the kinetic term on the matrix cores */
   double ms;          /* mean duration of one apply */
 } wvl_tune_point;
 wvl_status wvl_plan_autotune(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const void* psi_c,
                              const void* pot, void* hpsi_c, void* workspace, int32_t reps,
                              wvl_tune_point* tried, int32_t max_tried, int32_t* ntried,
                              wvl_tune_point* best);
+
+/* Sets the plan's schedule directly (a point wvl_plan_autotune tries): nbins
+ * bins of the size-sorted functions, kin_mfma 1 for the z part of the
+ * kinetic term on the matrix cores.  Synchronous; graphs captured before are
+ * rejected afterwards.  Results agree with every other schedule to the
+ * parity tolerances (bitwise for a change of nbins alone).  Errors:
+ * WVL_EINVAL for nbins < 1, kin_mfma outside {0, 1}, or a schedule that
+ * needs more workspace than the plan reported (bins beyond 8 may). */
+wvl_status wvl_plan_set_schedule(wvl_plan* plan, int32_t nbins, int32_t kin_mfma);
 
 /* Kernel tracing.  With profiling enabled, every kernel the context launches
  * is bracketed by two HIP events recorded on the context's stream; times

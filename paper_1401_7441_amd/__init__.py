@@ -43,10 +43,10 @@ LOCREG_DTYPE = np.dtype([
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
             "wvl_compress", "wvl_apply_local_ham", "wvl_apply_local_ham_conf", "wvl_kinetic",
-            "wvl_sparse_overlap", "wvl_synthesize", "wvl_density", "wvl_foe",
+            "wvl_sparse_overlap", "wvl_synthesize", "wvl_density", "wvl_foe", "wvl_gradient",
             "wvl_update", "wvl_precondition", "wvl_graph_create", "wvl_graph_launch",
             "wvl_graph_destroy",
-            "wvl_plan_autotune",
+            "wvl_plan_autotune", "wvl_plan_set_schedule",
             "wvl_profile_enable", "wvl_profile_reset", "wvl_profile_count", "wvl_profile_read")
 
 
@@ -61,7 +61,7 @@ class _Grid(ctypes.Structure):
 
 
 class _TunePoint(ctypes.Structure):
-    _fields_ = [("nbins", ctypes.c_int32), ("ms", ctypes.c_double)]
+    _fields_ = [("nbins", ctypes.c_int32), ("kin_mfma", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -108,6 +108,7 @@ def _load():
         "wvl_foe": [P, P, P, I32, D, D, D, D, P, ctypes.POINTER(D), ctypes.POINTER(D), P,
                     ctypes.c_size_t],
         "wvl_density": [P, ctypes.c_int, P, P, P, P, I64, P, P],
+        "wvl_gradient": [P, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_size_t],
         "wvl_update": [P, ctypes.c_int, D, P, P, P],
         "wvl_precondition": [P, ctypes.c_int, P, P, P, I32, P, P, P],
         "wvl_graph_create": [P, ctypes.c_int, U32, P, P, P, P, P, P, P, P, ctypes.POINTER(P)],
@@ -115,6 +116,7 @@ def _load():
         "wvl_graph_destroy": [P],
         "wvl_plan_autotune": [P, ctypes.c_int, U32, P, P, P, P, I32, ctypes.POINTER(_TunePoint),
                               I32, ctypes.POINTER(I32), ctypes.POINTER(_TunePoint)],
+        "wvl_plan_set_schedule": [P, I32, I32],
         "wvl_profile_enable": [P, ctypes.c_int],
         "wvl_profile_reset": [P],
         "wvl_profile_count": [],
@@ -406,6 +408,33 @@ def sparse_overlap(plan: Plan, bra_c, ket_c, ket_is_output: bool, out=None, valu
     return rowptr, col[:nnz], val[:nnz]
 
 
+def gradient_scratch_bytes(plan: Plan):
+    return 56 * max(1, sparse_pattern_nnz(plan, False))
+
+
+def gradient(plan: Plan, s_val, h_val, k_val, psi_c, hpsi_c, g_c=None, scratch=None):
+    """wvl_gradient: the localized support-function gradients (input layout)
+    from S, H, the density kernel K (float64 device tensors in the CSR orders
+    of the S / H patterns), psi_c and hpsi_c.  Returns g_c."""
+    import torch
+    _need_cuda(s_val, h_val, k_val, psi_c, hpsi_c, g_c, scratch)
+    dt = _dtype_code(psi_c, hpsi_c) if g_c is None else _dtype_code(psi_c, hpsi_c, g_c)
+    nnz_s, nnz_h = sparse_pattern_nnz(plan, False), sparse_pattern_nnz(plan, True)
+    for t, n in ((s_val, nnz_s), (k_val, nnz_s), (h_val, nnz_h)):
+        if t.dtype != torch.float64 or t.numel() < n:
+            raise WvlError(WVL_EINVAL, "matrix values must be float64 on their pattern")
+    if psi_c.numel() < plan.info["in_coefs"] or hpsi_c.numel() < plan.info["out_coefs"]:
+        raise WvlError(WVL_EINVAL, "coefficient buffer smaller than the plan's layout")
+    if g_c is None:
+        g_c = torch.empty(max(1, plan.info["in_coefs"]), dtype=psi_c.dtype, device="cuda")
+    if scratch is None:
+        scratch = torch.empty(gradient_scratch_bytes(plan), dtype=torch.uint8, device="cuda")
+    _check(lib().wvl_gradient(plan._ptr, dt, _ptr(s_val), _ptr(h_val), _ptr(k_val), _ptr(psi_c),
+                             _ptr(hpsi_c), _ptr(g_c), _ptr(scratch),
+                             scratch.numel() * scratch.element_size()), plan.ctx.handle)
+    return g_c
+
+
 def update(plan: Plan, psi_c, hpsi_c, h_val, eta):
     """wvl_update: psi_c <- psi_c - eta (P_L hpsi_c - H_aa psi_c), in place;
     h_val are the H values (float64, the plan's CSR order)."""
@@ -560,8 +589,14 @@ class Graph:
             pass
 
 
+def set_schedule(plan: Plan, nbins=1, kin_mfma=0):
+    """wvl_plan_set_schedule: fix the plan's schedule (bins, z-kinetic form)."""
+    _check(lib().wvl_plan_set_schedule(plan._ptr, int(nbins), int(kin_mfma)), plan.ctx.handle)
+    plan.info = plan._read_info()
+
+
 def autotune(plan: Plan, psi_c, pot, hpsi_c, workspace, reps=3, terms=KIN | POT):
-    """wvl_plan_autotune -> (best, tried): dicts {nbins, ms}."""
+    """wvl_plan_autotune -> (best, tried): dicts {nbins, kin_mfma, ms}."""
     _need_cuda(psi_c, pot, hpsi_c, workspace)
     dt = _dtype_code(psi_c, pot, hpsi_c)
     _check_sizes(plan, psi_c, hpsi_c, None, None, workspace, dt)
@@ -571,6 +606,6 @@ def autotune(plan: Plan, psi_c, pot, hpsi_c, workspace, reps=3, terms=KIN | POT)
     _check(lib().wvl_plan_autotune(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
                                    _ptr(hpsi_c), _ptr(workspace), int(reps), tried, 32,
                                    ctypes.byref(n), ctypes.byref(best)), plan.ctx.handle)
-    as_dict = lambda t: {"nbins": t.nbins, "ms": t.ms}
+    as_dict = lambda t: {"nbins": t.nbins, "kin_mfma": t.kin_mfma, "ms": t.ms}
     plan.info = plan._read_info()
     return as_dict(best), [as_dict(tried[i]) for i in range(n.value)]

@@ -488,9 +488,14 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
   // AX = 1: where this lane's column starts in the output (-1: no column)
   const int colbase0 = active ? (int)(out0 - outb) : -1;   // < 8 N2 N0 O1
   const int colbase1 = active ? (int)(out1 - outb) : -1;
-  T x0[32], x1[32];
+  // the scaling-channel window in double: its differences are then exact
+  double x0[32];
+  T x1[32];
 #pragma unroll
-  for (int k = 0; k < 32; ++k) x0[k] = x1[k] = T(0);
+  for (int k = 0; k < 32; ++k) {
+    x0[k] = 0.0;
+    x1[k] = T(0);
+  }
   double eacc = 0.0;
   const int istart = 14 - e;           // emits i' = -e first
   const int iend = NA - 1 + e + 14;    // emits i' = NA - 1 + e last
@@ -501,25 +506,31 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
     for (int u = 0; u < 32; ++u) {
       const int i = i0 + u;
       const bool ok = active && i >= 0 && i < NA;
-      x0[u] = ok ? in0[(int64_t)i * istride] : T(0);
+      x0[u] = ok ? (double)in0[(int64_t)i * istride] : 0.0;
       x1[u] = ok ? in1[(int64_t)i * istride] : T(0);
       if (i >= istart && i <= iend) {
         const int ip = i - 14;            // output coarse index i'
         const int sc = (u + 18) & 31;     // slot of x(i') = x(i - 14)
         double r0, r1;
         if (sizeof(T) == 4) {
-          T s0 = T(0), s1 = T(0);
+          // scaling-channel taps in the difference form with FP64 taps,
+          // summed in double (the differences of FP32 values are exact
+          // there), completed by the row sums D_a; wavelet taps in FP32
+          double s0 = 0.0, s1 = 0.0;
+          T w0 = T(0), w1 = T(0);
 #pragma unroll
           for (int t = 0; t < 29; ++t) {
             if (t == 14) continue;
             const int sl = (u + 4 + t) & 31;    // x(i - 28 + t) = x(i' + t - 14)
-            const T d0 = x0[sl] - x0[sc];
-            s0 += Kt<T>(0, 0, t) * d0 + Kt<T>(0, 1, t) * x1[sl];
-            s1 += Kt<T>(1, 0, t) * d0 + Kt<T>(1, 1, t) * x1[sl];
+            const double d0 = x0[sl] - x0[sc];
+            s0 += fK64[0][0][t] * d0;
+            s1 += fK64[1][0][t] * d0;
+            w0 += Kt<T>(0, 1, t) * x1[sl];
+            w1 += Kt<T>(1, 1, t) * x1[sl];
           }
-          const double c0 = (double)x0[sc], c1 = (double)x1[sc];
-          r0 = fac * ((double)s0 + fKD64[0] * c0 + fK64[0][1][14] * c1);
-          r1 = fac * ((double)s1 + fKD64[1] * c0 + fK64[1][1][14] * c1);
+          const double c0 = x0[sc], c1 = (double)x1[sc];
+          r0 = fac * ((s0 + (double)w0) + fKD64[0] * c0 + fK64[0][1][14] * c1);
+          r1 = fac * ((s1 + (double)w1) + fKD64[1] * c0 + fK64[1][1][14] * c1);
         } else {
           double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -531,7 +542,7 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
           r0 = fac * s0;
           r1 = fac * s1;
         }
-        if (ip >= 0 && ip < NA) eacc += (double)x0[sc] * r0 + (double)x1[sc] * r1;
+        if (ip >= 0 && ip < NA) eacc += x0[sc] * r0 + (double)x1[sc] * r1;
         const int pp = ip + e;
         if (AX == 1) {
           st[(u & 15) * kSP + lane] = (T)r0;
@@ -559,6 +570,91 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
           }
         }
         __syncthreads();
+      }
+    }
+  }
+  const double bs = block_sum_any(eacc);
+  if (threadIdx.x == 0) kpart[w.kpart + slot0 + blockIdx.x] = bs;
+}
+
+// ---------------------------------------------------------------------------
+// k_kin_zmfma: the z part of the kinetic term as banded-Toeplitz matrix
+// products on the FP64 matrix cores (v_mfma_f64_16x16x4f64)
+// ---------------------------------------------------------------------------
+// Wave = 16 consecutive (x, y) columns of one component pair pr = a1 + 2 a2
+// of one function; it walks the output z' in tiles of 16.  For output
+// channel a (component pr + 4 a) and a tile starting at z'0:
+//   D_a[r][c] = sum_b sum_k A_ab[r][k] X_b[z'0 - e - 14 + k][c],
+//   A_ab[r][k] = K_ab[k - r] for 0 <= k - r <= 28 (else 0), k = 0..43,
+// i.e. 11 steps of k = 4 per input channel b: 22 MFMAs per output channel
+// (58 useful of 88 multiply-adds per output).  The same products as the
+// stencil of k_kin_col<T, 2>, in another order, summed in double for both
+// element types (FP32 inputs enter exactly).  Lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] of a step and holds D[l / 16 + 4 j][l % 16] in
+// element j (the FP64 form interleaves the rows; checked on the device).  Block = 4 waves; its e_kin slot gets
+// the sum of x_a(z) D_a over the outputs inside the box, in a fixed order.
+typedef double wvl_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_kin_zmfma(const SfDev* __restrict__ sfs,
+                                                   const SfWork* __restrict__ wk, int sf0,
+                                                   T* __restrict__ ws, double fac,
+                                                   double* __restrict__ kpart) {
+  const SfWork& w = wk[blockIdx.y];
+  const SfDev& sf = sfs[w.id];
+  const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
+  const int64_t plane = (int64_t)N0 * N1;
+  const int OA = N2 + 2 * e;
+  const int ngrp = (int)((plane + 15) / 16);            // 16-column groups per pair
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int item = blockIdx.x * 4 + wv;                  // (pair, group)
+  if (blockIdx.x * 4 >= 4 * ngrp) return;                // uniform over the block
+  const int slot0 = kin_blocks(0, N0, N1, N2) + kin_blocks(1, N0, N1, N2);
+  double eacc = 0.0;
+  if (item < 4 * ngrp) {
+    const int pr = item / ngrp, grp = item - pr * ngrp;
+    const int64_t icomp = (int64_t)N2 * plane, ocomp = (int64_t)OA * plane;
+    const int rsel = lane & 15, ksel = lane >> 4;
+    const int64_t col = (int64_t)grp * 16 + rsel;        // this lane's column (B and D)
+    const bool colok = col < plane;
+    const T* in0 = ws + w.c8x + (int64_t)pr * icomp + col;          // b = 0
+    const T* in1 = in0 + 4 * icomp;                                  // b = 1 (component + 4)
+    T* out0 = ws + w.oz + (int64_t)pr * ocomp + col;
+    T* out1 = out0 + 4 * ocomp;
+    // A operands of the 11 k-steps, per (a, b): K_ab[4 s + ksel - rsel]
+    double Ak[2][2][11];
+#pragma unroll
+    for (int s = 0; s < 11; ++s) {
+      const int t = 4 * s + ksel - rsel;
+      const bool ok = t >= 0 && t <= 28;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) Ak[a][b][s] = ok ? fac * fK64[a][b][ok ? t : 0] : 0.0;
+    }
+    for (int z0 = 0; z0 < OA; z0 += 16) {
+      const int zin0 = z0 - e - 14;
+      wvl_d4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 11; ++s) {
+        const int zi = zin0 + 4 * s + ksel;
+        const bool ok = colok && zi >= 0 && zi < N2;
+        const double x0 = ok ? (double)in0[(int64_t)zi * plane] : 0.0;
+        const double x1 = ok ? (double)in1[(int64_t)zi * plane] : 0.0;
+        d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ak[0][0][s], x0, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ak[1][0][s], x0, d1, 0, 0, 0);
+        d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ak[0][1][s], x1, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ak[1][1][s], x1, d1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int zp = z0 + ksel + 4 * j;
+        if (!colok || zp >= OA) continue;
+        out0[(int64_t)zp * plane] = (T)d0[j];
+        out1[(int64_t)zp * plane] = (T)d1[j];
+        const int z = zp - e;
+        if (z >= 0 && z < N2)
+          eacc += (double)in0[(int64_t)z * plane] * d0[j] + (double)in1[(int64_t)z * plane] * d1[j];
       }
     }
   }
@@ -856,6 +952,7 @@ int preload_fused_kernels() {
       (const void*)k_kin_col<double, 1>,    (const void*)k_kin_col<double, 2>,
       (const void*)k_back_y<float>,         (const void*)k_back_y<double>,
       (const void*)k_back_x<float>,         (const void*)k_back_x<double>,
+      (const void*)k_kin_zmfma<float>,      (const void*)k_kin_zmfma<double>,
       (const void*)k_pack_out<float>,       (const void*)k_pack_out<double>};
   for (const void* f : fns) {
     hipFuncAttributes a;
@@ -922,6 +1019,19 @@ int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, 
   else
     hipLaunchKernelGGL(k_pot_column<float>, g, dim3(256), 0, (hipStream_t)stream, sf, wk, sf0,
                        (float*)ws, (const float*)pot, nf1, nf2, epart, conf, hh);
+  return (int)hipGetLastError();
+}
+
+int launch_kin_zmfma(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                     int gridx, void* ws, double fac, double* kpart) {
+  if (nsf == 0 || gridx == 0) return 0;
+  const dim3 g((unsigned)gridx, (unsigned)nsf);
+  if (f64)
+    hipLaunchKernelGGL(k_kin_zmfma<double>, g, dim3(256), 0, (hipStream_t)stream, sf, wk, sf0,
+                       (double*)ws, fac, kpart);
+  else
+    hipLaunchKernelGGL(k_kin_zmfma<float>, g, dim3(256), 0, (hipStream_t)stream, sf, wk, sf0,
+                       (float*)ws, fac, kpart);
   return (int)hipGetLastError();
 }
 

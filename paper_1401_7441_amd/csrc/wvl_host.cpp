@@ -23,12 +23,12 @@ using namespace wvl;
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_UNPACK, KK_UP_X, KK_UP_Y, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
   KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
-  KK_UPDATE, KK_UP_Z, KK_DENS_TILE, KK_FOE_MM, KK_FOE, KK_COUNT
+  KK_UPDATE, KK_UP_Z, KK_DENS_TILE, KK_FOE_MM, KK_FOE, KK_GRADIENT, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "unpack", "up_x", "up_y", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
     "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update",
-    "up_z", "dens_tile", "foe_mm", "foe"};
+    "up_z", "dens_tile", "foe_mm", "foe", "gradient"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
 // less what their fixed-order reductions declare statically
@@ -63,11 +63,17 @@ wvl_status fail(wvl_ctx* ctx, wvl_status st, const char* fmt, ...) {
   return st;
 }
 
+// WVL_EDEVICE with the failing HIP call (name or expression), its status
+// name and its description, after `what` (the operation that needed it)
+static wvl_status hip_fail(wvl_ctx* ctx, const char* what, const char* call, hipError_t e) {
+  return fail(ctx, WVL_EDEVICE, "%s: %s returned %s (%s)", what, call, hipGetErrorName(e),
+              hipGetErrorString(e));
+}
+
 #define WVL_HIP(ctx, call)                                                               \
   do {                                                                                   \
     hipError_t e_ = (call);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(ctx, WVL_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    if (e_ != hipSuccess) return hip_fail(ctx, __func__, #call, e_);                     \
   } while (0)
 
 hipEvent_t take_event(wvl_ctx* ctx) {
@@ -112,8 +118,8 @@ struct Trace {
       e_ = (call);                                                                       \
     }                                                                                    \
     if (e_ != 0)                                                                         \
-      return fail(ctx, WVL_EDEVICE, "launch of %s failed: %s", kKernelNames[kind],       \
-                  hipGetErrorString((hipError_t)e_));                                    \
+      return fail(ctx, WVL_EDEVICE, "launch of %s failed: %s (%s)", kKernelNames[kind],  \
+                  hipGetErrorName((hipError_t)e_), hipGetErrorString((hipError_t)e_));   \
   } while (0)
 
 inline int64_t align64(int64_t n) { return (n + 63) & ~int64_t(63); }
@@ -167,6 +173,7 @@ struct Layout {
   std::vector<SfWork> wk;        // per position of the processing order
   bool disjoint = true;
   int nbins = 1;
+  bool zmfma = false;            // z part of the kinetic term on the matrix cores
   int64_t elems_span = 0;        // elements of the compute type before the partials
   int64_t parts_span = 0;        // doubles of energy partials
   int64_t bytes(int sz) const { return align_bytes(elems_span * sz) + parts_span * 8; }
@@ -407,7 +414,8 @@ wvl_status upload(wvl_ctx* ctx, P** dst, const void* src, size_t bytes) {
   hipError_t e = hipMalloc((void**)dst, bytes);
   if (e != hipSuccess) {
     *dst = nullptr;
-    return fail(ctx, WVL_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return fail(ctx, WVL_ENOMEM, "hipMalloc(%zu) returned %s (%s)", bytes, hipGetErrorName(e),
+                hipGetErrorString(e));
   }
   WVL_HIP(ctx, hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
   return WVL_OK;
@@ -718,11 +726,12 @@ static int64_t sf_elems(const SfDev& S) {
 
 // Builds the layout for `nbins` bins; false (with a message) when a box
 // does not fit the kernels' LDS stages.
-static bool make_layout(const wvl_plan* P, int nbins, Layout* L, std::string* err) {
+static bool make_layout(const wvl_plan* P, int nbins, bool zmfma, Layout* L, std::string* err) {
   const int nsf = P->nsf;
   L->chunks.clear();
   L->wk.assign(nsf, SfWork{});
   L->nbins = nbins;
+  L->zmfma = zmfma;
   L->disjoint = P->max_ws == 0;
   L->elems_span = 0;
   L->parts_span = 0;
@@ -776,7 +785,7 @@ static bool make_layout(const wvl_plan* P, int nbins, Layout* L, std::string* er
         ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
         ch.grid_kx = std::max(ch.grid_kx, kin_blocks(0, (int)n0, (int)n1, (int)n2));
         ch.grid_ky = std::max(ch.grid_ky, kin_blocks(1, (int)n0, (int)n1, (int)n2));
-        ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2));
+        ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2, zmfma));
         ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
         ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, ((4 * o1 + 63) / 64) * o2);
       }
@@ -790,7 +799,7 @@ static bool make_layout(const wvl_plan* P, int nbins, Layout* L, std::string* er
         poff += ch.nblk_pot;
         W.kpart = poff;
         W.nkpart = kin_blocks(0, S.n[0], S.n[1], S.n[2]) + kin_blocks(1, S.n[0], S.n[1], S.n[2]) +
-                   kin_blocks(2, S.n[0], S.n[1], S.n[2]);
+                   kin_blocks(2, S.n[0], S.n[1], S.n[2], zmfma);
         poff += ch.nblk_kin;
       }
       L->chunks.push_back(ch);
@@ -941,17 +950,18 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   for (int k = 0; k < nsf; ++k)
     P->max_in_segs = std::max<int64_t>(P->max_in_segs, lr[k].nseg_c + lr[k].nseg_f);
   // the workspace reported covers every layout the autotuner may pick
-  for (int nb : kTuneBins) {
-    Layout L;
-    std::string err;
-    if (!make_layout(P, nb, &L, &err)) {
-      wvl_plan_destroy(P);
-      return fail(ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
+  for (int zm = 0; zm < 2; ++zm)
+    for (int nb : kTuneBins) {
+      Layout L;
+      std::string err;
+      if (!make_layout(P, nb, zm != 0, &L, &err)) {
+        wvl_plan_destroy(P);
+        return fail(ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
+      }
+      P->ws_cap[0] = std::max(P->ws_cap[0], L.bytes(4));
+      P->ws_cap[1] = std::max(P->ws_cap[1], L.bytes(8));
+      if (nb == 1 && zm == 0) P->lay = std::move(L);
     }
-    P->ws_cap[0] = std::max(P->ws_cap[0], L.bytes(4));
-    P->ws_cap[1] = std::max(P->ws_cap[1], L.bytes(8));
-    if (nb == 1) P->lay = std::move(L);
-  }
   const int64_t best_f32 = P->ws_cap[0], best_f64 = P->ws_cap[1];
   P->info.nsf = nsf;
   P->info.in_coefs = in_coefs;
@@ -981,7 +991,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     wvl_plan_destroy(P);
-    return fail(ctx, WVL_EDEVICE, "plan upload failed: %s", hipGetErrorString(e));
+    return hip_fail(ctx, "plan upload", "hipStreamSynchronize", e);
   }
   if (workspace_bytes) *workspace_bytes = (size_t)best_f64;
   *plan_out = P;
@@ -1085,8 +1095,12 @@ static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, co
                                                 ch.grid_kx, workspace, fac, parts));
     WVL_LAUNCH(ctx, KK_KIN_YCOL, launch_kin_col(f64, st, 1, P->d_sf, wk, ch.sf0, ch.nsf,
                                                 ch.grid_ky, workspace, fac, parts));
-    WVL_LAUNCH(ctx, KK_KIN_ZCOL, launch_kin_col(f64, st, 2, P->d_sf, wk, ch.sf0, ch.nsf,
-                                                ch.grid_kz, workspace, fac, parts));
+    if (P->lay.zmfma)
+      WVL_LAUNCH(ctx, KK_KIN_ZCOL, launch_kin_zmfma(f64, st, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                    ch.grid_kz, workspace, fac, parts));
+    else
+      WVL_LAUNCH(ctx, KK_KIN_ZCOL, launch_kin_col(f64, st, 2, P->d_sf, wk, ch.sf0, ch.nsf,
+                                                  ch.grid_kz, workspace, fac, parts));
     if (e_kin)
       WVL_LAUNCH(ctx, KK_FINALIZE,
                  launch_finalize(st, wk, ch.sf0, ch.nsf, parts, 1, ch.nblk_kin, e_kin));
@@ -1152,19 +1166,23 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
   if (nsf > 0) {
     WVL_HIP(ctx, hipMalloc((void**)&d_count, sizeof(int64_t) * nsf));
     int e;
+    const char* call = "launch of pattern (count)";
     {
       Trace tr(ctx, KK_PATTERN);
       e = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, d_count, nullptr,
                          nullptr);
     }
-    if (e == 0)
+    if (e == 0) {
+      call = "hipMemcpyAsync";
       e = (int)hipMemcpyAsync(cnt.data(), d_count, sizeof(int64_t) * nsf, hipMemcpyDeviceToHost,
                               ctx->stream);
-    if (e == 0) e = (int)hipStreamSynchronize(ctx->stream);
+    }
+    if (e == 0) {
+      call = "hipStreamSynchronize";
+      e = (int)hipStreamSynchronize(ctx->stream);
+    }
     (void)hipFree(d_count);
-    if (e != 0)
-      return fail(ctx, WVL_EDEVICE, "sparsity pattern count failed: %s",
-                  hipGetErrorString((hipError_t)e));
+    if (e != 0) return hip_fail(ctx, "sparsity pattern count", call, (hipError_t)e);
   }
   for (int a = 0; a < nsf; ++a) rowptr[a + 1] = rowptr[a] + cnt[a];
   const int64_t nnz = rowptr[nsf];
@@ -1182,25 +1200,29 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
     hipError_t e = hipMalloc((void**)&pc.d_col, sizeof(int32_t) * nnz);
     if (e != hipSuccess) {
       free_pattern(pc);
-      return fail(ctx, WVL_ENOMEM, "pattern columns: %s", hipGetErrorString(e));
+      return fail(ctx, WVL_ENOMEM, "pattern columns: hipMalloc returned %s (%s)",
+                  hipGetErrorName(e), hipGetErrorString(e));
     }
     int le;
+    const char* call = "launch of pattern (fill)";
     {
       Trace tr(ctx, KK_PATTERN);
       le = launch_pattern(ctx->stream, P->d_sf, P->d_seg, P->d_rt, nsf, ket_out, nullptr,
                           pc.d_rowptr, pc.d_col);
     }
-    if (le == 0) le = (int)hipStreamSynchronize(ctx->stream);
+    if (le == 0) {
+      call = "hipStreamSynchronize";
+      le = (int)hipStreamSynchronize(ctx->stream);
+    }
     if (le != 0) {
       free_pattern(pc);
-      return fail(ctx, WVL_EDEVICE, "sparsity pattern fill failed: %s",
-                  hipGetErrorString((hipError_t)le));
+      return hip_fail(ctx, "sparsity pattern fill", call, (hipError_t)le);
     }
   } else {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
       free_pattern(pc);
-      return fail(ctx, WVL_EDEVICE, "pattern upload failed: %s", hipGetErrorString(e));
+      return hip_fail(ctx, "pattern upload", "hipStreamSynchronize", e);
     }
   }
   // Value pairs are processed in groups of kPairGroup rows, the rows in the
@@ -1221,12 +1243,16 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
     }
     std::sort(key.begin(), key.end());
     std::vector<int32_t> col(nnz);
+    const char* call = "hipMemcpyAsync";
     hipError_t ce = hipMemcpyAsync(col.data(), pc.d_col, sizeof(int32_t) * nnz,
                                    hipMemcpyDeviceToHost, ctx->stream);
-    if (ce == hipSuccess) ce = hipStreamSynchronize(ctx->stream);
+    if (ce == hipSuccess) {
+      call = "hipStreamSynchronize";
+      ce = hipStreamSynchronize(ctx->stream);
+    }
     if (ce != hipSuccess) {
       free_pattern(pc);
-      return fail(ctx, WVL_EDEVICE, "pattern columns: %s", hipGetErrorString(ce));
+      return hip_fail(ctx, "pattern columns", call, ce);
     }
     std::vector<int32_t> order;
     order.reserve(nnz);
@@ -1280,7 +1306,7 @@ static wvl_status ensure_pattern(wvl_plan* P, int ket_out) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
       free_pattern(pc);
-      return fail(ctx, WVL_EDEVICE, "pattern order upload failed: %s", hipGetErrorString(e));
+      return hip_fail(ctx, "pattern order upload", "hipStreamSynchronize", e);
     }
   }
   pc.nnz = nnz;
@@ -1424,9 +1450,9 @@ static wvl_status ensure_cover(wvl_plan* P) {
     drop();
     return st;
   }
-  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+  if (hipError_t e = hipStreamSynchronize(ctx->stream); e != hipSuccess) {
     drop();
-    return fail(ctx, WVL_EDEVICE, "density tile lists upload failed");
+    return hip_fail(ctx, "density tile lists upload", "hipStreamSynchronize", e);
   }
   return WVL_OK;
 }
@@ -1719,6 +1745,62 @@ wvl_status wvl_foe(wvl_plan* P, const double* s_val, const double* h_val, int32_
   return WVL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// support-function gradient (Eq. (gradient), Sec. IV.A)
+// ---------------------------------------------------------------------------
+
+static size_t gradient_scratch_bytes(int64_t nnz) { return 8 * (size_t)7 * (size_t)nnz; }
+
+wvl_status wvl_gradient(wvl_plan* P, wvl_dtype dt, const double* s_val, const double* h_val,
+                        const double* k_val, const void* psi_c, const void* hpsi_c, void* g_c,
+                        void* scratch, size_t scratch_bytes) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_gradient: null plan");
+  wvl_ctx* ctx = P->ctx;
+  if (check_dt(ctx, dt) != WVL_OK) return WVL_EINVAL;
+  if (P->nsf == 0) return WVL_OK;
+  if (!s_val || !h_val || !k_val || !psi_c || !hpsi_c || !g_c || !scratch)
+    return fail(ctx, WVL_EINVAL, "wvl_gradient: null buffer");
+  wvl_status st;
+  if ((st = ensure_pattern(P, 0)) != WVL_OK || (st = ensure_pattern(P, 1)) != WVL_OK ||
+      (st = ensure_foe_maps(P)) != WVL_OK)
+    return st;
+  const PatternCache& pc = P->pat[0];
+  const int64_t nnz = pc.nnz;
+  if (scratch_bytes < gradient_scratch_bytes(nnz))
+    return fail(ctx, WVL_EINVAL, "wvl_gradient: scratch of %zu bytes, at least %zu needed",
+                scratch_bytes, gradient_scratch_bytes(nnz));
+  hipStream_t s = ctx->stream;
+  const int n = P->nsf;
+  double* w = (double*)scratch;
+  double *Ss = w, *Hp = w + nnz, *A = w + 2 * nnz, *X = w + 3 * nnz, *Lam = w + 4 * nnz;
+  double *Si = w + 5 * nnz, *M = w + 6 * nnz;
+  int lognb = 5;
+  while ((1 << lognb) < pc.maxdeg) ++lognb;
+  auto mm = [&](const double* L, const double* R, double* C) {
+    return launch_foe_mm(s, n, pc.d_foe_rows, pc.d_rowptr, pc.d_col, 1.0, L, R, 0.0, nullptr, C,
+                         lognb, pc.maxdeg);
+  };
+  // the matrices on the overlap pattern P, every product truncated to P:
+  // A = S K; Lambda = (H K) S; M = 1/2 (2 I - S) (Lambda + Lambda^T)
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, pc.d_tpos, s_val, Ss));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_gather(s, nnz, pc.d_hpos, h_val, Hp));
+  WVL_LAUNCH(ctx, KK_FOE_MM, mm(Ss, k_val, A));
+  WVL_LAUNCH(ctx, KK_FOE_MM, mm(Hp, k_val, X));
+  WVL_LAUNCH(ctx, KK_FOE_MM, mm(X, Ss, Lam));
+  WVL_LAUNCH(ctx, KK_FOE, launch_foe_sym(s, nnz, pc.d_tpos, Lam, X));   // (Lambda + Lambda^T) / 2
+  WVL_LAUNCH(ctx, KK_FOE,
+             launch_foe_axpby(s, nnz, -1.0, Ss, 0.0, nullptr, pc.d_row, pc.d_col, 2.0, Si));
+  WVL_LAUNCH(ctx, KK_FOE_MM, mm(Si, X, M));
+  // g_a = L^a [sum_d A_ad H phi_d - M_ad phi_d]
+  for (int s0 = 0; s0 < n; s0 += 65535) {
+    const int cnt = std::min(65535, n - s0);
+    WVL_LAUNCH(ctx, KK_GRADIENT,
+               launch_grad_rows(dt == WVL_F64, s, P->d_sf, P->d_seg, P->d_rt, P->d_rr,
+                                pc.d_rowptr, pc.d_col, A, M, psi_c, hpsi_c, s0, cnt, g_c));
+  }
+  return WVL_OK;
+}
+
 wvl_status wvl_update(wvl_plan* P, wvl_dtype dt, double eta, const void* hpsi_c,
                       const double* h_val, void* psi_c) {
   if (!P) return fail(nullptr, WVL_EINVAL, "wvl_update: null plan");
@@ -1804,7 +1886,8 @@ static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const 
   int pe = preload_kernels();
   if (pe == 0) pe = preload_fused_kernels();
   if (pe != 0)
-    return fail(ctx, WVL_EDEVICE, "kernel preload failed: %s", hipGetErrorString((hipError_t)pe));
+    return hip_fail(ctx, "graph capture", "kernel preload (hipFuncGetAttributes)",
+                    (hipError_t)pe);
   const size_t nbr = P->lay.disjoint ? std::min<size_t>(nch, 4) : 0;
   // streams[0] is the capture origin (the context's stream may be the
   // legacy default stream, which cannot be captured); 1.. are branches
@@ -1820,9 +1903,9 @@ static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const 
   };
   for (size_t k = 0; k < nbr + 1; ++k) {
     hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    if (hipError_t he = hipEventCreateWithFlags(&e, hipEventDisableTiming); he != hipSuccess) {
       cleanup();
-      return fail(ctx, WVL_EDEVICE, "graph events could not be created");
+      return hip_fail(ctx, "graph capture", "hipEventCreateWithFlags", he);
     }
     ev.push_back(e);
   }
@@ -1831,23 +1914,25 @@ static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const 
   hipStream_t cs = P->streams[0];
   hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   wvl_status st = he == hipSuccess ? WVL_OK
-                                   : fail(ctx, WVL_EDEVICE, "capture: %s", hipGetErrorString(he));
+                                   : hip_fail(ctx, "graph capture", "hipStreamBeginCapture", he);
+  // fork/join steps: the first failing call ends the capture with its name
+  auto step = [&](hipError_t e, const char* call) {
+    if (st == WVL_OK && e != hipSuccess) st = hip_fail(ctx, "graph capture", call, e);
+  };
   if (st == WVL_OK && P->nsf > 0) {
     if (nbr > 0) {
       // fork: every branch waits for the capture origin
-      if (hipEventRecord(ev[0], cs) != hipSuccess) st = WVL_EDEVICE;
+      step(hipEventRecord(ev[0], cs), "hipEventRecord (fork)");
       for (size_t b = 0; st == WVL_OK && b < nbr; ++b)
-        if (hipStreamWaitEvent(P->streams[b + 1], ev[0], 0) != hipSuccess) st = WVL_EDEVICE;
+        step(hipStreamWaitEvent(P->streams[b + 1], ev[0], 0), "hipStreamWaitEvent (fork)");
       for (size_t c = 0; st == WVL_OK && c < nch; ++c)
         st = apply_chunk(P, c, f64, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0,
                          P->streams[1 + c % nbr]);
       // join
       for (size_t b = 0; st == WVL_OK && b < nbr; ++b) {
-        if (hipEventRecord(ev[b + 1], P->streams[b + 1]) != hipSuccess ||
-            hipStreamWaitEvent(cs, ev[b + 1], 0) != hipSuccess)
-          st = WVL_EDEVICE;
+        step(hipEventRecord(ev[b + 1], P->streams[b + 1]), "hipEventRecord (join)");
+        if (st == WVL_OK) step(hipStreamWaitEvent(cs, ev[b + 1], 0), "hipStreamWaitEvent (join)");
       }
-      if (st == WVL_EDEVICE) st = fail(ctx, WVL_EDEVICE, "graph fork/join failed");
     } else {
       for (size_t c = 0; st == WVL_OK && c < nch; ++c)
         st = apply_chunk(P, c, f64, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0, cs);
@@ -1863,14 +1948,14 @@ static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const 
                                          half ? pc.d_order_u : pc.d_order,
                                          half ? pc.d_mirror_u : nullptr,
                                          half ? pc.nnz_u : pc.nnz, val);
-      if (e != 0) st = fail(ctx, WVL_EDEVICE, "capture of sparse values failed");
+      if (e != 0) st = hip_fail(ctx, "graph capture", "launch of sparse_values", (hipError_t)e);
     }
   }
   hipGraph_t g = nullptr;
   if (he == hipSuccess) {
     const hipError_t ee = hipStreamEndCapture(cs, &g);
     if (st == WVL_OK && ee != hipSuccess)
-      st = fail(ctx, WVL_EDEVICE, "end of capture: %s", hipGetErrorString(ee));
+      st = hip_fail(ctx, "graph capture", "hipStreamEndCapture", ee);
   }
   ctx->prof = prof;
   if (st != WVL_OK) {
@@ -1883,7 +1968,7 @@ static wvl_status capture_step(wvl_plan* P, wvl_dtype dt, uint32_t terms, const 
   if (he != hipSuccess) {
     (void)hipGraphDestroy(g);
     cleanup();
-    return fail(ctx, WVL_EDEVICE, "graph instantiation: %s", hipGetErrorString(he));
+    return hip_fail(ctx, "graph capture", "hipGraphInstantiate", he);
   }
   G->plan = P;
   G->graph = g;
@@ -1942,6 +2027,20 @@ static wvl_status set_layout(wvl_plan* P, Layout&& L) {
   return WVL_OK;
 }
 
+wvl_status wvl_plan_set_schedule(wvl_plan* P, int32_t nbins, int32_t kin_mfma) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "wvl_plan_set_schedule: null plan");
+  if (nbins < 1 || (kin_mfma != 0 && kin_mfma != 1))
+    return fail(P->ctx, WVL_EINVAL, "wvl_plan_set_schedule: nbins >= 1, kin_mfma 0 or 1");
+  Layout L;
+  std::string err;
+  if (!make_layout(P, nbins, kin_mfma != 0, &L, &err))
+    return fail(P->ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
+  if (L.bytes(4) > P->ws_cap[0] || L.bytes(8) > P->ws_cap[1])
+    return fail(P->ctx, WVL_EINVAL,
+                "wvl_plan_set_schedule: this schedule needs more workspace than the plan reported");
+  return set_layout(P, std::move(L));
+}
+
 wvl_status wvl_plan_autotune(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
                              const void* pot, void* hpsi_c, void* workspace, int32_t reps,
                              wvl_tune_point* tried, int32_t max_tried, int32_t* ntried,
@@ -1955,35 +2054,43 @@ wvl_status wvl_plan_autotune(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
   const int sz = dt == WVL_F64 ? 8 : 4;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   WVL_HIP(ctx, hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
+  if (hipError_t he = hipEventCreate(&e1); he != hipSuccess) {
     (void)hipEventDestroy(e0);
-    return fail(ctx, WVL_EDEVICE, "wvl_plan_autotune: event creation failed");
+    return hip_fail(ctx, "wvl_plan_autotune", "hipEventCreate", he);
   }
-  wvl_tune_point top{0, 1e300};
+  wvl_tune_point top{0, 0, 1e300};
   int n = 0;
+  for (int zm = 0; zm < 2; ++zm)
   for (int nb : kTuneBins) {
     Layout L;
     std::string err;
-    if (!make_layout(P, nb, &L, &err) || L.bytes(sz) > P->ws_cap[sz == 8]) continue;
+    if (!make_layout(P, nb, zm != 0, &L, &err) || L.bytes(sz) > P->ws_cap[sz == 8]) continue;
     if ((st = set_layout(P, std::move(L))) != WVL_OK) break;
     // warm-up, then `reps` timed eager applies of this layout
     if ((st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
                          "wvl_plan_autotune")) != WVL_OK)
       break;
+    const char* call = "hipEventRecord";
     hipError_t he = hipEventRecord(e0, ctx->stream);
     for (int r = 0; he == hipSuccess && st == WVL_OK && r < reps; ++r)
       st = apply_impl(P, dt, terms, psi_c, pot, hpsi_c, nullptr, nullptr, workspace, 0,
                       "wvl_plan_autotune");
     if (st != WVL_OK) break;
     if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
-    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) {
+      call = "hipEventSynchronize";
+      he = hipEventSynchronize(e1);
+    }
     float ms = 0.f;
-    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he == hipSuccess) {
+      call = "hipEventElapsedTime";
+      he = hipEventElapsedTime(&ms, e0, e1);
+    }
     if (he != hipSuccess) {
-      st = fail(ctx, WVL_EDEVICE, "wvl_plan_autotune: %s", hipGetErrorString(he));
+      st = hip_fail(ctx, "wvl_plan_autotune", call, he);
       break;
     }
-    const wvl_tune_point pt{nb, (double)ms / reps};
+    const wvl_tune_point pt{nb, zm, (double)ms / reps};
     if (tried && n < max_tried) tried[n] = pt;
     ++n;
     if (pt.ms < top.ms) top = pt;
@@ -1995,7 +2102,7 @@ wvl_status wvl_plan_autotune(wvl_plan* P, wvl_dtype dt, uint32_t terms, const vo
   if (n == 0) return fail(ctx, WVL_EUNSUPPORTED, "wvl_plan_autotune: no candidate fits");
   Layout L;
   std::string err;
-  if (!make_layout(P, top.nbins, &L, &err))
+  if (!make_layout(P, top.nbins, top.kin_mfma != 0, &L, &err))
     return fail(ctx, WVL_EUNSUPPORTED, "%s", err.c_str());
   if ((st = set_layout(P, std::move(L))) != WVL_OK) return st;
   if (best) *best = top;

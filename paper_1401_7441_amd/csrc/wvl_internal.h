@@ -69,9 +69,11 @@ struct SfWork {
 // e_kin partial slots of one function: the blocks of k_kin_col along x, then
 // y, then z, counted on the function's own box (so that the summation order
 // does not depend on the other functions of the chunk)
-__host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2) {
+// (the z part by k_kin_zmfma when zmfma: one block per 16 columns)
+__host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2, bool zmfma = false) {
   return axis == 0 ? (4 * n1 * n2 + 255) / 256
-                   : axis == 1 ? (4 * n0 * n2 + 63) / 64 : (4 * n0 * n1 + 255) / 256;
+         : axis == 1 ? (4 * n0 * n2 + 63) / 64
+         : zmfma ? (n0 * n1 + 15) / 16 : (4 * n0 * n1 + 255) / 256;
 }
 
 // per-chunk launch geometry of the fused kernels, for dtype d (0 f32, 1 f64)
@@ -123,6 +125,9 @@ int launch_dens_tile(int f64, void* stream, const SfDev* sf, const int64_t* foff
 int launch_pot_column(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                       int gridx, void* ws, const void* pot, int nf1, int nf2, double* epart,
                       const double* conf, double hh);
+// the z part of the kinetic term on the FP64 matrix cores (banded Toeplitz)
+int launch_kin_zmfma(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
+                     int gridx, void* ws, double fac, double* kpart);
 int launch_kin_col(int f64, void* stream, int axis, const SfDev* sf, const SfWork* wk, int sf0,
                    int nsf, int gridx, void* ws, double fac, double* kpart);
 int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
@@ -169,6 +174,12 @@ int launch_update(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, co
                   double eta, const void* hpsi, const int64_t* hrow, const int32_t* hcol,
                   const double* hval, void* psi, int sf0, int nsf, int64_t maxsegs, int mode,
                   const double* shift, void* out);
+// g_a = L^a [sum_d A_ad H phi_d - M_ad phi_d] over the rows of a CSR pattern
+// (A and M in its order), one block per function a of [sf0, sf0 + nsf)
+int launch_grad_rows(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
+                     const int32_t* rt, const RowRun* rr, const int64_t* rowptr,
+                     const int32_t* col, const double* av, const double* mv, const void* psi,
+                     const void* hpsi, int sf0, int nsf, void* g);
 int launch_sf_dot(int f64, void* stream, const SfDev* sf, const void* a, const void* b,
                   double* out, int sf0, int nsf);
 int launch_cg_init(int f64, void* stream, const SfDev* sf, const void* g, void* x, void* r,

@@ -1027,6 +1027,136 @@ __global__ __launch_bounds__(TPB) void k_cg_init(const SfDev* __restrict__ sfs,
 // launchers
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// gradient: g_a = L^a [ sum_d A_ad H|phi_d> - sum_d M_ad |phi_d> ] over row a
+// of the overlap pattern (Eq. (gradient), Sec. IV.A, localized as Sec. III.A)
+// ---------------------------------------------------------------------------
+// Block = function a (four waves), the neighbours d of row a staged in LDS
+// (their box rows, row-table bases and coefficient offsets, A_ad and M_ad),
+// kGradNb at a time.  Wave w takes the rows w, w + 4, ... of a's input box;
+// for each segment of a row (the scaling coefficients of the coarse pattern,
+// then the seven wavelets of each point of the fine pattern) lane j owns the
+// elements j, j + 64, ... and sums, over the neighbours in CSR order, the
+// values of H|phi_d> and |phi_d> at its point (0 where d's pattern lacks
+// it), in double; each element of g_a is written once, by its owner.
+constexpr int kGradNb = 256;
+
+struct GradNb {
+  int32_t in_y0, in_z0, in_by, in_nz;       // input box rows: origin, rows per plane, planes
+  int32_t out_y0, out_z0, out_by, out_nz;   // output box rows
+  int64_t rr_in[2], rr_out[2];              // RowRun bases (coarse, fine)
+  int64_t rt_in[2], rt_out[2];              // row-table bases (coarse, fine)
+  int64_t cin, cout, n_c, on_c;
+  double a, m;
+};
+
+// index of global point gx in row r of a pattern (RowRun base rrb, row-table
+// base rtb), or -1
+__device__ __forceinline__ int64_t grad_find(const RowRun* __restrict__ rr,
+                                             const int32_t* __restrict__ rt,
+                                             const wvl_seg* __restrict__ seg, int64_t rrb,
+                                             int64_t rtb, int64_t r, int gx) {
+  const RowRun w = rr[rrb + r];
+  if (w.len == 0) return -1;
+  if (w.len != kMultiRun)
+    return (gx >= (int)w.x0 && gx < (int)w.x0 + (int)w.len) ? (int64_t)w.off + gx - w.x0 : -1;
+  for (int q = rt[rtb + r], q1 = rt[rtb + r + 1]; q < q1; ++q) {
+    const wvl_seg g = seg[q];
+    if (gx >= g.i1s && gx <= g.i1e) return g.off + (gx - g.i1s);
+  }
+  return -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_rows(const SfDev* __restrict__ sfs,
+                                                   const wvl_seg* __restrict__ seg,
+                                                   const int32_t* __restrict__ rt,
+                                                   const RowRun* __restrict__ rr,
+                                                   const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ av,
+                                                   const double* __restrict__ mv,
+                                                   const T* __restrict__ psi,
+                                                   const T* __restrict__ hpsi, int sf0,
+                                                   T* __restrict__ g) {
+  __shared__ GradNb nb[kGradNb];
+  const int a = sf0 + blockIdx.x;
+  const SfDev& A = sfs[a];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int N1 = A.n[1], N2 = A.n[2];
+  const int64_t nrows = (int64_t)N1 * N2;
+  const int64_t q0 = rowptr[a], q1 = rowptr[a + 1];
+  // neighbours in batches of kGradNb: each element's sum runs over the
+  // batches in order, the first batch writing g and the next ones adding to
+  // it (an element has the same owner, lane and wave, in every batch; rows of
+  // more than kGradNb entries round once per batch)
+  const int64_t nbatch = max((int64_t)1, (q1 - q0 + kGradNb - 1) / kGradNb);
+  for (int64_t bi = 0; bi < nbatch; ++bi) {
+    const int64_t b0 = q0 + bi * kGradNb;
+    const int nn = (int)max((int64_t)0, min((int64_t)kGradNb, q1 - b0));
+    __syncthreads();
+    for (int t = threadIdx.x; t < nn; t += 256) {
+      const int d = col[b0 + t];
+      const SfDev& D = sfs[d];
+      GradNb x;
+      const int e = D.ext;
+      x.in_y0 = D.lo[1]; x.in_z0 = D.lo[2]; x.in_by = D.n[1]; x.in_nz = D.n[2];
+      x.out_y0 = D.lo[1] - e; x.out_z0 = D.lo[2] - e; x.out_by = D.n[1] + 2 * e;
+      x.out_nz = D.n[2] + 2 * e;
+      x.rr_in[0] = D.rr[0]; x.rr_in[1] = D.rr[1]; x.rr_out[0] = D.rr[2]; x.rr_out[1] = D.rr[3];
+      x.rt_in[0] = D.rt[0]; x.rt_in[1] = D.rt[1]; x.rt_out[0] = D.rt[2]; x.rt_out[1] = D.rt[3];
+      x.cin = D.cin; x.cout = D.cout; x.n_c = D.n_c; x.on_c = D.on_c;
+      x.a = av[b0 + t];
+      x.m = mv[b0 + t];
+      nb[t] = x;
+    }
+    __syncthreads();
+    for (int64_t r = wv; r < nrows; r += 4) {
+      const int y = A.lo[1] + (int)(r % N1), z = A.lo[2] + (int)(r / N1);
+#pragma unroll
+      for (int fine = 0; fine < 2; ++fine) {
+        const int per = fine ? 7 : 1;
+        const int64_t abase = A.cin + (fine ? A.n_c : 0);
+        for (int q = rt[A.rt[fine] + r], qe = rt[A.rt[fine] + r + 1]; q < qe; ++q) {
+          const wvl_seg sa = seg[q];
+          const int len = per * (sa.i1e - sa.i1s + 1);
+          for (int j0 = 0; j0 < len; j0 += 64) {
+            const int j = j0 + lane;
+            const bool own = j < len;
+            const int pt = own ? j / per : 0;
+            const int comp = own ? j - per * pt : 0;
+            const int gx = sa.i1s + pt;
+            double acc = 0.0;
+            for (int t = 0; t < nn; ++t) {
+              const GradNb& x = nb[t];
+              // H phi_d on d's output pattern
+              const int ry = y - x.out_y0, rz = z - x.out_z0;
+              if (ry >= 0 && ry < x.out_by && rz >= 0 && rz < x.out_nz && x.a != 0.0) {
+                const int64_t k = own ? grad_find(rr, rt, seg, x.rr_out[fine], x.rt_out[fine],
+                                                  (int64_t)rz * x.out_by + ry, gx)
+                                      : -1;
+                if (k >= 0) acc += x.a * (double)hpsi[x.cout + (fine ? x.on_c : 0) + per * k + comp];
+              }
+              // phi_d on d's input pattern
+              const int sy = y - x.in_y0, sz = z - x.in_z0;
+              if (sy >= 0 && sy < x.in_by && sz >= 0 && sz < x.in_nz && x.m != 0.0) {
+                const int64_t k = own ? grad_find(rr, rt, seg, x.rr_in[fine], x.rt_in[fine],
+                                                  (int64_t)sz * x.in_by + sy, gx)
+                                      : -1;
+                if (k >= 0) acc -= x.m * (double)psi[x.cin + (fine ? x.n_c : 0) + per * k + comp];
+              }
+            }
+            if (own) {
+              T* o = g + abase + per * sa.off + j;
+              *o = bi == 0 ? (T)acc : (T)((double)*o + acc);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 static inline dim3 grid2(int64_t maxvol, int nsf) {
   return dim3((unsigned)((maxvol + TPB - 1) / TPB), (unsigned)nsf);
 }
@@ -1039,7 +1169,8 @@ int preload_kernels() {
                        (const void*)k_sf_dot<double>, (const void*)k_dens_tile<float, true>,
                        (const void*)k_dens_tile<float, false>,
                        (const void*)k_dens_tile<double, true>,
-                       (const void*)k_dens_tile<double, false>};
+                       (const void*)k_dens_tile<double, false>, (const void*)k_grad_rows<float>,
+                       (const void*)k_grad_rows<double>};
   for (const void* f : fns) {
     hipFuncAttributes a;
     const hipError_t e = hipFuncGetAttributes(&a, f);
@@ -1296,6 +1427,22 @@ int launch_cg_p(int f64, void* stream, const SfDev* sf, double* rr, const double
   else
     hipLaunchKernelGGL(k_cg_p<float>, dim3(nsf), dim3(TPB), 0, (hipStream_t)stream, sf, rr,
                        rr_new, (const float*)r, (float*)p, sf0);
+  return (int)hipGetLastError();
+}
+
+int launch_grad_rows(int f64, void* stream, const SfDev* sf, const wvl_seg* seg,
+                     const int32_t* rt, const RowRun* rr, const int64_t* rowptr,
+                     const int32_t* col, const double* av, const double* mv, const void* psi,
+                     const void* hpsi, int sf0, int nsf, void* g) {
+  if (nsf == 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(k_grad_rows<double>, dim3((unsigned)nsf), dim3(256), 0, (hipStream_t)stream,
+                       sf, seg, rt, rr, rowptr, col, av, mv, (const double*)psi,
+                       (const double*)hpsi, sf0, (double*)g);
+  else
+    hipLaunchKernelGGL(k_grad_rows<float>, dim3((unsigned)nsf), dim3(256), 0, (hipStream_t)stream,
+                       sf, seg, rt, rr, rowptr, col, av, mv, (const float*)psi,
+                       (const float*)hpsi, sf0, (float*)g);
   return (int)hipGetLastError();
 }
 

@@ -230,17 +230,13 @@ def _fmt32(vals):
     return ", ".join(float(f32_nearest(v)).hex() + "f" for v in vals)
 
 
-def kinetic_f32_diagonal(K):
-    """FP64 diagonal of the scaling-channel difference form used by the FP32
-    kinetic kernel: sum_{j != 0} K~_j (x_{i+j} - x_i) implies the diagonal
-    -sum_{j != 0} K~_j (K~ = FP32 taps); adding D_a x_i, accumulated in
-    double, restores the exact diagonal K_a0[0]:
-    D_a = K_a0[0] + sum_{j != 0} K~_a0[j]."""
-    D = []
-    for a in range(2):
-        k0 = K[a][0]
-        D.append(k0[14] + sum(mp.mpf(f32_nearest(v)) for j, v in enumerate(k0) if j != 14))
-    return D
+def kinetic_row_sums(K):
+    """Diagonal completing the scaling-channel difference form of the FP32
+    kinetic kernels: they sum sum_{j != 0} K_a0[j] (x_{i+j} - x_i) in double
+    with the FP64 taps (the differences of FP32 values are exact there), so
+    adding D_a x_i with the row sum D_a = sum_j K_a0[j] gives
+    sum_j K_a0[j] x_{i+j}."""
+    return [sum(K[a][0]) for a in range(2)]
 
 
 def write_header(path):
@@ -268,10 +264,10 @@ def write_header(path):
             lines.append(f"#define WVL_K{ao}{bi}_F64 {{{_fmt(t['K'][ao][bi])}}}")
             lines.append(f"#define WVL_K{ao}{bi}_F32 {{{_fmt32(t['K'][ao][bi])}}}")
     with mp.workdps(DPS):
-        D = kinetic_f32_diagonal(t["K"])
+        D = kinetic_row_sums(t["K"])
     lines += [
-        "// FP32 kinetic: FP64 diagonal D_a (output channel a = 0, 1) completing the",
-        "// scaling-channel difference form to the exact diagonal tap",
+        "// FP32 kinetic: row sums D_a = sum_j K_a0[j] (output channel a = 0, 1) that",
+        "// complete the scaling-channel difference form to the full filter",
         f"#define WVL_KD_F64 {{{_fmt(D)}}}",
     ]
     with open(path, "w") as f:

@@ -10,14 +10,20 @@ support functions is what the method relies on between geometry steps and
 between neutral and charged runs (paper Sec. VIII).
 
 Scheduling:
-  * admission by HBM footprint: a waiting request is admitted at a tick
-    boundary, in arrival order, when its footprint (coefficients, H psi,
-    potential, workspace, patterns) fits in the budget left by the active
-    requests;
-  * continuous batching: every tick enqueues the next step of every active
-    request, each on its own HIP stream, so their kernels overlap on the
-    device; a tick ends when all of them are done; requests that finished
-    their last step leave and free their memory, new ones join;
+  * admission by HBM footprint: a waiting request is admitted, in arrival
+    order, as soon as its footprint (coefficients, H psi, potential,
+    workspace, patterns) fits in the budget left by the active requests;
+    after its plan exists the estimate is replaced by the bytes the request
+    actually holds;
+  * continuous batching: every active request runs its steps on its own
+    HIP stream, so the kernels of different requests overlap on the device;
+    the host polls each request's last step and enqueues its next one as
+    soon as it is done, independently of the others (a small request is
+    never held back by a large one), retires it after its last step and
+    admits waiting requests into the memory it frees;
+  * failure isolation: a request whose set-up or step fails (a malformed
+    request, an allocation that does not fit) is moved to `failed` with its
+    error, its memory is returned, and the others go on;
   * latency = arrival -> completion of the last step (host clock).
 
 The per-function baseline (`run_per_function`) is the plain path: FP64, one
@@ -59,6 +65,7 @@ class Request:
     done: float = math.nan
     steps_done: int = 0
     footprint: int = 0
+    error: str = ""
     result: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -120,10 +127,15 @@ class _Active:
             self.s_val, self.h_val = self.s_out[2], self.h_out[2]
         self.eta = eta
         self.graph = None
+        self.done_event = None
         if use_graph:
             self.graph = Graph(self.plan, self.psi, self.pot, self.hpsi, self.ek, self.ep,
                                workspace=self.ws, s_val=self.s_val, h_val=self.h_val)
-        self.done_event = None
+        # device bytes this request holds (the graph's own are small)
+        self.bytes = int(sum(t.numel() * t.element_size() for t in
+                             (self.psi, self.pot, self.hpsi, self.ek, self.ep, self.ws,
+                              *self.s_out, *self.h_out)))
+        self.bytes += 24 * (self.nnz_s + self.nnz_h) + 8 * 1024 * req.nsf   # plan patterns, keys
 
     def enqueue_step(self):
         import torch
@@ -149,23 +161,40 @@ class _Active:
 
     def close(self):
         self.stream.synchronize()
-        if self.graph is not None:
+        if getattr(self, "graph", None) is not None:
             self.graph.close()
-        self.plan.close()
-        self.ctx.close()
+        for name in ("plan", "ctx"):
+            obj = getattr(self, name, None)
+            if obj is not None:
+                obj.close()
+
+
+def _activate(req, dtype, eta, use_graph, max_workspace, stream):
+    """_Active(req, ...), releasing whatever was created when it fails."""
+    a = _Active.__new__(_Active)
+    try:
+        a.__init__(req, dtype, eta, use_graph, max_workspace, stream)
+    except Exception:
+        try:
+            a.close()
+        except Exception:
+            pass
+        raise
+    return a
 
 
 class Engine:
     """Continuous-batching engine (see the module docstring)."""
 
     def __init__(self, dtype="f32", hbm_budget=None, eta=0.01, steps=5, use_graph=True,
-                 max_workspace=8 << 30, keep_results=False, n_streams=8):
+                 max_workspace=8 << 30, keep_results=False, n_streams=8, streams=None):
         import torch
         # a fixed pool of streams (default priority): requests take the one
         # with the fewest active requests; buffers are allocated on it, so
         # freed memory returns to a stream that stays in use
-        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
-        self.stream_load = [0] * n_streams
+        self.streams = streams if streams is not None else \
+            [torch.cuda.Stream() for _ in range(n_streams)]
+        self.stream_load = [0] * len(self.streams)
         self.dtype = torch.float32 if dtype == "f32" else torch.float64
         self.sz = 4 if dtype == "f32" else 8
         if hbm_budget is None:
@@ -180,9 +209,10 @@ class Engine:
         self.waiting = []
         self.active = []
         self.finished = []
-        self.rejected = []
+        self.rejected = []       # footprint above the whole budget
+        self.failed = []         # set-up or a step raised (req.error holds why)
         self.used = 0
-        self.ticks = 0
+        self.step_completions = 0
         self.sf_steps = 0
 
     def _footprint(self, req):
@@ -198,65 +228,117 @@ class Engine:
         else:
             self.waiting.append(req)
 
-    def _admit(self, now):
-        admitted = []
-        for r in admissible(self.waiting, now, self.budget - self.used):
+    def _now(self):
+        return time.perf_counter() - self.t0
+
+    def _release(self, a):
+        self.stream_load[a.stream_index] -= 1
+        self.used -= a.held
+
+    def _fail(self, req, err, a=None):
+        req.error = f"{type(err).__name__}: {err}"
+        req.done = self._now()
+        if a is not None:
+            try:
+                a.close()
+            except Exception:
+                pass
+            self._release(a)
+        self.failed.append(req)
+
+    def _admit(self):
+        """Admits every waiting request that has arrived and fits, in order;
+        each starts its first step at once."""
+        for r in admissible(self.waiting, self._now(), self.budget - self.used):
             self.waiting.remove(r)
-            r.admitted = time.perf_counter() - self.t0
-            self.used += r.footprint
+            r.admitted = self._now()
             si = min(range(len(self.streams)), key=lambda i: self.stream_load[i])
             self.stream_load[si] += 1
-            act = _Active(r, self.dtype, self.eta, self.use_graph, self.max_workspace,
-                          self.streams[si])
+            self.used += r.footprint
+            try:
+                act = _activate(r, self.dtype, self.eta, self.use_graph, self.max_workspace,
+                                self.streams[si])
+            except Exception as err:            # malformed request, no memory, ...
+                self.stream_load[si] -= 1
+                self.used -= r.footprint
+                self._fail(r, err)
+                continue
             act.stream_index = si
+            # what the request actually holds replaces the estimate
+            act.held = int(getattr(act, "bytes", r.footprint))
+            self.used += act.held - r.footprint
             self.active.append(act)
-            admitted.append(r)
-        return admitted
+            self._step(act)
 
-    def tick(self):
-        """One engine tick: admit, enqueue one step of every active request,
-        wait for them, retire the finished ones.  Returns False when idle
-        (nothing active and nothing admissible yet)."""
-        now = time.perf_counter() - self.t0
-        self._admit(now)
-        if not self.active:
-            return False
-        for a in self.active:
+    def _step(self, a):
+        try:
             a.enqueue_step()
-        for a in self.active:
-            a.done_event.synchronize()
-        t = time.perf_counter() - self.t0
-        self.ticks += 1
-        still = []
-        for a in self.active:
+        except Exception as err:
+            self.active.remove(a)
+            self._fail(a.req, err, a)
+
+    def poll(self):
+        """One pass over the active requests: each whose last step is done
+        counts it, then retires or enqueues its next step.  Returns the
+        number of steps completed in this pass."""
+        n = 0
+        for a in list(self.active):
+            if not a.done_event.query():
+                continue
+            n += 1
+            self.step_completions += 1
             a.req.steps_done += 1
             self.sf_steps += a.req.nsf
-            if a.req.steps_done >= self.steps:
-                a.req.done = t
+            if a.req.steps_done < self.steps:
+                self._step(a)
+                continue
+            a.req.done = self._now()
+            self.active.remove(a)
+            try:
                 if self.keep_results:
                     a.req.result = a.snapshot()
                 a.close()
-                self.stream_load[a.stream_index] -= 1
-                self.used -= a.req.footprint
-                self.finished.append(a.req)
-            else:
-                still.append(a)
-        self.active = still
-        return True
+            except Exception as err:
+                self._release(a)
+                a.req.error = f"{type(err).__name__}: {err}"
+                self.failed.append(a.req)
+                continue
+            self._release(a)
+            self.finished.append(a.req)
+        return n
 
-    def run(self, requests, t0=None):
+    def run(self, requests, t0=None, poll_s=50e-6, progress=None, every=100):
         """Serve `requests` (their `arrival` times in seconds from now) until
-        all are finished.  Returns the finished requests."""
+        all are finished or failed.  Returns the finished requests.
+        `progress(ended, total, seconds)` is called each time another
+        `every` requests have ended (finished or failed)."""
         self.t0 = time.perf_counter() if t0 is None else t0
         for r in requests:
             self.submit(r)
+        total = len(self.waiting)
+        reported = 0
         while self.waiting or self.active:
-            if not self.tick():
-                # idle until the next arrival
+            self._admit()
+            if self.poll():
+                ended = len(self.finished) + len(self.failed)
+                if progress is not None and ended - reported >= every:
+                    reported = ended
+                    progress(ended, total, self._now())
+                continue
+            if self.active:
+                time.sleep(poll_s)
+            elif self.waiting:
+                # idle until the next arrival (or until memory frees, which
+                # cannot happen with nothing active: the head does not fit)
                 nxt = min(r.arrival for r in self.waiting)
-                delay = nxt - (time.perf_counter() - self.t0)
+                delay = nxt - self._now()
                 if delay > 0:
                     time.sleep(min(delay, 0.05))
+                elif not admissible(self.waiting, self._now(), self.budget - self.used):
+                    # the head of the queue can never fit: fail it
+                    head = min(self.waiting, key=lambda r: (r.arrival, r.rid))
+                    self.waiting.remove(head)
+                    self._fail(head, MemoryError("footprint above the free budget"))
         return self.finished
 
 
@@ -334,19 +416,21 @@ def _single_plan(ctx, one, segs):
     return Plan(ctx, one, np.concatenate(parts)), in_off, out_off
 
 
-def make_requests(n, dtype_sz=4, rate=None, seed=0, max_nsf=None, ngauss=32, fast=False):
+def make_requests(n, dtype_sz=4, rate=None, seed=0, max_nsf=None, ngauss=32, fast=False,
+                  nsf=None):
     """`n` serving requests drawn as the serving workload (systems of 50-4000
     support functions, log-uniform) with Poisson arrivals at `rate` per
     second (all at t = 0 when rate is None).  Host inputs only.  With
     `fast`, each request's coefficients are N(0, 1/n_coef) from one stream
     per request instead of the per-function enveloped draws (the work done
-    does not depend on the values)."""
+    does not depend on the values).  `nsf` fixes the size, `max_nsf` caps
+    the drawn one."""
     import inputs
     rng = np.random.default_rng(7000 + seed)
     t = 0.0
     reqs = []
     for i in range(n):
-        g = inputs.geometry("serve", seed_offset=seed * 100000 + i)
+        g = inputs.geometry("serve", nsf=nsf, seed_offset=seed * 100000 + i)
         if max_nsf is not None and len(g.radii) > max_nsf:
             g = inputs.geometry("serve", nsf=max_nsf, seed_offset=seed * 100000 + i)
         lr, segs = build_locregs(g.h, g.grid_n, g.centers, g.radii, g.fine_radii, g.ext)
@@ -378,6 +462,10 @@ def _pts(segs, r, kind):
                            for s in rows])
 
 
+# request sizes (support functions) of the per-bucket latencies
+SIZE_BUCKETS = ((50, 200), (200, 1000), (1000, 4001))
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -387,66 +475,181 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def _trace(pool, n, rate, seed):
+    """n requests drawn uniformly from the prepared systems of `pool`, with
+    Poisson arrivals at `rate` per second (all at t = 0 when rate is None);
+    each is a fresh request on its system's host inputs."""
+    rng = np.random.default_rng(9000 + seed)
+    pick = rng.integers(0, len(pool), n)
+    t = np.cumsum(rng.exponential(1.0 / rate, n)) if rate else np.zeros(n)
+    out = []
+    for j, (i, a) in enumerate(zip(pick, t)):
+        r = pool[int(i)].fresh(float(a))
+        r.rid = j
+        out.append(r)
+    return out
+
+
+def _latencies(done):
+    lat = [r.latency for r in done]
+    buckets = {}
+    for lo, hi in SIZE_BUCKETS:
+        bl = [r.latency for r in done if lo <= r.nsf < hi]
+        buckets[f"{lo}-{hi - 1}"] = {"requests": len(bl), "p50_s": percentile(bl, 50),
+                                     "p99_s": percentile(bl, 99)}
+    return lat, buckets
+
+
 def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_requests=4,
-              baseline_budget_s=60.0, log=print, loads=(0.5, 0.95)):
-    """Serving measurement: (1) saturated throughput with every request
-    queued at t = 0; (2) Poisson arrivals at `load` x that request rate, p50
-    and p99 latency (and at each of `loads` as well); (3) the per-function
-    FP64 baseline on the first `baseline_requests` requests of the `load`
-    arrival trace (one at a time).  Returns a dict of the figures."""
+              log=print, loads=(0.5, 0.95), pool_size=None, n_other=None, n_saturated=None,
+              progress_every=100, mu=None):
+    """Serving measurement on requests drawn from a pool of `pool_size`
+    prepared systems (sizes log-uniform, as the serving workload; by default
+    one system per request): (1) saturated throughput with `n_saturated`
+    requests queued at t = 0; (2) Poisson arrivals at `load` x that request
+    rate, `n_requests` of them, p50 and p99 latency overall and by size;
+    (3) the same at each of `loads` with `n_other` requests; (4) the
+    per-function FP64 baseline: the first `baseline_requests` requests of
+    the `load` trace, each served alone (its service time: the plain path
+    cannot keep up with the offered rate, so under that arrival stream its
+    queue, and its latency, grow without bound).  A log line is written
+    each time another `progress_every` requests of a run have ended.  With
+    `mu` (requests/s, from an earlier saturated run on the same pool and
+    seed) the saturated run is skipped and the loads are fractions of `mu`.
+    Returns a dict of the figures."""
     import torch
+    pool_size = pool_size or n_requests
+    n_other = n_other or n_requests
+    n_saturated = n_saturated or n_requests
     t0 = time.perf_counter()
-    base_reqs = make_requests(n_requests, seed=seed, fast=True)
+    pool = make_requests(pool_size, seed=seed, fast=True)
     t_prep = time.perf_counter() - t0
-    reqs = [r.fresh() for r in base_reqs]
-    sizes = [r.nsf for r in reqs]
-    log(f"serving: {n_requests} requests, {sum(sizes)} functions "
+    sizes = [r.nsf for r in pool]
+    log(f"serving: pool of {pool_size} systems, {sum(sizes)} functions "
         f"(min {min(sizes)}, median {int(np.median(sizes))}, max {max(sizes)}), "
         f"inputs prepared in {t_prep:.1f} s")
     # warm-up on a small request (kernel loads, allocator)
     Engine(dtype=dtype, steps=1).run(make_requests(1, seed=seed + 99, max_nsf=50, fast=True))
     torch.cuda.synchronize()
-    eng = Engine(dtype=dtype, steps=steps)
-    t1 = time.perf_counter()
-    eng.run(reqs)
-    t_sat = time.perf_counter() - t1
-    mu = n_requests / t_sat
-    sat = {"seconds": t_sat, "requests_per_s": mu, "sf_steps_per_s": eng.sf_steps / t_sat,
-           "ticks": eng.ticks}
-    log(f"serving: saturated {t_sat:.2f} s, {mu:.2f} requests/s, "
-        f"{eng.sf_steps / t_sat:.0f} support-function steps/s")
-    def poisson(ld):
+    free0 = torch.cuda.mem_get_info()[0]
+
+    def prog(name):
+        return lambda k, n, t: log(f"serving: {name}: {k}/{n} requests ended, {t:.1f} s")
+
+    if mu is None:
+        reqs = _trace(pool, n_saturated, None, seed)
+        eng = Engine(dtype=dtype, steps=steps)
+        t1 = time.perf_counter()
+        eng.run(reqs, progress=prog("saturated"), every=progress_every)
+        t_sat = time.perf_counter() - t1
+        mu = len(eng.finished) / t_sat
+        sat = {"requests": n_saturated, "seconds": t_sat, "requests_per_s": mu,
+               "sf_steps_per_s": eng.sf_steps / t_sat,
+               "step_completions": eng.step_completions, "failed": len(eng.failed)}
+        log(f"serving: saturated {t_sat:.2f} s, {mu:.2f} requests/s, "
+            f"{eng.sf_steps / t_sat:.0f} support-function steps/s")
+        if eng.failed:
+            raise RuntimeError(f"serving: request {eng.failed[0].rid} failed: "
+                               f"{eng.failed[0].error}")
+    else:
+        sat = {"requests_per_s": float(mu), "note": "given (earlier saturated run)"}
+
+    def poisson(ld, n):
         rate = ld * mu
-        rng = np.random.default_rng(9000 + seed)
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
-        reqs2 = [r.fresh(float(a)) for r, a in zip(base_reqs, arrivals)]
+        reqs2 = _trace(pool, n, rate, seed + int(100 * ld))
         eng2 = Engine(dtype=dtype, steps=steps)
         t2 = time.perf_counter()
-        done = eng2.run(reqs2)
+        done = eng2.run(reqs2, progress=prog(f"load {ld}"), every=progress_every)
         t_run = time.perf_counter() - t2
-        lat = [r.latency for r in done]
-        res = {"offered_requests_per_s": rate, "load": ld, "seconds": t_run,
+        if eng2.failed:
+            raise RuntimeError(f"serving: load {ld}: request {eng2.failed[0].rid} failed: "
+                               f"{eng2.failed[0].error}")
+        lat, buckets = _latencies(done)
+        res = {"requests": n, "offered_requests_per_s": rate, "load": ld, "seconds": t_run,
                "requests_per_s": len(done) / t_run, "sf_steps_per_s": eng2.sf_steps / t_run,
                "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
-               "max_s": max(lat), "rejected": len(eng2.rejected)}
-        log(f"serving: load {ld}: p50 {res['p50_s']:.3f} s, p99 {res['p99_s']:.3f} s")
-        return res, arrivals, lat
+               "max_s": max(lat), "rejected": len(eng2.rejected), "failed": len(eng2.failed),
+               "by_size": buckets}
+        log(f"serving: load {ld}, {n} requests: p50 {res['p50_s']:.3f} s, "
+            f"p99 {res['p99_s']:.3f} s")
+        return res, reqs2, done
 
-    served, arrivals, lat = poisson(load)
-    others = [poisson(ld)[0] for ld in loads if ld != load]
+    served, trace, done = poisson(load, n_requests)
+    others = [poisson(ld, n_other)[0] for ld in loads if ld != load]
+    torch.cuda.synchronize()
+    # device memory the runs left held (graphs, plans, streams)
+    held_mib = (free0 - torch.cuda.mem_get_info()[0]) / 2**20
     base = None
     if baseline_requests:
-        breqs = [r.fresh(float(a)) for r, a in zip(base_reqs[:baseline_requests], arrivals)]
+        svc, sz = [], []
         tb = time.perf_counter()
-        bdone = run_per_function(breqs, steps=steps)
-        blat = [r.latency for r in bdone]
+        for k, r in enumerate(trace[:baseline_requests]):
+            one = run_per_function([r.fresh(0.0)], steps=steps)[0]
+            svc.append(one.latency)
+            sz.append(r.nsf)
+            if progress_every and (k + 1) % max(1, progress_every // 10) == 0:
+                log(f"serving: per-function baseline: {k + 1}/{baseline_requests} requests")
+        eng_lat = {r.rid: r.latency for r in done}
+        same = [eng_lat[r.rid] for r in trace[:baseline_requests] if r.rid in eng_lat]
         base = {"requests": baseline_requests, "seconds": time.perf_counter() - tb,
-                "p50_s": percentile(blat, 50), "p99_s": percentile(blat, 99),
-                "engine_p50_s_same_requests": percentile(lat[:baseline_requests], 50),
-                "kind": "FP64, one support function per apply, no graphs, FIFO"}
-        log(f"serving: per-function FP64 baseline p50 {base['p50_s']:.3f} s, "
-            f"p99 {base['p99_s']:.3f} s over its {baseline_requests} requests")
-    return {"requests": n_requests, "functions": sum(sizes), "steps": steps, "dtype": dtype,
+                "service_p50_s": percentile(svc, 50), "service_p99_s": percentile(svc, 99),
+                "requests_per_s": len(svc) / sum(svc),
+                "offered_requests_per_s": served["offered_requests_per_s"],
+                "engine_p50_s_same_requests": percentile(same, 50),
+                "engine_p99_s_same_requests": percentile(same, 99),
+                "sizes": sz,
+                "kind": "FP64, one support function per apply, no graphs, each request "
+                        "alone (service time, no queueing)"}
+        log(f"serving: per-function FP64 baseline, {baseline_requests} requests alone: "
+            f"service p50 {base['service_p50_s']:.3f} s, p99 {base['service_p99_s']:.3f} s, "
+            f"{base['requests_per_s']:.3f} requests/s")
+    return {"pool": pool_size, "functions_in_pool": sum(sizes), "steps": steps, "dtype": dtype,
             "saturated": sat, "poisson": served,
             "poisson_other_loads": others, "per_function_fp64": base,
-            "latency_note": "arrival -> end of the last step, host clock"}
+            "device_mib_held_after_runs": held_mib,
+            "latency_note": "arrival -> end of the last step, host clock; requests drawn "
+                            "from the pool's systems"}
+
+
+def main(argv=None):
+    """Serving benchmark from the command line; writes one JSON document."""
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--requests", type=int, default=1000, help="Poisson requests at --load")
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--loads", type=float, nargs="*", default=[],
+                    help="further load levels, --other requests each")
+    ap.add_argument("--other", type=int, default=1000)
+    ap.add_argument("--saturated", type=int, default=200)
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--baseline", type=int, default=0,
+                    help="requests of the trace served alone by the per-function FP64 path")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--progress-every", type=int, default=100)
+    ap.add_argument("--mu", type=float, default=None,
+                    help="saturated requests/s from an earlier run (skips the saturated run)")
+    ap.add_argument("--out", default="-")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    res = benchmark(n_requests=args.requests, load=args.load, dtype=args.dtype,
+                    steps=args.steps, seed=args.seed, baseline_requests=args.baseline, log=log,
+                    loads=tuple(args.loads), pool_size=args.pool, n_other=args.other,
+                    n_saturated=args.saturated, progress_every=args.progress_every,
+                    mu=args.mu)
+    text = json.dumps(res, indent=1)
+    if args.out == "-":
+        print(text)
+    else:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+
+
+if __name__ == "__main__":
+    main()

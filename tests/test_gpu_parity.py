@@ -132,6 +132,31 @@ def test_sphere_batch_every_function(spheres, dtype, tol):
         assert abs(ek[k] - rk) < etol and abs(ep[k] - rp) < etol, k
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_kinetic_z_on_matrix_cores(spheres, dtype, tol):
+    """The schedule with the z part of the kinetic term as banded-Toeplitz
+    products on the FP64 matrix cores (k_kin_zmfma), 1 and 3 bins: H|phi>,
+    e_kin, e_pot and the kinetic term alone against the oracle."""
+    _print(f"case: z kinetic on the matrix cores, {dtype}")
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    for nbins in (1, 3):
+        ctx = W.Context(spheres.g.h, spheres.g.grid_n)
+        plan = W.Plan(ctx, spheres.rec, spheres.segs)
+        W.set_schedule(plan, nbins, 1)
+        _, _, out, ek, ep = spheres.run(dt, plan=plan)
+        _, _, outk, _, _ = spheres.run(dt, terms=W.KIN, plan=plan)
+        worst = 0.0
+        for k in range(len(spheres.lrs)):
+            ref, rk, rp = spheres.oracle(k)
+            refk, _, _ = spheres.oracle(k, potential=False)
+            worst = max(worst, rel_err(out[spheres.out_slice(k)], ref))
+            assert rel_err(out[spheres.out_slice(k)], ref) < tol, k
+            assert rel_err(outk[spheres.out_slice(k)], refk) < tol, k
+            etol = 1e-12 * abs(rk) if dtype == "f64" else 1e-6
+            assert abs(ek[k] - rk) < etol and abs(ep[k] - rp) < etol, k
+        _print(f"  {nbins} bins: worst relative error {worst:.2e}")
+
+
 def test_kinetic_and_potential_terms_separately(spheres):
     _print("case: separate terms FP64")
     _, _, outk, ek, _ = spheres.run(torch.float64, terms=W.KIN)
@@ -400,12 +425,15 @@ def test_confining_potential(spheres, dtype, tol):
         assert abs(gek[k] - oek) <= (1e-12 * max(1.0, abs(oek)) if dtype == "f64" else 1e-6)
 
 
-@pytest.mark.parametrize("dtype,tol,conf", [("f64", 1e-11, True), ("f64", 1e-11, False),
+@pytest.mark.parametrize("dtype,tol,conf", [("f64", 1e-12, True), ("f64", 1e-12, False),
                                             ("f32", 1e-5, True)])
 def test_preconditioner(spheres, dtype, tol, conf):
     """wvl_precondition (5 conjugate-gradient steps) against the oracle's
-    steps.  The FP64 bound is the apply's 1e-12 allowed to grow over the
-    five steps; FP32 keeps the 1e-5 of the apply."""
+    steps, to the apply's bounds (FP64 1e-12, FP32 1e-5 relative).  Each step
+    applies the operator once (relative error ~1e-15 in FP64) and forms its
+    coefficients from dot products in double; over five steps of a
+    well-conditioned operator (kinetic plus a positive shift) the error
+    grows by a small factor: measured 7.8e-16 (FP64), 9.4e-8 (FP32)."""
     from oracle import precond as PC
     _print(f"case: preconditioner {dtype} conf={conf}")
     dt = torch.float64 if dtype == "f64" else torch.float32

@@ -30,7 +30,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
     reqs = _requests(4, 8, seed=11)
     eng = S.Engine(dtype="f32", steps=3, keep_results=True)
     done = {r.rid: r for r in eng.run(reqs)}
-    assert sorted(done) == [0, 1, 2, 3] and eng.ticks == 3
+    assert sorted(done) == [0, 1, 2, 3] and eng.step_completions == 12
     for r in _requests(4, 8, seed=11):
         alone = S.Engine(dtype="f32", steps=3, keep_results=True)
         a = alone.run([r])[0]
@@ -38,7 +38,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
             assert np.array_equal(a.result[key], done[r.rid].result[key]), (r.rid, key)
 
 
-def test_staggered_arrivals_join_at_tick_boundaries():
+def test_staggered_arrivals_join_as_memory_frees():
     _print("case: serving, staggered arrivals and a tight budget")
     reqs = _requests(3, 6, seed=12)
     for i, r in enumerate(reqs):
@@ -82,3 +82,44 @@ def test_per_function_baseline_agrees_with_engine():
     a = S.run_per_function(_requests(1, 5, seed=14), steps=2, keep_results=True)[0]
     b = S.Engine(dtype="f64", steps=2, keep_results=True).run(_requests(1, 5, seed=14))[0]
     assert rel_err(a.result["psi"], b.result["psi"]) < 1e-13
+
+
+def test_malformed_request_fails_alone():
+    """A request whose segment offsets are not running sums is rejected by
+    the library at plan creation; it lands in `failed` with the library's
+    message, its memory is returned, and the requests around it finish with
+    the same results as without it."""
+    _print("case: serving, a malformed request among good ones")
+    reqs = _requests(3, 6, seed=15)
+    bad = reqs[1].fresh()
+    bad.rid = 99
+    bad.segs = bad.segs.copy()
+    bad.segs["off"][1] += 1
+    eng = S.Engine(dtype="f32", steps=2, keep_results=True)
+    done = {r.rid: r for r in eng.run(reqs + [bad])}
+    assert sorted(done) == [0, 1, 2]
+    assert [r.rid for r in eng.failed] == [99] and "running sum" in eng.failed[0].error
+    assert eng.used == 0 and not eng.active and all(v == 0 for v in eng.stream_load)
+    ref = {r.rid: r for r in S.Engine(dtype="f32", steps=2, keep_results=True).run(
+        _requests(3, 6, seed=15))}
+    for k in done:
+        assert np.array_equal(done[k].result["psi"], ref[k].result["psi"])
+
+
+def test_small_request_is_not_held_back_by_a_large_one():
+    """Steps advance per request: a 20-function request admitted beside a
+    2,000-function one runs its 5 steps in a fraction of the large one's time
+    (from admission: the host builds each plan at admission, one after the
+    other, which the small one waits for)."""
+    _print("case: serving, a small request beside a large one")
+    big = S.make_requests(1, nsf=2000, seed=16, fast=True)[0]
+    small = S.make_requests(1, nsf=20, seed=17, fast=True)[0]
+    small.rid = 1
+    eng = S.Engine(dtype="f32", steps=5)
+    eng.run([big, small])
+    got = {r.rid: r for r in eng.finished}
+    assert got[1].nsf == 20 and got[0].nsf == 2000
+    small_t = got[1].done - got[1].admitted
+    big_t = got[0].done - got[0].admitted
+    _print(f"  from admission: small {small_t:.3f} s, large {big_t:.3f} s")
+    assert small_t < 0.5 * big_t, (small_t, big_t)

@@ -34,3 +34,38 @@ def test_percentile_interpolates():
     assert S.percentile(xs, 50) == 3.0
     assert S.percentile(xs, 100) == 5.0
     assert abs(S.percentile(xs, 99) - 4.96) < 1e-12
+
+
+class _FakeEvent:
+    def query(self):
+        return True
+
+
+class _FakeActive:
+    """Stands in for the device state of a request (no GPU)."""
+    def __init__(self, req, dtype, eta, use_graph, max_workspace, stream):
+        if req.rid == 1:
+            raise ValueError("malformed request")
+        self.req, self.bytes, self.done_event = req, 123, None
+
+    def enqueue_step(self):
+        self.done_event = _FakeEvent()
+
+    def close(self):
+        pass
+
+
+def test_engine_isolates_a_failing_request(monkeypatch):
+    monkeypatch.setattr(S, "_Active", _FakeActive)
+    reqs = []
+    for i in range(3):
+        r = S.Request(rid=i, h=0.45, grid_n=(4, 4, 4), locregs=np.zeros(0), segs=None,
+                      psi=None, geom=None, pot_params=None)
+        reqs.append(r)
+    eng = S.Engine.__new__(S.Engine)
+    S.Engine.__init__(eng, hbm_budget=10 ** 9, steps=3, streams=[object(), object()])
+    monkeypatch.setattr(eng, "_footprint", lambda r: 1000)
+    done = eng.run(reqs)
+    assert sorted(r.rid for r in done) == [0, 2]
+    assert [r.rid for r in eng.failed] == [1] and "malformed" in eng.failed[0].error
+    assert eng.used == 0 and eng.stream_load == [0, 0] and eng.step_completions == 6
