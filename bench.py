@@ -126,8 +126,8 @@ def path_bytes(locregs, sz):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("wvl_kernels.hip", "wvl_fused.hip", "wvl_host.cpp", "wvl_internal.h",
-              "wvl_filters.h"):
+    for f in ("wvl_kernels.hip", "wvl_fused.hip", "wvl_static.hip", "wvl_host.cpp",
+              "wvl_internal.h", "wvl_filters.h"):
         with open(os.path.join(ROOT, "paper_1401_7441_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -203,6 +203,26 @@ wvl_status wvl_apply_local_ham_conf(wvl_plan* plan, wvl_dtype dt, uint32_t terms
                                     const void* psi_c, const void* pot, const double* conf,
                                     void* hpsi_c, double* e_kin, double* e_pot, void* workspace);
 
+/* Allocation-free variant of wvl_apply_local_ham, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device array
+ * of WVL_STATIC_WORKSPACE_BYTES that the library holds on every GPU it runs
+ * on until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call.  The plan's workspace size for dt (wvl_plan_info;
+ * bounded at plan creation by max_workspace_bytes, which makes the functions
+ * run in chunks that reuse one region) must not exceed it: larger plans are
+ * rejected with WVL_EINVAL before anything is launched.  Every call on one
+ * GPU uses the same array: calls that overlap on one GPU (two streams, two
+ * threads, or one call still running on another stream) race; the array
+ * keeps the last call's contents, and the apply reads nothing of it that it
+ * has not written in the same call.  The GPU is the one of the context's
+ * stream (the current device for the NULL stream).  Other arguments and
+ * errors as wvl_apply_local_ham. */
+#define WVL_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
+wvl_status wvl_apply_local_ham_static(wvl_plan* plan, wvl_dtype dt, uint32_t terms,
+                                      const void* psi_c, const void* pot, void* hpsi_c,
+                                      double* e_kin, double* e_pot);
+
 /* Kinetic term only (Sec. III.B, the -1/2 nabla^2 part), ACCUMULATED into
  * hpsi_c (device, output layout): hpsi += L' T L psi.  e_kin as above. */
 wvl_status wvl_kinetic(wvl_plan* plan, wvl_dtype dt, const void* psi_c, void* hpsi_c,

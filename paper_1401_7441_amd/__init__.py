@@ -42,7 +42,8 @@ LOCREG_DTYPE = np.dtype([
 
 EXPORTED = ("wvl_build_locregs", "wvl_create", "wvl_destroy", "wvl_last_error",
             "wvl_plan_create", "wvl_plan_destroy", "wvl_plan_info_get", "wvl_uncompress",
-            "wvl_compress", "wvl_apply_local_ham", "wvl_apply_local_ham_conf", "wvl_kinetic",
+            "wvl_compress", "wvl_apply_local_ham", "wvl_apply_local_ham_conf",
+            "wvl_apply_local_ham_static", "wvl_kinetic",
             "wvl_sparse_overlap", "wvl_synthesize", "wvl_density", "wvl_foe", "wvl_gradient",
             "wvl_update", "wvl_precondition", "wvl_graph_create", "wvl_graph_launch",
             "wvl_graph_destroy",
@@ -103,6 +104,7 @@ def _load():
         "wvl_apply_local_ham": [P, ctypes.c_int, U32, P, P, P, P, P, P],
         "wvl_kinetic": [P, ctypes.c_int, P, P, P, P],
         "wvl_apply_local_ham_conf": [P, ctypes.c_int, U32, P, P, P, P, P, P, P],
+        "wvl_apply_local_ham_static": [P, ctypes.c_int, U32, P, P, P, P, P],
         "wvl_sparse_overlap": [P, P, ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(I64), P, P, P],
         "wvl_synthesize": [P, ctypes.c_int, P, P, P],
         "wvl_foe": [P, P, P, I32, D, D, D, D, P, ctypes.POINTER(D), ctypes.POINTER(D), P,
@@ -362,6 +364,27 @@ def apply_local_ham(plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None, work
         return
     _check(lib().wvl_apply_local_ham(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
                                     _ptr(hpsi_c), _ptr(e_kin), _ptr(e_pot), _ptr(workspace)),
+           plan.ctx.handle)
+
+
+STATIC_WORKSPACE_BYTES = 128 << 20     # WVL_STATIC_WORKSPACE_BYTES
+
+
+def apply_local_ham_static(plan: Plan, psi_c, pot, hpsi_c, e_kin=None, e_pot=None,
+                           terms=KIN | POT):
+    """wvl_apply_local_ham_static: the apply on the library's static
+    workspace (no device allocation in the call); the plan's workspace must
+    fit STATIC_WORKSPACE_BYTES (bound it with Plan(max_workspace=...))."""
+    _need_cuda(psi_c, pot, hpsi_c, e_kin, e_pot)
+    dt = _dtype_code(psi_c, pot, hpsi_c)
+    _check_sizes(plan, psi_c, hpsi_c, e_kin, e_pot, None, dt)
+    if pot is not None:
+        n = plan.ctx.grid_n
+        need = (2 * n[0] + 29) * (2 * n[1] + 29) * (2 * n[2] + 29)
+        if pot.numel() != need:
+            raise WvlError(WVL_EINVAL, f"potential has {pot.numel()} points, the grid needs {need}")
+    _check(lib().wvl_apply_local_ham_static(plan._ptr, dt, int(terms), _ptr(psi_c), _ptr(pot),
+                                           _ptr(hpsi_c), _ptr(e_kin), _ptr(e_pot)),
            plan.ctx.handle)
 
 

@@ -54,7 +54,7 @@ def build(regen_filters: bool = True) -> str:
     os.makedirs(bdir, exist_ok=True)
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     kobjs = []
-    for src in ("wvl_kernels.hip", "wvl_fused.hip"):
+    for src in ("wvl_kernels.hip", "wvl_fused.hip", "wvl_static.hip"):
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         kobjs.append(obj)

@@ -1136,6 +1136,30 @@ wvl_status wvl_apply_local_ham(wvl_plan* plan, wvl_dtype dt, uint32_t terms, con
                     "wvl_apply_local_ham");
 }
 
+}  // extern "C"
+
+wvl_status wvl::apply_in_workspace(wvl_plan* P, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                                   const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                                   void* workspace, size_t cap, const char* who) {
+  if (!P) return fail(nullptr, WVL_EINVAL, "%s: null plan", who);
+  if (check_dt(P->ctx, dt) != WVL_OK) return WVL_EINVAL;
+  const int64_t need = dt == WVL_F64 ? P->info.workspace_f64 : P->info.workspace_f32;
+  if (P->nsf > 0 && need > (int64_t)cap)
+    return fail(P->ctx, WVL_EINVAL,
+                "%s: the plan needs a workspace of %lld bytes for %s, the static one holds %zu; "
+                "create the plan with a smaller max_workspace_bytes",
+                who, (long long)need, dt == WVL_F64 ? "WVL_F64" : "WVL_F32", cap);
+  return apply_impl(P, dt, terms, psi_c, pot, hpsi_c, e_kin, e_pot, workspace, 0, who);
+}
+
+wvl_status wvl::plan_error(wvl_plan* P, wvl_status st, const char* msg) {
+  return fail(P ? P->ctx : nullptr, st, "%s", msg);
+}
+
+void* wvl::plan_stream(const wvl_plan* P) { return P ? (void*)P->ctx->stream : nullptr; }
+
+extern "C" {
+
 wvl_status wvl_apply_local_ham_conf(wvl_plan* plan, wvl_dtype dt, uint32_t terms,
                                     const void* psi_c, const void* pot, const double* conf,
                                     void* hpsi_c, double* e_kin, double* e_pot, void* workspace) {

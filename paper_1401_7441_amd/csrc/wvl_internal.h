@@ -91,6 +91,16 @@ struct ChunkDev {
   int32_t nblk_pot, nblk_kin;      // partial slots per function
 };
 
+// the apply of wvl_apply_local_ham on a workspace of `cap` bytes that the
+// caller vouches for (wvl_host.cpp); rejects plans that need more
+wvl_status apply_in_workspace(wvl_plan* plan, wvl_dtype dt, uint32_t terms, const void* psi_c,
+                              const void* pot, void* hpsi_c, double* e_kin, double* e_pot,
+                              void* workspace, size_t cap, const char* who);
+// records an error on the plan's context (or the thread's, for a NULL plan)
+wvl_status plan_error(wvl_plan* plan, wvl_status st, const char* msg);
+// the HIP stream of the plan's context
+void* plan_stream(const wvl_plan* plan);
+
 // load every kernel's code object before a stream capture (hipError_t as int)
 int preload_kernels();         // wvl_kernels.hip
 int preload_fused_kernels();   // wvl_fused.hip

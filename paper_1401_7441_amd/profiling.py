@@ -32,8 +32,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("wvl_kernels.hip", "wvl_fused.hip", "wvl_host.cpp", "wvl_internal.h",
-              "wvl_filters.h"):
+    for f in ("wvl_kernels.hip", "wvl_fused.hip", "wvl_static.hip", "wvl_host.cpp",
+              "wvl_internal.h", "wvl_filters.h"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
