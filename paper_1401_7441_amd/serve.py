@@ -214,6 +214,11 @@ class Engine:
         self.used = 0
         self.step_completions = 0
         self.sf_steps = 0
+        self.held_back = False   # admission waits for a retirement (see _admit)
+        # device memory probes (replaceable for host-only tests)
+        self.free_device_bytes = lambda: torch.cuda.mem_get_info()[0]
+        self.release_cache = torch.cuda.empty_cache
+        self.deferred = 0        # admissions put back for lack of device memory
 
     def _footprint(self, req):
         # the workspace of a plan bounded by max_workspace is at most that bound
@@ -234,6 +239,7 @@ class Engine:
     def _release(self, a):
         self.stream_load[a.stream_index] -= 1
         self.used -= a.held
+        self.held_back = False
 
     def _fail(self, req, err, a=None):
         req.error = f"{type(err).__name__}: {err}"
@@ -246,9 +252,32 @@ class Engine:
             self._release(a)
         self.failed.append(req)
 
+    def _activate_with_memory(self, r, si):
+        """_activate, making room first: device memory that torch's caching
+        allocator keeps for the tensors of retired requests is not available
+        to the library's own allocations (plans, patterns, graphs), so the
+        cache is released when the device's free memory is below the
+        request's footprint, and once more after an allocation failure."""
+        if self.free_device_bytes() < r.footprint + (1 << 30):
+            self.release_cache()
+        try:
+            return _activate(r, self.dtype, self.eta, self.use_graph, self.max_workspace,
+                             self.streams[si])
+        except Exception as err:
+            if not _out_of_memory(err):
+                raise
+        self.release_cache()
+        return _activate(r, self.dtype, self.eta, self.use_graph, self.max_workspace,
+                         self.streams[si])
+
     def _admit(self):
         """Admits every waiting request that has arrived and fits, in order;
-        each starts its first step at once."""
+        each starts its first step at once.  A request that fits the budget
+        but finds too little device memory (fragmentation the accounting
+        does not see) goes back to the head of the queue while other
+        requests are active, and is retried when one of them retires."""
+        if self.held_back:
+            return
         for r in admissible(self.waiting, self._now(), self.budget - self.used):
             self.waiting.remove(r)
             r.admitted = self._now()
@@ -256,11 +285,16 @@ class Engine:
             self.stream_load[si] += 1
             self.used += r.footprint
             try:
-                act = _activate(r, self.dtype, self.eta, self.use_graph, self.max_workspace,
-                                self.streams[si])
+                act = self._activate_with_memory(r, si)
             except Exception as err:            # malformed request, no memory, ...
                 self.stream_load[si] -= 1
                 self.used -= r.footprint
+                if _out_of_memory(err) and self.active:
+                    r.admitted = math.nan
+                    self.waiting.append(r)
+                    self.held_back = True
+                    self.deferred += 1
+                    return
                 self._fail(r, err)
                 continue
             act.stream_index = si
@@ -340,6 +374,15 @@ class Engine:
                     self.waiting.remove(head)
                     self._fail(head, MemoryError("footprint above the free budget"))
         return self.finished
+
+
+def _out_of_memory(err):
+    """Whether an exception is a device allocation failure (the library's
+    WVL_ENOMEM or torch's out-of-memory error)."""
+    from . import WVL_ENOMEM, WvlError
+    if isinstance(err, WvlError):
+        return err.status == WVL_ENOMEM
+    return type(err).__name__ == "OutOfMemoryError" or "out of memory" in str(err)
 
 
 def admissible(waiting, now, free):
@@ -545,7 +588,8 @@ def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_re
         mu = len(eng.finished) / t_sat
         sat = {"requests": n_saturated, "seconds": t_sat, "requests_per_s": mu,
                "sf_steps_per_s": eng.sf_steps / t_sat,
-               "step_completions": eng.step_completions, "failed": len(eng.failed)}
+               "step_completions": eng.step_completions, "failed": len(eng.failed),
+               "deferred_for_memory": eng.deferred}
         log(f"serving: saturated {t_sat:.2f} s, {mu:.2f} requests/s, "
             f"{eng.sf_steps / t_sat:.0f} support-function steps/s")
         if eng.failed:
@@ -569,7 +613,7 @@ def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_re
                "requests_per_s": len(done) / t_run, "sf_steps_per_s": eng2.sf_steps / t_run,
                "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
                "max_s": max(lat), "rejected": len(eng2.rejected), "failed": len(eng2.failed),
-               "by_size": buckets}
+               "deferred_for_memory": eng2.deferred, "by_size": buckets}
         log(f"serving: load {ld}, {n} requests: p50 {res['p50_s']:.3f} s, "
             f"p99 {res['p99_s']:.3f} s")
         return res, reqs2, done

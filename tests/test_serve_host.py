@@ -65,7 +65,41 @@ def test_engine_isolates_a_failing_request(monkeypatch):
     eng = S.Engine.__new__(S.Engine)
     S.Engine.__init__(eng, hbm_budget=10 ** 9, steps=3, streams=[object(), object()])
     monkeypatch.setattr(eng, "_footprint", lambda r: 1000)
+    eng.free_device_bytes = lambda: 1 << 40
     done = eng.run(reqs)
     assert sorted(r.rid for r in done) == [0, 2]
     assert [r.rid for r in eng.failed] == [1] and "malformed" in eng.failed[0].error
     assert eng.used == 0 and eng.stream_load == [0, 0] and eng.step_completions == 6
+
+
+class _TightActive(_FakeActive):
+    """Request 1's set-up runs out of device memory while request 0 is
+    active (twice: the first try and the retry after the cache release)."""
+    tries = 0
+
+    def __init__(self, req, *args):
+        if req.rid == 1 and _TightActive.tries < 2:
+            _TightActive.tries += 1
+            from paper_1401_7441_amd import WVL_ENOMEM, WvlError
+            raise WvlError(WVL_ENOMEM, "hipMalloc(1) returned hipErrorOutOfMemory")
+        self.req, self.bytes, self.done_event = req, 123, None
+
+
+def test_engine_defers_a_request_that_finds_no_device_memory(monkeypatch):
+    """A request whose set-up fails for device memory while another is
+    active goes back to the queue (after one retry with the cache released)
+    and is admitted when that request retires; nothing fails."""
+    monkeypatch.setattr(S, "_Active", _TightActive)
+    _TightActive.tries = 0
+    reqs = [S.Request(rid=i, h=0.45, grid_n=(4, 4, 4), locregs=np.zeros(0), segs=None,
+                      psi=None, geom=None, pot_params=None) for i in range(2)]
+    eng = S.Engine.__new__(S.Engine)
+    S.Engine.__init__(eng, hbm_budget=10 ** 9, steps=2, streams=[object()])
+    monkeypatch.setattr(eng, "_footprint", lambda r: 1000)
+    eng.free_device_bytes = lambda: 0          # always below the footprint
+    released = []
+    eng.release_cache = lambda: released.append(1)
+    done = eng.run(reqs)
+    assert sorted(r.rid for r in done) == [0, 1] and not eng.failed
+    assert eng.deferred == 1 and _TightActive.tries == 2 and len(released) >= 2
+    assert eng.used == 0 and eng.stream_load == [0]
