@@ -9,7 +9,10 @@
 // work done).  A step is one local-Hamiltonian apply over every function plus
 // the overlap and Hamiltonian matrix values on their resident patterns.  With
 // a copy size, one plain device-to-device copy kernel of that size runs first
-// (a known-traffic reference for the memory counters).  Prints one JSON line.
+// (a known-traffic reference for the memory counters).  With WVL_BENCH_FOE
+// set to a degree, one Fermi-operator-expansion call on synthetic S and H of
+// the step's patterns follows (its kernels then appear in counter runs).
+// Prints one JSON line.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -150,10 +153,48 @@ static int run(const char* path, int steps, int warmup, int copy_mib) {
   for (int i = 0; i < steps; ++i) step();
   HIPCHECK(hipStreamSynchronize(st));
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  // with WVL_BENCH_FOE=<npl>: one density kernel by the Fermi operator
+  // expansion (after a warm-up call) on synthetic S and H of the step's
+  // patterns: S = I + small symmetric terms, H symmetric, half the
+  // functions occupied, Gershgorin bounds
+  double foe_ms = -1.0, foe_mu = 0.0, foe_ebs = 0.0;
+  if (const char* fe = getenv("WVL_BENCH_FOE")) {
+    const int npl = atoi(fe);
+    std::vector<int64_t> hrs(nsf + 1), hrh(nsf + 1);
+    std::vector<int32_t> hcs(nnz_s), hch(nnz_h);
+    HIPCHECK(hipMemcpy(hrs.data(), rs, 8 * (nsf + 1), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(hrh.data(), rh, 8 * (nsf + 1), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(hcs.data(), cs, 4 * nnz_s, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(hch.data(), chh, 4 * nnz_h, hipMemcpyDeviceToHost));
+    auto sval = [](int a, int b) { return a == b ? 1.0 : 0.01 * std::sin(0.37 * (a + 1) * (b + 1)); };
+    auto hval = [](int a, int b) {
+      return a == b ? -0.3 + 0.6 * std::sin(0.11 * a) : 0.05 * std::cos(0.23 * (a + 1) * (b + 1));
+    };
+    std::vector<double> sv(nnz_s), hv(nnz_h);
+    for (int a = 0; a < nsf; ++a) {
+      for (int64_t q = hrs[a]; q < hrs[a + 1]; ++q) sv[q] = sval(a, hcs[q]);
+      for (int64_t q = hrh[a]; q < hrh[a + 1]; ++q) hv[q] = hval(a, hch[q]);
+    }
+    HIPCHECK(hipMemcpy(vs, sv.data(), 8 * nnz_s, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(vh, hv.data(), 8 * nnz_h, hipMemcpyHostToDevice));
+    double* kv;
+    void* scr;
+    const size_t scr_bytes = 8 * ((size_t)(npl + 7) * nnz_s + 2 * npl + 6);
+    HIPCHECK(hipMalloc(&kv, 8 * std::max<int64_t>(1, nnz_s)));
+    HIPCHECK(hipMalloc(&scr, scr_bytes));
+    WCHECK(ctx, wvl_foe(plan, vs, vh, npl, 1.0, 0.5 * nsf, 1.0, 0.0, kv, &foe_mu, &foe_ebs, scr,
+                        scr_bytes));
+    const auto f0 = std::chrono::steady_clock::now();
+    WCHECK(ctx, wvl_foe(plan, vs, vh, npl, 1.0, 0.5 * nsf, 1.0, 0.0, kv, &foe_mu, &foe_ebs, scr,
+                        scr_bytes));
+    foe_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - f0).count();
+    HIPCHECK(hipFree(kv));
+    HIPCHECK(hipFree(scr));
+  }
   printf("{\"driver\": \"wvl_bench\", \"nsf\": %d, \"dtype\": \"%s\", \"steps\": %d, \"ms_per_step\": %.4f, "
-         "\"s_nnz\": %lld, \"h_nnz\": %lld, \"kernels\": {",
+         "\"s_nnz\": %lld, \"h_nnz\": %lld, \"foe_ms\": %.4f, \"foe_mu\": %.6f, \"kernels\": {",
          nsf, sizeof(T) == 8 ? "f64" : "f32", steps, ms / std::max(1, steps), (long long)nnz_s,
-         (long long)nnz_h);
+         (long long)nnz_h, foe_ms, foe_mu);
   bool first = true;
   for (int k = 0; k < wvl_profile_count(); ++k) {
     const char* name;

@@ -15,6 +15,9 @@ Scheduling:
     workspace, patterns) fits in the budget left by the active requests;
     after its plan exists the estimate is replaced by the bytes the request
     actually holds;
+  * set-up off the loop: an admitted request's plan, patterns, potential
+    and step graph are built on a worker thread while the host goes on
+    enqueuing the active requests' steps;
   * continuous batching: every active request runs its steps on its own
     HIP stream, so the kernels of different requests overlap on the device;
     the host polls each request's last step and enqueues its next one as
@@ -65,6 +68,7 @@ class Request:
     done: float = math.nan
     steps_done: int = 0
     footprint: int = 0
+    memory_retries: int = 0
     error: str = ""
     result: dict = dataclasses.field(default_factory=dict)
 
@@ -187,7 +191,8 @@ class Engine:
     """Continuous-batching engine (see the module docstring)."""
 
     def __init__(self, dtype="f32", hbm_budget=None, eta=0.01, steps=5, use_graph=True,
-                 max_workspace=8 << 30, keep_results=False, n_streams=8, streams=None):
+                 max_workspace=8 << 30, keep_results=False, n_streams=8, streams=None,
+                 admit_workers=2):
         import torch
         # a fixed pool of streams (default priority): requests take the one
         # with the fewest active requests; buffers are allocated on it, so
@@ -215,6 +220,13 @@ class Engine:
         self.step_completions = 0
         self.sf_steps = 0
         self.held_back = False   # admission waits for a retirement (see _admit)
+        # set-up of admitted requests (plan, patterns, potential, graph) runs
+        # on worker threads, so the host keeps enqueuing the active requests'
+        # steps meanwhile, and a small request's set-up need not wait behind
+        # a large one's; 0 workers: set-up inline
+        self.admit_workers = admit_workers
+        self.setting_up = []     # (request, stream index, future)
+        self._pool = None
         # device memory probes (replaceable for host-only tests)
         self.free_device_bytes = lambda: torch.cuda.mem_get_info()[0]
         self.release_cache = torch.cuda.empty_cache
@@ -284,25 +296,63 @@ class Engine:
             si = min(range(len(self.streams)), key=lambda i: self.stream_load[i])
             self.stream_load[si] += 1
             self.used += r.footprint
+            if self.admit_workers:
+                if self._pool is None:
+                    from concurrent.futures import ThreadPoolExecutor
+                    self._pool = ThreadPoolExecutor(self.admit_workers)
+                self.setting_up.append((r, si, self._pool.submit(self._activate_with_memory,
+                                                                 r, si)))
+                continue
             try:
                 act = self._activate_with_memory(r, si)
             except Exception as err:            # malformed request, no memory, ...
-                self.stream_load[si] -= 1
-                self.used -= r.footprint
-                if _out_of_memory(err) and self.active:
-                    r.admitted = math.nan
-                    self.waiting.append(r)
-                    self.held_back = True
-                    self.deferred += 1
+                if not self._setup_failed(r, si, err):
                     return
-                self._fail(r, err)
                 continue
-            act.stream_index = si
-            # what the request actually holds replaces the estimate
-            act.held = int(getattr(act, "bytes", r.footprint))
-            self.used += act.held - r.footprint
-            self.active.append(act)
-            self._step(act)
+            self._start(act, si)
+
+    def _setup_failed(self, r, si, err):
+        """Undoes an admission whose set-up raised: the request goes back to
+        the queue when it found no device memory while others are active
+        (returns False: stop admitting), else it fails (returns True)."""
+        self.stream_load[si] -= 1
+        self.used -= r.footprint
+        busy = bool(self.active or self.setting_up)
+        # with a worker, the requests it ran beside may have retired since
+        if _out_of_memory(err) and (busy or r.memory_retries < 1):
+            r.memory_retries += 0 if busy else 1
+            r.admitted = math.nan
+            self.waiting.append(r)
+            self.held_back = busy
+            self.deferred += 1
+            return False
+        self._fail(r, err)
+        return True
+
+    def _start(self, act, si):
+        act.stream_index = si
+        # what the request actually holds replaces the estimate
+        act.held = int(getattr(act, "bytes", act.req.footprint))
+        self.used += act.held - act.req.footprint
+        self.active.append(act)
+        self._step(act)
+
+    def _collect(self):
+        """Starts the requests whose set-up has finished; returns how many."""
+        n = 0
+        for item in list(self.setting_up):
+            r, si, fut = item
+            if not fut.done():
+                continue
+            self.setting_up.remove(item)
+            n += 1
+            try:
+                act = fut.result()
+            except Exception as err:
+                self._setup_failed(r, si, err)
+                continue
+            self._start(act, si)
+        return n
 
     def _step(self, a):
         try:
@@ -351,15 +401,15 @@ class Engine:
             self.submit(r)
         total = len(self.waiting)
         reported = 0
-        while self.waiting or self.active:
+        while self.waiting or self.active or self.setting_up:
             self._admit()
-            if self.poll():
+            if self._collect() + self.poll():
                 ended = len(self.finished) + len(self.failed)
                 if progress is not None and ended - reported >= every:
                     reported = ended
                     progress(ended, total, self._now())
                 continue
-            if self.active:
+            if self.active or self.setting_up:
                 time.sleep(poll_s)
             elif self.waiting:
                 # idle until the next arrival (or until memory frees, which
@@ -373,6 +423,9 @@ class Engine:
                     head = min(self.waiting, key=lambda r: (r.arrival, r.rid))
                     self.waiting.remove(head)
                     self._fail(head, MemoryError("footprint above the free budget"))
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
+            self._pool = None
         return self.finished
 
 
@@ -574,6 +627,7 @@ def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_re
     # warm-up on a small request (kernel loads, allocator)
     Engine(dtype=dtype, steps=1).run(make_requests(1, seed=seed + 99, max_nsf=50, fast=True))
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     free0 = torch.cuda.mem_get_info()[0]
 
     def prog(name):
@@ -621,7 +675,9 @@ def benchmark(n_requests=24, load=0.8, dtype="f32", steps=5, seed=1, baseline_re
     served, trace, done = poisson(load, n_requests)
     others = [poisson(ld, n_other)[0] for ld in loads if ld != load]
     torch.cuda.synchronize()
-    # device memory the runs left held (graphs, plans, streams)
+    # device memory the runs left held (graphs, plans, streams), torch's
+    # cache of freed blocks released first on both sides of the difference
+    torch.cuda.empty_cache()
     held_mib = (free0 - torch.cuda.mem_get_info()[0]) / 2**20
     base = None
     if baseline_requests:

@@ -107,10 +107,10 @@ def test_malformed_request_fails_alone():
 
 
 def test_small_request_is_not_held_back_by_a_large_one():
-    """Steps advance per request: a 20-function request admitted beside a
-    2,000-function one runs its 5 steps in a fraction of the large one's time
-    (from admission: the host builds each plan at admission, one after the
-    other, which the small one waits for)."""
+    """Steps advance per request and set-ups run side by side on worker
+    threads: a 20-function request admitted beside a 2,000-function one
+    finishes its 5 steps in a fraction of the large one's time, counted from
+    admission."""
     _print("case: serving, a small request beside a large one")
     big = S.make_requests(1, nsf=2000, seed=16, fast=True)[0]
     small = S.make_requests(1, nsf=20, seed=17, fast=True)[0]

@@ -1,5 +1,6 @@
 """Host logic of the request loop (no GPU): admission order and footprints."""
 import numpy as np
+import pytest
 
 from paper_1401_7441_amd import serve as S
 
@@ -55,7 +56,8 @@ class _FakeActive:
         pass
 
 
-def test_engine_isolates_a_failing_request(monkeypatch):
+@pytest.mark.parametrize("workers", [0, 1])
+def test_engine_isolates_a_failing_request(monkeypatch, workers):
     monkeypatch.setattr(S, "_Active", _FakeActive)
     reqs = []
     for i in range(3):
@@ -63,7 +65,8 @@ def test_engine_isolates_a_failing_request(monkeypatch):
                       psi=None, geom=None, pot_params=None)
         reqs.append(r)
     eng = S.Engine.__new__(S.Engine)
-    S.Engine.__init__(eng, hbm_budget=10 ** 9, steps=3, streams=[object(), object()])
+    S.Engine.__init__(eng, hbm_budget=10 ** 9, steps=3, streams=[object(), object()],
+                      admit_workers=workers)
     monkeypatch.setattr(eng, "_footprint", lambda r: 1000)
     eng.free_device_bytes = lambda: 1 << 40
     done = eng.run(reqs)
@@ -85,7 +88,8 @@ class _TightActive(_FakeActive):
         self.req, self.bytes, self.done_event = req, 123, None
 
 
-def test_engine_defers_a_request_that_finds_no_device_memory(monkeypatch):
+@pytest.mark.parametrize("workers", [0, 1])
+def test_engine_defers_a_request_that_finds_no_device_memory(monkeypatch, workers):
     """A request whose set-up fails for device memory while another is
     active goes back to the queue (after one retry with the cache released)
     and is admitted when that request retires; nothing fails."""
@@ -94,7 +98,8 @@ def test_engine_defers_a_request_that_finds_no_device_memory(monkeypatch):
     reqs = [S.Request(rid=i, h=0.45, grid_n=(4, 4, 4), locregs=np.zeros(0), segs=None,
                       psi=None, geom=None, pot_params=None) for i in range(2)]
     eng = S.Engine.__new__(S.Engine)
-    S.Engine.__init__(eng, hbm_budget=10 ** 9, steps=2, streams=[object()])
+    S.Engine.__init__(eng, hbm_budget=10 ** 9, steps=2, streams=[object()],
+                      admit_workers=workers)
     monkeypatch.setattr(eng, "_footprint", lambda r: 1000)
     eng.free_device_bytes = lambda: 0          # always below the footprint
     released = []
