@@ -35,8 +35,12 @@
  * No C++ exception crosses this interface.
  *
  * Threading: a context is bound to one HIP stream and must not be used from
- * two threads at once.  Plans are immutable after creation and may be
- * applied any number of times.
+ * two threads at once; distinct contexts, with the plans created on them,
+ * may be used from different threads at the same time (graph capture is
+ * thread-local).  A plan may be applied any number of times; it builds its
+ * sparsity patterns on first use and changes its layout only under
+ * wvl_plan_autotune / wvl_plan_set_schedule, so one plan is used by one
+ * thread at a time.
  */
 #ifndef WVL_H
 #define WVL_H
