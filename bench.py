@@ -103,11 +103,9 @@ def work_model(locregs, sz):
         for name, kout in (("kin_xcol", kx), ("kin_ycol", ky), ("kin_zcol", kz)):
             add(name, sz * (c8 + kout), 2 * 58 * kout)
         add("back_y", sz * (g2 + q), 2 * 2 * 2 * r0 * o2 * _count_down(n1, e))
-        # x down pass + the three kinetic parts -> dense output box
-        add("back_x", sz * (q + kx + ky + kz + 8 * o0 * o1 * o2),
+        # x down pass + the three kinetic parts -> compressed output pattern
+        add("back_x", sz * (q + kx + ky + kz + nout),
             2 * 2 * 4 * o1 * o2 * _count_down(n0, e) + 3 * 8 * o0 * o1 * o2)
-        # dense output box -> compressed output pattern
-        add("pack_out", sz * 2 * nout, 0)
     return out
 
 

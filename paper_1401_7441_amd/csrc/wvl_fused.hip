@@ -22,11 +22,10 @@
 //   k_back_y     one fine (channel, z', x) column per thread, streaming along
 //                y: the y down pass; 16-wide LDS stages transpose the result
 //                so that y' is the fastest axis of the x down pass' input.
-//   k_back_x     one output (z', y', channel) row per thread, streaming along
-//                x: the x down pass plus the three kinetic parts, written
-//                through 16-wide LDS stages to a dense x'-fastest box.
-//   k_pack_out   one dense output point per thread: compress onto the
-//                output pattern.
+//   k_back_out   one output (z', y', channel) row per thread, streaming along
+//                x: the x down pass plus the three kinetic parts; each
+//                wave's 16 rows x 8 components are staged 16 x' at a time in
+//                LDS and written straight onto the compressed output pattern.
 // Register ring slots are compile-time constants after unrolling by the ring
 // period, so the rings stay in VGPRs.
 #include <hip/hip_runtime.h>
@@ -747,55 +746,153 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
 }
 
 // ---------------------------------------------------------------------------
-// k_back_x: block = (function, output plane z', 64 (channel, y') rows)
+// k_back_out: block = (function, kBackOutRows output rows (y', z')), streaming along x
 // ---------------------------------------------------------------------------
-// Thread = output row (y', z') of channel ch = a2 + 2 a3, components
-// c = a1 + 2 a2 + 4 a3 (a1 = 0, 1).  Streaming along x: fine pair p = 2q,
-// 2q+1 of Q[ch][z'][p][y'] is scattered into the potential accumulators of
-// coarse i' = q-15..q; i' = q-15 is then complete and gets the x, y and z
-// kinetic parts (from k_kin_col, all read with y' across the lanes).  Every
-// 16 results are staged in LDS and written to the dense output box
-// OB[c][z'][y'][x'] (x' fastest), 4 rows x 16 x' per store; k_pack_out then
-// compresses OB onto the output pattern.
+// Block = 4 kBackOutRows threads = output rows (y', z') x the 4 channel pairs
+// ch = a2 + 2 a3 (thread t: row t / 4, ch = t % 4), rows in (z', y') order,
+// so that one wave holds all 8 components of its 16 rows.  Thread = output
+// row (y', z') of channel ch, components c = a1 + 2 a2 + 4 a3 (a1 = 0, 1).
+// Streaming along x: fine pair p = 2q, 2q+1 of Q[ch][z'][p][y'] is scattered
+// into the potential accumulators of coarse i' = q-15..q; i' = q-15 is then
+// complete and gets the x, y and z kinetic parts (from k_kin_col).  Every
+// 16 x' the block's values [component][x'][row] are staged in LDS and written
+// straight to the compressed output: per row and pattern, the points of its
+// run that fall in the window are contiguous in the output (scaling values
+// one per point, wavelets seven per point), so the window's runs of each row
+// (first and last window index, output point index; from the row's single
+// run or, for rows with several, its segments) make the stores consecutive.
+// The dense output box and a separate compression pass are not needed.
+constexpr int kBoRows = kBackOutRows, kBoThreads = 4 * kBackOutRows;
+// Orders a wave's LDS accesses across the lanes of that wave (LDS requests of
+// one wave are served in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// A 16-point window of a row meets at most 16 segments of a pattern (each
+// holds at least one point; segments may touch).
+constexpr int kBoRuns = 16;
 template <typename T>
-__global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
-                                               const SfWork* __restrict__ wk, int sf0,
-                                               T* __restrict__ ws, int pot_on, int kin_on) {
-  __shared__ T st[2 * 16 * kSP];
+__global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict__ sfs,
+                                                  const wvl_seg* __restrict__ seg,
+                                                  const int32_t* __restrict__ rt,
+                                                  const RowRun* __restrict__ rr,
+                                                  const SfWork* __restrict__ wk, int sf0,
+                                                  const T* __restrict__ ws, T* __restrict__ out,
+                                                  int pot_on, int kin_on, int accumulate) {
+  constexpr int SR = kBoRows + 1;                   // LDS stride of one (component, x') row
+  __shared__ T st[8 * 16 * SR];                     // [component][x' in window][row]
+  // per pattern (scaling, wavelets) and row, the runs in the window: window
+  // indices [js, je) and the point index (within the pattern) of js
+  __shared__ int8_t od_js[2][kBoRuns][kBoRows], od_je[2][kBoRuns][kBoRows];
+  __shared__ int32_t od_o[2][kBoRuns][kBoRows];
+  __shared__ int32_t od_n[2][kBoRows];
   const SfWork& w = wk[blockIdx.y];
   const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int R0 = 2 * N0 + 29;
   const int O0 = N0 + 2 * e, O1 = N1 + 2 * e, O2 = N2 + 2 * e;
-  const int nty = (4 * O1 + 63) >> 6;
-  const int bx = blockIdx.x;
-  const int tt = bx % nty, zp = bx / nty;
-  const int lane = threadIdx.x;
-  if (zp >= O2) return;   // uniform over the block
-  const int id = tt * 64 + lane;
-  const bool active = id < 4 * O1;
-  const int ch = active ? id / O1 : 0, yp = active ? id % O1 : 0;
+  const int64_t nout = (int64_t)O1 * O2;
+  const int64_t r0 = (int64_t)blockIdx.x * kBoRows;
+  if (r0 >= nout) return;   // uniform over the block
+  const int tid = threadIdx.x;
+  const int rl = tid >> 2, ch = tid & 3;
+  const int64_t orw = r0 + rl;
+  const bool active = orw < nout;
+  const int zp = active ? (int)(orw / O1) : 0, yp = active ? (int)(orw % O1) : 0;
   const int a2 = ch & 1, a3 = ch >> 1;
   const int z = zp - e, y = yp - e;
   const bool zin = kin_on && z >= 0 && z < N2;
   const bool yin = y >= 0 && y < N1;
   const int64_t plane = (int64_t)N0 * N1;
+  // Wave wv computes, stages and writes rows 16 wv .. 16 wv + 15 on its own
+  // (all 8 components of a row sit in one wave), so the waves of a block
+  // never wait for each other.  Lanes 0..31 describe (pattern lane / 16,
+  // row 16 wv + lane % 16).
+  const int lane = tid & 63, wv = tid >> 6;
+  const int drow = 16 * wv + (lane & 15), dpat = (lane >> 4) & 1;
+  RowRun myrun{0, 0, 0};
+  int64_t mygrow = -1;   // the row's index in the pattern's row table, -1: none
+  if (lane < 32) {
+    const int64_t r = r0 + drow;
+    if (r < nout) {
+      mygrow = sf.rt[2 + dpat] + r;
+      myrun = rr[sf.rr[2 + dpat] + r];
+    }
+  }
+  const int xg0 = sf.lo[0] - e;   // global x of x' = 0
+  // runs of the window x' = xw + j, jlo <= j < jhi
+  auto describe = [&](int xw, int jlo, int jhi) {
+    if (lane >= 32) return;
+    int n = 0;
+    auto add = [&](int gx0, int len, int64_t off) {   // run [gx0, gx0 + len) from point off
+      const int b = gx0 - xg0 - xw;                     // its window index
+      const int js = max(jlo, b), je = min(jhi, b + len);
+      if (js < je && n < kBoRuns) {
+        od_js[dpat][n][drow] = (int8_t)js;
+        od_je[dpat][n][drow] = (int8_t)je;
+        od_o[dpat][n][drow] = (int32_t)(off + (js - b));
+        ++n;
+      }
+    };
+    if (mygrow >= 0 && myrun.len != 0) {
+      if (myrun.len != kMultiRun) {
+        add(myrun.x0, myrun.len, myrun.off);
+      } else {
+        for (int q = rt[mygrow]; q < rt[mygrow + 1]; ++q)
+          add(seg[q].i1s, seg[q].i1e - seg[q].i1s + 1, seg[q].off);
+      }
+    }
+    od_n[dpat][drow] = n;
+  };
   const T* qin = ws + w.q + ((int64_t)(ch * O2 + zp) * R0) * O1 + yp;
   const int c0 = 2 * a2 + 4 * a3, c1 = c0 + 1;
-  // OB row (c0, z', y') start; component c1 is one component further
-  const int orow = active ? ((c0 * O2 + zp) * O1 + yp) * O0 : -1;   // < 8 O2 O1 O0
-  const int oc = O2 * O1 * O0;
-  T* ob = ws + w.ob;
-  if (e == 16 && active) {  // coarse i' = -16 lies beyond every filter's reach
-    ob[orow] = T(0);
-    ob[oc + orow] = T(0);
-  }
-  // kinetic parts, each with y or y' across the lanes
   const int64_t comp_x = (int64_t)N2 * O0 * N1, comp_y = (int64_t)N2 * N0 * O1;
   const int64_t comp_z = (int64_t)O2 * plane;
   const T* oxp = ws + w.ox + ((int64_t)(zin ? z : 0) * O0) * N1 + (yin ? y : 0);  // [c][z][x'][y]
   const T* oyp = ws + w.oy + (int64_t)(zin ? z : 0) * N0 * O1 + yp;               // [c][z][x][y']
   const T* ozp = ws + w.oz + (int64_t)zp * plane + (yin ? y : 0);                // [c][z'][x][y]
+  T* const outc = out + sf.cout;
+  T* const outf = out + sf.cout + sf.on_c;
+  auto put = [&](T* o, T v) { *o = accumulate ? *o + v : v; };
+  // writes the described runs from the staged values (vals false: zeros, for
+  // points no filter reaches); wave wv writes rows 16 wv .. 16 wv + 15
+  auto flush = [&](bool vals) {
+    // scaling values: 4 rows of 16 lanes per pass
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * wv + 4 * i + (lane >> 4), j = lane & 15;
+      const int n = od_n[0][r];
+      for (int u = 0; u < n; ++u) {
+        const int js = od_js[0][u][r];
+        if (j >= js && j < od_je[0][u][r]) {
+          put(outc + od_o[0][u][r] + (j - js), vals ? st[j * SR + r] : T(0));
+          break;
+        }
+      }
+    }
+    // wavelets: one run at a time, seven consecutive outputs per point
+    for (int i = 0; i < 16; ++i) {
+      const int r = 16 * wv + i;
+      const int n = __builtin_amdgcn_readfirstlane(od_n[1][r]);
+      for (int u = 0; u < n; ++u) {
+        const int js = __builtin_amdgcn_readfirstlane(od_js[1][u][r]);
+        const int n7 = 7 * (__builtin_amdgcn_readfirstlane(od_je[1][u][r]) - js);
+        T* const ob = outf + 7 * (int64_t)__builtin_amdgcn_readfirstlane(od_o[1][u][r]);
+        for (int t = lane; t < n7; t += 64) {
+          const int jj = t / 7, c = t - 7 * jj + 1;
+          put(ob + t, vals ? st[(c * 16 + js + jj) * SR + r] : T(0));
+        }
+      }
+    }
+  };
+  if (e == 16) {   // coarse i' = -16 lies beyond every filter's reach
+    describe(0, 0, 1);
+    wave_lds_sync();
+    flush(false);
+    wave_lds_sync();
+  }
   T p0[16], p1[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) p0[k] = p1[k] = T(0);
@@ -847,89 +944,16 @@ __global__ __launch_bounds__(64) void k_back_x(const SfDev* __restrict__ sfs,
           v1 += k1;
         }
       }
-      st[u * kSP + lane] = v0;
-      st[(16 + u) * kSP + lane] = v1;
+      st[(c0 * 16 + u) * SR + rl] = v0;
+      st[(c1 * 16 + u) * SR + rl] = v1;
     }
-    // flush x' = q0 - 15 + e + j, j = 0..15
-    __syncthreads();
-    const int j = lane & 15;
-    const int xp = q0 - 15 + e + j;
-    const bool okx = xp >= 0 && xp < O0 && q0 + j <= qend;
-#pragma unroll
-    for (int it = 0; it < 16; ++it) {
-      const int rl = it * 4 + (lane >> 4);
-      const int orl = __shfl(orow, rl, 64);
-      if (okx && orl >= 0) {
-        ob[orl + xp] = st[j * kSP + rl];
-        ob[oc + orl + xp] = st[(16 + j) * kSP + rl];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// k_pack_out: block = 64 consecutive segments of one output pattern of one
-// function (coarse pattern blocks first, then fine).  The segment
-// descriptors are staged in LDS once; the block then streams the covered
-// run of compressed coefficients (one contiguous range per component),
-// locating each coefficient's segment by a binary search in LDS and reading
-// its value from the dense box OB.
-// ---------------------------------------------------------------------------
-constexpr int kPackSegs = 64;
-template <typename T>
-__global__ __launch_bounds__(256) void k_pack_out(const SfDev* __restrict__ sfs,
-                                                  const wvl_seg* __restrict__ seg,
-                                                  const int32_t* __restrict__ rt,
-                                                  const SfWork* __restrict__ wk, int sf0,
-                                                  const T* __restrict__ ws, T* __restrict__ out,
-                                                  int accumulate) {
-  __shared__ int s_off[kPackSegs + 1];   // coefficient offset relative to the first segment
-  __shared__ int s_ob[kPackSegs];        // OB index of the segment's first point (component 0)
-  const SfWork& w = wk[blockIdx.y];
-  const SfDev& sf = sfs[w.id];
-  const int e = sf.ext;
-  const int O0 = sf.n[0] + 2 * e, O1 = sf.n[1] + 2 * e, O2 = sf.n[2] + 2 * e;
-  const int64_t nrows = (int64_t)O2 * O1;
-  const int cb0 = rt[sf.rt[2]], ce0 = rt[sf.rt[2] + nrows];   // coarse output segments
-  const int fb0 = rt[sf.rt[3]], fe0 = rt[sf.rt[3] + nrows];   // fine output segments
-  const int nbc = (ce0 - cb0 + kPackSegs - 1) / kPackSegs;
-  const int nbf = (fe0 - fb0 + kPackSegs - 1) / kPackSegs;
-  int bx = blockIdx.x;
-  const bool fine = bx >= nbc;
-  if (fine) bx -= nbc;
-  if (bx >= (fine ? nbf : nbc)) return;   // uniform over the block
-  const int sA = (fine ? fb0 : cb0) + bx * kPackSegs;
-  const int nseg = min(kPackSegs, (fine ? fe0 : ce0) - sA);
-  const int tid = threadIdx.x;
-  const int64_t off0 = seg[sA].off;
-  if (tid < nseg) {
-    const wvl_seg g = seg[sA + tid];
-    s_off[tid] = (int)(g.off - off0);
-    s_ob[tid] = ((g.i3 - (sf.lo[2] - e)) * O1 + (g.i2 - (sf.lo[1] - e))) * O0 +
-                (g.i1s - (sf.lo[0] - e));
-    if (tid == nseg - 1) s_off[nseg] = (int)(g.off - off0) + (g.i1e - g.i1s + 1);
-  }
-  __syncthreads();
-  const int total = s_off[nseg];
-  const int oc = O2 * O1 * O0;
-  // coarse: one value per point; fine: the seven wavelets of each point are
-  // consecutive in the output, so thread t writes element t of the block's
-  // stretch (point t / 7, component t % 7 + 1)
-  const int per = fine ? 7 : 1;
-  const int64_t obase = sf.cout + (fine ? sf.on_c + 7 * off0 : off0);
-  for (int t = tid; t < per * total; t += 256) {
-    const int k = fine ? t / 7 : t;
-    const int c = fine ? t - 7 * k + 1 : 0;
-    int lo = 0, hi = nseg - 1;   // last segment with s_off <= k
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= k) lo = mid; else hi = mid - 1;
-    }
-    const int src = s_ob[lo] + (k - s_off[lo]);
-    const T v = ws[w.ob + (int64_t)c * oc + src];
-    T* o = out + obase + t;
-    *o = accumulate ? *o + v : v;
+    // window x' = q0 - 15 + e + j, j = 0..15: the part inside [0, O0) with
+    // q = q0 + j <= qend
+    const int xw = q0 - 15 + e;
+    describe(xw, max(0, -xw), min(16, min(O0 - xw, qend - q0 + 1)));
+    wave_lds_sync();
+    flush(true);
+    wave_lds_sync();
   }
 }
 
@@ -951,9 +975,8 @@ int preload_fused_kernels() {
       (const void*)k_kin_col<float, 2>,     (const void*)k_kin_col<double, 0>,
       (const void*)k_kin_col<double, 1>,    (const void*)k_kin_col<double, 2>,
       (const void*)k_back_y<float>,         (const void*)k_back_y<double>,
-      (const void*)k_back_x<float>,         (const void*)k_back_x<double>,
-      (const void*)k_kin_zmfma<float>,      (const void*)k_kin_zmfma<double>,
-      (const void*)k_pack_out<float>,       (const void*)k_pack_out<double>};
+      (const void*)k_back_out<float>,       (const void*)k_back_out<double>,
+      (const void*)k_kin_zmfma<float>,      (const void*)k_kin_zmfma<double>};
   for (const void* f : fns) {
     hipFuncAttributes a;
     const hipError_t e = hipFuncGetAttributes(&a, f);
@@ -1073,32 +1096,17 @@ int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int 
   return (int)hipGetLastError();
 }
 
-int launch_back_x(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                  int gridx, void* ws, int pot_on, int kin_on) {
+int launch_back_out(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                    const RowRun* rr, const SfWork* wk, int sf0, int nsf, int gridx,
+                    const void* ws, void* out, int pot_on, int kin_on, int accumulate) {
   if (nsf == 0 || gridx == 0) return 0;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
   if (f64)
-    hipLaunchKernelGGL(k_back_x<double>, g, dim3(64), 0, (hipStream_t)stream, sf, wk, sf0,
-                       (double*)ws, pot_on, kin_on);
+    hipLaunchKernelGGL(k_back_out<double>, g, dim3(kBoThreads), 0, (hipStream_t)stream, sf, seg, rt, rr,
+                       wk, sf0, (const double*)ws, (double*)out, pot_on, kin_on, accumulate);
   else
-    hipLaunchKernelGGL(k_back_x<float>, g, dim3(64), 0, (hipStream_t)stream, sf, wk, sf0,
-                       (float*)ws, pot_on, kin_on);
-  return (int)hipGetLastError();
-}
-
-int launch_pack_out(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                    const SfWork* wk, int sf0, int nsf, int64_t maxsegs, const void* ws, void* out,
-                    int accumulate) {
-  // maxsegs: the chunk's largest (coarse + fine) output segment count, so
-  // that ceil(coarse / 64) + ceil(fine / 64) blocks fit in maxsegs / 64 + 2
-  if (nsf == 0) return 0;
-  const dim3 g((unsigned)(maxsegs / kPackSegs + 2), (unsigned)nsf);
-  if (f64)
-    hipLaunchKernelGGL(k_pack_out<double>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, wk,
-                       sf0, (const double*)ws, (double*)out, accumulate);
-  else
-    hipLaunchKernelGGL(k_pack_out<float>, g, dim3(256), 0, (hipStream_t)stream, sf, seg, rt, wk,
-                       sf0, (const float*)ws, (float*)out, accumulate);
+    hipLaunchKernelGGL(k_back_out<float>, g, dim3(kBoThreads), 0, (hipStream_t)stream, sf, seg, rt, rr,
+                       wk, sf0, (const float*)ws, (float*)out, pot_on, kin_on, accumulate);
   return (int)hipGetLastError();
 }
 

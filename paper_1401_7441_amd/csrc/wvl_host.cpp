@@ -22,12 +22,12 @@ using namespace wvl;
 // kernel kinds for tracing
 enum KernelKind {
   KK_GATHER, KK_SCATTER, KK_UNPACK, KK_UP_X, KK_UP_Y, KK_POT_COLUMN, KK_KIN_XCOL, KK_KIN_YCOL, KK_KIN_ZCOL,
-  KK_BACK_Y, KK_BACK_X, KK_PACK_OUT, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
+  KK_BACK_Y, KK_BACK_X, KK_FINALIZE, KK_PATTERN, KK_SPARSE_S, KK_SPARSE_H,
   KK_UPDATE, KK_UP_Z, KK_DENS_TILE, KK_FOE_MM, KK_FOE, KK_GRADIENT, KK_COUNT
 };
 static const char* kKernelNames[KK_COUNT] = {
     "uncompress", "compress", "unpack", "up_x", "up_y", "pot_column", "kin_xcol", "kin_ycol", "kin_zcol",
-    "back_y", "back_x", "pack_out", "finalize", "pattern", "sparse_s", "sparse_h", "update",
+    "back_y", "back_x", "finalize", "pattern", "sparse_s", "sparse_h", "update",
     "up_z", "dens_tile", "foe_mm", "foe", "gradient"};
 
 // LDS a block of the fused plane kernels may use (gfx950: 160 KiB per block),
@@ -247,7 +247,6 @@ struct wvl_plan {
   int nsf = 0;
   std::vector<SfDev> h_sf;
   std::vector<int32_t> order;         // processing position -> function index
-  std::vector<int64_t> nsegs_out;     // output segments (coarse + fine) per function
   size_t max_ws = 0;                  // the caller's workspace bound (0: none)
   Layout lay;
   int64_t ws_cap[2] = {0, 0};         // workspace bytes reported (F32, F64)
@@ -721,7 +720,7 @@ static int64_t sf_elems(const SfDev& S) {
   const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
   return 2 * align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) + align64(2 * o2 * r0 * r1) +
          align64(4 * o2 * r0 * o1) + align64(8 * n2 * o0 * n1) + align64(8 * n2 * o1 * n0) +
-         align64(8 * o2 * n0 * n1) + align64(8 * o0 * o1 * o2) + align64(4 * n2 * n1 * r0);
+         align64(8 * o2 * n0 * n1) + align64(4 * n2 * n1 * r0);
 }
 
 // Builds the layout for `nbins` bins; false (with a message) when a box
@@ -772,7 +771,6 @@ static bool make_layout(const wvl_plan* P, int nbins, bool zmfma, Layout* L, std
         W.ox = off;  off += align64(8 * n2 * o0 * n1);
         W.oy = off;  off += align64(8 * n2 * o1 * n0);
         W.oz = off;  off += align64(8 * o2 * n0 * n1);
-        W.ob = off;  off += align64(8 * o0 * o1 * o2);
         W.gx = off;  off += align64(4 * n2 * n1 * r0);
         ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
         ch.grid_u = (int32_t)std::max<int64_t>(ch.grid_u, 8 * n2);
@@ -780,14 +778,12 @@ static bool make_layout(const wvl_plan* P, int nbins, bool zmfma, Layout* L, std
         ch.grid_uy = (int32_t)std::max<int64_t>(ch.grid_uy, (2 * n2 * r0 + 255) / 256);
         for (int d = 0; d < 2; ++d)
           ch.lds_u[d] = std::max<int64_t>(ch.lds_u[d], n1 * (n0 + 1) * (d ? 8 : 4));
-        ch.maxbox_out = std::max(ch.maxbox_out, 8 * o0 * o1 * o2);
-        ch.maxsegs_out = std::max<int64_t>(ch.maxsegs_out, P->nsegs_out[id]);
         ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
         ch.grid_kx = std::max(ch.grid_kx, kin_blocks(0, (int)n0, (int)n1, (int)n2));
         ch.grid_ky = std::max(ch.grid_ky, kin_blocks(1, (int)n0, (int)n1, (int)n2));
         ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2, zmfma));
         ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
-        ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, ((4 * o1 + 63) / 64) * o2);
+        ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, (o1 * o2 + kBackOutRows - 1) / kBackOutRows);
       }
       ch.nblk_pot = ch.grid_b;
       ch.nblk_kin = ch.grid_kx + ch.grid_ky + ch.grid_kz;
@@ -936,11 +932,7 @@ wvl_status wvl_plan_create(wvl_ctx* ctx, int32_t nsf, const wvl_locreg* lr, cons
   }
   // processing order: largest boxes first, ties by index
   P->order.resize(nsf);
-  P->nsegs_out.resize(nsf);
-  for (int k = 0; k < nsf; ++k) {
-    P->order[k] = k;
-    P->nsegs_out[k] = lr[k].noseg_c + lr[k].noseg_f;
-  }
+  for (int k = 0; k < nsf; ++k) P->order[k] = k;
   std::stable_sort(P->order.begin(), P->order.end(), [&](int a, int b) {
     const SfDev &A = P->h_sf[a], &B = P->h_sf[b];
     return (int64_t)A.n[0] * A.n[1] * A.n[2] > (int64_t)B.n[0] * B.n[1] * B.n[2];
@@ -1108,11 +1100,11 @@ static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, co
   if (pot_on)
     WVL_LAUNCH(ctx, KK_BACK_Y,
                launch_back_y(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_by, workspace));
-  WVL_LAUNCH(ctx, KK_BACK_X, launch_back_x(f64, st, P->d_sf, wk, ch.sf0, ch.nsf, ch.grid_bx,
-                                           workspace, pot_on, kin_on));
-  WVL_LAUNCH(ctx, KK_PACK_OUT,
-             launch_pack_out(f64, st, P->d_sf, P->d_seg, P->d_rt, wk, ch.sf0, ch.nsf,
-                             ch.maxsegs_out, workspace, hpsi_c, accumulate));
+  // the x down pass, the kinetic parts and the compression onto the output
+  // pattern in one kernel
+  WVL_LAUNCH(ctx, KK_BACK_X,
+             launch_back_out(f64, st, P->d_sf, P->d_seg, P->d_rt, P->d_rr, wk, ch.sf0, ch.nsf,
+                             ch.grid_bx, workspace, hpsi_c, pot_on, kin_on, accumulate));
   return WVL_OK;
 }
 

@@ -44,6 +44,10 @@ struct RowRun {
 };
 constexpr uint16_t kMultiRun = 0xFFFF;
 
+// k_back_out: output rows (y', z') per block, 16 per wave (one wave per block
+// measured fastest: the waves share no LDS, more blocks fit a CU)
+constexpr int kBackOutRows = 16;
+
 // Workspace offsets (elements of the compute type) of one support function
 // in the workspace (R = 2N + 29, O = N + 2 ext).  The plan keeps these
 // records in its processing order (functions sorted by box size, cut into
@@ -56,11 +60,10 @@ constexpr uint16_t kMultiRun = 0xFFFF;
 //   ox   x part of the kinetic term      [8][N2][O0][N1]
 //   oy   y part of the kinetic term      [8][N2][N0][O1]
 //   oz   z part of the kinetic term      [8][O2][N0][N1]
-//   ob   dense output box                [8][O2][O1][O0]
 //   gx   after the x up pass             [4][N2][N1][R0]   (channel a2 + 2 a3)
 struct SfWork {
   int64_t id;         // the function's index in the plan (SfDev array, outputs)
-  int64_t c8, c8x, g1, g2, q, ox, oy, oz, ob, gx;
+  int64_t c8, c8x, g1, g2, q, ox, oy, oz, gx;
   int64_t epart;      // offset (in doubles) of its e_pot partials
   int64_t kpart;      // offset (in doubles) of its e_kin partials
   int64_t nkpart;     // number of e_kin partials: its own k_kin_col blocks
@@ -79,15 +82,14 @@ __host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2, bool
 // per-chunk launch geometry of the fused kernels, for dtype d (0 f32, 1 f64)
 struct ChunkDev {
   int32_t sf0, nsf;                // positions [sf0, sf0 + nsf) of the processing order
-  int64_t maxbox_in, maxbox_out;   // largest dense input / output box (elements)
+  int64_t maxbox_in;               // largest dense input box (elements)
   int32_t grid_u;                  // k_unpack: 8 planes per input z
   int32_t grid_ux, grid_uy;        // k_up_x, k_up_y
   int64_t lds_u[2];
   int32_t grid_b;                  // k_pot_column
   int32_t grid_kx, grid_ky, grid_kz;   // k_kin_col (x, y, z)
   int32_t grid_by;                 // k_back_y
-  int32_t grid_bx;                 // k_back_x
-  int64_t maxsegs_out;             // k_pack_out: largest output segment count
+  int32_t grid_bx;                 // k_back_out
   int32_t nblk_pot, nblk_kin;      // partial slots per function
 };
 
@@ -142,11 +144,9 @@ int launch_kin_col(int f64, void* stream, int axis, const SfDev* sf, const SfWor
                    int nsf, int gridx, void* ws, double fac, double* kpart);
 int launch_back_y(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
                   int gridx, void* ws);
-int launch_back_x(int f64, void* stream, const SfDev* sf, const SfWork* wk, int sf0, int nsf,
-                  int gridx, void* ws, int pot_on, int kin_on);
-int launch_pack_out(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
-                    const SfWork* wk, int sf0, int nsf, int64_t maxsegs, const void* ws, void* out,
-                    int accumulate);
+int launch_back_out(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
+                    const RowRun* rr, const SfWork* wk, int sf0, int nsf, int gridx,
+                    const void* ws, void* out, int pot_on, int kin_on, int accumulate);
 int launch_finalize(void* stream, const SfWork* wk, int sf0, int nsf, const double* parts,
                     int which, int nblk, double* out);
 int launch_pattern(void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt, int nsf,

@@ -57,6 +57,8 @@ def kind_of(name: str):
         return "uncompress"
     if base == "scatter":
         return "compress"
+    if base == "back_out":       # the x analysis pass, writing the compressed output
+        return "back_x"
     return base          # sparse_values is split into S and H by dispatch order
 
 
