@@ -46,6 +46,31 @@ __constant__ double fKD64[2] = WVL_KD_F64;
 // whose banks 4 j + row are all distinct
 constexpr int kSP = 68;
 
+// Register prefetch of the streaming passes: with distance PF > 0 the loads
+// of step q + PF are issued at step q into a ring of PF registers (slot
+// q mod PF, a compile-time constant after unrolling), so a step's inputs
+// have been in flight for PF steps when it uses them instead of costing one
+// load latency per step.  Prefetched indices are clamped into the stream, so
+// every load is in bounds; values of steps outside the stream are replaced by
+// zeros where they are used, so results do not depend on PF.  PF = 0 loads
+// at the step itself.  The distances per pass and precision are the fastest
+// of {0, 4, 8} measured on gfx950 (more VGPRs can cost more occupancy than
+// the prefetch gains).
+template <typename T> constexpr int pf_up_x() { return sizeof(T) == 8 ? 8 : 0; }
+template <typename T> constexpr int pf_up_y() { return 8; }
+template <typename T> constexpr int pf_pot() { return sizeof(T) == 8 ? 4 : 0; }
+template <typename T, int AX> constexpr int pf_kin() {
+  return sizeof(T) == 8 ? (AX == 1 ? 4 : 0) : (AX == 1 ? 8 : 4);
+}
+template <typename T> constexpr int pf_back_y() { return sizeof(T) == 8 ? 0 : 8; }
+constexpr int kPfBackQ = 8, kPfBackK = 4;   // k_back_out: Q pairs, kinetic parts
+constexpr int pf_slots(int pf) { return pf > 0 ? pf : 1; }
+// element min(max(i, 0), n - 1) of a stream with the given stride (n >= 1)
+template <typename T>
+__device__ __forceinline__ T ld_clamp(const T* p, int i, int n, int64_t stride) {
+  return p[(int64_t)min(max(i, 0), n - 1) * stride];
+}
+
 template <typename T>
 __device__ __forceinline__ T Ct(int b, int n);
 template <>
@@ -180,17 +205,30 @@ __global__ __launch_bounds__(64) void k_up_x(const SfDev* __restrict__ sfs,
   const T* in1 = in0 + (int64_t)N2 * plane;                               // component c0 + 1
   const int obase = active ? row * R0 : -1;                               // GX row start
   T* gx = ws + w.gx;
-  T xs[16], xd[16];
+  constexpr int PF = pf_up_x<T>();
+  T xs[16], xd[16], f0[pf_slots(PF)], f1[pf_slots(PF)];
 #pragma unroll
   for (int k = 0; k < 16; ++k) xs[k] = xd[k] = T(0);
+#pragma unroll
+  for (int d = 0; d < PF; ++d) {
+    f0[d] = ld_clamp(in0, d, N0, N1);
+    f1[d] = ld_clamp(in1, d, N0, N1);
+  }
   const int qend = N0 + 14;
   for (int q0 = 0; q0 <= qend; q0 += 16) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int q = q0 + u;
+      const int q = q0 + u, sp = u % pf_slots(PF);
       const bool ok = active && q < N0;
-      xs[u] = ok ? in0[(int64_t)q * N1] : T(0);
-      xd[u] = ok ? in1[(int64_t)q * N1] : T(0);
+      if constexpr (PF > 0) {
+        xs[u] = ok ? f0[sp] : T(0);
+        xd[u] = ok ? f1[sp] : T(0);
+        f0[sp] = ld_clamp(in0, q + PF, N0, N1);
+        f1[sp] = ld_clamp(in1, q + PF, N0, N1);
+      } else {
+        xs[u] = ok ? in0[(int64_t)q * N1] : T(0);
+        xd[u] = ok ? in1[(int64_t)q * N1] : T(0);
+      }
       T fe = T(0), fo = T(0);
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
@@ -239,19 +277,29 @@ __global__ __launch_bounds__(256) void k_up_y(const SfDev* __restrict__ sfs,
   const T* in0 = ws + w.gx + ((int64_t)(2 * a3) * N2 + z) * N1 * R0 + px;   // a2 = 0
   const T* in1 = in0 + gxc;                                                   // a2 = 1
   T* out = ws + w.g1 + ((int64_t)a3 * N2 + z) * ((int64_t)R1 * R0) + px;
-  // (in0, in1 and out move forward as the stream advances)
-  T xs[16], xd[16];
+  // (out moves forward as the stream advances)
+  constexpr int PF = pf_up_y<T>();
+  static_assert(PF > 0, "k_up_y streams through its prefetch ring");
+  T xs[16], xd[16], f0[PF], f1[PF];
 #pragma unroll
   for (int k = 0; k < 16; ++k) xs[k] = xd[k] = T(0);
+#pragma unroll
+  for (int d = 0; d < PF; ++d) {
+    f0[d] = ld_clamp(in0, d, N1, R0);
+    f1[d] = ld_clamp(in1, d, N1, R0);
+  }
   const int qend = N1 + 14;
-  const int64_t gstep = 16 * (int64_t)R0;   // pointers advance by 16 rows per block
-  for (int q0 = 0; q0 <= qend; q0 += 16, in0 += gstep, in1 += gstep, out += 2 * gstep) {
+  const int64_t gstep = 16 * (int64_t)R0;   // out advances by 16 coarse rows per block
+  for (int q0 = 0; q0 <= qend; q0 += 16, out += 2 * gstep) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int q = q0 + u;
+      const int q = q0 + u, sp = u % PF;
+      const T v0 = f0[sp], v1 = f1[sp];
+      f0[sp] = ld_clamp(in0, q + PF, N1, R0);
+      f1[sp] = ld_clamp(in1, q + PF, N1, R0);
       if (q <= qend) {
-        xs[u] = q < N1 ? in0[u * R0] : T(0);
-        xd[u] = q < N1 ? in1[u * R0] : T(0);
+        xs[u] = q < N1 ? v0 : T(0);
+        xd[u] = q < N1 ? v1 : T(0);
         T fe = T(0), fo = T(0);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -289,18 +337,26 @@ __global__ __launch_bounds__(256) void k_up_z(const SfDev* __restrict__ sfs,
   const T* in0 = ws + w.g1 + col;                 // a3 = 0
   const T* in1 = in0 + (int64_t)N2 * plane;       // a3 = 1
   T* out = fine + fine_off[w.id] + col;
-  T xs[16], xd[16];
+  constexpr int PF = pf_up_y<T>();   // the same stream shape as k_up_y
+  T xs[16], xd[16], f0[PF], f1[PF];
 #pragma unroll
   for (int k = 0; k < 16; ++k) xs[k] = xd[k] = T(0);
+#pragma unroll
+  for (int d = 0; d < PF; ++d) {
+    f0[d] = ld_clamp(in0, d, N2, plane);
+    f1[d] = ld_clamp(in1, d, N2, plane);
+  }
   const int qend = N2 + 14;
-  for (int q0 = 0; q0 <= qend; q0 += 16, in0 += 16 * plane, in1 += 16 * plane,
-           out += 32 * plane) {
+  for (int q0 = 0; q0 <= qend; q0 += 16, out += 32 * plane) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int q = q0 + u;
+      const int q = q0 + u, sp = u % PF;
+      const T v0 = f0[sp], v1 = f1[sp];
+      f0[sp] = ld_clamp(in0, q + PF, N2, plane);
+      f1[sp] = ld_clamp(in1, q + PF, N2, plane);
       if (q <= qend) {
-        xs[u] = q < N2 ? in0[u * plane] : T(0);
-        xd[u] = q < N2 ? in1[u * plane] : T(0);
+        xs[u] = q < N2 ? v0 : T(0);
+        xd[u] = q < N2 ? v1 : T(0);
         T fe = T(0), fo = T(0);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -355,9 +411,17 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
     const double cdy = (double)(2 * sf.lo[1] + py - 14) * hh - sf.c[1];
     const double cxy = cdx * cdx + cdy * cdy;
     const double cz0 = (double)(2 * sf.lo[2] - 14) * hh - sf.c[2];
-    T xs[16], xd[16], a0[16], a1[16];
+    constexpr int PF = pf_pot<T>(), NS = pf_slots(PF);
+    T xs[16], xd[16], a0[16], a1[16], f0[NS], f1[NS], fve[NS], fvo[NS];
 #pragma unroll
     for (int k = 0; k < 16; ++k) xs[k] = xd[k] = a0[k] = a1[k] = T(0);
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+      f0[d] = ld_clamp(in0, d, N2, ncol);
+      f1[d] = ld_clamp(in1, d, N2, ncol);
+      fve[d] = vp ? ld_clamp(vp, 2 * d, R2, vstride) : T(0);
+      fvo[d] = vp ? ld_clamp(vp, 2 * d + 1, R2, vstride) : T(0);
+    }
     if (e == 16) {  // coarse i' = -16 lies beyond the filter reach
       out0[0] = T(0);
       out1[0] = T(0);
@@ -366,10 +430,30 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
     for (int q0 = 0; q0 <= qend; q0 += 16) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        const int q = q0 + u;
+        const int q = q0 + u, sp = u % NS;
+        T v0 = T(0), v1 = T(0), pve = T(0), pvo = T(0);
+        if constexpr (PF > 0) {
+          v0 = f0[sp];
+          v1 = f1[sp];
+          pve = fve[sp];
+          pvo = fvo[sp];
+          f0[sp] = ld_clamp(in0, q + PF, N2, ncol);
+          f1[sp] = ld_clamp(in1, q + PF, N2, ncol);
+          if (vp) {
+            fve[sp] = ld_clamp(vp, 2 * (q + PF), R2, vstride);
+            fvo[sp] = ld_clamp(vp, 2 * (q + PF) + 1, R2, vstride);
+          }
+        }
         if (q <= qend) {
-        xs[u] = q < N2 ? in0[(int64_t)q * ncol] : T(0);
-        xd[u] = q < N2 ? in1[(int64_t)q * ncol] : T(0);
+        if constexpr (PF == 0) {
+          const int p = 2 * q;
+          v0 = q < N2 ? in0[(int64_t)q * ncol] : T(0);
+          v1 = q < N2 ? in1[(int64_t)q * ncol] : T(0);
+          pve = (vp && p < R2) ? vp[(int64_t)p * vstride] : T(0);
+          pvo = (vp && p + 1 < R2) ? vp[(int64_t)(p + 1) * vstride] : T(0);
+        }
+        xs[u] = q < N2 ? v0 : T(0);
+        xd[u] = q < N2 ? v1 : T(0);
         T fe = T(0), fo = T(0);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -378,8 +462,8 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
           if (k < 15) fo += Ct<T>(0, 2 * k + 1) * xs[sl] + Ct<T>(1, 2 * k + 1) * xd[sl];
         }
         const int p = 2 * q;
-        T ve = (vp && p < R2) ? vp[(int64_t)p * vstride] : T(0);
-        T vo = (vp && p + 1 < R2) ? vp[(int64_t)(p + 1) * vstride] : T(0);
+        T ve = (vp && p < R2) ? pve : T(0);
+        T vo = (vp && p + 1 < R2) ? pvo : T(0);
         if (ca != 0.0) {
           const double dze = cz0 + (double)p * hh, dzo = dze + hh;
           const double re = cxy + dze * dze, ro = cxy + dzo * dzo;
@@ -488,8 +572,9 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
   const int colbase0 = active ? (int)(out0 - outb) : -1;   // < 8 N2 N0 O1
   const int colbase1 = active ? (int)(out1 - outb) : -1;
   // the scaling-channel window in double: its differences are then exact
+  constexpr int PF = pf_kin<T, AX>(), NS = pf_slots(PF);
   double x0[32];
-  T x1[32];
+  T x1[32], f0[NS], f1[NS];
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     x0[k] = 0.0;
@@ -500,13 +585,25 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
   const int iend = NA - 1 + e + 14;    // emits i' = NA - 1 + e last
   const int ilo = istart - 28;
   const int i0first = (ilo >= 0) ? (ilo & ~31) : -(((-ilo) + 31) & ~31);
+#pragma unroll
+  for (int d = 0; d < PF; ++d) {
+    f0[d] = ld_clamp(in0, i0first + d, NA, istride);
+    f1[d] = ld_clamp(in1, i0first + d, NA, istride);
+  }
   for (int i0 = i0first; i0 <= iend; i0 += 32) {
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
-      const int i = i0 + u;
+      const int i = i0 + u, sp = u % NS;
       const bool ok = active && i >= 0 && i < NA;
-      x0[u] = ok ? (double)in0[(int64_t)i * istride] : 0.0;
-      x1[u] = ok ? in1[(int64_t)i * istride] : T(0);
+      if constexpr (PF > 0) {
+        x0[u] = ok ? (double)f0[sp] : 0.0;
+        x1[u] = ok ? f1[sp] : T(0);
+        f0[sp] = ld_clamp(in0, i + PF, NA, istride);
+        f1[sp] = ld_clamp(in1, i + PF, NA, istride);
+      } else {
+        x0[u] = ok ? (double)in0[(int64_t)i * istride] : 0.0;
+        x1[u] = ok ? in1[(int64_t)i * istride] : T(0);
+      }
       if (i >= istart && i <= iend) {
         const int ip = i - 14;            // output coarse index i'
         const int sc = (u + 18) & 31;     // slot of x(i') = x(i - 14)
@@ -698,18 +795,35 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
     qo[qcol] = T(0);
     qo[qa + qcol] = T(0);
   }
-  T a0[16], a1[16];
+  constexpr int PF = pf_back_y<T>();
+  T a0[16], a1[16], fe_[pf_slots(PF)], fo_[pf_slots(PF)];
 #pragma unroll
   for (int k = 0; k < 16; ++k) a0[k] = a1[k] = T(0);
+#pragma unroll
+  for (int d = 0; d < PF; ++d) {
+    fe_[d] = ld_clamp(in, 2 * d, R1, R0);
+    fo_[d] = ld_clamp(in, 2 * d + 1, R1, R0);
+  }
   const int qend = N1 + e + 14;
   for (int q0 = 0; q0 <= qend; q0 += 16) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int q = q0 + u;
+      const int q = q0 + u, sp = u % pf_slots(PF);
+      T ve = T(0), vo = T(0);
+      if constexpr (PF > 0) {
+        ve = fe_[sp];
+        vo = fo_[sp];
+        fe_[sp] = ld_clamp(in, 2 * (q + PF), R1, R0);
+        fo_[sp] = ld_clamp(in, 2 * (q + PF) + 1, R1, R0);
+      }
       if (q <= qend) {
         const int p = 2 * q;
-        const T ge = (active && p < R1) ? in[(int64_t)p * R0] : T(0);
-        const T go = (active && p + 1 < R1) ? in[(int64_t)(p + 1) * R0] : T(0);
+        if constexpr (PF == 0) {
+          ve = (active && p < R1) ? in[(int64_t)p * R0] : T(0);
+          vo = (active && p + 1 < R1) ? in[(int64_t)(p + 1) * R0] : T(0);
+        }
+        const T ge = (active && p < R1) ? ve : T(0);
+        const T go = (active && p + 1 < R1) ? vo : T(0);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           const int sl = (u - k) & 15;
@@ -896,16 +1010,50 @@ __global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict
   T p0[16], p1[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) p0[k] = p1[k] = T(0);
+  // prefetch rings: Q pairs kPfBackQ steps ahead, the kinetic parts (x part
+  // at x' = q - 15 + e, y and z parts at i' = q - 15) kPfBackK steps ahead
+  const T* const ox0 = oxp + c0 * comp_x;
+  const T* const ox1 = oxp + c1 * comp_x;
+  const T* const oy0 = oyp + c0 * comp_y;
+  const T* const oy1 = oyp + c1 * comp_y;
+  const T* const oz0 = ozp + c0 * comp_z;
+  const T* const oz1 = ozp + c1 * comp_z;
+  T fe_[kPfBackQ], fo_[kPfBackQ], kx0[kPfBackK], kx1[kPfBackK], ky0[kPfBackK], ky1[kPfBackK],
+      kz0[kPfBackK], kz1[kPfBackK];
+  auto fetch_q = [&](int q, int s) {
+    fe_[s] = ld_clamp(qin, 2 * q, R0, O1);
+    fo_[s] = ld_clamp(qin, 2 * q + 1, R0, O1);
+  };
+  auto fetch_k = [&](int q, int s) {
+    kx0[s] = ld_clamp(ox0, q - 15 + e, O0, N1);
+    kx1[s] = ld_clamp(ox1, q - 15 + e, O0, N1);
+    ky0[s] = ld_clamp(oy0, q - 15, N0, O1);
+    ky1[s] = ld_clamp(oy1, q - 15, N0, O1);
+    kz0[s] = ld_clamp(oz0, q - 15, N0, N1);
+    kz1[s] = ld_clamp(oz1, q - 15, N0, N1);
+  };
+  if (pot_on) {
+#pragma unroll
+    for (int d = 0; d < kPfBackQ; ++d) fetch_q(d, d);
+  }
+  if (kin_on) {
+#pragma unroll
+    for (int d = 0; d < kPfBackK; ++d) fetch_k(d, d);
+  }
   const int qend = N0 + e + 14;
   for (int q0 = 0; q0 <= qend; q0 += 16) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int q = q0 + u;
+      const int q = q0 + u, sp = u % kPfBackQ, sk = u % kPfBackK;
       if (q > qend) continue;
+      const T vx0 = kx0[sk], vx1 = kx1[sk], vy0 = ky0[sk], vy1 = ky1[sk];
+      const T vz0 = kz0[sk], vz1 = kz1[sk];
+      if (kin_on) fetch_k(q + kPfBackK, sk);
       if (pot_on) {
         const int p = 2 * q;
-        const T ge = (active && p < R0) ? qin[(int64_t)p * O1] : T(0);
-        const T go = (active && p + 1 < R0) ? qin[(int64_t)(p + 1) * O1] : T(0);
+        const T ge = (active && p < R0) ? fe_[sp] : T(0);
+        const T go = (active && p + 1 < R0) ? fo_[sp] : T(0);
+        fetch_q(q + kPfBackQ, sp);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           const int sl = (u - k) & 15;
@@ -927,18 +1075,18 @@ __global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict
       if (active && kin_on && xp >= 0 && xp < O0) {
         const bool xin = ip >= 0 && ip < N0;
         if (zin && yin) {            // x part: ox[c][z][x'][y]
-          v0 += oxp[c0 * comp_x + (int64_t)xp * N1];
-          v1 += oxp[c1 * comp_x + (int64_t)xp * N1];
+          v0 += vx0;
+          v1 += vx1;
         }
         if (xin) {
           T k0 = T(0), k1 = T(0);
           if (zin) {                 // y part: oy[c][z][x][y']
-            k0 += oyp[c0 * comp_y + (int64_t)ip * O1];
-            k1 += oyp[c1 * comp_y + (int64_t)ip * O1];
+            k0 += vy0;
+            k1 += vy1;
           }
           if (yin) {                 // z part: oz[c][z'][x][y]
-            k0 += ozp[c0 * comp_z + (int64_t)ip * N1];
-            k1 += ozp[c1 * comp_z + (int64_t)ip * N1];
+            k0 += vz0;
+            k1 += vz1;
           }
           v0 += k0;
           v1 += k1;
