@@ -765,7 +765,10 @@ __global__ __launch_bounds__(256) void k_kin_zmfma(const SfDev* __restrict__ sfs
 // p = 2q, 2q+1 arrives and is scattered into the accumulators of coarse
 // i' = q-15..q (out_b(i') += C_b[p - 2i'] g_p, b = a2); i' = q-15 is then
 // complete.  Every 16 results are staged in LDS and written out as
-// Q[a2 + 2 a3][z'][px][y'] (y' fastest), 4 columns x 16 y' per store.
+// Q[a2 + 2 a3][z'][px][y'] (y' fastest, rows qrow_stride(O1) apart), 4
+// columns x 16 y' per store.  The stream starts up to 15 steps early (zero
+// inputs) so that every window is y' = 16 m .. 16 m + 15: each store is then
+// one whole aligned piece of a row.
 template <typename T>
 __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
                                                const SfWork* __restrict__ wk, int sf0,
@@ -788,8 +791,9 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
   const T* in = ws + w.g2 + slab * R1 * R0 + px;
   // Q[a2 + 2 a3][z'][px][y']: start of this column's y' run for a2 = 0
   const int a3 = (int)(slab / O2), zp = (int)(slab - (int64_t)a3 * O2);
-  const int qcol = active ? ((2 * a3 * O2 + zp) * R0 + px) * O1 : -1;
-  const int qa = O2 * R0 * O1;                      // a2 stride (< 2^31 elements)
+  const int QS = qrow_stride(O1);
+  const int qcol = active ? ((2 * a3 * O2 + zp) * R0 + px) * QS : -1;
+  const int qa = O2 * R0 * QS;                      // a2 stride (< 2^31 elements)
   T* qo = ws + w.q;
   if (e == 16 && active) {  // coarse i' = -16 lies beyond the filter reach
     qo[qcol] = T(0);
@@ -799,13 +803,16 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
   T a0[16], a1[16], fe_[pf_slots(PF)], fo_[pf_slots(PF)];
 #pragma unroll
   for (int k = 0; k < 16; ++k) a0[k] = a1[k] = T(0);
+  // first window y' = q0s - 15 + e: a multiple of 16 at or below 0
+  const int ph = (15 - e) & 15;
+  const int q0s = ph > 0 ? ph - 16 : 0;
 #pragma unroll
   for (int d = 0; d < PF; ++d) {
-    fe_[d] = ld_clamp(in, 2 * d, R1, R0);
-    fo_[d] = ld_clamp(in, 2 * d + 1, R1, R0);
+    fe_[d] = ld_clamp(in, 2 * (q0s + d), R1, R0);
+    fo_[d] = ld_clamp(in, 2 * (q0s + d) + 1, R1, R0);
   }
   const int qend = N1 + e + 14;
-  for (int q0 = 0; q0 <= qend; q0 += 16) {
+  for (int q0 = q0s; q0 <= qend; q0 += 16) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int q = q0 + u, sp = u % pf_slots(PF);
@@ -819,11 +826,11 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
       if (q <= qend) {
         const int p = 2 * q;
         if constexpr (PF == 0) {
-          ve = (active && p < R1) ? in[(int64_t)p * R0] : T(0);
-          vo = (active && p + 1 < R1) ? in[(int64_t)(p + 1) * R0] : T(0);
+          ve = (active && p >= 0 && p < R1) ? in[(int64_t)p * R0] : T(0);
+          vo = (active && p >= 0 && p + 1 < R1) ? in[(int64_t)(p + 1) * R0] : T(0);
         }
-        const T ge = (active && p < R1) ? ve : T(0);
-        const T go = (active && p + 1 < R1) ? vo : T(0);
+        const T ge = (active && p >= 0 && p < R1) ? ve : T(0);
+        const T go = (active && p >= 0 && p + 1 < R1) ? vo : T(0);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           const int sl = (u - k) & 15;
@@ -960,7 +967,8 @@ __global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict
     }
     od_n[dpat][drow] = n;
   };
-  const T* qin = ws + w.q + ((int64_t)(ch * O2 + zp) * R0) * O1 + yp;
+  const int QS = qrow_stride(O1);
+  const T* qin = ws + w.q + ((int64_t)(ch * O2 + zp) * R0) * QS + yp;
   const int c0 = 2 * a2 + 4 * a3, c1 = c0 + 1;
   const int64_t comp_x = (int64_t)N2 * O0 * N1, comp_y = (int64_t)N2 * N0 * O1;
   const int64_t comp_z = (int64_t)O2 * plane;
@@ -1021,8 +1029,8 @@ __global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict
   T fe_[kPfBackQ], fo_[kPfBackQ], kx0[kPfBackK], kx1[kPfBackK], ky0[kPfBackK], ky1[kPfBackK],
       kz0[kPfBackK], kz1[kPfBackK];
   auto fetch_q = [&](int q, int s) {
-    fe_[s] = ld_clamp(qin, 2 * q, R0, O1);
-    fo_[s] = ld_clamp(qin, 2 * q + 1, R0, O1);
+    fe_[s] = ld_clamp(qin, 2 * q, R0, QS);
+    fo_[s] = ld_clamp(qin, 2 * q + 1, R0, QS);
   };
   auto fetch_k = [&](int q, int s) {
     kx0[s] = ld_clamp(ox0, q - 15 + e, O0, N1);

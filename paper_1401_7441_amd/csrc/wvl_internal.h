@@ -73,6 +73,10 @@ struct SfWork {
 // y, then z, counted on the function's own box (so that the summation order
 // does not depend on the other functions of the chunk)
 // (the z part by k_kin_zmfma when zmfma: one block per 16 columns)
+// row stride (elements) of Q[ch][z'][px][y'], the y analysis output: O1
+// rounded up to 16, so that the 16-value chunks k_back_y writes (aligned by
+// its window phase) are whole 64-byte (FP32) or 128-byte (FP64) pieces
+__host__ __device__ inline int qrow_stride(int o1) { return (o1 + 15) & ~15; }
 __host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2, bool zmfma = false) {
   return axis == 0 ? (4 * n1 * n2 + 255) / 256
          : axis == 1 ? (4 * n0 * n2 + 63) / 64
