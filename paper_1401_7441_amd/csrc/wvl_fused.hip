@@ -511,7 +511,9 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
 //   AX = 0: c8x [c][z][x][y] -> ox[8][N2][O0][N1]   (256 threads, y fastest)
 //   AX = 1: c8  [c][z][y][x] -> oy[8][N2][N0][O1]   (64 threads, one column
 //           per lane along x; every 16 outputs are staged in LDS and written
-//           out 4 columns x 16 consecutive y' per store, y' fastest)
+//           out 4 columns x 16 consecutive y' per store, y' fastest; rows
+//           qrow_stride(O1) apart and windows at y' = 16 m, so that each
+//           store is one whole aligned piece of a row)
 //   AX = 2: c8x [c][z][x][y] -> oz[8][O2][N0][N1]   (256 threads, y fastest)
 template <typename T, int AX>
 __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
     const int x = (int)(col % N0), z = (int)(col / N0);
     ibase = (int64_t)z * plane + x;
     istride = N0;
-    obase = ((int64_t)z * N0 + x) * OA;
+    obase = ((int64_t)z * N0 + x) * qrow_stride(OA);
     ostride = 1;
   } else {                // column (y, z), y fastest
     const int y = (int)(col % N1), z = (int)(col / N1);
@@ -559,7 +561,7 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
     ostride = N1;
   }
   const int64_t icomp = (int64_t)N2 * plane;                          // component size
-  const int64_t ocomp = AX == 2 ? (int64_t)OA * plane : AX == 1 ? (int64_t)N2 * N0 * OA
+  const int64_t ocomp = AX == 2 ? (int64_t)OA * plane : AX == 1 ? (int64_t)N2 * N0 * qrow_stride(OA)
                                                                 : (int64_t)N2 * OA * N1;
   const T* inb = ws + (AX == 1 ? w.c8 : w.c8x);
   const T* in0 = inb + cb0 * icomp + ibase;
@@ -584,7 +586,9 @@ __global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
   const int istart = 14 - e;           // emits i' = -e first
   const int iend = NA - 1 + e + 14;    // emits i' = NA - 1 + e last
   const int ilo = istart - 28;
-  const int i0first = (ilo >= 0) ? (ilo & ~31) : -(((-ilo) + 31) & ~31);
+  // first window: the largest i0 <= ilo with i0 = 14 - e (mod 16), so that
+  // the staged outputs (AX = 1) start at y' = 16 m
+  const int i0first = ilo - ((((ilo - (14 - e)) % 16) + 16) % 16);
 #pragma unroll
   for (int d = 0; d < PF; ++d) {
     f0[d] = ld_clamp(in0, i0first + d, NA, istride);
@@ -970,10 +974,10 @@ __global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict
   const int QS = qrow_stride(O1);
   const T* qin = ws + w.q + ((int64_t)(ch * O2 + zp) * R0) * QS + yp;
   const int c0 = 2 * a2 + 4 * a3, c1 = c0 + 1;
-  const int64_t comp_x = (int64_t)N2 * O0 * N1, comp_y = (int64_t)N2 * N0 * O1;
+  const int64_t comp_x = (int64_t)N2 * O0 * N1, comp_y = (int64_t)N2 * N0 * QS;
   const int64_t comp_z = (int64_t)O2 * plane;
   const T* oxp = ws + w.ox + ((int64_t)(zin ? z : 0) * O0) * N1 + (yin ? y : 0);  // [c][z][x'][y]
-  const T* oyp = ws + w.oy + (int64_t)(zin ? z : 0) * N0 * O1 + yp;               // [c][z][x][y']
+  const T* oyp = ws + w.oy + (int64_t)(zin ? z : 0) * N0 * QS + yp;   // [c][z][x][y'], rows QS apart
   const T* ozp = ws + w.oz + (int64_t)zp * plane + (yin ? y : 0);                // [c][z'][x][y]
   T* const outc = out + sf.cout;
   T* const outf = out + sf.cout + sf.on_c;
@@ -1035,8 +1039,8 @@ __global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict
   auto fetch_k = [&](int q, int s) {
     kx0[s] = ld_clamp(ox0, q - 15 + e, O0, N1);
     kx1[s] = ld_clamp(ox1, q - 15 + e, O0, N1);
-    ky0[s] = ld_clamp(oy0, q - 15, N0, O1);
-    ky1[s] = ld_clamp(oy1, q - 15, N0, O1);
+    ky0[s] = ld_clamp(oy0, q - 15, N0, QS);
+    ky1[s] = ld_clamp(oy1, q - 15, N0, QS);
     kz0[s] = ld_clamp(oz0, q - 15, N0, N1);
     kz1[s] = ld_clamp(oz1, q - 15, N0, N1);
   };

@@ -720,7 +720,7 @@ static int64_t sf_elems(const SfDev& S) {
   const int64_t o0 = n0 + 2 * e, o1 = n1 + 2 * e, o2 = n2 + 2 * e;
   return 2 * align64(8 * n0 * n1 * n2) + align64(2 * n2 * r0 * r1) + align64(2 * o2 * r0 * r1) +
          align64(4 * o2 * r0 * qrow_stride((int)o1)) + align64(8 * n2 * o0 * n1) +
-         align64(8 * n2 * o1 * n0) +
+         align64(8 * n2 * qrow_stride((int)o1) * n0) +
          align64(8 * o2 * n0 * n1) + align64(4 * n2 * n1 * r0);
 }
 
@@ -770,7 +770,7 @@ static bool make_layout(const wvl_plan* P, int nbins, bool zmfma, Layout* L, std
         W.g2 = off;  off += align64(2 * o2 * r0 * r1);
         W.q = off;   off += align64(4 * o2 * r0 * qrow_stride((int)o1));
         W.ox = off;  off += align64(8 * n2 * o0 * n1);
-        W.oy = off;  off += align64(8 * n2 * o1 * n0);
+        W.oy = off;  off += align64(8 * n2 * qrow_stride((int)o1) * n0);
         W.oz = off;  off += align64(8 * o2 * n0 * n1);
         W.gx = off;  off += align64(4 * n2 * n1 * r0);
         ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
