@@ -888,6 +888,7 @@ __global__ __launch_bounds__(64) void k_back_y(const SfDev* __restrict__ sfs,
 // run or, for rows with several, its segments) make the stores consecutive.
 // The dense output box and a separate compression pass are not needed.
 constexpr int kBoRows = kBackOutRows, kBoThreads = 4 * kBackOutRows;
+constexpr uint32_t kBoGroup = 8;   // row blocks per XCD run (a power of two)
 // Orders a wave's LDS accesses across the lanes of that wave (LDS requests of
 // one wave are served in order; this keeps the compiler from moving them).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -913,13 +914,23 @@ __global__ __launch_bounds__(kBoThreads) void k_back_out(const SfDev* __restrict
   __shared__ int8_t od_js[2][kBoRuns][kBoRows], od_je[2][kBoRuns][kBoRows];
   __shared__ int32_t od_o[2][kBoRuns][kBoRows];
   __shared__ int32_t od_n[2][kBoRows];
-  const SfWork& w = wk[blockIdx.y];
+  // XCD-aware order: the 8 XCDs take blocks round-robin; each run of
+  // kBoGroup consecutive row blocks (logical order: rows fastest, then
+  // functions) goes to one XCD, whose L2 then serves the cache lines of Q
+  // and of the kinetic parts that neighbouring row blocks share
+  uint32_t lb = blockIdx.x + blockIdx.y * gridDim.x;
+  if (lb < ((gridDim.x * gridDim.y) & ~(8u * kBoGroup - 1u))) {
+    const uint32_t x = lb & 7, sl = lb >> 3;
+    lb = kBoGroup * (8 * (sl / kBoGroup) + x) + sl % kBoGroup;
+  }
+  const int bxl = (int)(lb % gridDim.x), byl = (int)(lb / gridDim.x);
+  const SfWork& w = wk[byl];
   const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2], e = sf.ext;
   const int R0 = 2 * N0 + 29;
   const int O0 = N0 + 2 * e, O1 = N1 + 2 * e, O2 = N2 + 2 * e;
   const int64_t nout = (int64_t)O1 * O2;
-  const int64_t r0 = (int64_t)blockIdx.x * kBoRows;
+  const int64_t r0 = (int64_t)bxl * kBoRows;
   if (r0 >= nout) return;   // uniform over the block
   const int tid = threadIdx.x;
   const int rl = tid >> 2, ch = tid & 3;
