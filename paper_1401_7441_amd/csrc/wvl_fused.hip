@@ -118,12 +118,15 @@ __device__ __forceinline__ T coef_at(const SfDev& sf, const wvl_seg* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// k_unpack: block = (function, component c, input plane z)
+// k_unpack: block = (function, group of G components, input plane z)
 // ---------------------------------------------------------------------------
-// Uncompress one coarse plane of one component into LDS through the compact
-// row runs (one record per row; rows with several runs walk the segments),
-// then write it twice: C8[c][z][y][x] (x fastest) and C8X[c][z][x][y]
-// (y fastest), both with consecutive threads on consecutive addresses.
+// Uncompress one coarse plane of G components (G = 8, 4, 2 or 1: as many as
+// the plane's LDS stage fits; the host picks it per chunk) through the
+// compact row runs (one record per row; rows with several runs walk the
+// segments), then write each twice: C8[c][z][y][x] (x fastest) and
+// C8X[c][z][x][y] (y fastest), both with consecutive threads on consecutive
+// addresses.  With G = 8 a thread reads the seven wavelets of its point, which
+// are consecutive in the compressed layout, in one block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(const SfDev* __restrict__ sfs,
                                                 const wvl_seg* __restrict__ seg,
@@ -131,44 +134,59 @@ __global__ __launch_bounds__(256) void k_unpack(const SfDev* __restrict__ sfs,
                                                 const RowRun* __restrict__ rr,
                                                 const T* __restrict__ psi,
                                                 const SfWork* __restrict__ wk,
-                                                T* __restrict__ ws) {
+                                                T* __restrict__ ws, int G) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* pl = reinterpret_cast<T*>(smem_raw);   // [N1][N0 + 1]
+  T* pl = reinterpret_cast<T*>(smem_raw);   // [G][N1][N0 + 1]
   const SfWork& w = wk[blockIdx.y];
   const SfDev& sf = sfs[w.id];
   const int N0 = sf.n[0], N1 = sf.n[1], N2 = sf.n[2];
-  const int c = blockIdx.x & 7, z = blockIdx.x >> 3;
+  const int ng = 8 / G;
+  const int cg = blockIdx.x % ng, z = blockIdx.x / ng;
   if (z >= N2) return;   // uniform over the block
-  const int fine = c == 0 ? 0 : 1;
-  const int ld = N0 + 1;
-  const int64_t fbase = sf.cin + sf.n_c + (c - 1);   // fine point k at fbase + 7 k
-  for (int idx = threadIdx.x; idx < N0 * N1; idx += 256) {
+  const int c0 = cg * G;                      // first component of the group
+  const int ld = N0 + 1, pls = N1 * ld;       // LDS row and plane strides
+  const int np = N0 * N1;
+  const int cf0 = max(c0, 1), cf1 = c0 + G;   // wavelet components of the group
+  const int64_t fbase = sf.cin + sf.n_c;      // fine point k at fbase + 7 k
+  for (int idx = threadIdx.x; idx < np; idx += 256) {
     const int y = idx / N0, x = idx - y * N0;
     const int64_t r = (int64_t)z * N1 + y;
-    const RowRun run = rr[sf.rr[fine] + r];
-    T v = T(0);
-    if (run.len == kMultiRun) {
-      v = coef_at<T>(sf, seg, rt, psi, c, r, sf.lo[0] + x);
-    } else {
-      const int dx = sf.lo[0] + x - (int)run.x0;
-      if (dx >= 0 && dx < (int)run.len) {
-        const int64_t k = run.off + dx;
-        v = fine ? psi[fbase + 7 * k] : psi[sf.cin + k];
+    const int gx = sf.lo[0] + x;
+    T* const o = pl + y * ld + x;
+    if (c0 == 0) {   // scaling coefficients
+      const RowRun run = rr[sf.rr[0] + r];
+      T v = T(0);
+      if (run.len == kMultiRun) {
+        v = coef_at<T>(sf, seg, rt, psi, 0, r, gx);
+      } else {
+        const int dx = gx - (int)run.x0;
+        if (dx >= 0 && dx < (int)run.len) v = psi[sf.cin + run.off + dx];
+      }
+      o[0] = v;
+    }
+    if (cf0 < cf1) {   // wavelets
+      const RowRun run = rr[sf.rr[1] + r];
+      if (run.len == kMultiRun) {
+        for (int c = cf0; c < cf1; ++c) o[(c - c0) * pls] = coef_at<T>(sf, seg, rt, psi, c, r, gx);
+      } else {
+        const int dx = gx - (int)run.x0;
+        const bool in = dx >= 0 && dx < (int)run.len;
+        const T* f = psi + fbase + 7 * (int64_t)(in ? run.off + dx : 0);
+        for (int c = cf0; c < cf1; ++c) o[(c - c0) * pls] = in ? f[c - 1] : T(0);
       }
     }
-    pl[y * ld + x] = v;
   }
   __syncthreads();
-  const int64_t plane = (int64_t)N0 * N1;
-  T* c8 = ws + w.c8 + ((int64_t)c * N2 + z) * plane;
-  T* c8x = ws + w.c8x + ((int64_t)c * N2 + z) * plane;
-  for (int idx = threadIdx.x; idx < N0 * N1; idx += 256) {
-    const int y = idx / N0, x = idx - y * N0;
-    c8[idx] = pl[y * ld + x];
+  const int64_t plane = (int64_t)np;
+  for (int idx = threadIdx.x; idx < G * np; idx += 256) {
+    const int c = idx / np, rem = idx - c * np;
+    const int y = rem / N0, x = rem - y * N0;
+    ws[w.c8 + ((int64_t)(c0 + c) * N2 + z) * plane + rem] = pl[c * pls + y * ld + x];
   }
-  for (int idx = threadIdx.x; idx < N0 * N1; idx += 256) {
-    const int x = idx / N1, y = idx - x * N1;
-    c8x[idx] = pl[y * ld + x];
+  for (int idx = threadIdx.x; idx < G * np; idx += 256) {
+    const int c = idx / np, rem = idx - c * np;
+    const int x = rem / N1, y = rem - x * N1;
+    ws[w.c8x + ((int64_t)(c0 + c) * N2 + z) * plane + rem] = pl[c * pls + y * ld + x];
   }
 }
 
@@ -515,8 +533,12 @@ __global__ __launch_bounds__(256) void k_pot_column(const SfDev* __restrict__ sf
 //           qrow_stride(O1) apart and windows at y' = 16 m, so that each
 //           store is one whole aligned piece of a row)
 //   AX = 2: c8x [c][z][x][y] -> oz[8][O2][N0][N1]   (256 threads, y fastest)
+// (FP32, y axis: the register allocator is asked for 3 waves per SIMD, which
+// costs a few spilled values and measured 7% faster than the 2 waves its
+// 184 VGPRs allow)
 template <typename T, int AX>
-__global__ __launch_bounds__(AX == 1 ? 64 : 256) void k_kin_col(
+__global__ __launch_bounds__(AX == 1 ? 64 : 256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && AX == 1 ? 3 : 1))) void k_kin_col(
     const SfDev* __restrict__ sfs, const SfWork* __restrict__ wk, int sf0, T* __restrict__ ws,
     double fac, double* __restrict__ kpart) {
   __shared__ T st[AX == 1 ? 2 * 16 * kSP : 1];   // AX = 1: [a][16 outputs][kSP]
@@ -1158,15 +1180,16 @@ int preload_fused_kernels() {
 
 int launch_unpack(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                   const RowRun* rr, const void* psi, const SfWork* wk, int nsf, int gridx,
-                  size_t lds, void* ws) {
+                  int group, size_t lds, void* ws) {
   if (nsf == 0 || gridx == 0) return 0;
+  if (group != 1 && group != 2 && group != 4 && group != 8) return (int)hipErrorInvalidValue;
   const dim3 g((unsigned)gridx, (unsigned)nsf);
   if (f64)
     hipLaunchKernelGGL(k_unpack<double>, g, dim3(256), lds, (hipStream_t)stream, sf, seg, rt, rr,
-                       (const double*)psi, wk, (double*)ws);
+                       (const double*)psi, wk, (double*)ws, group);
   else
     hipLaunchKernelGGL(k_unpack<float>, g, dim3(256), lds, (hipStream_t)stream, sf, seg, rt, rr,
-                       (const float*)psi, wk, (float*)ws);
+                       (const float*)psi, wk, (float*)ws, group);
   return (int)hipGetLastError();
 }
 

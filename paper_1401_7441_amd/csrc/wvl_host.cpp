@@ -774,17 +774,31 @@ static bool make_layout(const wvl_plan* P, int nbins, bool zmfma, Layout* L, std
         W.oz = off;  off += align64(8 * o2 * n0 * n1);
         W.gx = off;  off += align64(4 * n2 * n1 * r0);
         ch.maxbox_in = std::max(ch.maxbox_in, 8 * n0 * n1 * n2);
-        ch.grid_u = (int32_t)std::max<int64_t>(ch.grid_u, 8 * n2);
+        ch.grid_u[0] = (int32_t)std::max<int64_t>(ch.grid_u[0], n2);   // planes; scaled below
         ch.grid_ux = (int32_t)std::max<int64_t>(ch.grid_ux, (4 * n2 * n1 + 63) / 64);
         ch.grid_uy = (int32_t)std::max<int64_t>(ch.grid_uy, (2 * n2 * r0 + 255) / 256);
         for (int d = 0; d < 2; ++d)
-          ch.lds_u[d] = std::max<int64_t>(ch.lds_u[d], n1 * (n0 + 1) * (d ? 8 : 4));
+          ch.lds_u[d] = std::max<int64_t>(ch.lds_u[d], n1 * (n0 + 1) * (d ? 8 : 4));   // one plane
         ch.grid_b = (int32_t)std::max<int64_t>(ch.grid_b, (r0 * r1 + 255) / 256);
         ch.grid_kx = std::max(ch.grid_kx, kin_blocks(0, (int)n0, (int)n1, (int)n2));
         ch.grid_ky = std::max(ch.grid_ky, kin_blocks(1, (int)n0, (int)n1, (int)n2));
         ch.grid_kz = std::max(ch.grid_kz, kin_blocks(2, (int)n0, (int)n1, (int)n2, zmfma));
         ch.grid_by = (int32_t)std::max<int64_t>(ch.grid_by, (2 * o2 * r0 + 63) / 64);
         ch.grid_bx = (int32_t)std::max<int64_t>(ch.grid_bx, (o1 * o2 + kBackOutRows - 1) / kBackOutRows);
+      }
+      // k_unpack: as many components per block as the LDS stage fits
+      const int64_t nz = ch.grid_u[0];
+      for (int d = 0; d < 2; ++d) {
+        if (ch.lds_u[d] > kLdsBudget) {
+          *err = "a box's x-y plane (" + std::to_string(ch.lds_u[d]) +
+                 " bytes) does not fit the unpack stage's LDS";
+          return false;
+        }
+        int g = 8;   // grouped stages stay within 64 KiB of dynamic LDS
+        while (g > 1 && g * ch.lds_u[d] > 64 * 1024) g /= 2;
+        ch.group_u[d] = g;
+        ch.grid_u[d] = (int32_t)((8 / g) * nz);
+        ch.lds_u[d] *= g;
       }
       ch.nblk_pot = ch.grid_b;
       ch.nblk_kin = ch.grid_kx + ch.grid_ky + ch.grid_kz;
@@ -1072,7 +1086,7 @@ static wvl_status apply_chunk(wvl_plan* P, size_t c, int f64, uint32_t terms, co
   double* parts = (double*)((char*)workspace + align_bytes(P->lay.elems_span * sz));
   WVL_LAUNCH(ctx, KK_UNPACK,
              launch_unpack(f64, st, P->d_sf, P->d_seg, P->d_rt, P->d_rr, psi_c, wk, ch.nsf,
-                           ch.grid_u, (size_t)ch.lds_u[d], workspace));
+                           ch.grid_u[d], ch.group_u[d], (size_t)ch.lds_u[d], workspace));
   if (pot_on) {
     WVL_LAUNCH(ctx, KK_UP_X, launch_up(f64, st, 0, wk, P->d_sf, ch.nsf, ch.grid_ux, workspace));
     WVL_LAUNCH(ctx, KK_UP_Y, launch_up(f64, st, 1, wk, P->d_sf, ch.nsf, ch.grid_uy, workspace));
@@ -1376,7 +1390,7 @@ wvl_status wvl_synthesize(wvl_plan* P, wvl_dtype dt, const void* psi_c, void* fi
     hipStream_t st = ctx->stream;
     WVL_LAUNCH(ctx, KK_UNPACK,
                launch_unpack(f64, st, P->d_sf, P->d_seg, P->d_rt, P->d_rr, psi_c, wk, ch.nsf,
-                             ch.grid_u, (size_t)ch.lds_u[f64], workspace));
+                             ch.grid_u[f64], ch.group_u[f64], (size_t)ch.lds_u[f64], workspace));
     WVL_LAUNCH(ctx, KK_UP_X, launch_up(f64, st, 0, wk, P->d_sf, ch.nsf, ch.grid_ux, workspace));
     WVL_LAUNCH(ctx, KK_UP_Y, launch_up(f64, st, 1, wk, P->d_sf, ch.nsf, ch.grid_uy, workspace));
     WVL_LAUNCH(ctx, KK_UP_Z, launch_up_z(f64, st, wk, P->d_sf, ch.nsf, ch.grid_b, workspace,

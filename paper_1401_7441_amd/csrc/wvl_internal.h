@@ -87,7 +87,7 @@ __host__ __device__ inline int kin_blocks(int axis, int n0, int n1, int n2, bool
 struct ChunkDev {
   int32_t sf0, nsf;                // positions [sf0, sf0 + nsf) of the processing order
   int64_t maxbox_in;               // largest dense input box (elements)
-  int32_t grid_u;                  // k_unpack: 8 planes per input z
+  int32_t grid_u[2], group_u[2];   // k_unpack: (8 / group) blocks per input z
   int32_t grid_ux, grid_uy;        // k_up_x, k_up_y
   int64_t lds_u[2];
   int32_t grid_b;                  // k_pot_column
@@ -119,7 +119,7 @@ int launch_scatter(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, c
 int launch_fill(int f64, void* stream, void* ptr, int64_t n);
 int launch_unpack(int f64, void* stream, const SfDev* sf, const wvl_seg* seg, const int32_t* rt,
                   const RowRun* rr, const void* psi, const SfWork* wk, int nsf, int gridx,
-                  size_t lds, void* ws);
+                  int group, size_t lds, void* ws);
 int launch_up(int f64, void* stream, int axis, const SfWork* wk, const SfDev* sf, int nsf,
               int gridx, void* ws);
 int launch_up_z(int f64, void* stream, const SfWork* wk, const SfDev* sf, int nsf, int gridx,
