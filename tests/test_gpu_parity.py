@@ -247,6 +247,56 @@ def test_edge_boxes_fp64():
         assert abs(ek[k] - rk) <= 1e-12 * max(1.0, abs(rk)), k
 
 
+def _one_point_segments(seg):
+    """The same points as one-point segments: segments may touch, so a row
+    then holds as many runs as points."""
+    out = [(x, x, s[2], s[3]) for s in seg for x in range(int(s[0]), int(s[1]) + 1)]
+    return np.array(out, dtype=np.int64).reshape(-1, 4)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_output_rows_with_many_runs(dtype, tol):
+    """Rows of 18-24 points (several 16-point windows of the x analysis
+    pass) whose patterns hold many runs: random masks, and for every other
+    function the same masks as one-point segments, so that a window meets
+    up to 16 runs of a row (the most it can).  Dense and sparse output
+    masks, ext 2 and 3."""
+    _print(f"case: output rows with many runs, {dtype}")
+    g = inputs.geometry("batch1k", nsf=1)
+    g.grid_n = (56, 24, 24)
+    rng = np.random.default_rng(29)
+    lrs = []
+    for k in range(4):
+        lo = (int(rng.integers(6, 10)), int(rng.integers(6, 9)), int(rng.integers(6, 9)))
+        dims = (int(rng.integers(18, 25)), int(rng.integers(3, 6)), int(rng.integers(3, 6)))
+        ext = 2 if k % 2 == 0 else 3
+        m = rng.random((dims[2], dims[1], dims[0])) < 0.7
+        m.flat[0] = True
+        fm = m & (rng.random(m.shape) < 0.6)
+        olo = [lo[a] - ext for a in range(3)]
+        oshape = (dims[2] + 2 * ext, dims[1] + 2 * ext, dims[0] + 2 * ext)
+        om = rng.random(oshape) < (0.95 if k < 2 else 0.5)
+        ofm = om & (rng.random(oshape) < 0.8)
+        segs = [LR.segments_from_mask(m, lo), LR.segments_from_mask(fm, lo),
+                LR.segments_from_mask(om, olo), LR.segments_from_mask(ofm, olo)]
+        if k % 2 == 1:
+            segs = [_one_point_segments(s) for s in segs]
+        lrs.append(LR.Locreg(lo=lo, dims=dims, ext=ext, cseg=segs[0], fseg=segs[1],
+                             ocseg=segs[2], ofseg=segs[3]))
+    g.centers = np.zeros((len(lrs), 3))
+    g.envelope_sigma = np.full(len(lrs), 100.0)
+    g.domain_lo = np.zeros(3)
+    g.domain_hi = np.array(g.grid_n) * g.h
+    case = Case(g, lrs, normalize=False)
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    _, _, out, ek, _ = case.run(dt)
+    for k in range(len(lrs)):
+        ref, rk, _ = case.oracle(k)
+        assert rel_err(out[case.out_slice(k)], ref) < tol, k
+        if dtype == "f64":
+            assert abs(ek[k] - rk) <= 1e-12 * max(1.0, abs(rk)), k
+
+
 def test_chunked_plan_matches_single_chunk_bitwise(spheres):
     _print("case: chunked workspace")
     plan1, _, out1, ek1, ep1 = spheres.run(torch.float64)
