@@ -297,6 +297,36 @@ def test_output_rows_with_many_runs(dtype, tol):
             assert abs(ek[k] - rk) <= 1e-12 * max(1.0, abs(rk)), k
 
 
+def test_wide_flat_box_fp64():
+    """A 70 x 70 x 2 box in FP64: its x-y plane (39.8 KB) leaves room in the
+    unpack stage for one component per block only, and its 74-point output
+    rows span five windows of the x analysis pass."""
+    _print("case: wide flat box, f64")
+    g = inputs.geometry("batch1k", nsf=1)
+    g.grid_n = (80, 80, 12)
+    rng = np.random.default_rng(31)
+    lo, dims, ext = (5, 5, 5), (70, 70, 2), 2
+    m = rng.random((dims[2], dims[1], dims[0])) < 0.8
+    m.flat[0] = True
+    fm = m & (rng.random(m.shape) < 0.3)
+    olo = [lo[a] - ext for a in range(3)]
+    oshape = (dims[2] + 2 * ext, dims[1] + 2 * ext, dims[0] + 2 * ext)
+    om = rng.random(oshape) < 0.85
+    ofm = om & (rng.random(oshape) < 0.3)
+    lrs = [LR.Locreg(lo=lo, dims=dims, ext=ext, cseg=LR.segments_from_mask(m, lo),
+                     fseg=LR.segments_from_mask(fm, lo), ocseg=LR.segments_from_mask(om, olo),
+                     ofseg=LR.segments_from_mask(ofm, olo))]
+    g.centers = np.zeros((1, 3))
+    g.envelope_sigma = np.full(1, 100.0)
+    g.domain_lo = np.zeros(3)
+    g.domain_hi = np.array(g.grid_n) * g.h
+    case = Case(g, lrs, normalize=False)
+    _, _, out, ek, _ = case.run(torch.float64)
+    ref, rk, _ = case.oracle(0)
+    assert rel_err(out[case.out_slice(0)], ref) < 1e-12
+    assert abs(ek[0] - rk) <= 1e-12 * max(1.0, abs(rk))
+
+
 def test_chunked_plan_matches_single_chunk_bitwise(spheres):
     _print("case: chunked workspace")
     plan1, _, out1, ek1, ep1 = spheres.run(torch.float64)
